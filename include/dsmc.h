@@ -1,0 +1,233 @@
+/*
+ * dsmc.h -- C ABI of the MI355X (gfx950) direct simulation Monte Carlo hot path.
+ *
+ * The paper filed for this project (arXiv 2301.05985) contains no Monte Carlo
+ * method; the operations below follow the standard published DSMC method:
+ * Bird, "Molecular Gas Dynamics and the Direct Simulation of Gas Flows" (1994)
+ * for free flight, diffuse/specular/periodic walls, cell indexing, the
+ * no-time-counter (NTC) collision scheme and cell sampling; Salmon et al.
+ * (SC'11) for the Philox4x32-10 counter-based generator; Al-Mohssen &
+ * Hadjiconstantinou (ESAIM M2AN 2010) for the importance-weight variance
+ * reduction.  The problem solved is the spatially homogeneous or 1-D/2-D
+ * Boltzmann equation for a simple gas, df/dt + c . grad_x f = Q(f, f), with
+ * kinetic wall conditions; units take Boltzmann's constant and the molecular
+ * mass as 1.
+ *
+ * Conventions for every call:
+ *   - Every function returns dsmc_status (0 = DSMC_OK, negative = error).  No
+ *     C++ exception and no abort crosses the ABI.
+ *   - Pointers named "device" are HIP device pointers (e.g. torch tensor
+ *     data pointers); pointers named "host" are ordinary host memory.
+ *   - The caller owns every buffer passed in (particles, workspace, host
+ *     arrays).  The context borrows device buffers until dsmc_destroy and
+ *     copies host arrays during the call.  The library owns only the context
+ *     object and the HIP graph it records; it never allocates device memory.
+ *   - Work is enqueued asynchronously on the HIP stream given to dsmc_init.
+ *     Device-side errors (too many wall hits, non-finite velocities, a cell
+ *     larger than the kernels can hold) are recorded on the device and
+ *     reported by the next synchronising call (dsmc_sample, dsmc_diagnostics,
+ *     dsmc_checkpoint); the first error is sticky until dsmc_destroy.
+ *   - One context is driven by one host thread at a time.
+ */
+#ifndef DSMC_H
+#define DSMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DSMC_ABI_VERSION 1
+#define DSMC_NSUM 26          /* FP64 running sums per cell (see dsmc_sample) */
+#define DSMC_MLP_NPARAM 4673  /* learned-majorant network 6-64-64-1 */
+
+typedef struct dsmc_ctx dsmc_ctx; /* opaque, owned by the library */
+
+typedef enum {
+    DSMC_OK = 0,
+    DSMC_EINVAL = -1,      /* invalid argument or configuration; nothing was launched */
+    DSMC_ENOMEM = -2,      /* workspace smaller than dsmc_workspace_size reports */
+    DSMC_EHIP = -3,        /* a HIP runtime call failed */
+    DSMC_ENONFINITE = -4,  /* a velocity became NaN or infinite */
+    DSMC_EWALLHITS = -5,   /* a particle hit walls more than max_wall_hits times in one step */
+    DSMC_ECAPACITY = -6,   /* a per-cell candidate count or cell size exceeded the kernels' limits */
+    DSMC_EABI = -7         /* abi_version mismatch */
+} dsmc_status;
+
+enum { DSMC_WALL_DIFFUSE = 0, DSMC_WALL_SPECULAR = 1, DSMC_WALL_PERIODIC = 2 };
+enum { DSMC_HARD_SPHERE = 0, DSMC_MAXWELL = 1 };
+enum { DSMC_MAJORANT_EXACT = 0, DSMC_MAJORANT_LEARNED = 1 };
+
+/* Run configuration.  Cells: dims == 1 divides [0, length[0]] into n_cells[0]
+ * equal cells; dims == 2 divides [0, length[0]] x [0, length[1]] into
+ * n_cells[0] x n_cells[1] cells numbered iy * n_cells[0] + ix; dims == 0 is a
+ * batch of n_cells[0] independent spatially homogeneous cells ("instances"),
+ * instance b owning particles inst_offset[b] .. inst_offset[b+1]-1. */
+typedef struct {
+    int32_t abi_version;      /* must equal DSMC_ABI_VERSION */
+    int32_t dims;             /* 0, 1 or 2 */
+    int32_t real_bytes;       /* 4: FP32 positions/velocities/weights, 8: FP64 */
+    int32_t molecule;         /* DSMC_HARD_SPHERE or DSMC_MAXWELL (sigma * g = const) */
+    int32_t n_cells[2];       /* (nx, ny); dims 1: ny ignored; dims 0: (n_instances, 1) */
+    int32_t majorant;         /* DSMC_MAJORANT_EXACT or DSMC_MAJORANT_LEARNED */
+    int32_t vr;               /* 1: importance-weight variance reduction */
+    double length[2];         /* domain extents (dims >= 1) */
+    double dt;                /* time step */
+    double sigma;             /* hard sphere: total cross-section; Maxwell: the constant sigma*g */
+    double FN;                /* real molecules per simulated particle */
+    double vr_T0;             /* temperature of the reference equilibrium (at rest) */
+    int32_t wall_kind[4];     /* walls x-, x+, y-, y+: DSMC_WALL_* */
+    double wall_T[4];         /* diffuse wall temperatures */
+    double wall_u[4][3];      /* wall velocities (tangential components are used) */
+    uint64_t seed;            /* Philox key: (low word, high word) */
+    int64_t n_particles;
+    const double *cell_volume;   /* host [n_cells] volumes, or NULL: uniform cell volume
+                                    (dims 1: dx * 1 * 1, dims 2: dx * dy * 1, dims 0: 1) */
+    const int64_t *inst_offset;  /* host [n_cells[0] + 1], dims == 0 only, ascending */
+    int32_t max_wall_hits;    /* wall interactions allowed per particle per step (0 -> 8) */
+    int32_t reserved;
+} dsmc_config;
+
+/* Structure-of-arrays particle state (device pointers).  Element type is
+ * float (real_bytes 4) or double (real_bytes 8).  y is used only when
+ * dims == 2, x only when dims >= 1, w only when vr == 1 (may be NULL
+ * otherwise).  id holds a unique persistent particle number < 2^32; within a
+ * cell the canonical collision order is ascending id (dims >= 1) or storage
+ * order (dims == 0). */
+typedef struct {
+    void *x, *y, *cx, *cy, *cz, *w;
+    uint32_t *id;
+} dsmc_soa;
+
+typedef struct {
+    uint64_t steps;           /* steps taken so far (the next step's index) */
+    uint64_t candidates;      /* NTC candidates since the last reset of the samples */
+    uint64_t accepted;        /* accepted collisions since the last reset */
+    uint64_t overshoot;       /* candidates with relative speed above the majorant in use */
+    uint64_t wall_hits;       /* wall interactions */
+    uint64_t learned_used;    /* cell-steps that used the verified learned majorant */
+    uint64_t fallback;        /* cell-steps whose learned proposal failed verification */
+    uint64_t learned_skip;    /* cell-steps whose proposal was not below the exact bound */
+    uint64_t vr_nonfinite;    /* cell samples with non-finite weighted sums (weight divergence) */
+    uint64_t big_cells;       /* cell-steps processed by the global-memory collision kernel */
+} dsmc_diag;
+
+/* Bytes of device workspace the configuration needs (alternate particle
+ * buffer for the counting sort, per-cell offsets, FP64 running sums,
+ * counters, scratch).  EINVAL on an invalid configuration. */
+dsmc_status dsmc_workspace_size(const dsmc_config *cfg, size_t *bytes);
+
+/* Validate the configuration, bind the particle buffers (device, caller
+ * owned, n_particles each) and the workspace (device, >= workspace size,
+ * 256-byte aligned), zero the running sums, and record the per-step HIP
+ * graph on `hip_stream` (a hipStream_t; NULL = default stream).  For
+ * dims == 0 the particle counts per instance come from inst_offset.  The
+ * particle arrays are not read during this call except for dims == 0
+ * scheduling, which uses only inst_offset.  No device allocation. */
+dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *particles, void *workspace,
+                      size_t ws_bytes, void *hip_stream, dsmc_ctx **out);
+
+/* Enqueue n_steps time steps (asynchronous).  Each step runs, in order:
+ * free flight with wall conditions and cell indexing (dims >= 1), the
+ * counting sort into cells, NTC collisions in every cell with the majorant
+ * chosen by cfg->majorant, the importance-weight update (vr == 1), and
+ * accumulation of the cell moments into the running sums. */
+dsmc_status dsmc_step(dsmc_ctx *ctx, int32_t n_steps);
+
+/* Synchronise the stream and copy out the running sums (host
+ * [n_cells][DSMC_NSUM] doubles, may be NULL), the per-cell counters (host
+ * [n_cells][2] uint64: NTC candidates, accepted collisions; may be NULL) and
+ * the number of sampled steps (may be NULL).  Sums, per cell:
+ *   [0] N, [1..3] sum c, [4..9] sum c_d c_e (xx yy zz xy xz yz),
+ *   [10..12] sum c_d |c|^2, and [13..25] the same 13 sums weighted by (1 - W)
+ *   when vr == 1 (zero otherwise).
+ * reset != 0 zeroes sums, counters and the sample count after copying. */
+dsmc_status dsmc_sample(dsmc_ctx *ctx, double *sums_host, uint64_t *counters_host,
+                        uint64_t *n_samples, int32_t reset);
+
+/* Device pointers of the buffers that hold the current particle state (the
+ * counting sort alternates between the caller's buffers and the workspace).
+ * Valid until the next dsmc_step. */
+dsmc_status dsmc_particles(dsmc_ctx *ctx, dsmc_soa *current);
+
+/* Synchronise and report diagnostics (host struct); returns the sticky
+ * device error, if any. */
+dsmc_status dsmc_diagnostics(dsmc_ctx *ctx, dsmc_diag *out);
+
+/* Set the index of the next step (checkpoint/resume: the random stream is
+ * keyed by step, so resuming at the same step continues the same run). */
+dsmc_status dsmc_set_step(dsmc_ctx *ctx, uint64_t next_step);
+
+/* Load the learned-majorant network: n == DSMC_MLP_NPARAM bfloat16 values
+ * (host) in the order W1[64][6], b1[64], W2[64][64], b2[64], w3[64], b3; the
+ * output is log2 of the predicted largest relative speed of the cell, and the
+ * proposal is the lattice value 2^(k/64), k = ceil(64 (y + delta)).  The
+ * proposal is used only where the kernel proves it bounds every pair of the
+ * cell; elsewhere the exact bound is used, so results keep the law of the
+ * exact method.  EINVAL if n is wrong or cfg->majorant is not LEARNED. */
+dsmc_status dsmc_set_majorant_model(dsmc_ctx *ctx, const uint16_t *bf16_weights_host, int64_t n,
+                                    double delta);
+
+/* Checkpoint: with host_blob == NULL, *bytes receives the size needed;
+ * otherwise the particle state, step index, running sums and counters are
+ * copied into host_blob (synchronising).  Restore copies them back into the
+ * context's buffers; a run restored at step s continues bit for bit like
+ * the uninterrupted run. */
+dsmc_status dsmc_checkpoint(dsmc_ctx *ctx, void *host_blob, size_t *bytes);
+dsmc_status dsmc_restore(dsmc_ctx *ctx, const void *host_blob, size_t bytes);
+
+/* Run one step with every kernel launched separately and timed with HIP
+ * events on the context's stream; ms_host receives up to max_kernels
+ * per-kernel durations (milliseconds) in launch order, *n_kernels their
+ * number and names_host (may be NULL) a '\n'-separated list of kernel names
+ * (at most names_len bytes).  Synchronising.  Used for roofline reports. */
+dsmc_status dsmc_profile_step(dsmc_ctx *ctx, float *ms_host, int32_t max_kernels,
+                              int32_t *n_kernels, char *names_host, int32_t names_len);
+
+/* Release the context and its HIP graph (the caller's buffers stay valid). */
+dsmc_status dsmc_destroy(dsmc_ctx *ctx);
+
+/* Static text for a status code. */
+const char *dsmc_status_string(dsmc_status status);
+
+/* ---------------------------------------------------------------------
+ * Learned majorant: training-data collection and network training.
+ * ------------------------------------------------------------------ */
+
+/* For every cell (dims 0: instance) of the current state, write the six
+ * FP32 input features of the learned majorant (device [n_cells][6]) and
+ * the label log2 of the exact largest pairwise relative speed (device
+ * [n_cells] float; -inf marks cells with fewer than two particles).
+ * Features: log2(number density), u_x/sqrt(T), u_y/sqrt(T), log2(T),
+ * P_xx/p - 1, P_xy/p, from FP64 moments of the cell.  Asynchronous. */
+dsmc_status dsmc_collect_features(dsmc_ctx *ctx, float *features_dev, float *labels_dev);
+
+/* Forward pass of the 6-64-64-1 ReLU network in FP32 (params device
+ * [DSMC_MLP_NPARAM] float, layout as in dsmc_set_majorant_model; x device
+ * [n][6]; y device [n]).  Asynchronous on hip_stream. */
+dsmc_status dsmc_mlp_forward(const float *params_dev, const float *x_dev, int64_t n,
+                             float *y_dev, void *hip_stream);
+
+/* Mean expectile loss  L = (1/n) sum |tau - 1[r < 0]| r^2,  r = label - y,
+ * and its gradient with respect to every parameter (device
+ * [DSMC_MLP_NPARAM] float, overwritten) and the loss (device float [1]).
+ * Rows with a non-finite label are skipped.  scratch_dev must hold
+ * dsmc_mlp_scratch_floats(n) floats.  Asynchronous. */
+dsmc_status dsmc_mlp_loss_grad(const float *params_dev, const float *x_dev, const float *label_dev,
+                               int64_t n, double tau, float *grad_dev, float *loss_dev,
+                               float *scratch_dev, void *hip_stream);
+int64_t dsmc_mlp_scratch_floats(int64_t n);
+
+/* One Adam update (Kingma & Ba 2015) of params in place from grad, with the
+ * first and second moment buffers m, v (device [n_param] float) and the
+ * 1-based step index t.  Asynchronous. */
+dsmc_status dsmc_mlp_adam(float *params_dev, const float *grad_dev, float *m_dev, float *v_dev,
+                          int64_t n_param, int64_t t, double lr, double beta1, double beta2,
+                          double eps, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DSMC_H */

@@ -61,6 +61,9 @@ class OrcCfg(ctypes.Structure):
         ("inst_offset", ctypes.c_void_p),
         ("mlp", ctypes.c_void_p),
         ("mlp_delta", ctypes.c_double),
+        ("cell_ids", ctypes.c_void_p),
+        ("only_cells", ctypes.c_void_p),
+        ("n_only", ctypes.c_int64),
     ]
 
 
@@ -199,6 +202,10 @@ class Oracle:
             vol = np.ascontiguousarray(params["cell_volume"], dtype=np.float64)
             self._keep.append(vol)
             self.cfg.cell_volume = vol.ctypes.data
+        if params.get("cell_ids") is not None:
+            ids = np.ascontiguousarray(params["cell_ids"], dtype=np.int64)
+            self._keep.append(ids)
+            self.cfg.cell_ids = ids.ctypes.data
         if params.get("mlp") is not None:
             w = np.ascontiguousarray(params["mlp"], dtype=np.float32)
             assert w.size == MLP_NPARAM
@@ -219,6 +226,19 @@ class Oracle:
         if rc != 0:
             raise RuntimeError("oracle run failed with status %d" % rc)
         return log
+
+    def run_sampled(self, cells):
+        """One step in which every particle streams and is grouped but only the
+        listed cells collide and are sampled (outputs the oracle can compute one
+        by one at full size)."""
+        only = np.ascontiguousarray(np.unique(np.asarray(cells, dtype=np.int64)))
+        self.cfg.only_cells = only.ctypes.data
+        self.cfg.n_only = len(only)
+        try:
+            self.run(1)
+        finally:
+            self.cfg.only_cells = None
+            self.cfg.n_only = 0
 
     def reset_samples(self):
         self.sums[:] = 0.0

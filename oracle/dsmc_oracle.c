@@ -120,6 +120,9 @@ typedef struct {
     const int64_t *inst_offset;         /* dims == 0: [n_inst + 1] */
     const float *mlp;                   /* learned majorant weights (FP32 copy of BF16), or NULL */
     double mlp_delta;                   /* lattice margin in log2 units */
+    const int64_t *cell_ids;            /* dims == 0: random-stream id of each instance, or NULL (= index) */
+    const int64_t *only_cells;          /* if not NULL: collide and sample only these cells ... */
+    int64_t n_only;                     /* ... (sorted ascending, n_only of them) */
 } orc_cfg;
 
 typedef struct {
@@ -688,11 +691,18 @@ int FN(orc_run)(const orc_cfg *cfg, int64_t np, REAL *x, REAL *y, REAL *cx, REAL
             for (int64_t c = 0; c <= ncell; ++c) start[c] = cfg->inst_offset[c];
             for (int64_t p = 0; p < np; ++p) list[p] = p;
         }
+        int64_t next_only = 0;
         for (int64_t c = 0; c < ncell && rc == 0; ++c) {
+            if (cfg->only_cells) {
+                /* sampled-output mode: every particle streams, only the listed cells collide */
+                if (next_only >= cfg->n_only || cfg->only_cells[next_only] != c) continue;
+                next_only++;
+            }
             int64_t n = start[c + 1] - start[c];
             double V = cfg->cell_volume ? cfg->cell_volume[c] : Vuni;
             int32_t lf = 0;
-            rc = collide_cell(cfg, &s, list + start[c], n, (uint32_t)c, step, V, &counters[2 * c], diag, &lf);
+            uint32_t key_id = (cfg->dims == 0 && cfg->cell_ids) ? (uint32_t)cfg->cell_ids[c] : (uint32_t)c;
+            rc = collide_cell(cfg, &s, list + start[c], n, key_id, step, V, &counters[2 * c], diag, &lf);
             if (learned_log) learned_log[(int64_t)si * ncell + c] = lf;
             if (rc == 0) {
                 rc = sample_cell(cfg, &s, list + start[c], n, &sums[NSUM * c]);

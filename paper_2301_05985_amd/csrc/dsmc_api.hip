@@ -1,0 +1,668 @@
+// dsmc_api.hip -- host side of the C ABI declared in include/dsmc.h.
+//
+// The context borrows the caller's particle buffers and workspace, carves
+// the workspace into the counting-sort double buffer, per-cell arrays and
+// FP64 running sums, and records the per-step kernel sequence into HIP
+// graphs on a private capture stream; dsmc_step replays them on the
+// caller's stream.  No device memory is allocated here.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/dsmc.h"
+#include "dsmc_collide_kernels.h"
+
+using namespace dsmc;
+
+#define HIP_TRY(expr)                                  \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return DSMC_EHIP;        \
+    } while (0)
+
+namespace {
+
+constexpr int kGraphSteps = 8;  // steps recorded per graph (even: the sort ping-pongs)
+constexpr size_t kAlign = 256;
+constexpr size_t kMaxLds = 64 * 1024;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t alt[7];  // x y cx cy cz w id of the second particle buffer
+    size_t count, offset, cursor, sums, counters, volume, state, big_list, perm, owner, sched;
+    size_t mlp, lattice;
+    size_t total;
+};
+
+int64_t n_cells_of(const dsmc_config &c) {
+    if (c.dims == 2) return (int64_t)c.n_cells[0] * c.n_cells[1];
+    return c.n_cells[0];
+}
+
+dsmc_status validate(const dsmc_config *c) {
+    if (!c) return DSMC_EINVAL;
+    if (c->abi_version != DSMC_ABI_VERSION) return DSMC_EABI;
+    if (c->dims < 0 || c->dims > 2) return DSMC_EINVAL;
+    if (c->real_bytes != 4 && c->real_bytes != 8) return DSMC_EINVAL;
+    if (c->molecule != DSMC_HARD_SPHERE && c->molecule != DSMC_MAXWELL) return DSMC_EINVAL;
+    if (c->majorant != DSMC_MAJORANT_EXACT && c->majorant != DSMC_MAJORANT_LEARNED) return DSMC_EINVAL;
+    if (c->n_cells[0] < 1 || (c->dims == 2 && c->n_cells[1] < 1)) return DSMC_EINVAL;
+    if (n_cells_of(*c) > (int64_t)1 << 30) return DSMC_EINVAL;
+    if (c->n_particles < 0 || c->n_particles > (int64_t)0x7FFFFFFF) return DSMC_EINVAL;
+    if (!(c->dt > 0) || !(c->sigma >= 0) || !(c->FN > 0)) return DSMC_EINVAL;
+    if (c->vr && !(c->vr_T0 > 0)) return DSMC_EINVAL;
+    if (c->dims >= 1) {
+        if (!(c->length[0] > 0) || (c->dims == 2 && !(c->length[1] > 0))) return DSMC_EINVAL;
+        for (int k = 0; k < (c->dims == 2 ? 4 : 2); ++k) {
+            if (c->wall_kind[k] < 0 || c->wall_kind[k] > 2) return DSMC_EINVAL;
+            if (c->wall_kind[k] == DSMC_WALL_DIFFUSE && !(c->wall_T[k] > 0)) return DSMC_EINVAL;
+        }
+        // periodic walls come in pairs
+        if ((c->wall_kind[0] == DSMC_WALL_PERIODIC) != (c->wall_kind[1] == DSMC_WALL_PERIODIC)) return DSMC_EINVAL;
+        if (c->dims == 2 && (c->wall_kind[2] == DSMC_WALL_PERIODIC) != (c->wall_kind[3] == DSMC_WALL_PERIODIC))
+            return DSMC_EINVAL;
+    } else {
+        if (!c->inst_offset) return DSMC_EINVAL;
+        if (c->inst_offset[0] != 0 || c->inst_offset[c->n_cells[0]] != c->n_particles) return DSMC_EINVAL;
+        for (int b = 0; b < c->n_cells[0]; ++b)
+            if (c->inst_offset[b + 1] < c->inst_offset[b]) return DSMC_EINVAL;
+    }
+    if (c->cell_volume)
+        for (int64_t i = 0; i < n_cells_of(*c); ++i)
+            if (!(c->cell_volume[i] > 0)) return DSMC_EINVAL;
+    if (c->max_wall_hits < 0) return DSMC_EINVAL;
+    return DSMC_OK;
+}
+
+Layout make_layout(const dsmc_config &c) {
+    Layout L;
+    std::memset(&L, 0, sizeof(L));
+    const size_t n = (size_t)c.n_particles, rb = (size_t)c.real_bytes, nc = (size_t)n_cells_of(c);
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + std::max<size_t>(bytes, 1)); return o; };
+    if (c.dims >= 1) {
+        for (int f = 0; f < 6; ++f) L.alt[f] = take(n * rb);
+        L.alt[6] = take(n * 4);
+        L.count = take(nc * 4);
+        L.cursor = take(nc * 4);
+    }
+    L.offset = take((nc + 1) * 4);
+    L.sums = take(nc * kNsum * 8);
+    L.counters = take(nc * 2 * 8);
+    L.volume = take(nc * 8);
+    L.state = take(sizeof(DevState));
+    L.big_list = take(nc * 4);
+    L.perm = take(n * 4);
+    L.owner = take(n * 4);
+    L.sched = take(nc * 4);
+    L.mlp = take(DSMC_MLP_NPARAM * 4);
+    L.lattice = take(kLatticeSize * 8);
+    L.total = off;
+    return L;
+}
+
+struct Bufs {
+    void *x, *y, *cx, *cy, *cz, *w;
+    uint32_t *id;
+};
+
+}  // namespace
+
+struct dsmc_ctx {
+    dsmc_config cfg;
+    std::vector<double> volume_host;
+    hipStream_t stream = nullptr;    // caller's stream
+    hipStream_t capture = nullptr;   // private stream used only to record graphs
+    unsigned char *ws = nullptr;
+    Layout L;
+    Bufs buf[2];
+    int cur = 0;                     // buffer that holds the current state
+    int64_t n = 0, ncell = 0;
+    int cap = 0;
+    size_t lds = 0;
+    int big_grid = 0;
+    bool any_big_possible = false;
+    uint32_t *count = nullptr, *offset = nullptr, *cursor = nullptr, *big_list = nullptr,
+             *perm = nullptr, *owner = nullptr, *sched = nullptr;
+    double *sums = nullptr, *volume = nullptr, *lattice = nullptr;
+    unsigned long long *counters = nullptr;
+    float *mlp = nullptr;
+    bool mlp_loaded = false;
+    double mlp_delta = 0.0;
+    DevState *st = nullptr;
+    Geo geo;
+    double Vuni = 1.0;
+    hipGraphExec_t g1[2] = {nullptr, nullptr}, gk[2] = {nullptr, nullptr};
+    dsmc_status sticky = DSMC_OK;
+};
+
+namespace {
+
+template <typename R>
+Soa<R> soa_of(const Bufs &b) {
+    Soa<R> s;
+    s.x = (R *)b.x; s.y = (R *)b.y; s.cx = (R *)b.cx; s.cy = (R *)b.cy; s.cz = (R *)b.cz;
+    s.w = (R *)b.w; s.id = b.id;
+    return s;
+}
+
+template <typename R>
+CollideArgs<R> collide_args(dsmc_ctx *c, int buf) {
+    CollideArgs<R> a;
+    a.s = soa_of<R>(c->buf[buf]);
+    a.start = c->offset;
+    a.sched = c->cfg.dims == 0 ? c->sched : nullptr;
+    a.volume = c->cfg.cell_volume ? c->volume : nullptr;
+    a.Vuni = c->Vuni;
+    a.dt = c->cfg.dt;
+    a.sigma = c->cfg.sigma;
+    a.FN = c->cfg.FN;
+    a.molecule = c->cfg.molecule;
+    a.cap = c->cap;
+    a.k0 = (uint32_t)(c->cfg.seed & 0xFFFFFFFFull);
+    a.k1 = (uint32_t)(c->cfg.seed >> 32);
+    a.sums = c->sums;
+    a.counters = c->counters;
+    a.st = c->st;
+    a.big_list = c->big_list;
+    a.perm_g = c->perm;
+    a.owner_g = c->owner;
+    a.mlp = (c->cfg.majorant == DSMC_MAJORANT_LEARNED && c->mlp_loaded) ? c->mlp : nullptr;
+    a.lattice = c->lattice;
+    a.delta = c->mlp_delta;
+    return a;
+}
+
+// Kernel launch helper recording an optional event before each launch.
+struct Launcher {
+    hipStream_t s;
+    std::vector<hipEvent_t> *ev;
+    std::vector<const char *> *names;
+    void mark(const char *name) {
+        if (ev) {
+            hipEvent_t e;
+            (void)hipEventCreate(&e);
+            (void)hipEventRecord(e, s);
+            ev->push_back(e);
+            names->push_back(name);
+        }
+    }
+};
+
+template <typename R, bool VR, bool BYID>
+void launch_collide(dsmc_ctx *c, Launcher &L, int buf) {
+    CollideArgs<R> a = collide_args<R>(c, buf);
+    const bool learned = a.mlp != nullptr && c->cfg.molecule == DSMC_HARD_SPHERE;
+    L.mark(learned ? "collide_learned" : "collide");
+    if (learned)
+        hipLaunchKernelGGL((k_collide_learned<R, VR, BYID>), dim3((unsigned)c->ncell), dim3(64), c->lds,
+                           L.s, a);
+    else
+        hipLaunchKernelGGL((k_collide<R, VR, BYID>), dim3((unsigned)c->ncell), dim3(64), c->lds, L.s, a);
+    if (c->any_big_possible) {
+        L.mark("collide_big");
+        if (learned)
+            hipLaunchKernelGGL((k_collide_big_learned<R, VR, BYID>), dim3(c->big_grid), dim3(64), 0, L.s, a);
+        else
+            hipLaunchKernelGGL((k_collide_big<R, VR, BYID>), dim3(c->big_grid), dim3(64), 0, L.s, a);
+    }
+}
+
+template <typename R, int D, bool VR>
+void launch_sort(dsmc_ctx *c, Launcher &L, int src) {
+    const int dst = src ^ 1;
+    const unsigned grid = (unsigned)((c->n + 255) / 256);
+    const Soa<R> s = soa_of<R>(c->buf[src]), d = soa_of<R>(c->buf[dst]);
+    if (c->n > 0) {
+        L.mark("stream_count");
+        hipLaunchKernelGGL((k_stream_count<R, D>), dim3(grid), dim3(256), 0, L.s, c->geo, s, (int64_t)c->n,
+                           c->count, c->st);
+    }
+    L.mark("scan");
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, L.s, c->count, c->offset, c->cursor, (int)c->ncell,
+                       c->st);
+    if (c->n > 0) {
+        L.mark("stream_scatter");
+        hipLaunchKernelGGL((k_stream_scatter<R, D, VR>), dim3(grid), dim3(256), 0, L.s, c->geo, s, d,
+                           (int64_t)c->n, c->cursor, c->st);
+    }
+}
+
+template <typename R, bool VR>
+void enqueue_step_t(dsmc_ctx *c, Launcher &L, int src) {
+    if (c->cfg.dims == 0) {
+        L.mark("begin_step");
+        hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(64), 0, L.s, c->st);
+        launch_collide<R, VR, false>(c, L, src);
+        return;
+    }
+    if (c->cfg.dims == 1) launch_sort<R, 1, VR>(c, L, src);
+    else launch_sort<R, 2, VR>(c, L, src);
+    launch_collide<R, VR, true>(c, L, src ^ 1);
+}
+
+// Enqueue one step reading buffer `src`; returns the buffer holding the result.
+int enqueue_step(dsmc_ctx *c, Launcher &L, int src) {
+    const bool vr = c->cfg.vr != 0;
+    if (c->cfg.real_bytes == 4) {
+        if (vr) enqueue_step_t<float, true>(c, L, src); else enqueue_step_t<float, false>(c, L, src);
+    } else {
+        if (vr) enqueue_step_t<double, true>(c, L, src); else enqueue_step_t<double, false>(c, L, src);
+    }
+    return c->cfg.dims == 0 ? src : src ^ 1;
+}
+
+dsmc_status record_graph(dsmc_ctx *c, int src, int steps, hipGraphExec_t *out) {
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
+    Launcher L{c->capture, nullptr, nullptr};
+    int b = src;
+    for (int k = 0; k < steps; ++k) b = enqueue_step(c, L, b);
+    hipError_t e = hipStreamEndCapture(c->capture, &g);
+    if (e != hipSuccess) return DSMC_EHIP;
+    e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    return e == hipSuccess ? DSMC_OK : DSMC_EHIP;
+}
+
+dsmc_status device_status(dsmc_ctx *c) {
+    if (c->sticky != DSMC_OK) return c->sticky;
+    unsigned int err = 0;
+    if (hipMemcpy(&err, &c->st->error, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess) {
+        c->sticky = DSMC_EHIP;
+        return c->sticky;
+    }
+    if (err) c->sticky = (dsmc_status)(-(int)err);
+    return c->sticky;
+}
+
+struct BlobHeader {
+    uint64_t magic, n, real_bytes, dims, ncell, step_next, n_samples, vr;
+};
+constexpr uint64_t kBlobMagic = 0x44534d4330314b50ull;
+
+}  // namespace
+
+extern "C" {
+
+const char *dsmc_status_string(dsmc_status s) {
+    switch (s) {
+        case DSMC_OK: return "ok";
+        case DSMC_EINVAL: return "invalid argument or configuration";
+        case DSMC_ENOMEM: return "workspace too small";
+        case DSMC_EHIP: return "HIP runtime error";
+        case DSMC_ENONFINITE: return "non-finite velocity";
+        case DSMC_EWALLHITS: return "too many wall hits in one step";
+        case DSMC_ECAPACITY: return "per-cell capacity exceeded";
+        case DSMC_EABI: return "ABI version mismatch";
+    }
+    return "unknown status";
+}
+
+dsmc_status dsmc_workspace_size(const dsmc_config *cfg, size_t *bytes) {
+    dsmc_status s = validate(cfg);
+    if (s != DSMC_OK) return s;
+    if (!bytes) return DSMC_EINVAL;
+    *bytes = make_layout(*cfg).total;
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace, size_t ws_bytes,
+                      void *hip_stream, dsmc_ctx **out) {
+    if (!out) return DSMC_EINVAL;
+    *out = nullptr;
+    dsmc_status s = validate(cfg);
+    if (s != DSMC_OK) return s;
+    if (!p || !workspace || ((uintptr_t)workspace % kAlign) != 0) return DSMC_EINVAL;
+    if (cfg->n_particles > 0 && (!p->cx || !p->cy || !p->cz || !p->id)) return DSMC_EINVAL;
+    if (cfg->n_particles > 0 && cfg->dims >= 1 && !p->x) return DSMC_EINVAL;
+    if (cfg->n_particles > 0 && cfg->dims == 2 && !p->y) return DSMC_EINVAL;
+    if (cfg->n_particles > 0 && cfg->vr && !p->w) return DSMC_EINVAL;
+    const Layout L = make_layout(*cfg);
+    if (ws_bytes < L.total) return DSMC_ENOMEM;
+
+    dsmc_ctx *c = new (std::nothrow) dsmc_ctx();
+    if (!c) return DSMC_EINVAL;
+    c->cfg = *cfg;
+    if (c->cfg.max_wall_hits == 0) c->cfg.max_wall_hits = 8;
+    c->cfg.cell_volume = nullptr;
+    c->cfg.inst_offset = nullptr;
+    c->stream = (hipStream_t)hip_stream;
+    c->ws = (unsigned char *)workspace;
+    c->L = L;
+    c->n = cfg->n_particles;
+    c->ncell = n_cells_of(*cfg);
+    const size_t rb = (size_t)cfg->real_bytes;
+    c->buf[0] = Bufs{p->x, p->y, p->cx, p->cy, p->cz, p->w, p->id};
+    if (cfg->dims >= 1) {
+        c->buf[1] = Bufs{c->ws + L.alt[0], c->ws + L.alt[1], c->ws + L.alt[2], c->ws + L.alt[3],
+                         c->ws + L.alt[4], c->ws + L.alt[5], (uint32_t *)(c->ws + L.alt[6])};
+        c->count = (uint32_t *)(c->ws + L.count);
+        c->cursor = (uint32_t *)(c->ws + L.cursor);
+    } else {
+        c->buf[1] = c->buf[0];
+    }
+    c->offset = (uint32_t *)(c->ws + L.offset);
+    c->sums = (double *)(c->ws + L.sums);
+    c->counters = (unsigned long long *)(c->ws + L.counters);
+    c->volume = (double *)(c->ws + L.volume);
+    c->st = (DevState *)(c->ws + L.state);
+    c->big_list = (uint32_t *)(c->ws + L.big_list);
+    c->perm = (uint32_t *)(c->ws + L.perm);
+    c->owner = (uint32_t *)(c->ws + L.owner);
+    c->sched = (uint32_t *)(c->ws + L.sched);
+    c->mlp = (float *)(c->ws + L.mlp);
+    c->lattice = (double *)(c->ws + L.lattice);
+
+    // geometry
+    Geo &g = c->geo;
+    std::memset(&g, 0, sizeof(g));
+    g.dims = cfg->dims;
+    g.nx = cfg->n_cells[0];
+    g.ny = cfg->dims == 2 ? cfg->n_cells[1] : 1;
+    g.max_hits = c->cfg.max_wall_hits;
+    g.Lx = cfg->length[0];
+    g.Ly = cfg->length[1];
+    g.dt = cfg->dt;
+    g.invx = cfg->dims >= 1 ? (double)cfg->n_cells[0] / cfg->length[0] : 0.0;
+    g.invy = cfg->dims == 2 ? (double)cfg->n_cells[1] / cfg->length[1] : 0.0;
+    for (int k = 0; k < 4; ++k) {
+        g.kind[k] = cfg->wall_kind[k];
+        g.Tw[k] = cfg->wall_T[k];
+        for (int d = 0; d < 3; ++d) g.uw[3 * k + d] = cfg->wall_u[k][d];
+    }
+    g.T0 = cfg->vr ? cfg->vr_T0 : 1.0;
+    g.k0 = (uint32_t)(cfg->seed & 0xFFFFFFFFull);
+    g.k1 = (uint32_t)(cfg->seed >> 32);
+    if (cfg->dims == 2) c->Vuni = (cfg->length[0] / cfg->n_cells[0]) * (cfg->length[1] / cfg->n_cells[1]);
+    else if (cfg->dims == 1) c->Vuni = cfg->length[0] / cfg->n_cells[0];
+    else c->Vuni = 1.0;
+
+    // LDS capacity per cell (one wave per cell)
+    const size_t per = 3 * rb + (cfg->vr ? rb : 0) + 4 + (cfg->dims >= 1 ? 2 : 0);
+    const int cap_fit = (int)std::min<size_t>(kMaxLds / per, 65535) / 32 * 32;
+    std::vector<uint32_t> start_host;
+    std::vector<uint32_t> sched_host;
+    if (cfg->dims == 0) {
+        int64_t maxn = 0;
+        start_host.resize(c->ncell + 1);
+        for (int64_t b = 0; b <= c->ncell; ++b) start_host[b] = (uint32_t)cfg->inst_offset[b];
+        for (int64_t b = 0; b < c->ncell; ++b) maxn = std::max<int64_t>(maxn, cfg->inst_offset[b + 1] - cfg->inst_offset[b]);
+        c->cap = (int)std::min<int64_t>(std::max<int64_t>((maxn + 31) / 32 * 32, 32), cap_fit);
+        int nbig = 0;
+        for (int64_t b = 0; b < c->ncell; ++b)
+            if (cfg->inst_offset[b + 1] - cfg->inst_offset[b] > c->cap) ++nbig;
+        c->any_big_possible = nbig > 0;
+        c->big_grid = std::max(1, std::min(nbig, 256));
+        // longest-processing-time order: instances by decreasing N^2 work
+        sched_host.resize(c->ncell);
+        std::iota(sched_host.begin(), sched_host.end(), 0u);
+        std::stable_sort(sched_host.begin(), sched_host.end(), [&](uint32_t a, uint32_t b) {
+            return (cfg->inst_offset[a + 1] - cfg->inst_offset[a]) > (cfg->inst_offset[b + 1] - cfg->inst_offset[b]);
+        });
+    } else {
+        const double mean = (double)c->n / (double)c->ncell;
+        int want = (int)std::ceil(3.0 * mean + 64.0);
+        want = (want + 31) / 32 * 32;
+        c->cap = std::max(64, std::min(want, cap_fit));
+        const int64_t maxbig = c->n / (c->cap + 1);
+        c->any_big_possible = maxbig > 0;
+        c->big_grid = (int)std::max<int64_t>(1, std::min<int64_t>(maxbig, 256));
+    }
+    c->lds = (size_t)c->cap * per;
+
+    // graphs are recorded on a private stream (capture is not allowed on
+    // the legacy default stream the caller may use)
+    if (hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return DSMC_EHIP;
+    }
+    auto fail = [&](dsmc_status e) { dsmc_destroy(c); return e; };
+    // initial device state, on the caller's stream
+    if (hipMemsetAsync(c->ws + L.sums, 0, L.counters + (size_t)c->ncell * 16 - L.sums, c->stream) != hipSuccess)
+        return fail(DSMC_EHIP);
+    if (hipMemsetAsync(c->st, 0, sizeof(DevState), c->stream) != hipSuccess) return fail(DSMC_EHIP);
+    if (cfg->dims >= 1 && hipMemsetAsync(c->count, 0, (size_t)c->ncell * 4, c->stream) != hipSuccess)
+        return fail(DSMC_EHIP);
+    if (cfg->cell_volume) {
+        c->volume_host.assign(cfg->cell_volume, cfg->cell_volume + c->ncell);
+        c->cfg.cell_volume = c->volume_host.data();
+        if (hipMemcpyAsync(c->volume, c->volume_host.data(), (size_t)c->ncell * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+            return fail(DSMC_EHIP);
+    }
+    if (cfg->dims == 0) {
+        if (hipMemcpyAsync(c->offset, start_host.data(), start_host.size() * 4, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+            hipMemcpyAsync(c->sched, sched_host.data(), sched_host.size() * 4, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+            return fail(DSMC_EHIP);
+    }
+    {
+        std::vector<double> lat(kLatticeSize);
+        for (int k = 0; k < kLatticeSize; ++k) lat[k] = std::exp2((double)(k - kLatticeHalf) / 64.0);
+        if (hipMemcpyAsync(c->lattice, lat.data(), lat.size() * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+            return fail(DSMC_EHIP);
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return fail(DSMC_EHIP);
+    }
+    if (c->lds > 64 * 1024) return fail(DSMC_EINVAL);
+    dsmc_status r = DSMC_OK;
+    for (int b = 0; b < (cfg->dims >= 1 ? 2 : 1) && r == DSMC_OK; ++b) {
+        r = record_graph(c, b, 1, &c->g1[b]);
+        if (r == DSMC_OK) r = record_graph(c, b, kGraphSteps, &c->gk[b]);
+    }
+    if (r != DSMC_OK) return fail(r);
+    *out = c;
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_step(dsmc_ctx *c, int32_t n_steps) {
+    if (!c || n_steps < 0) return DSMC_EINVAL;
+    if (c->sticky != DSMC_OK) return c->sticky;
+    const int nb = c->cfg.dims >= 1 ? 2 : 1;
+    (void)nb;
+    while (n_steps >= kGraphSteps) {
+        HIP_TRY(hipGraphLaunch(c->gk[c->cur], c->stream));
+        n_steps -= kGraphSteps;  // even number of steps: the current buffer is unchanged
+    }
+    while (n_steps > 0) {
+        HIP_TRY(hipGraphLaunch(c->g1[c->cur], c->stream));
+        if (c->cfg.dims >= 1) c->cur ^= 1;
+        --n_steps;
+    }
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_sample(dsmc_ctx *c, double *sums_host, uint64_t *counters_host, uint64_t *n_samples,
+                        int32_t reset) {
+    if (!c) return DSMC_EINVAL;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    dsmc_status s = device_status(c);
+    if (sums_host) HIP_TRY(hipMemcpy(sums_host, c->sums, (size_t)c->ncell * kNsum * 8, hipMemcpyDeviceToHost));
+    if (counters_host)
+        HIP_TRY(hipMemcpy(counters_host, c->counters, (size_t)c->ncell * 16, hipMemcpyDeviceToHost));
+    if (n_samples) HIP_TRY(hipMemcpy(n_samples, &c->st->n_samples, 8, hipMemcpyDeviceToHost));
+    if (reset) {
+        HIP_TRY(hipMemsetAsync(c->sums, 0, (size_t)c->ncell * kNsum * 8, c->stream));
+        HIP_TRY(hipMemsetAsync(c->counters, 0, (size_t)c->ncell * 16, c->stream));
+        HIP_TRY(hipMemsetAsync(&c->st->n_samples, 0, 8, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    }
+    return s;
+}
+
+dsmc_status dsmc_particles(dsmc_ctx *c, dsmc_soa *cur) {
+    if (!c || !cur) return DSMC_EINVAL;
+    const Bufs &b = c->buf[c->cur];
+    cur->x = b.x; cur->y = b.y; cur->cx = b.cx; cur->cy = b.cy; cur->cz = b.cz; cur->w = b.w; cur->id = b.id;
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_diagnostics(dsmc_ctx *c, dsmc_diag *out) {
+    if (!c || !out) return DSMC_EINVAL;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    DevState st;
+    HIP_TRY(hipMemcpy(&st, c->st, sizeof(st), hipMemcpyDeviceToHost));
+    std::vector<unsigned long long> cnt((size_t)c->ncell * 2);
+    HIP_TRY(hipMemcpy(cnt.data(), c->counters, cnt.size() * 8, hipMemcpyDeviceToHost));
+    std::memset(out, 0, sizeof(*out));
+    out->steps = st.step_next;
+    for (int64_t i = 0; i < c->ncell; ++i) {
+        out->candidates += cnt[2 * i];
+        out->accepted += cnt[2 * i + 1];
+    }
+    out->overshoot = st.diag[kDiagOvershoot];
+    out->wall_hits = st.diag[kDiagWallHits];
+    out->learned_used = st.diag[kDiagLearned];
+    out->fallback = st.diag[kDiagFallback];
+    out->learned_skip = st.diag[kDiagSkip];
+    out->vr_nonfinite = st.diag[kDiagVrNonfinite];
+    out->big_cells = st.diag[kDiagBig];
+    return device_status(c);
+}
+
+dsmc_status dsmc_set_step(dsmc_ctx *c, uint64_t next_step) {
+    if (!c) return DSMC_EINVAL;
+    HIP_TRY(hipMemcpyAsync(&c->st->step_next, &next_step, 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_set_majorant_model(dsmc_ctx *c, const uint16_t *bf16, int64_t n, double delta) {
+    if (!c || !bf16 || n != DSMC_MLP_NPARAM || c->cfg.majorant != DSMC_MAJORANT_LEARNED || !std::isfinite(delta))
+        return DSMC_EINVAL;
+    std::vector<float> in(DSMC_MLP_NPARAM), w(DSMC_MLP_NPARAM);
+    for (int64_t i = 0; i < n; ++i) {
+        const uint32_t bits = (uint32_t)bf16[i] << 16;
+        std::memcpy(&in[i], &bits, 4);
+        if (!std::isfinite(in[i])) return DSMC_EINVAL;
+    }
+    // device layout: the hidden-to-hidden matrix is stored transposed so that
+    // lane h reads W2[h][i] at i * 64 + h (coalesced across the wave)
+    w = in;
+    const int o_w2 = kMlpH * kMlpIn + kMlpH;
+    for (int h = 0; h < kMlpH; ++h)
+        for (int i = 0; i < kMlpH; ++i) w[o_w2 + i * kMlpH + h] = in[o_w2 + h * kMlpH + i];
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(c->mlp, w.data(), w.size() * 4, hipMemcpyHostToDevice));
+    const bool was = c->mlp_loaded;
+    c->mlp_loaded = true;
+    c->mlp_delta = delta;
+    // the collision kernel's arguments change: re-record the graphs
+    for (int b = 0; b < 2; ++b) {
+        if (c->g1[b]) { (void)hipGraphExecDestroy(c->g1[b]); c->g1[b] = nullptr; }
+        if (c->gk[b]) { (void)hipGraphExecDestroy(c->gk[b]); c->gk[b] = nullptr; }
+    }
+    (void)was;
+    dsmc_status r = DSMC_OK;
+    for (int b = 0; b < (c->cfg.dims >= 1 ? 2 : 1) && r == DSMC_OK; ++b) {
+        r = record_graph(c, b, 1, &c->g1[b]);
+        if (r == DSMC_OK) r = record_graph(c, b, kGraphSteps, &c->gk[b]);
+    }
+    return r;
+}
+
+dsmc_status dsmc_checkpoint(dsmc_ctx *c, void *blob, size_t *bytes) {
+    if (!c || !bytes) return DSMC_EINVAL;
+    const size_t n = (size_t)c->n, rb = (size_t)c->cfg.real_bytes, nc = (size_t)c->ncell;
+    const size_t need = sizeof(BlobHeader) + 6 * n * rb + n * 4 + nc * kNsum * 8 + nc * 16;
+    if (!blob) { *bytes = need; return DSMC_OK; }
+    if (*bytes < need) return DSMC_EINVAL;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    dsmc_status s = device_status(c);
+    if (s != DSMC_OK) return s;
+    DevState st;
+    HIP_TRY(hipMemcpy(&st, c->st, sizeof(st), hipMemcpyDeviceToHost));
+    BlobHeader h{kBlobMagic, n, rb, (uint64_t)c->cfg.dims, nc, st.step_next, st.n_samples, (uint64_t)c->cfg.vr};
+    unsigned char *o = (unsigned char *)blob;
+    std::memcpy(o, &h, sizeof(h));
+    o += sizeof(h);
+    const Bufs &b = c->buf[c->cur];
+    void *fields[6] = {b.x, b.y, b.cx, b.cy, b.cz, b.w};
+    for (int f = 0; f < 6; ++f) {
+        if (fields[f] && n) HIP_TRY(hipMemcpy(o, fields[f], n * rb, hipMemcpyDeviceToHost));
+        else std::memset(o, 0, n * rb);
+        o += n * rb;
+    }
+    if (n) HIP_TRY(hipMemcpy(o, b.id, n * 4, hipMemcpyDeviceToHost));
+    o += n * 4;
+    HIP_TRY(hipMemcpy(o, c->sums, nc * kNsum * 8, hipMemcpyDeviceToHost));
+    o += nc * kNsum * 8;
+    HIP_TRY(hipMemcpy(o, c->counters, nc * 16, hipMemcpyDeviceToHost));
+    *bytes = need;
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_restore(dsmc_ctx *c, const void *blob, size_t bytes) {
+    if (!c || !blob || bytes < sizeof(BlobHeader)) return DSMC_EINVAL;
+    BlobHeader h;
+    std::memcpy(&h, blob, sizeof(h));
+    const size_t n = (size_t)c->n, rb = (size_t)c->cfg.real_bytes, nc = (size_t)c->ncell;
+    const size_t need = sizeof(BlobHeader) + 6 * n * rb + n * 4 + nc * kNsum * 8 + nc * 16;
+    if (h.magic != kBlobMagic || h.n != n || h.real_bytes != rb || h.dims != (uint64_t)c->cfg.dims || h.ncell != nc ||
+        bytes < need)
+        return DSMC_EINVAL;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const unsigned char *o = (const unsigned char *)blob + sizeof(h);
+    const Bufs &b = c->buf[c->cur];
+    void *fields[6] = {b.x, b.y, b.cx, b.cy, b.cz, b.w};
+    for (int f = 0; f < 6; ++f) {
+        if (fields[f] && n) HIP_TRY(hipMemcpy(fields[f], o, n * rb, hipMemcpyHostToDevice));
+        o += n * rb;
+    }
+    if (n) HIP_TRY(hipMemcpy(b.id, o, n * 4, hipMemcpyHostToDevice));
+    o += n * 4;
+    HIP_TRY(hipMemcpy(c->sums, o, nc * kNsum * 8, hipMemcpyHostToDevice));
+    o += nc * kNsum * 8;
+    HIP_TRY(hipMemcpy(c->counters, o, nc * 16, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(&c->st->step_next, &h.step_next, 8, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(&c->st->n_samples, &h.n_samples, 8, hipMemcpyHostToDevice));
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_profile_step(dsmc_ctx *c, float *ms_host, int32_t max_kernels, int32_t *n_kernels,
+                              char *names_host, int32_t names_len) {
+    if (!c || !ms_host || !n_kernels || max_kernels <= 0) return DSMC_EINVAL;
+    if (c->sticky != DSMC_OK) return c->sticky;
+    std::vector<hipEvent_t> ev;
+    std::vector<const char *> names;
+    Launcher L{c->stream, &ev, &names};
+    c->cur = enqueue_step(c, L, c->cur);
+    L.mark("end");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const int nk = (int)ev.size() - 1;
+    *n_kernels = std::min(nk, max_kernels);
+    std::string all;
+    for (int k = 0; k < nk; ++k) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+        if (k < max_kernels) ms_host[k] = ms;
+        all += names[k];
+        all += '\n';
+    }
+    for (auto e : ev) (void)hipEventDestroy(e);
+    if (names_host && names_len > 0) {
+        std::strncpy(names_host, all.c_str(), (size_t)names_len - 1);
+        names_host[names_len - 1] = 0;
+    }
+    return device_status(c);
+}
+
+dsmc_status dsmc_destroy(dsmc_ctx *c) {
+    if (!c) return DSMC_EINVAL;
+    (void)hipStreamSynchronize(c->stream);
+    for (int b = 0; b < 2; ++b) {
+        if (c->g1[b]) (void)hipGraphExecDestroy(c->g1[b]);
+        if (c->gk[b]) (void)hipGraphExecDestroy(c->gk[b]);
+    }
+    if (c->capture) (void)hipStreamDestroy(c->capture);
+    delete c;
+    return DSMC_OK;
+}
+
+}  // extern "C"

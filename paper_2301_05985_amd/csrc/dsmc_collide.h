@@ -1,0 +1,329 @@
+// dsmc_collide.h -- per-cell NTC collisions, importance weights and moment
+// sampling, one 64-lane wave per cell.
+//
+// Method (Bird 1994, no-time-counter scheme): a cell of N particles takes
+//   M = floor( 1/2 N (N-1) F_N sigma g_max dt / V  +  U0 )
+// candidates; candidate k draws an ordered pair of distinct canonical ranks
+// (i, j) and is accepted with probability g_ij / g_max (hard spheres; Maxwell
+// molecules accept every candidate and use sigma*g = const in place of
+// sigma*g_max).  An accepted pair scatters isotropically about its centre of
+// mass.  Candidates are sequential by definition -- candidate k sees the
+// velocities left by candidates 0..k-1.
+//
+// Wave mapping: 64 consecutive candidates are drawn at once, one per lane.
+// Lanes that will write (accepted pairs; every candidate when importance
+// weights are carried) mark their two particles in an LDS owner array with
+// an atomic min of their lane number.  The first lane whose particles were
+// marked by an earlier lane ends the batch: every lane before it read exactly
+// the state the sequential definition gives it, and the writers among them
+// touch disjoint particles, so they commit in parallel.  The next batch
+// starts at the first uncommitted candidate.  Results are bit-identical to
+// the sequential loop.
+#pragma once
+#include "dsmc_kernels.h"
+
+namespace dsmc {
+
+template <typename R>
+struct CollideArgs {
+    Soa<R> s;                      // particles grouped by cell (or instance storage)
+    const uint32_t *start;         // [ncell + 1] first particle of each cell
+    const uint32_t *sched;         // block -> cell, or null for the identity
+    const double *volume;          // per-cell volume, or null for Vuni
+    double Vuni, dt, sigma, FN;
+    int molecule, cap;
+    uint32_t k0, k1;
+    double *sums;                  // [ncell][26] running FP64 sums
+    unsigned long long *counters;  // [ncell][2] candidates, accepted
+    DevState *st;
+    uint32_t *big_list;            // cells too large for the LDS kernel
+    uint32_t *perm_g, *owner_g;    // [n] scratch of the global-memory kernel
+    // learned majorant
+    const float *mlp;              // [4673] FP32 weights or null
+    const double *lattice;         // lattice values 2^(k/64), k in [-4096, 4096]
+    double delta;
+};
+
+constexpr int kNsum = 26;
+
+// Cell staged in LDS (index = canonical rank).
+template <typename R>
+struct LdsView {
+    R *vx, *vy, *vz, *w;
+    uint32_t *owner;
+    __device__ __forceinline__ void get(uint32_t r, R &a, R &b, R &c) const { a = vx[r]; b = vy[r]; c = vz[r]; }
+    __device__ __forceinline__ void put(uint32_t r, R a, R b, R c) const { vx[r] = a; vy[r] = b; vz[r] = c; }
+    __device__ __forceinline__ R getw(uint32_t r) const { return w[r]; }
+    __device__ __forceinline__ void putw(uint32_t r, R v) const { w[r] = v; }
+    __device__ __forceinline__ uint32_t *own(uint32_t r) const { return &owner[r]; }
+    __device__ __forceinline__ uint32_t read_own(uint32_t r) const { return owner[r]; }
+    __device__ __forceinline__ void clear_own(uint32_t r) const { owner[r] = 0xFFFFFFFFu; }
+};
+
+// Cell operated on in place in global memory, through a rank -> slot map.
+template <typename R>
+struct GlobalView {
+    R *cx, *cy, *cz, *w;
+    const uint32_t *perm;  // rank -> slot inside the cell, or null for the identity
+    uint32_t *owner;
+    __device__ __forceinline__ uint32_t at(uint32_t r) const { return perm ? perm[r] : r; }
+    __device__ __forceinline__ void get(uint32_t r, R &a, R &b, R &c) const {
+        const uint32_t q = at(r); a = cx[q]; b = cy[q]; c = cz[q];
+    }
+    __device__ __forceinline__ void put(uint32_t r, R a, R b, R c) const {
+        const uint32_t q = at(r); cx[q] = a; cy[q] = b; cz[q] = c;
+    }
+    __device__ __forceinline__ R getw(uint32_t r) const { return w[at(r)]; }
+    __device__ __forceinline__ void putw(uint32_t r, R v) const { w[at(r)] = v; }
+    __device__ __forceinline__ uint32_t *own(uint32_t r) const { return &owner[r]; }
+    // the marks are set by device-scope atomics; read and clear them at the
+    // same scope so no stale L1 line is seen
+    __device__ __forceinline__ uint32_t read_own(uint32_t r) const {
+        return __hip_atomic_load(&owner[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ __forceinline__ void clear_own(uint32_t r) const {
+        __hip_atomic_store(&owner[r], 0xFFFFFFFFu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+};
+
+// Exact per-cell majorant: m = midpoint of the velocity bounding box,
+// r_p = |c_p - m|, bound = (r_(1) + r_(2)) (1 + eps) >= |c_i - c_j| for every
+// pair (triangle inequality); computed in double from max/min and top-two
+// reductions, so the value does not depend on the order of the particles.
+template <typename R, typename View>
+__device__ double exact_bound(const View &v, uint32_t N, double &r_top) {
+    const int lane = lane_id();
+    double lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY;
+    double hi0 = -INFINITY, hi1 = -INFINITY, hi2 = -INFINITY;
+    for (uint32_t r = lane; r < N; r += 64) {
+        R a, b, c;
+        v.get(r, a, b, c);
+        lo0 = fmin(lo0, (double)a); hi0 = fmax(hi0, (double)a);
+        lo1 = fmin(lo1, (double)b); hi1 = fmax(hi1, (double)b);
+        lo2 = fmin(lo2, (double)c); hi2 = fmax(hi2, (double)c);
+    }
+    lo0 = wave_min(lo0); lo1 = wave_min(lo1); lo2 = wave_min(lo2);
+    hi0 = wave_max(hi0); hi1 = wave_max(hi1); hi2 = wave_max(hi2);
+    const double m0 = 0.5 * (hi0 + lo0), m1 = 0.5 * (hi1 + lo1), m2 = 0.5 * (hi2 + lo2);
+    double a1 = 0.0, a2 = 0.0;  // largest, second largest r^2 of this lane
+    for (uint32_t r = lane; r < N; r += 64) {
+        R a, b, c;
+        v.get(r, a, b, c);
+        const double dx = (double)a - m0, dy = (double)b - m1, dz = (double)c - m2;
+        const double r2 = (dx * dx + dy * dy) + dz * dz;
+        if (r2 > a1) { a2 = a1; a1 = r2; }
+        else if (r2 > a2) { a2 = r2; }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double o1 = __shfl_xor(a1, off, 64), o2 = __shfl_xor(a2, off, 64);
+        const double n1 = fmax(a1, o1);
+        const double n2 = fmax(fmin(a1, o1), fmax(a2, o2));
+        a1 = n1; a2 = n2;
+    }
+    r_top = sqrt(a1);
+    const double eps = sizeof(R) == 4 ? 0x1.0p-20 : 0x1.0p-50;
+    return (sqrt(a1) + sqrt(a2)) * (1.0 + eps);
+}
+
+// Uniform direction (Marsaglia 1972) from blocks 1, 2, ... of candidate k's
+// PAIR stream; one attempt per block in double, two in float.  Lanes with
+// `pending` set iterate until success (at most 64 blocks, then (0,0,1)).
+template <typename R>
+__device__ __forceinline__ void direction(bool pending, uint32_t k, uint32_t cell, uint32_t step,
+                                          uint32_t k0, uint32_t k1, R &nx, R &ny, R &nz) {
+    nx = (R)0; ny = (R)0; nz = (R)1;
+    for (uint32_t blk = 1; blk <= 64; ++blk) {
+        if (!__ballot(pending)) break;
+        if (pending) {
+            const u32x4 r = draw(k, kTagPair, blk, cell, step, k0, k1);
+#pragma unroll
+            for (int a = 0; a < (sizeof(R) == 4 ? 2 : 1); ++a) {
+                if (!pending) break;
+                R u, v;
+                if (sizeof(R) == 4) {
+                    u = (R)2 * (R)unif24(r.v[2 * a]) - (R)1;
+                    v = (R)2 * (R)unif24(r.v[2 * a + 1]) - (R)1;
+                } else {
+                    u = (R)2 * (R)unif53(r.v[0], r.v[1]) - (R)1;
+                    v = (R)2 * (R)unif53(r.v[2], r.v[3]) - (R)1;
+                }
+                const R s = u * u + v * v;
+                if (s < (R)1 && s > (R)0) {
+                    const R h = sqrt((R)1 - s);
+                    nx = ((R)2 * u) * h;
+                    ny = ((R)2 * v) * h;
+                    nz = (R)1 - (R)2 * s;
+                    pending = false;
+                }
+            }
+        }
+    }
+}
+
+// The NTC candidate loop of one cell in conflict-free wave batches.
+template <typename R, bool VR, typename View>
+__device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uint32_t cell,
+                         uint32_t step, uint32_t k0, uint32_t k1, int molecule, uint32_t &n_acc,
+                         uint32_t &n_over) {
+    const int lane = lane_id();
+    const R gm = (R)gmax;
+    const R gm2 = gm * gm;
+    uint32_t kb = 0, acc = 0, over = 0;
+    while (kb < M) {
+        const uint32_t B = min(64u, M - kb);
+        const bool act = (uint32_t)lane < B;
+        const uint32_t k = kb + (uint32_t)lane;
+        uint32_t i = 0, j = 0;
+        R U = (R)0;
+        if (act) {
+            const u32x4 r = draw(k, kTagPair, 0, cell, step, k0, k1);
+            i = scale_index(r.v[0], N);
+            j = scale_index(r.v[1], N - 1);
+            j += (j >= i) ? 1u : 0u;
+            U = sizeof(R) == 4 ? (R)unif24(r.v[2]) : (R)unif53(r.v[2], r.v[3]);
+        }
+        R ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0, g2 = 0;
+        bool accept = false;
+        double p = 0.0;
+        if (act) {
+            v.get(i, ax, ay, az);
+            v.get(j, bx, by, bz);
+            const R dx = ax - bx, dy = ay - by, dz = az - bz;
+            g2 = (dx * dx + dy * dy) + dz * dz;
+            if (molecule == DSMC_MAXWELL) {
+                accept = true;
+                p = 1.0;
+            } else {
+                const R a = U * gm;
+                accept = (a * a) < g2;
+                p = sqrt((double)g2) / gmax;
+            }
+        }
+        const bool writer = act && (VR || accept);
+        if (writer) {
+            atomicMin(v.own(i), (uint32_t)lane);
+            atomicMin(v.own(j), (uint32_t)lane);
+        }
+        __syncthreads();
+        const bool bad = act && (v.read_own(i) < (uint32_t)lane || v.read_own(j) < (uint32_t)lane);
+        const unsigned long long badm = __ballot(bad);
+        const uint32_t P = badm ? (uint32_t)(__ffsll((long long)badm) - 1) : B;
+        const bool commit = act && (uint32_t)lane < P;
+        __syncthreads();
+        if (writer) {
+            v.clear_own(i);
+            v.clear_own(j);
+        }
+        if (VR && commit) {
+            // importance weights (Al-Mohssen & Hadjiconstantinou 2010):
+            // accepted -> both W_i W_j; rejected -> W_i (1 - p W_j) / (1 - p)
+            const double wa = (double)v.getw(i), wb = (double)v.getw(j);
+            if (accept) {
+                const double ab = wa * wb;
+                v.putw(i, (R)ab);
+                v.putw(j, (R)ab);
+            } else {
+                const double q = 1.0 - p;
+                if (q > 0.0) {
+                    v.putw(i, (R)((wa * (1.0 - p * wb)) / q));
+                    v.putw(j, (R)((wb * (1.0 - p * wa)) / q));
+                }
+            }
+        }
+        const bool coll = commit && accept;
+        R nx, ny, nz;
+        direction<R>(coll, k, cell, step, k0, k1, nx, ny, nz);
+        if (coll) {
+            const R g = sqrt(g2);
+            const R hg = (R)0.5 * g;
+            const R mx = (R)0.5 * (ax + bx), my = (R)0.5 * (ay + by), mz = (R)0.5 * (az + bz);
+            const R tx = hg * nx, ty = hg * ny, tz = hg * nz;
+            v.put(i, mx + tx, my + ty, mz + tz);
+            v.put(j, mx - tx, my - ty, mz - tz);
+        }
+        if (molecule != DSMC_MAXWELL && commit && g2 > gm2) over++;
+        acc += (uint32_t)__popcll(__ballot(coll));
+        __syncthreads();
+        kb += P;
+    }
+    n_acc = acc;
+    n_over = wave_sum_u32(over);
+}
+
+// FP64 moment sums of the post-collision state of one cell, added to the
+// running sums; per-cell counters and diagnostics.
+template <typename R, bool VR, typename View>
+__device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cell, uint32_t N, uint32_t M,
+                            uint32_t acc, uint32_t over) {
+    const int lane = lane_id();
+    double q[kNsum];
+#pragma unroll
+    for (int t = 0; t < kNsum; ++t) q[t] = 0.0;
+    for (uint32_t r = lane; r < N; r += 64) {
+        R x, y, z;
+        v.get(r, x, y, z);
+        const double vx = (double)x, vy = (double)y, vz = (double)z;
+        const double c2 = (vx * vx + vy * vy) + vz * vz;
+        const double t[13] = {1.0, vx, vy, vz, vx * vx, vy * vy, vz * vz, vx * vy, vx * vz, vy * vz,
+                              vx * c2, vy * c2, vz * c2};
+#pragma unroll
+        for (int u = 0; u < 13; ++u) q[u] += t[u];
+        if (VR) {
+            const double f = 1.0 - (double)v.getw(r);
+#pragma unroll
+            for (int u = 0; u < 13; ++u) q[13 + u] += f * t[u];
+        }
+    }
+    double mine = 0.0;
+    bool bad_plain = false, bad_vr = false;
+#pragma unroll
+    for (int u = 0; u < kNsum; ++u) {
+        if (!VR && u >= 13) break;
+        const double tot = wave_sum(q[u]);
+        if (!isfinite(tot)) { if (u < 13) bad_plain = true; else bad_vr = true; }
+        if (lane == u) mine = tot;
+    }
+    const int nsum = VR ? kNsum : 13;
+    if (lane < nsum) a.sums[(size_t)cell * kNsum + lane] += mine;
+    if (lane == 0) {
+        a.counters[2 * (size_t)cell] += M;
+        a.counters[2 * (size_t)cell + 1] += acc;
+        if (over) atomicAdd(&a.st->diag[kDiagOvershoot], (unsigned long long)over);
+        if (bad_plain) set_error(a.st, DSMC_ENONFINITE);
+        if (bad_vr) atomicAdd(&a.st->diag[kDiagVrNonfinite], 1ull);
+    }
+}
+
+// Majorant, candidate count, NTC loop and sampling of one cell; the view
+// already holds the cell in canonical order.
+template <typename R, bool VR, typename View>
+__device__ void process_cell(const CollideArgs<R> &a, const View &v, uint32_t cell, uint32_t N,
+                             uint32_t step) {
+    const int lane = lane_id();
+    uint32_t M = 0, acc = 0, over = 0;
+    if (N >= 2) {
+        double rt;
+        double gmax = 1.0;
+        if (a.molecule != DSMC_MAXWELL) gmax = exact_bound<R>(v, N, rt);
+        const double V = a.volume ? a.volume[cell] : a.Vuni;
+        const double Nd = (double)N;
+        double Mreal;
+        if (a.molecule == DSMC_MAXWELL)
+            Mreal = (((((0.5 * Nd) * (Nd - 1.0)) * a.FN) * a.sigma) * a.dt) / V;
+        else
+            Mreal = ((((((0.5 * Nd) * (Nd - 1.0)) * a.FN) * a.sigma) * gmax) * a.dt) / V;
+        const u32x4 r = draw(0, kTagNcand, 0, cell, step, a.k0, a.k1);
+        double Mf = floor(Mreal + unif53(r.v[0], r.v[1]));
+        if (!(Mf >= 0.0)) Mf = 0.0;
+        if (Mf > 2147483647.0) {
+            if (lane == 0) set_error(a.st, DSMC_ECAPACITY);
+            Mf = 0.0;
+        }
+        M = (uint32_t)Mf;
+        ntc_loop<R, VR>(v, N, gmax, M, cell, step, a.k0, a.k1, a.molecule, acc, over);
+    }
+    sample_cell<R, VR>(a, v, cell, N, M, acc, over);
+}
+
+}  // namespace dsmc

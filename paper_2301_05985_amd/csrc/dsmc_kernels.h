@@ -1,0 +1,280 @@
+// dsmc_kernels.h -- the per-step kernels of the DSMC hot path on gfx950.
+//
+// One time step (Bird 1994, direct simulation Monte Carlo):
+//   k_stream_count    free flight with wall conditions, cell index, per-cell
+//                     counts (counting sort, pass 1)            [grid over particles]
+//   k_scan            exclusive scan of the counts, step bookkeeping [one workgroup]
+//   k_stream_scatter  the same flight recomputed, particles written to their
+//                     cell's range of the other buffer (pass 2)  [grid over particles]
+//   k_collide         per cell: stage the cell in LDS in canonical (ascending
+//                     id) order, exact majorant, NTC candidates in
+//                     conflict-free wave batches, importance weights, FP64
+//                     moment sums, write back                     [one wave per cell]
+// Homogeneous instances (dims == 0) skip the first three and run k_begin_step.
+#pragma once
+#include "dsmc_device.h"
+#include "../../include/dsmc.h"
+
+namespace dsmc {
+
+struct DevState {
+    unsigned long long step_next;   // index of the next step to stream
+    unsigned long long step_cur;    // index of the step being collided
+    unsigned long long n_samples;   // sampled steps since the last reset
+    unsigned int error;             // first device error (positive code), 0 = none
+    unsigned int big_count;         // cells queued for the global-memory collision kernel
+    unsigned long long diag[8];
+};
+enum { kDiagOvershoot = 0, kDiagWallHits, kDiagLearned, kDiagFallback, kDiagSkip, kDiagVrNonfinite,
+       kDiagBig };
+
+__device__ __forceinline__ void set_error(DevState *st, int code) {
+    atomicCAS(&st->error, 0u, (unsigned int)(-code));
+}
+
+struct Geo {
+    int dims, nx, ny, max_hits;
+    double Lx, Ly, dt, invx, invy;
+    int kind[4];
+    double Tw[4];
+    double uw[12];
+    double T0;
+    uint32_t k0, k1;
+};
+
+template <typename R>
+struct Soa {
+    R *x, *y, *cx, *cy, *cz, *w;
+    uint32_t *id;
+};
+
+// ------------------------------------------------------------ diffuse wall
+// Outgoing velocity drawn from the wall's normalized flux Maxwellian:
+// normal speed sqrt(-2 Tw ln(1-U1)), tangential Box-Muller pair from
+// (U2, U3) scaled by sqrt(Tw).  Double: U1, U2 from block 0 (two words
+// each), U3 from block 1; float: U1..U3 from words 0..2 of block 0.
+__device__ __forceinline__ void wall_draw(float Tw, uint32_t hit, uint32_t pid, uint32_t step,
+                                          uint32_t k0, uint32_t k1, float &cn, float &t1, float &t2) {
+    const u32x4 b = draw(hit, kTagWall, 0, pid, step, k0, k1);
+    const float U1 = unif24(b.v[0]), U2 = unif24(b.v[1]), U3 = unif24(b.v[2]);
+    const float rad = sqrtf(-2.0f * logf(1.0f - U2));
+    const float th = 6.28318530717958647692f * U3;
+    const float sT = sqrtf(Tw);
+    cn = sqrtf((-2.0f * Tw) * logf(1.0f - U1));
+    t1 = sT * (rad * cosf(th));
+    t2 = sT * (rad * sinf(th));
+}
+__device__ __forceinline__ void wall_draw(double Tw, uint32_t hit, uint32_t pid, uint32_t step,
+                                          uint32_t k0, uint32_t k1, double &cn, double &t1, double &t2) {
+    const u32x4 b0 = draw(hit, kTagWall, 0, pid, step, k0, k1);
+    const u32x4 b1 = draw(hit, kTagWall, 1, pid, step, k0, k1);
+    const double U1 = unif53(b0.v[0], b0.v[1]), U2 = unif53(b0.v[2], b0.v[3]);
+    const double U3 = unif53(b1.v[0], b1.v[1]);
+    const double rad = sqrt(-2.0 * log(1.0 - U2));
+    const double th = 6.28318530717958647692 * U3;
+    const double sT = sqrt(Tw);
+    cn = sqrt((-2.0 * Tw) * log(1.0 - U1));
+    t1 = sT * (rad * cos(th));
+    t2 = sT * (rad * sin(th));
+}
+
+// Importance-weight factor at a diffuse wall: flux Maxwellian of the
+// reference equilibrium (T0, at rest) over that of the wall (Tw, uw).
+__device__ __forceinline__ double wall_weight_ratio(double vx, double vy, double vz, double Tw,
+                                                    const double *uw, double T0) {
+    const double c2_0 = (vx * vx + vy * vy) + vz * vz;
+    const double dx = vx - uw[0], dy = vy - uw[1], dz = vz - uw[2];
+    const double c2_w = (dx * dx + dy * dy) + dz * dz;
+    const double ex = c2_w / (2.0 * Tw) - c2_0 / (2.0 * T0);
+    return ((Tw * Tw) / (T0 * T0)) * exp(ex);
+}
+
+// ------------------------------------------------------------ free flight
+// Exact times of flight to the walls the particle moves toward; a hit snaps
+// the particle onto the wall, applies the wall condition and continues with
+// the remaining time; on a tie the x wall goes first.  Returns 0 or
+// DSMC_EWALLHITS.  The particle id is read only when a diffuse wall is hit.
+template <typename R, int D, bool WANT_W>
+__device__ __forceinline__ int fly(const Geo &g, R &x, R &y, R &cx, R &cy, R &cz, R &w,
+                                   const uint32_t *ids, int64_t p, uint32_t step, uint32_t &hits) {
+    const R Lx = (R)g.Lx, Ly = (R)g.Ly, zero = (R)0;
+    const R inf = (R)INFINITY;
+    R tau = (R)g.dt;
+    hits = 0;
+    uint32_t pid = 0;
+    bool have_pid = false;
+    for (;;) {
+        R tx = inf, ty = inf;
+        if (cx > zero) tx = (Lx - x) / cx;
+        else if (cx < zero) tx = (zero - x) / cx;
+        if (D == 2) {
+            if (cy > zero) ty = (Ly - y) / cy;
+            else if (cy < zero) ty = (zero - y) / cy;
+        }
+        R t = tx <= ty ? tx : ty;
+        if (t < zero) t = zero;
+        if (t >= tau) {
+            x = x + cx * tau;
+            if (D == 2) y = y + cy * tau;
+            return 0;
+        }
+        const bool xwall = tx <= ty;
+        x = x + cx * t;
+        if (D == 2) y = y + cy * t;
+        tau = tau - t;
+        int wall;
+        if (xwall) { wall = cx > zero ? 1 : 0; x = wall ? Lx : zero; }
+        else       { wall = cy > zero ? 3 : 2; y = wall == 3 ? Ly : zero; }
+        if ((int)hits >= g.max_hits) return DSMC_EWALLHITS;
+        const int kind = g.kind[wall];
+        if (kind == DSMC_WALL_PERIODIC) {
+            if (xwall) x = wall ? zero : Lx;
+            else       y = wall == 3 ? zero : Ly;
+        } else if (kind == DSMC_WALL_SPECULAR) {
+            if (xwall) cx = -cx; else cy = -cy;
+        } else {
+            if (!have_pid) { pid = ids[p]; have_pid = true; }
+            R dn, d1, d2;
+            wall_draw((R)g.Tw[wall], hits, pid, step, g.k0, g.k1, dn, d1, d2);
+            const R sign = (wall & 1) ? (R)-1 : (R)1;
+            const double *uw = &g.uw[3 * wall];
+            if (xwall) { cx = sign * dn; cy = d1 + (R)uw[1]; cz = d2 + (R)uw[2]; }
+            else       { cy = sign * dn; cx = d1 + (R)uw[0]; cz = d2 + (R)uw[2]; }
+            if (WANT_W) {
+                const double ratio = wall_weight_ratio((double)cx, (double)cy, (double)cz, g.Tw[wall], uw, g.T0);
+                w = (R)((double)w * ratio);
+            }
+        }
+        hits++;
+    }
+}
+
+// Cell index floor(x nx / Lx) clamped to [0, nx-1], in double; 2-D cells are
+// numbered iy * nx + ix.
+__device__ __forceinline__ uint32_t cell_index(const Geo &g, double x, double y) {
+    const double fx = floor(x * g.invx);
+    const int ix = !(fx >= 0.0) ? 0 : (fx > (double)(g.nx - 1) ? g.nx - 1 : (int)fx);
+    if (g.dims < 2) return (uint32_t)ix;
+    const double fy = floor(y * g.invy);
+    const int iy = !(fy >= 0.0) ? 0 : (fy > (double)(g.ny - 1) ? g.ny - 1 : (int)fy);
+    return (uint32_t)iy * (uint32_t)g.nx + (uint32_t)ix;
+}
+
+// Pass 1 of the counting sort: fly, index, count.  Reads x, (y), cx, cy only
+// (16 B per particle in FP32 2-D) -- the post-flight state is recomputed by
+// pass 2 instead of being written and re-read.
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_stream_count(Geo g, Soa<R> s, int64_t n, uint32_t *count,
+                                                      DevState *st) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool act = p < n;
+    const uint32_t step = (uint32_t)st->step_next;
+    uint32_t cell = 0;
+    if (act) {
+        R x = s.x[p], y = D == 2 ? s.y[p] : (R)0, cx = s.cx[p], cy = s.cy[p], cz = (R)0, w = (R)0;
+        uint32_t hits;
+        const int rc = fly<R, D, false>(g, x, y, cx, cy, cz, w, s.id, p, step, hits);
+        if (rc) set_error(st, rc);
+        cell = cell_index(g, (double)x, D == 2 ? (double)y : 0.0);
+    }
+    (void)wave_aggregated_inc(count, cell, act);
+}
+
+// Pass 2: fly again (same bits), claim a slot in the cell's range and write
+// the whole particle to the other buffer.  Order inside a cell is arbitrary;
+// the collision kernel restores the canonical order.
+template <typename R, int D, bool VR>
+__global__ __launch_bounds__(256) void k_stream_scatter(Geo g, Soa<R> src, Soa<R> dst, int64_t n,
+                                                        uint32_t *cursor, DevState *st) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool act = p < n;
+    const uint32_t step = (uint32_t)st->step_cur;
+    uint32_t cell = 0, hits = 0, pid = 0;
+    R x = 0, y = 0, cx = 0, cy = 0, cz = 0, w = 0;
+    if (act) {
+        x = src.x[p];
+        if (D == 2) y = src.y[p];
+        cx = src.cx[p]; cy = src.cy[p]; cz = src.cz[p];
+        if (VR) w = src.w[p];
+        pid = src.id[p];
+        const int rc = fly<R, D, VR>(g, x, y, cx, cy, cz, w, src.id, p, step, hits);
+        if (rc) set_error(st, rc);
+        cell = cell_index(g, (double)x, D == 2 ? (double)y : 0.0);
+    }
+    const uint32_t slot = wave_aggregated_inc(cursor, cell, act);
+    if (act && (int64_t)slot >= n) {
+        // both passes compute the same cell by construction; never write
+        // outside the buffer if they ever disagree
+        set_error(st, DSMC_ECAPACITY);
+        return;
+    }
+    if (act) {
+        dst.x[slot] = x;
+        if (D == 2) dst.y[slot] = y;
+        dst.cx[slot] = cx; dst.cy[slot] = cy; dst.cz[slot] = cz;
+        if (VR) dst.w[slot] = w;
+        dst.id[slot] = pid;
+    }
+    const uint32_t hsum = wave_sum_u32(hits);
+    if (lane_id() == 0 && hsum) atomicAdd(&st->diag[kDiagWallHits], (unsigned long long)hsum);
+}
+
+// Exclusive scan of the per-cell counts (one workgroup of 1024 threads, each
+// owning a contiguous chunk), writing offsets and cursors and clearing the
+// counts for the next step.  Thread 0 also advances the step bookkeeping.
+__global__ __launch_bounds__(1024) void k_scan(uint32_t *count, uint32_t *offset, uint32_t *cursor,
+                                               int ncell, DevState *st) {
+    __shared__ uint32_t wave_tot[16];
+    const int t = threadIdx.x, lane = lane_id(), wv = t >> 6;
+    const int per = (ncell + 1023) / 1024;
+    const int b = t * per, e = min(b + per, ncell);
+    uint32_t local = 0;
+    for (int i = b; i < e; ++i) local += count[i];
+    // inclusive scan inside the wave
+    uint32_t inc = local;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t v = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += v;
+    }
+    if (lane == 63) wave_tot[wv] = inc;
+    __syncthreads();
+    if (wv == 0) {
+        uint32_t v = lane < 16 ? wave_tot[lane] : 0u, s = v;
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+            const uint32_t u = __shfl_up(s, off, 64);
+            if (lane >= off) s += u;
+        }
+        if (lane < 16) wave_tot[lane] = s - v;  // exclusive prefix of the wave totals
+    }
+    __syncthreads();
+    uint32_t run = wave_tot[wv] + inc - local;
+    for (int i = b; i < e; ++i) {
+        const uint32_t c = count[i];
+        offset[i] = run;
+        cursor[i] = run;
+        count[i] = 0;
+        run += c;
+    }
+    if (e == ncell && b < e) offset[ncell] = run;
+    if (ncell <= t * per && t == 0) offset[ncell] = 0;
+    if (t == 0) {
+        st->step_cur = st->step_next;
+        st->step_next = st->step_next + 1;
+        st->n_samples = st->n_samples + 1;
+        st->big_count = 0;
+    }
+}
+
+// Step bookkeeping for homogeneous instances (no sort pass).
+__global__ void k_begin_step(DevState *st) {
+    if (threadIdx.x == 0) {
+        st->step_cur = st->step_next;
+        st->step_next = st->step_next + 1;
+        st->n_samples = st->n_samples + 1;
+        st->big_count = 0;
+    }
+}
+
+}  // namespace dsmc

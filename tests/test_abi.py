@@ -1,0 +1,83 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point
+the header declares, and rejects invalid configurations before any launch.
+No GPU is touched (dsmc_workspace_size is pure host validation)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2301_05985_amd import binding, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "dsmc.h")).read()
+    return sorted(set(re.findall(r"^(?:dsmc_status|const char \*|int64_t)\s*(dsmc_[a-z0-9_]+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(binding.lib_path()):
+        from paper_2301_05985_amd import build
+        build.build()
+    return binding.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    syms = declared_symbols()
+    assert len(syms) >= 15
+    for s in syms:
+        assert hasattr(lib, s), s
+
+
+def test_status_strings(lib):
+    for code in range(0, -8, -1):
+        assert lib.dsmc_status_string(code)
+
+
+def _ws(lib, cfg):
+    n = ctypes.c_size_t()
+    return lib.dsmc_workspace_size(ctypes.byref(cfg), ctypes.byref(n)), n.value
+
+
+def test_workspace_size_valid_configs(lib):
+    for p, parts in (W.cavity(nx=8, ny=8, per_cell=10), W.fourier(n_cells=10, per_cell=10),
+                     W.batched(n_inst=8, nmin=10, nmax=20)):
+        cfg = binding.make_config(p, len(parts["cx"]))
+        keep = []
+        if p["dims"] == 0:
+            off = np.ascontiguousarray(p["inst_offset"], dtype=np.int64)
+            keep.append(off)
+            cfg.inst_offset = off.ctypes.data
+        rc, n = _ws(lib, cfg)
+        assert rc == 0 and n > 0
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("abi_version", 99, -7), ("dims", 3, -1), ("real_bytes", 2, -1), ("dt", 0.0, -1),
+    ("FN", -1.0, -1), ("molecule", 5, -1), ("majorant", 7, -1), ("n_particles", -5, -1),
+])
+def test_workspace_size_rejects_invalid(lib, field, value, code):
+    p, parts = W.cavity(nx=4, ny=4, per_cell=5)
+    cfg = binding.make_config(p, len(parts["cx"]))
+    setattr(cfg, field, value)
+    rc, _ = _ws(lib, cfg)
+    assert rc == code
+
+
+def test_rejects_unpaired_periodic_wall_and_bad_offsets(lib):
+    p, parts = W.cavity(nx=4, ny=4, per_cell=5)
+    cfg = binding.make_config(p, len(parts["cx"]))
+    cfg.wall_kind[0] = 2
+    assert _ws(lib, cfg)[0] == -1
+    p, parts = W.batched(n_inst=4, nmin=10, nmax=20)
+    cfg = binding.make_config(p, len(parts["cx"]))
+    bad = np.ascontiguousarray(p["inst_offset"], dtype=np.int64).copy()
+    bad[-1] += 1  # does not end at n_particles
+    cfg.inst_offset = bad.ctypes.data
+    assert _ws(lib, cfg)[0] == -1
+    cfg.inst_offset = None
+    assert _ws(lib, cfg)[0] == -1

@@ -1,0 +1,237 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs, element by element.
+
+Bar: pair choices and counts bit-exact; FP64 state bit-exact where no
+transcendental function enters (homogeneous cells, specular and periodic
+walls) and within 1e-12 relative where diffuse walls call log/sin/cos/exp
+(the device and host libraries may differ in the last ulp); FP32 state
+bit-exact against the oracle's single-precision build where no transcendental
+enters.  Sums are compared within 1e-12 relative (summation order differs).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2301_05985_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _announce(name):
+    print("[gpu case] %s" % name, flush=True)
+    sys.stdout.flush()
+
+
+def _run(gpu_unused, p, parts, steps, real, chunks=1):
+    from paper_2301_05985_amd.binding import Simulation
+    p = dict(p)
+    p["real"] = real
+    dtype = np.float64 if real == "f64" else np.float32
+    sim = Simulation(p, parts)
+    orc = oracle.Oracle(p, parts, dtype)
+    per = steps // chunks
+    for _ in range(chunks):
+        sim.step(per)
+        orc.run(per)
+    sums, cnt, ns = sim.sample()
+    st = sim.particles()
+    diag = sim.diagnostics()
+    sim.close()
+    return dict(sums=sums, cnt=cnt, ns=ns, st=st, diag=diag), orc
+
+
+def _compare(g, orc, exact, rtol=1e-12, fields=("x", "y", "cx", "cy", "cz", "w"), dims=None):
+    o = orc.state()
+    assert np.array_equal(g["st"]["id"], o["id"])
+    assert np.array_equal(g["cnt"], orc.counters), "per-cell candidate/accepted counts differ"
+    for k in fields:
+        a, b = g["st"][k], o[k]
+        if a is None:
+            continue
+        if exact:
+            bad = np.flatnonzero(a != b)
+            assert bad.size == 0, (k, bad[:5], a[bad[:5]], b[bad[:5]])
+        else:
+            fa, fb = np.isfinite(a), np.isfinite(b)
+            assert np.array_equal(fa, fb), (k, "non-finite entries differ")
+            a, b = a[fa], b[fb]
+            scale = np.maximum(np.abs(b), 1.0)
+            err = np.abs(a.astype(np.float64) - b.astype(np.float64)) / scale
+            assert err.size == 0 or err.max() <= rtol, (k, err.max())
+    # running sums: same terms, different summation order
+    s_g, s_o = g["sums"], orc.sums
+    ok = np.isfinite(s_o)
+    assert np.array_equal(ok, np.isfinite(s_g))
+    s_o = np.where(ok, s_o, 0.0)
+    s_g = np.where(ok, s_g, 0.0)
+    scale = np.abs(s_o).max(axis=0, keepdims=True) + 1.0
+    assert (np.abs(s_g - s_o) / scale).max() < 1e-11
+    assert g["ns"] == orc.step - 0 or g["ns"] > 0
+
+
+def _homog(counts, seed=0, dt=0.2, molecule=0, shift=1.0):
+    rng = np.random.default_rng(seed)
+    off = np.zeros(len(counts) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(counts)
+    tot = int(off[-1])
+    c = rng.standard_normal((3, tot))
+    for b in range(len(counts)):
+        s, e = off[b], off[b + 1]
+        h = (e - s + 1) // 2
+        c[0, s:s + h] += shift
+        c[0, s + h:e] -= shift
+    p = dict(dims=0, n_cells=(len(counts), 1), dt=dt, sigma=0.01, FN=1.0, molecule=molecule, seed=seed + 11,
+             inst_offset=off, cell_volume=np.ones(len(counts)))
+    if molecule == W.MAXWELL:
+        p["sigma"] = 0.02
+    return p, dict(cx=c[0], cy=c[1], cz=c[2], id=np.arange(tot, dtype=np.uint32))
+
+
+@pytest.mark.parametrize("real", ["f64", "f32"])
+def test_homogeneous_bit_exact(gpu, real):
+    _announce("homogeneous %s" % real)
+    p, parts = _homog([0, 1, 2, 3, 50, 64, 65, 127, 257, 300, 611, 1024], dt=0.3)
+    g, orc = _run(gpu, p, parts, 12, real, chunks=2)
+    assert orc.counters[:, 1].sum() > 500
+    _compare(g, orc, exact=True)
+
+
+def test_homogeneous_maxwell_bit_exact(gpu):
+    _announce("homogeneous maxwell f64")
+    p, parts = _homog([2, 40, 300, 900], molecule=W.MAXWELL, dt=0.1)
+    g, orc = _run(gpu, p, parts, 10, "f64")
+    _compare(g, orc, exact=True)
+
+
+@pytest.mark.parametrize("real", ["f64", "f32"])
+def test_homogeneous_large_cell_global_path_bit_exact(gpu, real):
+    # a cell above the LDS capacity runs in the global-memory kernel
+    _announce("homogeneous big cell %s" % real)
+    p, parts = _homog([30, 6000, 200], dt=0.05)
+    p["sigma"] = 0.0005
+    g, orc = _run(gpu, p, parts, 6, real)
+    assert g["diag"]["big_cells"] > 0
+    _compare(g, orc, exact=True)
+
+
+@pytest.mark.parametrize("real", ["f64", "f32"])
+def test_fourier_specular_bit_exact(gpu, real):
+    _announce("fourier specular %s" % real)
+    p, parts = W.fourier(n_cells=16, per_cell=40, Kn=0.02, dt=4e-3, real=real)
+    p["wall_kind"] = (W.WALL_SPECULAR, W.WALL_SPECULAR, 0, 0)
+    parts = W.shuffle_storage(parts, seed=2)
+    g, orc = _run(gpu, p, parts, 10, real, chunks=2)
+    assert orc.counters[:, 1].sum() > 100
+    _compare(g, orc, exact=True)
+
+
+@pytest.mark.parametrize("real", ["f64", "f32"])
+def test_cavity_periodic_specular_bit_exact(gpu, real):
+    _announce("cavity periodic/specular %s" % real)
+    p, parts = W.cavity(nx=12, ny=10, per_cell=25, Kn=0.01, real=real, dt=0.01)
+    p["wall_kind"] = (W.WALL_PERIODIC, W.WALL_PERIODIC, W.WALL_SPECULAR, W.WALL_SPECULAR)
+    g, orc = _run(gpu, p, parts, 10, real, chunks=2)
+    assert orc.counters[:, 1].sum() > 100 and orc.diag.wall_hits > 0
+    _compare(g, orc, exact=True)
+
+
+def test_fourier_diffuse_vr_f64(gpu):
+    _announce("fourier diffuse vr f64")
+    p, parts = W.fourier(n_cells=20, per_cell=50, Kn=0.05, dt=2e-3, real="f64")
+    g, orc = _run(gpu, p, parts, 16, "f64", chunks=2)
+    assert orc.diag.wall_hits > 0
+    _compare(g, orc, exact=False, rtol=1e-12)
+
+
+def test_cavity_diffuse_lid_vr_f64(gpu):
+    _announce("cavity diffuse lid vr f64")
+    p, parts = W.cavity(nx=10, ny=10, per_cell=30, Kn=0.02, real="f64", lid=0.3, dt=2e-3)
+    g, orc = _run(gpu, p, parts, 16, "f64")
+    assert np.isfinite(g["st"]["w"]).all()
+    assert orc.diag.wall_hits > 0 and orc.counters[:, 1].sum() > 100
+    _compare(g, orc, exact=False, rtol=1e-12)
+
+
+def test_cavity_big_cell_global_path_f64(gpu):
+    # one crowded cell above the LDS capacity in a walled run (id ranking in
+    # global memory)
+    _announce("cavity big cell f64")
+    p, parts = W.cavity(nx=4, ny=4, per_cell=40, Kn=0.05, real="f64", dt=1e-4)
+    rng = np.random.default_rng(5)
+    extra = 1500
+    n0 = len(parts["cx"])
+    add = dict(x=rng.random(extra) * 0.2 + 0.02, y=rng.random(extra) * 0.2 + 0.02,
+               cx=rng.standard_normal(extra), cy=rng.standard_normal(extra), cz=rng.standard_normal(extra),
+               w=np.ones(extra), id=np.arange(n0, n0 + extra, dtype=np.uint32))
+    parts = {k: np.concatenate([parts[k], add[k]]) for k in add}
+    g, orc = _run(gpu, p, parts, 4, "f64")
+    assert g["diag"]["big_cells"] > 0
+    _compare(g, orc, exact=False, rtol=1e-12)
+
+
+def test_relaxation_full_size_f64(gpu):
+    # relaxation workload at its full size: 10,000 particles in one cell,
+    # FP64, 200 steps, bit-exact against the oracle
+    _announce("relaxation full size f64")
+    p, parts = W.relaxation()
+    g, orc = _run(gpu, p, parts, 200, "f64", chunks=4)
+    _compare(g, orc, exact=True)
+    assert g["cnt"][0, 1] > 40000
+
+
+def test_checkpoint_restore_bit_exact(gpu):
+    _announce("checkpoint restore")
+    from paper_2301_05985_amd.binding import Simulation
+    p, parts = W.cavity(nx=8, ny=8, per_cell=20, Kn=0.05, real="f64", dt=2e-3)
+    a = Simulation(p, parts)
+    a.step(10)
+    sa = a.particles()
+    sums_a, cnt_a, _ = a.sample()
+    b = Simulation(p, parts)
+    b.step(5)
+    blob = b.checkpoint()
+    b.close()
+    c = Simulation(p, parts)
+    c.restore(blob)
+    c.step(5)
+    sc = c.particles()
+    sums_c, cnt_c, _ = c.sample()
+    for k in ("x", "y", "cx", "cy", "cz", "w"):
+        assert np.array_equal(sa[k], sc[k]), k
+    assert np.array_equal(cnt_a, cnt_c)
+    assert np.array_equal(sums_a, sums_c, equal_nan=True)
+    assert np.isfinite(sums_a).all()
+
+
+def test_repeatable_and_direct_launch_matches_graph(gpu):
+    _announce("repeatability")
+    from paper_2301_05985_amd.binding import Simulation
+    p, parts = W.cavity(nx=16, ny=16, per_cell=30, Kn=0.02, real="f32", dt=2e-3)
+    runs = []
+    for mode in ("graph", "graph", "direct"):
+        s = Simulation(p, parts)
+        if mode == "graph":
+            s.step(9)
+        else:
+            for _ in range(9):
+                s.profile_step()
+        runs.append(s.particles())
+        s.close()
+    for k in ("x", "y", "cx", "cy", "cz", "w"):
+        assert np.array_equal(runs[0][k], runs[1][k], equal_nan=True), k
+        assert np.array_equal(runs[0][k], runs[2][k], equal_nan=True), k
+
+
+def test_too_many_wall_hits_is_reported(gpu):
+    _announce("wall hit limit")
+    from paper_2301_05985_amd.binding import Simulation, DsmcError
+    p, parts = W.fourier(n_cells=4, per_cell=50, Kn=0.1, dt=0.5, real="f64")
+    p["max_wall_hits"] = 1
+    s = Simulation(p, parts)
+    s.step(1)
+    with pytest.raises(DsmcError) as e:
+        s.sample()
+    assert e.value.code == -5
