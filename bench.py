@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Benchmark of the DSMC hot path on one MI355X.
+
+Default (no flags): the 2-D lid-driven cavity at its full size -- 256 x 256
+cells, 100 particles per cell (6,553,600 particles), Kn = 0.01, diffuse walls,
+importance weights, FP32 state with FP64 moment sums -- W untimed warm-up
+steps, then exactly K timed steps (one step = free flight with walls, the
+two-pass counting sort, per-cell majorant + NTC collisions + weight update,
+moment sampling).  Rank 0 prints one JSON line.
+
+Also reported in the same line: per-kernel durations measured live with HIP
+events on the run's stream (roofline of the dominant kernel), the CPU oracle
+timed on a bounded sample of the same workload, and secondary workloads
+(1-D Fourier, batched homogeneous cells with the exact and, when a trained
+network is available, the learned majorant, and the single-cell relaxation).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+METRIC = "accepted collisions/s + particle-steps/s on 1 MI355X; learned vs exact majorant"
+
+# algorithmic bytes per particle and launch, FP32 2-D with weights
+ALGO_BYTES = {
+    "stream_count": 16.0,    # read x, y, cx, cy
+    "stream_scatter": 56.0,  # read x, y, cx, cy, cz, w, id; write the same 28 B
+    "collide": 36.0,         # read cx, cy, cz, w, id; write cx, cy, cz, w
+}
+
+
+def _timed_steps(sim, torch, steps, warmup):
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    s = sim.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    _, cnt0, _ = sim.sample()
+    t0 = time.perf_counter()
+    e0.record(s)
+    sim.step(steps)
+    e1.record(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    _, cnt1, _ = sim.sample()
+    d = (cnt1.astype(np.int64) - cnt0.astype(np.int64)).sum(0)
+    return ms, wall, int(d[0]), int(d[1])
+
+
+def run_workload(name, p, parts, steps, warmup, torch):
+    from paper_2301_05985_amd.binding import Simulation
+    sim = Simulation(p, parts)
+    ms, wall, cand, acc = _timed_steps(sim, torch, steps, warmup)
+    diag = sim.diagnostics()
+    n = len(parts["cx"])
+    out = {
+        "workload": name, "particles": n, "steps": steps, "ms_per_step": ms / steps,
+        "particle_steps_per_s": n * steps / (ms * 1e-3),
+        "collisions_per_s": acc / (ms * 1e-3), "candidates_per_s": cand / (ms * 1e-3),
+        "acceptance": acc / max(cand, 1), "dtype": p.get("real", "f64"),
+        "wall_clock_s": wall,
+    }
+    for k in ("learned_used", "fallback", "learned_skip", "overshoot", "vr_nonfinite", "big_cells"):
+        out[k] = diag[k]
+    sim.close()
+    return out
+
+
+def kernel_profile(sim, torch, steps):
+    """Per-kernel durations (ms) from HIP events around every launch."""
+    acc = {}
+    for _ in range(steps):
+        for name, ms in sim.profile_step():
+            acc.setdefault(name, []).append(ms)
+    return {k: float(np.mean(v)) for k, v in acc.items()}
+
+
+def cpu_baseline(p, parts, n_steps):
+    import oracle
+    dtype = np.float32 if p.get("real") == "f32" else np.float64
+    orc = oracle.Oracle(p, parts, dtype)
+    orc.run(1)  # the first step streams from the unsorted initial state, like the GPU warm-up
+    t0 = time.perf_counter()
+    orc.run(n_steps)
+    dt = time.perf_counter() - t0
+    n = len(parts["cx"])
+    acc = int(orc.counters[:, 1].sum())
+    return {"value": n * n_steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "%d steps of the same workload after 1 untimed step (%.1f s single-threaded, "
+                      "FP%d oracle build)" % (n_steps, dt, 32 if dtype == np.float32 else 64),
+            "collisions_per_s": acc / dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--kn", type=float, default=0.01)
+    ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--profile-steps", type=int, default=10)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the slab decomposition with particle migration is a design note only)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2301_05985_amd import workloads as W
+    from paper_2301_05985_amd.binding import Simulation
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+
+    # ---------------- headline: full-size cavity
+    p, parts = W.cavity(Kn=args.kn, real="f32")
+    name = "cavity 256x256 cells x 100 particles (6,553,600), Kn=%g, diffuse walls, lid 0.01*sqrt(2), " \
+           "VR weights, FP32 state / FP64 sums" % args.kn
+    print("[bench] headline: %s" % name, file=sys.stderr, flush=True)
+    sim = Simulation(p, parts)
+    ms, wall, cand, acc = _timed_steps(sim, torch, args.steps, args.warmup)
+    n = len(parts["cx"])
+    value = n * args.steps / (ms * 1e-3)
+    print("[bench] timed %d steps: %.3f ms/step" % (args.steps, ms / args.steps), file=sys.stderr, flush=True)
+    prof = kernel_profile(sim, torch, args.profile_steps)
+    diag = sim.diagnostics()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    # dominant kernel and its roofline (HBM bound)
+    kname = max(prof, key=prof.get)
+    per_kernel = {}
+    for k, v in prof.items():
+        gbs = ALGO_BYTES[k] * n / (v * 1e-3) / 1e9 if k in ALGO_BYTES else None
+        per_kernel[k] = {"ms": v, "algo_GBps": gbs, "frac": (gbs / HBM_PEAK_GBS) if gbs else None}
+    achieved = per_kernel[kname]["algo_GBps"]
+    roof = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+            "per_kernel": per_kernel}
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": name, "particles": n, "cells": 65536, "Kn": args.kn, "dt": p["dt"],
+                   "parallelism": "single GPU"},
+        "collisions_per_s": acc / (ms * 1e-3), "candidates_per_s": cand / (ms * 1e-3),
+        "acceptance": acc / max(cand, 1),
+        "diagnostics": {k: diag[k] for k in ("overshoot", "wall_hits", "vr_nonfinite", "big_cells")},
+        "roofline": roof,
+    }
+
+    if not args.no_secondary:
+        sec = []
+        print("[bench] secondary workloads", file=sys.stderr, flush=True)
+        p2, parts2 = W.fourier(real="f32")
+        sec.append(run_workload("fourier 200 cells x 200 (40,000), Kn=0.1, VR, FP32", p2, parts2, 2000, 100, torch))
+        p3, parts3 = W.batched(real="f32")
+        sec.append(run_workload("batched 4096 cells, N uniform in [50,2000], exact majorant, FP32", p3, parts3,
+                                200, 20, torch))
+        model = os.path.join(ROOT, "paper_2301_05985_amd", "models", "majorant_mlp.npz")
+        if os.path.exists(model):
+            from paper_2301_05985_amd import learned
+            p5 = dict(p3)
+            p5["majorant"] = 1
+            sim5 = learned.simulation_with_model(p5, parts3, model)
+            ms5, wall5, cand5, acc5 = _timed_steps(sim5, torch, 200, 20)
+            d5 = sim5.diagnostics()
+            sim5.close()
+            n3 = len(parts3["cx"])
+            sec.append({"workload": "batched 4096 cells, learned majorant, FP32", "particles": n3, "steps": 200,
+                        "ms_per_step": ms5 / 200, "particle_steps_per_s": n3 * 200 / (ms5 * 1e-3),
+                        "collisions_per_s": acc5 / (ms5 * 1e-3), "candidates_per_s": cand5 / (ms5 * 1e-3),
+                        "acceptance": acc5 / max(cand5, 1), "learned_used": d5["learned_used"],
+                        "fallback": d5["fallback"], "learned_skip": d5["learned_skip"]})
+        p1, parts1 = W.relaxation()
+        sec.append(run_workload("relaxation 10,000 particles one cell FP64", p1, parts1, 200, 0, torch))
+        line["secondary"] = sec
+
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(p, parts, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -62,6 +62,9 @@ def load():
     global _lib
     if _lib is not None:
         return _lib
+    # torch ships its own HIP runtime; importing it first makes the library
+    # bind to that same runtime instead of loading a second one
+    import torch  # noqa: F401
     path = lib_path()
     if not os.path.exists(path):
         raise RuntimeError("HIP library %s is missing: run __graft_entry__.build() or "

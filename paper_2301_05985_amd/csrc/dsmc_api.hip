@@ -377,7 +377,9 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
     for (int k = 0; k < 4; ++k) {
         g.kind[k] = cfg->wall_kind[k];
         g.Tw[k] = cfg->wall_T[k];
-        for (int d = 0; d < 3; ++d) g.uw[3 * k + d] = cfg->wall_u[k][d];
+        g.ux[k] = cfg->wall_u[k][0];
+        g.uy[k] = cfg->wall_u[k][1];
+        g.uz[k] = cfg->wall_u[k][2];
     }
     g.T0 = cfg->vr ? cfg->vr_T0 : 1.0;
     g.k0 = (uint32_t)(cfg->seed & 0xFFFFFFFFull);
@@ -387,8 +389,10 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
     else c->Vuni = 1.0;
 
     // LDS capacity per cell (one wave per cell)
+    // LDS per cell: velocities (+ weights), owner marks (+4 padding entries),
+    // rank of each slot (walled runs)
     const size_t per = 3 * rb + (cfg->vr ? rb : 0) + 4 + (cfg->dims >= 1 ? 2 : 0);
-    const int cap_fit = (int)std::min<size_t>(kMaxLds / per, 65535) / 32 * 32;
+    const int cap_fit = (int)std::min<size_t>((kMaxLds - 64) / per, 65535) / 32 * 32;
     std::vector<uint32_t> start_host;
     std::vector<uint32_t> sched_host;
     if (cfg->dims == 0) {
@@ -417,7 +421,7 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
         c->any_big_possible = maxbig > 0;
         c->big_grid = (int)std::max<int64_t>(1, std::min<int64_t>(maxbig, 256));
     }
-    c->lds = (size_t)c->cap * per;
+    c->lds = (size_t)c->cap * per + 16 + 16;
 
     // graphs are recorded on a private stream (capture is not allowed on
     // the legacy default stream the caller may use)
@@ -506,8 +510,9 @@ dsmc_status dsmc_particles(dsmc_ctx *c, dsmc_soa *cur) {
 dsmc_status dsmc_diagnostics(dsmc_ctx *c, dsmc_diag *out) {
     if (!c || !out) return DSMC_EINVAL;
     HIP_TRY(hipStreamSynchronize(c->stream));
-    DevState st;
-    HIP_TRY(hipMemcpy(&st, c->st, sizeof(st), hipMemcpyDeviceToHost));
+    std::vector<unsigned char> stbuf(sizeof(DevState));
+    DevState &st = *(DevState *)stbuf.data();
+    HIP_TRY(hipMemcpy(&st, c->st, sizeof(DevState), hipMemcpyDeviceToHost));
     std::vector<unsigned long long> cnt((size_t)c->ncell * 2);
     HIP_TRY(hipMemcpy(cnt.data(), c->counters, cnt.size() * 8, hipMemcpyDeviceToHost));
     std::memset(out, 0, sizeof(*out));
@@ -516,13 +521,16 @@ dsmc_status dsmc_diagnostics(dsmc_ctx *c, dsmc_diag *out) {
         out->candidates += cnt[2 * i];
         out->accepted += cnt[2 * i + 1];
     }
-    out->overshoot = st.diag[kDiagOvershoot];
-    out->wall_hits = st.diag[kDiagWallHits];
-    out->learned_used = st.diag[kDiagLearned];
-    out->fallback = st.diag[kDiagFallback];
-    out->learned_skip = st.diag[kDiagSkip];
-    out->vr_nonfinite = st.diag[kDiagVrNonfinite];
-    out->big_cells = st.diag[kDiagBig];
+    unsigned long long tot[kDiagPerStripe] = {0};
+    for (int sidx = 0; sidx < kDiagStripes; ++sidx)
+        for (int k = 0; k < kDiagPerStripe; ++k) tot[k] += st.diag[sidx * kDiagPerStripe + k];
+    out->overshoot = tot[kDiagOvershoot];
+    out->wall_hits = tot[kDiagWallHits];
+    out->learned_used = tot[kDiagLearned];
+    out->fallback = tot[kDiagFallback];
+    out->learned_skip = tot[kDiagSkip];
+    out->vr_nonfinite = tot[kDiagVrNonfinite];
+    out->big_cells = tot[kDiagBig];
     return device_status(c);
 }
 
@@ -576,9 +584,9 @@ dsmc_status dsmc_checkpoint(dsmc_ctx *c, void *blob, size_t *bytes) {
     HIP_TRY(hipStreamSynchronize(c->stream));
     dsmc_status s = device_status(c);
     if (s != DSMC_OK) return s;
-    DevState st;
-    HIP_TRY(hipMemcpy(&st, c->st, sizeof(st), hipMemcpyDeviceToHost));
-    BlobHeader h{kBlobMagic, n, rb, (uint64_t)c->cfg.dims, nc, st.step_next, st.n_samples, (uint64_t)c->cfg.vr};
+    unsigned long long hdr[3];
+    HIP_TRY(hipMemcpy(hdr, c->st, sizeof(hdr), hipMemcpyDeviceToHost));
+    BlobHeader h{kBlobMagic, n, rb, (uint64_t)c->cfg.dims, nc, hdr[0], hdr[2], (uint64_t)c->cfg.vr};
     unsigned char *o = (unsigned char *)blob;
     std::memcpy(o, &h, sizeof(h));
     o += sizeof(h);

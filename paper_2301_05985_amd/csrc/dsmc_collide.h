@@ -93,18 +93,20 @@ struct GlobalView {
 template <typename R, typename View>
 __device__ double exact_bound(const View &v, uint32_t N, double &r_top) {
     const int lane = lane_id();
-    double lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY;
-    double hi0 = -INFINITY, hi1 = -INFINITY, hi2 = -INFINITY;
+    // box extremes: min and max are exact in the working precision
+    R lo0 = (R)INFINITY, lo1 = (R)INFINITY, lo2 = (R)INFINITY;
+    R hi0 = -(R)INFINITY, hi1 = -(R)INFINITY, hi2 = -(R)INFINITY;
     for (uint32_t r = lane; r < N; r += 64) {
         R a, b, c;
         v.get(r, a, b, c);
-        lo0 = fmin(lo0, (double)a); hi0 = fmax(hi0, (double)a);
-        lo1 = fmin(lo1, (double)b); hi1 = fmax(hi1, (double)b);
-        lo2 = fmin(lo2, (double)c); hi2 = fmax(hi2, (double)c);
+        lo0 = fmin(lo0, a); hi0 = fmax(hi0, a);
+        lo1 = fmin(lo1, b); hi1 = fmax(hi1, b);
+        lo2 = fmin(lo2, c); hi2 = fmax(hi2, c);
     }
-    lo0 = wave_min(lo0); lo1 = wave_min(lo1); lo2 = wave_min(lo2);
-    hi0 = wave_max(hi0); hi1 = wave_max(hi1); hi2 = wave_max(hi2);
-    const double m0 = 0.5 * (hi0 + lo0), m1 = 0.5 * (hi1 + lo1), m2 = 0.5 * (hi2 + lo2);
+    lo0 = wave_min_t(lo0); lo1 = wave_min_t(lo1); lo2 = wave_min_t(lo2);
+    hi0 = wave_max_t(hi0); hi1 = wave_max_t(hi1); hi2 = wave_max_t(hi2);
+    const double m0 = 0.5 * ((double)hi0 + (double)lo0), m1 = 0.5 * ((double)hi1 + (double)lo1),
+                 m2 = 0.5 * ((double)hi2 + (double)lo2);
     double a1 = 0.0, a2 = 0.0;  // largest, second largest r^2 of this lane
     for (uint32_t r = lane; r < N; r += 64) {
         R a, b, c;
@@ -251,15 +253,38 @@ __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uin
     n_over = wave_sum_u32(over);
 }
 
+// The cell's running sums and counters, read at the start of the cell's work
+// so that the final read-modify-write does not wait on memory.  Lane L owns
+// sum index L >> 1 (with weights) or L >> 2 (without); lane 0 the counters.
+struct CellPrefetch {
+    double sum;
+    unsigned long long cand, acc;
+};
+
+template <typename R, bool VR>
+__device__ __forceinline__ CellPrefetch prefetch_cell(const CollideArgs<R> &a, uint32_t cell) {
+    const int lane = lane_id();
+    const uint32_t idx = (uint32_t)lane >> (VR ? 1 : 2);
+    const bool writer = (lane & (VR ? 1 : 3)) == 0 && idx < (uint32_t)(VR ? kNsum : 13);
+    CellPrefetch pf{0.0, 0ull, 0ull};
+    if (writer) pf.sum = a.sums[(size_t)cell * kNsum + idx];
+    if (lane == 0) {
+        pf.cand = a.counters[2 * (size_t)cell];
+        pf.acc = a.counters[2 * (size_t)cell + 1];
+    }
+    return pf;
+}
+
 // FP64 moment sums of the post-collision state of one cell, added to the
 // running sums; per-cell counters and diagnostics.
 template <typename R, bool VR, typename View>
 __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cell, uint32_t N, uint32_t M,
-                            uint32_t acc, uint32_t over) {
+                            uint32_t acc, uint32_t over, const CellPrefetch &pf) {
     const int lane = lane_id();
-    double q[kNsum];
+    constexpr int K = VR ? 32 : 16;  // 26 or 13 sums, padded to a power of two
+    double q[K];
 #pragma unroll
-    for (int t = 0; t < kNsum; ++t) q[t] = 0.0;
+    for (int t = 0; t < K; ++t) q[t] = 0.0;
     for (uint32_t r = lane; r < N; r += 64) {
         R x, y, z;
         v.get(r, x, y, z);
@@ -272,26 +297,23 @@ __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cel
         if (VR) {
             const double f = 1.0 - (double)v.getw(r);
 #pragma unroll
-            for (int u = 0; u < 13; ++u) q[13 + u] += f * t[u];
+            for (int u = 0; u < 13; ++u) q[(13 + u) % K] += f * t[u];
         }
     }
-    double mine = 0.0;
-    bool bad_plain = false, bad_vr = false;
-#pragma unroll
-    for (int u = 0; u < kNsum; ++u) {
-        if (!VR && u >= 13) break;
-        const double tot = wave_sum(q[u]);
-        if (!isfinite(tot)) { if (u < 13) bad_plain = true; else bad_vr = true; }
-        if (lane == u) mine = tot;
-    }
-    const int nsum = VR ? kNsum : 13;
-    if (lane < nsum) a.sums[(size_t)cell * kNsum + lane] += mine;
+    // lane L ends up with the total of sum index L >> (VR ? 1 : 2)
+    const double tot = wave_sum_many<K>(q);
+    const uint32_t idx = (uint32_t)lane >> (VR ? 1 : 2);
+    const bool writer = (lane & (VR ? 1 : 3)) == 0 && idx < (uint32_t)(VR ? kNsum : 13);
+    const bool nonfinite = writer && !isfinite(tot);
+    const bool bad_plain = __ballot(nonfinite && idx < 13) != 0ull;
+    const bool bad_vr = __ballot(nonfinite && idx >= 13) != 0ull;
+    if (writer) a.sums[(size_t)cell * kNsum + idx] = pf.sum + tot;
     if (lane == 0) {
-        a.counters[2 * (size_t)cell] += M;
-        a.counters[2 * (size_t)cell + 1] += acc;
-        if (over) atomicAdd(&a.st->diag[kDiagOvershoot], (unsigned long long)over);
+        a.counters[2 * (size_t)cell] = pf.cand + M;
+        a.counters[2 * (size_t)cell + 1] = pf.acc + acc;
+        if (over) diag_add(a.st, kDiagOvershoot, (unsigned long long)over);
         if (bad_plain) set_error(a.st, DSMC_ENONFINITE);
-        if (bad_vr) atomicAdd(&a.st->diag[kDiagVrNonfinite], 1ull);
+        if (bad_vr) diag_add(a.st, kDiagVrNonfinite, 1ull);
     }
 }
 
@@ -299,7 +321,7 @@ __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cel
 // already holds the cell in canonical order.
 template <typename R, bool VR, typename View>
 __device__ void process_cell(const CollideArgs<R> &a, const View &v, uint32_t cell, uint32_t N,
-                             uint32_t step) {
+                             uint32_t step, const CellPrefetch &pf) {
     const int lane = lane_id();
     uint32_t M = 0, acc = 0, over = 0;
     if (N >= 2) {
@@ -323,7 +345,7 @@ __device__ void process_cell(const CollideArgs<R> &a, const View &v, uint32_t ce
         M = (uint32_t)Mf;
         ntc_loop<R, VR>(v, N, gmax, M, cell, step, a.k0, a.k1, a.molecule, acc, over);
     }
-    sample_cell<R, VR>(a, v, cell, N, M, acc, over);
+    sample_cell<R, VR>(a, v, cell, N, M, acc, over, pf);
 }
 
 }  // namespace dsmc

@@ -24,27 +24,50 @@ __device__ __forceinline__ void collide_lds_body(const CollideArgs<R> &a, unsign
         return;
     }
     const uint32_t step = (uint32_t)a.st->step_cur;
+    const CellPrefetch pf = prefetch_cell<R, VR>(a, cell);
     const int cap = a.cap;
     R *vx = (R *)smem, *vy = vx + cap, *vz = vy + cap;
     R *w = VR ? vz + cap : nullptr;
-    uint32_t *owner = (uint32_t *)(VR ? w + cap : vz + cap);
-    uint16_t *rank_of_slot = (uint16_t *)(owner + cap);
+    uint32_t *owner = (uint32_t *)(VR ? w + cap : vz + cap);  // cap + 4 entries
+    uint16_t *rank_of_slot = (uint16_t *)(owner + cap + 4);
     if (BYID) {
+        // canonical order: rank of each slot by particle id, counted against
+        // the whole cell with 16-byte broadcast reads; up to four slots per
+        // lane per pass (cells of up to 256 particles take one pass)
         uint32_t *ids = owner;  // the owner array is free until the ranks are known
         for (uint32_t s = lane; s < N; s += 64) ids[s] = a.s.id[base + s];
+        if (lane < 4) ids[N + lane] = 0xFFFFFFFFu;  // padding never ranks below a real id
         __syncthreads();
-        for (uint32_t s0 = 0; s0 < N; s0 += 64) {
-            const uint32_t s = s0 + lane;
-            if (s < N) {
-                const R x = a.s.cx[base + s], y = a.s.cy[base + s], z = a.s.cz[base + s];
-                R ww = (R)0;
-                if (VR) ww = a.s.w[base + s];
-                const uint32_t me = ids[s];
-                uint32_t rank = 0;
-                for (uint32_t t = 0; t < N; ++t) rank += ids[t] < me ? 1u : 0u;
-                rank_of_slot[s] = (uint16_t)rank;
-                vx[rank] = x; vy[rank] = y; vz[rank] = z;
-                if (VR) w[rank] = ww;
+        const uint4 *ids4 = (const uint4 *)ids;
+        const uint32_t n4 = (N + 3) / 4;
+        for (uint32_t s0 = 0; s0 < N; s0 += 256) {
+            uint32_t me[4], rk[4] = {0u, 0u, 0u, 0u};
+            R x[4], y[4], z[4], ww[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t s = s0 + (uint32_t)j * 64 + lane;
+                me[j] = 0u;
+                if (s < N) {
+                    me[j] = ids[s];
+                    x[j] = a.s.cx[base + s]; y[j] = a.s.cy[base + s]; z[j] = a.s.cz[base + s];
+                    if (VR) ww[j] = a.s.w[base + s];
+                }
+            }
+            for (uint32_t t4 = 0; t4 < n4; ++t4) {
+                const uint4 q = ids4[t4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    rk[j] += (uint32_t)(q.x < me[j]) + (uint32_t)(q.y < me[j]) + (uint32_t)(q.z < me[j]) +
+                             (uint32_t)(q.w < me[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t s = s0 + (uint32_t)j * 64 + lane;
+                if (s < N) {
+                    rank_of_slot[s] = (uint16_t)rk[j];
+                    vx[rk[j]] = x[j]; vy[rk[j]] = y[j]; vz[rk[j]] = z[j];
+                    if (VR) w[rk[j]] = ww[j];
+                }
             }
         }
         __syncthreads();
@@ -57,8 +80,8 @@ __device__ __forceinline__ void collide_lds_body(const CollideArgs<R> &a, unsign
     for (uint32_t r = lane; r < N; r += 64) owner[r] = 0xFFFFFFFFu;
     __syncthreads();
     const LdsView<R> view{vx, vy, vz, w, owner};
-    if (LEARNED) process_cell_learned<R, VR>(a, view, cell, N, step);
-    else process_cell<R, VR>(a, view, cell, N, step);
+    if (LEARNED) process_cell_learned<R, VR>(a, view, cell, N, step, pf);
+    else process_cell<R, VR>(a, view, cell, N, step, pf);
     __syncthreads();
     for (uint32_t s = lane; s < N; s += 64) {
         const uint32_t r = BYID ? (uint32_t)rank_of_slot[s] : s;
@@ -91,9 +114,10 @@ __device__ __forceinline__ void collide_big_body(const CollideArgs<R> &a) {
                                  VR ? a.s.w + base : nullptr, perm, a.owner_g + base};
         for (uint32_t r = lane; r < N; r += 64) view.clear_own(r);
         __syncthreads();
-        if (LEARNED) process_cell_learned<R, VR>(a, view, cell, N, step);
-        else process_cell<R, VR>(a, view, cell, N, step);
-        if (lane == 0) atomicAdd(&a.st->diag[kDiagBig], 1ull);
+        const CellPrefetch pf = prefetch_cell<R, VR>(a, cell);
+        if (LEARNED) process_cell_learned<R, VR>(a, view, cell, N, step, pf);
+        else process_cell<R, VR>(a, view, cell, N, step, pf);
+        if (lane == 0) diag_add(a.st, kDiagBig, 1ull);
         __syncthreads();
     }
 }

@@ -80,26 +80,98 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
     return v;
 }
 
-// Wave-aggregated counter increment: lanes with equal `key` share one
-// atomic; returns the value each lane would have obtained from its own
-// atomicAdd(&ctr[key], 1) in some order.  The loop runs once per distinct
-// key in the wave, which after the first step is a handful, because the
-// particle arrays arrive sorted by cell.
-__device__ __forceinline__ uint32_t wave_aggregated_inc(uint32_t *ctr, uint32_t key, bool active) {
+// Wave-aggregated counter increment.  Lanes with equal `key` form a group;
+// each group's first lane (its leader) adds the group size with a single
+// atomic, all groups' atomics being issued by one instruction.  Returns the
+// value each lane would have obtained from its own atomicAdd(&ctr[key], 1) in
+// some order (or nothing, for the counting-only variant).  The grouping loop
+// runs once per distinct key in the wave: a handful, because the particle
+// arrays arrive sorted by cell after the first step.
+struct WaveGroup {
+    int leader;       // lane that carries the group's atomic
+    uint32_t rank;    // position of this lane inside its group
+    uint32_t size;    // group size (valid on the leader)
+};
+
+__device__ __forceinline__ WaveGroup wave_group(uint32_t key, bool active) {
     const int lane = lane_id();
+    const unsigned long long lt = (1ull << lane) - 1ull;
     unsigned long long rem = __ballot(active);
-    uint32_t slot = 0;
+    WaveGroup g{lane, 0u, 0u};
     while (rem) {
         const int leader = __ffsll((long long)rem) - 1;
-        const uint32_t lk = __shfl(key, leader, 64);
+        const uint32_t lk = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
         const unsigned long long same = __ballot(active && key == lk) & rem;
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(&ctr[lk], (uint32_t)__popcll(same));
-        base = __shfl(base, leader, 64);
-        if ((same >> lane) & 1ull) slot = base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+        if ((same >> lane) & 1ull) {
+            g.leader = leader;
+            g.rank = (uint32_t)__popcll(same & lt);
+        }
+        if (lane == leader) g.size = (uint32_t)__popcll(same);
         rem &= ~same;
     }
-    return slot;
+    return g;
+}
+
+__device__ __forceinline__ void wave_aggregated_add(uint32_t *ctr, uint32_t key, bool active) {
+    const WaveGroup g = wave_group(key, active);
+    if (active && g.leader == lane_id()) atomicAdd(&ctr[key], g.size);  // result unused: no-return atomic
+}
+
+__device__ __forceinline__ uint32_t wave_aggregated_inc(uint32_t *ctr, uint32_t key, bool active) {
+    const WaveGroup g = wave_group(key, active);
+    uint32_t base = 0;
+    if (active && g.leader == lane_id()) base = atomicAdd(&ctr[key], g.size);
+    base = __shfl(base, g.leader, 64);
+    return base + g.rank;
+}
+
+// Sum K per-lane values (K a power of two, at most 32) over the wave by
+// recursive halving: at stride 32 each half of the wave keeps half of the
+// values and receives the partner's copy of them, and so on until one value
+// per lane is left; the remaining strides add it up.  K + log2(64/K) - 1
+// shuffles instead of 6 K.  On return lane L holds the total of value index
+// L >> log2(64/K).
+template <int K, int HALF, int OFF>
+struct HalvingStep {
+    // one level: keep HALF values, receive the partner's copy of them
+    static __device__ __forceinline__ void run(double (&v)[K], int lane) {
+        const bool upper = (lane & OFF) != 0;
+#pragma unroll
+        for (int k = 0; k < HALF; ++k) {
+            const double keep = upper ? v[HALF + k] : v[k];
+            const double send = upper ? v[k] : v[HALF + k];
+            v[k] = keep + __shfl_xor(send, OFF, 64);
+        }
+        HalvingStep<K, HALF / 2, OFF / 2>::run(v, lane);
+    }
+};
+template <int K, int OFF>
+struct HalvingStep<K, 0, OFF> {
+    static __device__ __forceinline__ void run(double (&)[K], int) {}
+};
+
+template <int K>
+__device__ __forceinline__ double wave_sum_many(double (&v)[K]) {
+    static_assert(K >= 1 && K <= 32 && (K & (K - 1)) == 0, "K must be a power of two <= 32");
+    const int lane = lane_id();
+    HalvingStep<K, K / 2, 32>::run(v, lane);
+    double r = v[0];
+#pragma unroll
+    for (int o = 64 / (2 * K); o >= 1; o >>= 1) r += __shfl_xor(r, o, 64);
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_min_t(T v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_max_t(T v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
 }
 
 }  // namespace dsmc

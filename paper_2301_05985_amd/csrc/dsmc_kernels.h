@@ -17,16 +17,27 @@
 
 namespace dsmc {
 
+// Diagnostic counters are striped over kDiagStripes cache lines (workgroup
+// index modulo the stripe count): thousands of workgroups adding to one
+// address would serialize in a single L2 channel.  The host sums the stripes.
+constexpr int kDiagStripes = 1024;
+constexpr int kDiagPerStripe = 8;
+
 struct DevState {
     unsigned long long step_next;   // index of the next step to stream
     unsigned long long step_cur;    // index of the step being collided
     unsigned long long n_samples;   // sampled steps since the last reset
     unsigned int error;             // first device error (positive code), 0 = none
     unsigned int big_count;         // cells queued for the global-memory collision kernel
-    unsigned long long diag[8];
+    unsigned long long pad[4];
+    unsigned long long diag[kDiagStripes * kDiagPerStripe];
 };
 enum { kDiagOvershoot = 0, kDiagWallHits, kDiagLearned, kDiagFallback, kDiagSkip, kDiagVrNonfinite,
        kDiagBig };
+
+__device__ __forceinline__ void diag_add(DevState *st, int which, unsigned long long v) {
+    atomicAdd(&st->diag[(blockIdx.x & (kDiagStripes - 1)) * kDiagPerStripe + which], v);
+}
 
 __device__ __forceinline__ void set_error(DevState *st, int code) {
     atomicCAS(&st->error, 0u, (unsigned int)(-code));
@@ -37,7 +48,7 @@ struct Geo {
     double Lx, Ly, dt, invx, invy;
     int kind[4];
     double Tw[4];
-    double uw[12];
+    double ux[4], uy[4], uz[4];  // wall velocities by component
     double T0;
     uint32_t k0, k1;
 };
@@ -89,6 +100,13 @@ __device__ __forceinline__ double wall_weight_ratio(double vx, double vy, double
     return ((Tw * Tw) / (T0 * T0)) * exp(ex);
 }
 
+// Element w of a 4-entry argument array by selects (a dynamic index into a
+// kernel-argument array would copy the array to scratch memory).
+template <typename T>
+__device__ __forceinline__ T pick4(const T (&a)[4], int w) {
+    return w == 0 ? a[0] : (w == 1 ? a[1] : (w == 2 ? a[2] : a[3]));
+}
+
 // ------------------------------------------------------------ free flight
 // Exact times of flight to the walls the particle moves toward; a hit snaps
 // the particle onto the wall, applies the wall condition and continues with
@@ -126,7 +144,7 @@ __device__ __forceinline__ int fly(const Geo &g, R &x, R &y, R &cx, R &cy, R &cz
         if (xwall) { wall = cx > zero ? 1 : 0; x = wall ? Lx : zero; }
         else       { wall = cy > zero ? 3 : 2; y = wall == 3 ? Ly : zero; }
         if ((int)hits >= g.max_hits) return DSMC_EWALLHITS;
-        const int kind = g.kind[wall];
+        const int kind = pick4(g.kind, wall);
         if (kind == DSMC_WALL_PERIODIC) {
             if (xwall) x = wall ? zero : Lx;
             else       y = wall == 3 ? zero : Ly;
@@ -135,13 +153,14 @@ __device__ __forceinline__ int fly(const Geo &g, R &x, R &y, R &cx, R &cy, R &cz
         } else {
             if (!have_pid) { pid = ids[p]; have_pid = true; }
             R dn, d1, d2;
-            wall_draw((R)g.Tw[wall], hits, pid, step, g.k0, g.k1, dn, d1, d2);
+            const double Tw = pick4(g.Tw, wall);
+            wall_draw((R)Tw, hits, pid, step, g.k0, g.k1, dn, d1, d2);
             const R sign = (wall & 1) ? (R)-1 : (R)1;
-            const double *uw = &g.uw[3 * wall];
+            const double uw[3] = {pick4(g.ux, wall), pick4(g.uy, wall), pick4(g.uz, wall)};
             if (xwall) { cx = sign * dn; cy = d1 + (R)uw[1]; cz = d2 + (R)uw[2]; }
             else       { cy = sign * dn; cx = d1 + (R)uw[0]; cz = d2 + (R)uw[2]; }
             if (WANT_W) {
-                const double ratio = wall_weight_ratio((double)cx, (double)cy, (double)cz, g.Tw[wall], uw, g.T0);
+                const double ratio = wall_weight_ratio((double)cx, (double)cy, (double)cz, Tw, uw, g.T0);
                 w = (R)((double)w * ratio);
             }
         }
@@ -177,7 +196,7 @@ __global__ __launch_bounds__(256) void k_stream_count(Geo g, Soa<R> s, int64_t n
         if (rc) set_error(st, rc);
         cell = cell_index(g, (double)x, D == 2 ? (double)y : 0.0);
     }
-    (void)wave_aggregated_inc(count, cell, act);
+    wave_aggregated_add(count, cell, act);
 }
 
 // Pass 2: fly again (same bits), claim a slot in the cell's range and write
@@ -216,21 +235,41 @@ __global__ __launch_bounds__(256) void k_stream_scatter(Geo g, Soa<R> src, Soa<R
         dst.id[slot] = pid;
     }
     const uint32_t hsum = wave_sum_u32(hits);
-    if (lane_id() == 0 && hsum) atomicAdd(&st->diag[kDiagWallHits], (unsigned long long)hsum);
+    if (lane_id() == 0 && hsum) diag_add(st, kDiagWallHits, (unsigned long long)hsum);
 }
 
-// Exclusive scan of the per-cell counts (one workgroup of 1024 threads, each
-// owning a contiguous chunk), writing offsets and cursors and clearing the
-// counts for the next step.  Thread 0 also advances the step bookkeeping.
+// Exclusive scan of the per-cell counts in one workgroup of 1024 threads,
+// writing offsets and cursors and clearing the counts for the next step;
+// thread 0 also advances the step bookkeeping.  Each thread owns a
+// contiguous chunk; when the cell count is a multiple of 4 and at most
+// 65,536 the chunk is moved with 16-byte loads and stores, all issued before
+// the first is consumed.
 __global__ __launch_bounds__(1024) void k_scan(uint32_t *count, uint32_t *offset, uint32_t *cursor,
                                                int ncell, DevState *st) {
     __shared__ uint32_t wave_tot[16];
     const int t = threadIdx.x, lane = lane_id(), wv = t >> 6;
-    const int per = (ncell + 1023) / 1024;
-    const int b = t * per, e = min(b + per, ncell);
+    const bool vec = (ncell % 4) == 0 && ncell <= 65536;
+    constexpr int kV = 16;  // uint4 per thread in the vector path
+    uint4 q[kV];
+    int b, e;
     uint32_t local = 0;
-    for (int i = b; i < e; ++i) local += count[i];
-    // inclusive scan inside the wave
+    if (vec) {
+        const int n4 = ncell / 4;
+        const int per4 = (n4 + 1023) / 1024;
+        b = t * per4;
+        e = min(b + per4, n4);
+        const uint4 *c4 = (const uint4 *)count;
+#pragma unroll
+        for (int k = 0; k < kV; ++k) q[k] = (b + k < e) ? c4[b + k] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int k = 0; k < kV; ++k) local += (q[k].x + q[k].y) + (q[k].z + q[k].w);
+    } else {
+        const int per = (ncell + 1023) / 1024;
+        b = t * per;
+        e = min(b + per, ncell);
+        for (int i = b; i < e; ++i) local += count[i];
+    }
+    // block-wide exclusive scan of the chunk totals
     uint32_t inc = local;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -240,25 +279,43 @@ __global__ __launch_bounds__(1024) void k_scan(uint32_t *count, uint32_t *offset
     if (lane == 63) wave_tot[wv] = inc;
     __syncthreads();
     if (wv == 0) {
-        uint32_t v = lane < 16 ? wave_tot[lane] : 0u, s = v;
+        const uint32_t v = lane < 16 ? wave_tot[lane] : 0u;
+        uint32_t s = v;
 #pragma unroll
         for (int off = 1; off < 16; off <<= 1) {
             const uint32_t u = __shfl_up(s, off, 64);
             if (lane >= off) s += u;
         }
-        if (lane < 16) wave_tot[lane] = s - v;  // exclusive prefix of the wave totals
+        if (lane < 16) wave_tot[lane] = s - v;
     }
     __syncthreads();
     uint32_t run = wave_tot[wv] + inc - local;
-    for (int i = b; i < e; ++i) {
-        const uint32_t c = count[i];
-        offset[i] = run;
-        cursor[i] = run;
-        count[i] = 0;
-        run += c;
+    if (vec) {
+        uint4 *o4 = (uint4 *)offset, *u4 = (uint4 *)cursor, *c4 = (uint4 *)count;
+#pragma unroll
+        for (int k = 0; k < kV; ++k) {
+            if (b + k < e) {
+                uint4 r;
+                r.x = run; run += q[k].x;
+                r.y = run; run += q[k].y;
+                r.z = run; run += q[k].z;
+                r.w = run; run += q[k].w;
+                o4[b + k] = r;
+                u4[b + k] = r;
+                c4[b + k] = make_uint4(0, 0, 0, 0);
+            }
+        }
+        if (e == ncell / 4 && b < e) offset[ncell] = run;
+    } else {
+        for (int i = b; i < e; ++i) {
+            const uint32_t c = count[i];
+            offset[i] = run;
+            cursor[i] = run;
+            count[i] = 0;
+            run += c;
+        }
+        if (e == ncell && b < e) offset[ncell] = run;
     }
-    if (e == ncell && b < e) offset[ncell] = run;
-    if (ncell <= t * per && t == 0) offset[ncell] = 0;
     if (t == 0) {
         st->step_cur = st->step_next;
         st->step_next = st->step_next + 1;

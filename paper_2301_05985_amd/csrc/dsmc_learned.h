@@ -159,7 +159,7 @@ __device__ double learned_majorant(const CollideArgs<R> &a, const View &v, uint3
 // Same as process_cell, with the learned majorant.
 template <typename R, bool VR, typename View>
 __device__ void process_cell_learned(const CollideArgs<R> &a, const View &v, uint32_t cell, uint32_t N,
-                                     uint32_t step) {
+                                     uint32_t step, const CellPrefetch &pf) {
     const int lane = lane_id();
     uint32_t M = 0, acc = 0, over = 0;
     if (N >= 2) {
@@ -168,7 +168,7 @@ __device__ void process_cell_learned(const CollideArgs<R> &a, const View &v, uin
         const double gmax = learned_majorant<R>(a, v, cell, N, V, used);
         if (lane == 0) {
             const int slot = used == 1 ? kDiagLearned : (used == -1 ? kDiagFallback : kDiagSkip);
-            atomicAdd(&a.st->diag[slot], 1ull);
+            diag_add(a.st, slot, 1ull);
         }
         const double Nd = (double)N;
         const double Mreal = ((((((0.5 * Nd) * (Nd - 1.0)) * a.FN) * a.sigma) * gmax) * a.dt) / V;
@@ -182,7 +182,7 @@ __device__ void process_cell_learned(const CollideArgs<R> &a, const View &v, uin
         M = (uint32_t)Mf;
         ntc_loop<R, VR>(v, N, gmax, M, cell, step, a.k0, a.k1, a.molecule, acc, over);
     }
-    sample_cell<R, VR>(a, v, cell, N, M, acc, over);
+    sample_cell<R, VR>(a, v, cell, N, M, acc, over, pf);
 }
 
 }  // namespace dsmc
