@@ -37,7 +37,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t alt[7];  // x y cx cy cz w id of the second particle buffer
-    size_t count, offset, cursor, sums, counters, volume, state, big_list, perm, owner, sched;
+    size_t count, offset, cursor, sums, counters, volume, state, big_list, perm, owner, sched, flags, done;
     size_t mlp, lattice;
     size_t total;
 };
@@ -93,6 +93,8 @@ Layout make_layout(const dsmc_config &c) {
         L.alt[6] = take(n * 4);
         L.count = take(nc * 4);
         L.cursor = take(nc * 4);
+        L.flags = take(((nc + kScanTile - 1) / kScanTile) * 8);
+        L.done = take(4);
     }
     L.offset = take((nc + 1) * 4);
     L.sums = take(nc * kNsum * 8);
@@ -130,6 +132,8 @@ struct dsmc_ctx {
     size_t lds = 0;
     int big_grid = 0;
     bool any_big_possible = false;
+    uint64_t *flags = nullptr;
+    uint32_t *done = nullptr;
     uint32_t *count = nullptr, *offset = nullptr, *cursor = nullptr, *big_list = nullptr,
              *perm = nullptr, *owner = nullptr, *sched = nullptr;
     double *sums = nullptr, *volume = nullptr, *lattice = nullptr;
@@ -227,8 +231,8 @@ void launch_sort(dsmc_ctx *c, Launcher &L, int src) {
                            c->count, c->st);
     }
     L.mark("scan");
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, L.s, c->count, c->offset, c->cursor, (int)c->ncell,
-                       c->st);
+    hipLaunchKernelGGL(k_scan_lookback, dim3((unsigned)((c->ncell + kScanTile - 1) / kScanTile)), dim3(256), 0, L.s,
+                       c->count, c->offset, c->cursor, (int)c->ncell, c->flags, c->done, c->st);
     if (c->n > 0) {
         L.mark("stream_scatter");
         hipLaunchKernelGGL((k_stream_scatter<R, D, VR>), dim3(grid), dim3(256), 0, L.s, c->geo, s, d,
@@ -347,6 +351,8 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
                          c->ws + L.alt[4], c->ws + L.alt[5], (uint32_t *)(c->ws + L.alt[6])};
         c->count = (uint32_t *)(c->ws + L.count);
         c->cursor = (uint32_t *)(c->ws + L.cursor);
+        c->flags = (uint64_t *)(c->ws + L.flags);
+        c->done = (uint32_t *)(c->ws + L.done);
     } else {
         c->buf[1] = c->buf[0];
     }
@@ -435,6 +441,8 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
         return fail(DSMC_EHIP);
     if (hipMemsetAsync(c->st, 0, sizeof(DevState), c->stream) != hipSuccess) return fail(DSMC_EHIP);
     if (cfg->dims >= 1 && hipMemsetAsync(c->count, 0, (size_t)c->ncell * 4, c->stream) != hipSuccess)
+        return fail(DSMC_EHIP);
+    if (cfg->dims >= 1 && hipMemsetAsync(c->ws + L.flags, 0, L.done + 4 - L.flags, c->stream) != hipSuccess)
         return fail(DSMC_EHIP);
     if (cfg->cell_volume) {
         c->volume_host.assign(cfg->cell_volume, cfg->cell_volume + c->ncell);

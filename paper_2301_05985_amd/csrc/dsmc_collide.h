@@ -164,18 +164,28 @@ __device__ __forceinline__ void direction(bool pending, uint32_t k, uint32_t cel
 }
 
 // The NTC candidate loop of one cell in conflict-free wave batches.
+//
+// Velocities: only accepted candidates write them, so a batch ends at the
+// first candidate that reads a particle an earlier accepted candidate of the
+// batch has changed.  Importance weights: every candidate writes them; the
+// committed candidates of a batch replay their weight updates in order, in
+// sub-batches that end at the first candidate touching a particle whose
+// weight an earlier pending candidate updates.  Both chains give exactly the
+// sequential result, and separating them keeps the (expensive) velocity
+// batches long when weights are carried.
 template <typename R, bool VR, typename View>
 __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uint32_t cell,
                          uint32_t step, uint32_t k0, uint32_t k1, int molecule, uint32_t &n_acc,
                          uint32_t &n_over) {
     const int lane = lane_id();
+    const uint32_t ulane = (uint32_t)lane;
     const R gm = (R)gmax;
     const R gm2 = gm * gm;
     uint32_t kb = 0, acc = 0, over = 0;
     while (kb < M) {
         const uint32_t B = min(64u, M - kb);
-        const bool act = (uint32_t)lane < B;
-        const uint32_t k = kb + (uint32_t)lane;
+        const bool act = ulane < B;
+        const uint32_t k = kb + ulane;
         uint32_t i = 0, j = 0;
         R U = (R)0;
         if (act) {
@@ -187,7 +197,6 @@ __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uin
         }
         R ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0, g2 = 0;
         bool accept = false;
-        double p = 0.0;
         if (act) {
             v.get(i, ax, ay, az);
             v.get(j, bx, by, bz);
@@ -195,43 +204,25 @@ __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uin
             g2 = (dx * dx + dy * dy) + dz * dz;
             if (molecule == DSMC_MAXWELL) {
                 accept = true;
-                p = 1.0;
             } else {
                 const R a = U * gm;
                 accept = (a * a) < g2;
-                p = sqrt((double)g2) / gmax;
             }
         }
-        const bool writer = act && (VR || accept);
+        const bool writer = act && accept;
         if (writer) {
-            atomicMin(v.own(i), (uint32_t)lane);
-            atomicMin(v.own(j), (uint32_t)lane);
+            atomicMin(v.own(i), ulane);
+            atomicMin(v.own(j), ulane);
         }
         __syncthreads();
-        const bool bad = act && (v.read_own(i) < (uint32_t)lane || v.read_own(j) < (uint32_t)lane);
+        const bool bad = act && (v.read_own(i) < ulane || v.read_own(j) < ulane);
         const unsigned long long badm = __ballot(bad);
         const uint32_t P = badm ? (uint32_t)(__ffsll((long long)badm) - 1) : B;
-        const bool commit = act && (uint32_t)lane < P;
+        const bool commit = act && ulane < P;
         __syncthreads();
         if (writer) {
             v.clear_own(i);
             v.clear_own(j);
-        }
-        if (VR && commit) {
-            // importance weights (Al-Mohssen & Hadjiconstantinou 2010):
-            // accepted -> both W_i W_j; rejected -> W_i (1 - p W_j) / (1 - p)
-            const double wa = (double)v.getw(i), wb = (double)v.getw(j);
-            if (accept) {
-                const double ab = wa * wb;
-                v.putw(i, (R)ab);
-                v.putw(j, (R)ab);
-            } else {
-                const double q = 1.0 - p;
-                if (q > 0.0) {
-                    v.putw(i, (R)((wa * (1.0 - p * wb)) / q));
-                    v.putw(j, (R)((wb * (1.0 - p * wa)) / q));
-                }
-            }
         }
         const bool coll = commit && accept;
         R nx, ny, nz;
@@ -246,6 +237,47 @@ __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uin
         }
         if (molecule != DSMC_MAXWELL && commit && g2 > gm2) over++;
         acc += (uint32_t)__popcll(__ballot(coll));
+        if (VR) {
+            // importance weights (Al-Mohssen & Hadjiconstantinou 2010) of the
+            // committed candidates, in candidate order: accepted -> both
+            // W_i W_j; rejected -> W_i (1 - p W_j) / (1 - p), p = g / g_max
+            double p = 1.0;
+            if (commit && !accept && molecule != DSMC_MAXWELL) p = sqrt((double)g2) / gmax;
+            uint32_t q0 = 0;
+            __syncthreads();
+            while (q0 < P) {
+                const bool pend = commit && ulane >= q0;
+                if (pend) {
+                    atomicMin(v.own(i), ulane);
+                    atomicMin(v.own(j), ulane);
+                }
+                __syncthreads();
+                const bool wbad = pend && (v.read_own(i) < ulane || v.read_own(j) < ulane);
+                const unsigned long long wm = __ballot(wbad);
+                const uint32_t Q = wm ? (uint32_t)(__ffsll((long long)wm) - 1) : P;
+                __syncthreads();
+                if (pend) {
+                    v.clear_own(i);
+                    v.clear_own(j);
+                }
+                if (pend && ulane < Q) {
+                    const double wa = (double)v.getw(i), wb = (double)v.getw(j);
+                    if (accept) {
+                        const double ab = wa * wb;
+                        v.putw(i, (R)ab);
+                        v.putw(j, (R)ab);
+                    } else {
+                        const double q = 1.0 - p;
+                        if (q > 0.0) {
+                            v.putw(i, (R)((wa * (1.0 - p * wb)) / q));
+                            v.putw(j, (R)((wb * (1.0 - p * wa)) / q));
+                        }
+                    }
+                }
+                __syncthreads();
+                q0 = Q;
+            }
+        }
         __syncthreads();
         kb += P;
     }

@@ -7,6 +7,45 @@
 
 namespace dsmc {
 
+// One pass of the id ranking: J slots per lane (slots s0 + 64 j + lane),
+// each counted against every id of the cell with 16-byte broadcast reads;
+// the slot's particle is placed at its rank in the LDS arrays.
+template <typename R, bool VR, int J>
+__device__ __forceinline__ void rank_pass(const CollideArgs<R> &a, uint32_t base, uint32_t s0, uint32_t N,
+                                          uint32_t n4, const uint32_t *ids, const uint4 *ids4, R *vx, R *vy,
+                                          R *vz, R *w, uint16_t *rank_of_slot) {
+    const uint32_t lane = (uint32_t)lane_id();
+    uint32_t me[J], rk[J];
+    R x[J], y[J], z[J], ww[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const uint32_t s = s0 + (uint32_t)j * 64 + lane;
+        me[j] = 0u;
+        rk[j] = 0u;
+        if (s < N) {
+            me[j] = ids[s];
+            x[j] = a.s.cx[base + s]; y[j] = a.s.cy[base + s]; z[j] = a.s.cz[base + s];
+            if (VR) ww[j] = a.s.w[base + s];
+        }
+    }
+    for (uint32_t t4 = 0; t4 < n4; ++t4) {
+        const uint4 q = ids4[t4];
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+            rk[j] += (uint32_t)(q.x < me[j]) + (uint32_t)(q.y < me[j]) + (uint32_t)(q.z < me[j]) +
+                     (uint32_t)(q.w < me[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const uint32_t s = s0 + (uint32_t)j * 64 + lane;
+        if (s < N) {
+            rank_of_slot[s] = (uint16_t)rk[j];
+            vx[rk[j]] = x[j]; vy[rk[j]] = y[j]; vz[rk[j]] = z[j];
+            if (VR) w[rk[j]] = ww[j];
+        }
+    }
+}
+
 // LDS kernel: one wave per cell.  BYID: the cell arrives in arbitrary order
 // from the counting sort and is ranked by particle id in LDS (canonical
 // order); otherwise (homogeneous instances) storage order is canonical.
@@ -41,34 +80,11 @@ __device__ __forceinline__ void collide_lds_body(const CollideArgs<R> &a, unsign
         const uint4 *ids4 = (const uint4 *)ids;
         const uint32_t n4 = (N + 3) / 4;
         for (uint32_t s0 = 0; s0 < N; s0 += 256) {
-            uint32_t me[4], rk[4] = {0u, 0u, 0u, 0u};
-            R x[4], y[4], z[4], ww[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const uint32_t s = s0 + (uint32_t)j * 64 + lane;
-                me[j] = 0u;
-                if (s < N) {
-                    me[j] = ids[s];
-                    x[j] = a.s.cx[base + s]; y[j] = a.s.cy[base + s]; z[j] = a.s.cz[base + s];
-                    if (VR) ww[j] = a.s.w[base + s];
-                }
-            }
-            for (uint32_t t4 = 0; t4 < n4; ++t4) {
-                const uint4 q = ids4[t4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    rk[j] += (uint32_t)(q.x < me[j]) + (uint32_t)(q.y < me[j]) + (uint32_t)(q.z < me[j]) +
-                             (uint32_t)(q.w < me[j]);
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const uint32_t s = s0 + (uint32_t)j * 64 + lane;
-                if (s < N) {
-                    rank_of_slot[s] = (uint16_t)rk[j];
-                    vx[rk[j]] = x[j]; vy[rk[j]] = y[j]; vz[rk[j]] = z[j];
-                    if (VR) w[rk[j]] = ww[j];
-                }
-            }
+            const uint32_t left = N - s0;
+            if (left > 192) rank_pass<R, VR, 4>(a, base, s0, N, n4, ids, ids4, vx, vy, vz, w, rank_of_slot);
+            else if (left > 128) rank_pass<R, VR, 3>(a, base, s0, N, n4, ids, ids4, vx, vy, vz, w, rank_of_slot);
+            else if (left > 64) rank_pass<R, VR, 2>(a, base, s0, N, n4, ids, ids4, vx, vy, vz, w, rank_of_slot);
+            else rank_pass<R, VR, 1>(a, base, s0, N, n4, ids, ids4, vx, vy, vz, w, rank_of_slot);
         }
         __syncthreads();
     } else {

@@ -324,6 +324,105 @@ __global__ __launch_bounds__(1024) void k_scan(uint32_t *count, uint32_t *offset
     }
 }
 
+// Exclusive scan of the per-cell counts as a single-pass decoupled
+// look-back scan (Merrill & Garland 2016): each workgroup of 256 threads
+// scans a tile of 1024 cells, publishes its tile total (flag AGG) and, once
+// its prefix is known, its inclusive prefix (flag INC); a tile's prefix is
+// found by walking back over earlier tiles' flags.  Workgroups are dispatched
+// in index order, so every tile it waits on is resident or finished; the walk
+// still gives up (and reports an error) after a bounded number of polls.  The
+// last workgroup to finish clears the flags for the next launch and advances
+// the step bookkeeping.
+constexpr int kScanTile = 1024;
+constexpr uint64_t kFlagAgg = 1ull << 32, kFlagInc = 2ull << 32;
+
+__global__ __launch_bounds__(256) void k_scan_lookback(uint32_t *count, uint32_t *offset, uint32_t *cursor,
+                                                       int ncell, uint64_t *flags, uint32_t *done,
+                                                       DevState *st) {
+    __shared__ uint32_t wave_tot[4];
+    __shared__ uint32_t tile_prefix;
+    __shared__ bool last;
+    const int t = threadIdx.x, lane = lane_id(), wv = t >> 6;
+    const int tile = blockIdx.x;
+    const int c0 = tile * kScanTile + t * 4;
+    uint4 q = make_uint4(0, 0, 0, 0);
+    if (c0 + 3 < ncell) {
+        q = *(const uint4 *)(count + c0);
+    } else {
+        if (c0 < ncell) q.x = count[c0];
+        if (c0 + 1 < ncell) q.y = count[c0 + 1];
+        if (c0 + 2 < ncell) q.z = count[c0 + 2];
+    }
+    const uint32_t local = (q.x + q.y) + (q.z + q.w);
+    uint32_t inc = local;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t v = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += v;
+    }
+    if (lane == 63) wave_tot[wv] = inc;
+    __syncthreads();
+    const uint32_t w0 = wave_tot[0], w1 = wave_tot[1], w2 = wave_tot[2], w3 = wave_tot[3];
+    const uint32_t tile_total = (w0 + w1) + (w2 + w3);
+    const uint32_t wave_excl = wv == 0 ? 0u : (wv == 1 ? w0 : (wv == 2 ? w0 + w1 : (w0 + w1) + w2));
+    if (t == 0) {
+        uint32_t prefix = 0;
+        if (tile == 0) {
+            __hip_atomic_store(&flags[0], kFlagInc | (uint64_t)tile_total, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            __hip_atomic_store(&flags[tile], kFlagAgg | (uint64_t)tile_total, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            int j = tile - 1;
+            uint32_t polls = 0;
+            while (j >= 0) {
+                const uint64_t f = __hip_atomic_load(&flags[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                if (f & kFlagInc) { prefix += (uint32_t)f; break; }
+                if (f & kFlagAgg) { prefix += (uint32_t)f; --j; continue; }
+                if (++polls > (1u << 24)) { set_error(st, DSMC_EHIP); break; }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            __hip_atomic_store(&flags[tile], kFlagInc | (uint64_t)(prefix + tile_total), __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        tile_prefix = prefix;
+    }
+    __syncthreads();
+    uint32_t run = tile_prefix + wave_excl + inc - local;
+    uint4 r;
+    r.x = run; run += q.x;
+    r.y = run; run += q.y;
+    r.z = run; run += q.z;
+    r.w = run; run += q.w;
+    if (c0 + 3 < ncell) {
+        *(uint4 *)(offset + c0) = r;
+        *(uint4 *)(cursor + c0) = r;
+        *(uint4 *)(count + c0) = make_uint4(0, 0, 0, 0);
+    } else {
+        const uint32_t rv[4] = {r.x, r.y, r.z, r.w};
+        for (int k = 0; k < 4; ++k)
+            if (c0 + k < ncell) { offset[c0 + k] = rv[k]; cursor[c0 + k] = rv[k]; count[c0 + k] = 0u; }
+    }
+    if (c0 <= ncell - 1 && ncell - 1 <= c0 + 3) offset[ncell] = run;
+    // last workgroup out: clear the flags, advance the step
+    __syncthreads();
+    if (t == 0) {
+        __threadfence();
+        const uint32_t d = atomicAdd(done, 1u);
+        last = d == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last) {
+        for (int k = t; k < (int)gridDim.x; k += 256)
+            __hip_atomic_store(&flags[k], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (t == 0) {
+            *done = 0u;
+            st->step_cur = st->step_next;
+            st->step_next = st->step_next + 1;
+            st->n_samples = st->n_samples + 1;
+            st->big_count = 0;
+        }
+    }
+}
+
 // Step bookkeeping for homogeneous instances (no sort pass).
 __global__ void k_begin_step(DevState *st) {
     if (threadIdx.x == 0) {
