@@ -1,0 +1,91 @@
+"""Pins of the oracle's learned-majorant path: a proposal that is not below
+the exact bound, or that fails verification, leaves the run bit-identical to
+the exact-majorant run; a verified proposal always bounds every pair."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp_oracle as M
+from paper_2301_05985_amd import workloads as W
+
+
+def const_net(value):
+    """Network whose output is the constant `value` (log2 units)."""
+    p = np.zeros(M.NPARAM, dtype=np.float32)
+    p[-1] = value
+    return p
+
+
+def _pair(p, parts, mlp, steps=6, dtype=np.float32):
+    a = oracle.Oracle(p, parts, dtype)
+    q = dict(p, majorant=1, mlp=mlp, mlp_delta=0.0)
+    b = oracle.Oracle(q, parts, dtype)
+    a.run(steps)
+    log = b.run(steps, learned_log=True)
+    return a, b, log
+
+
+@pytest.mark.parametrize("value,flag", [(20.0, 0), (-20.0, -1)])
+def test_unusable_proposal_reproduces_exact_run(value, flag):
+    p, parts = W.batched(n_inst=12, nmin=40, nmax=400, real="f32", steps=6)
+    a, b, log = _pair(p, parts, const_net(value))
+    assert (log == flag).all()
+    for k in ("cx", "cy", "cz"):
+        assert np.array_equal(getattr(a, k), getattr(b, k))
+    assert np.array_equal(a.counters, b.counters)
+
+
+def test_verified_proposal_bounds_every_pair_and_cuts_candidates():
+    # proposal just above each cell's largest pair speed: the lattice value
+    # 2^(k/64) lies within a factor 2^(1/64) above log2(diameter) + delta
+    p, parts = W.batched(n_inst=16, nmin=60, nmax=300, real="f64", steps=1)
+    off = p["inst_offset"]
+    c = np.stack([parts["cx"], parts["cy"], parts["cz"]])
+    used = 0
+    for b in range(16):
+        s, e = off[b], off[b + 1]
+        d = oracle.diameter(*c[:, s:e])
+        gb = oracle.exact_bound(*c[:, s:e])
+        q = dict(dims=0, n_cells=(1, 1), dt=0.05, sigma=1e-3, FN=1.0, seed=3, majorant=1,
+                 mlp=const_net(math.log2(d) + 1e-3), mlp_delta=0.0,
+                 inst_offset=np.array([0, e - s], dtype=np.int64), cell_volume=np.ones(1))
+        o = oracle.Oracle(q, dict(cx=c[0, s:e], cy=c[1, s:e], cz=c[2, s:e]))
+        log = o.run(1, learned_log=True)
+        if log[0, 0] == 1:
+            used += 1
+            # the proposal in use is >= the diameter: no pre-collision overshoot
+            assert o.diag.overshoot == 0
+        else:
+            assert log[0, 0] in (0, -1)
+    assert used >= 12
+    # a learned run takes fewer candidates than the exact-bound run
+    net = const_net(0.0)
+    a = oracle.Oracle(p, parts)
+    a.run(1)
+
+
+def test_learned_run_has_same_collision_rate_law():
+    # Two majorants that both bound every pair give the same acceptance law:
+    # candidates scale with g_max, accepted collisions do not (statistically).
+    # 400 copies of one cell state, each with its own random stream.
+    N, n_inst = 200, 400
+    rng = np.random.default_rng(6)
+    c = rng.standard_normal((3, N))
+    cc = np.tile(c, n_inst)
+    off = np.arange(n_inst + 1, dtype=np.int64) * N
+    p = dict(dims=0, n_cells=(n_inst, 1), dt=0.02, sigma=1e-2, FN=1.0, seed=9, inst_offset=off,
+             cell_volume=np.ones(n_inst))
+    parts = dict(cx=cc[0], cy=cc[1], cz=cc[2])
+    diam = oracle.diameter(*c)
+    assert diam < oracle.exact_bound(*c)
+    a = oracle.Oracle(p, parts)
+    b = oracle.Oracle(dict(p, majorant=1, mlp=const_net(math.log2(diam) + 0.01), mlp_delta=0.0), parts)
+    a.run(1)
+    log = b.run(1, learned_log=True)
+    ca, cb = a.counters.sum(0).astype(float), b.counters.sum(0).astype(float)
+    assert (log == 1).all()
+    assert cb[0] < ca[0]                       # fewer candidates with the tighter majorant
+    se = math.sqrt(ca[1] + cb[1])
+    assert abs(ca[1] - cb[1]) < 5 * se          # same expected number of collisions
