@@ -58,7 +58,13 @@ typedef enum {
 
 enum { DSMC_WALL_DIFFUSE = 0, DSMC_WALL_SPECULAR = 1, DSMC_WALL_PERIODIC = 2 };
 enum { DSMC_HARD_SPHERE = 0, DSMC_MAXWELL = 1 };
-enum { DSMC_MAJORANT_EXACT = 0, DSMC_MAJORANT_LEARNED = 1 };
+/* Majorant of the relative speed used by the NTC scheme in each cell:
+ *   EXACT    (r_(1) + r_(2)) (1 + eps): radii about the velocity bounding-box
+ *            midpoint; a bound on every pair, O(N) per cell;
+ *   LEARNED  network proposal, used where proven to bound every pair,
+ *            otherwise EXACT;
+ *   DIAMETER the largest pair speed itself (1 + eps), O(N^2) per cell. */
+enum { DSMC_MAJORANT_EXACT = 0, DSMC_MAJORANT_LEARNED = 1, DSMC_MAJORANT_DIAMETER = 2 };
 
 /* Run configuration.  Cells: dims == 1 divides [0, length[0]] into n_cells[0]
  * equal cells; dims == 2 divides [0, length[0]] x [0, length[1]] into
@@ -71,7 +77,7 @@ typedef struct {
     int32_t real_bytes;       /* 4: FP32 positions/velocities/weights, 8: FP64 */
     int32_t molecule;         /* DSMC_HARD_SPHERE or DSMC_MAXWELL (sigma * g = const) */
     int32_t n_cells[2];       /* (nx, ny); dims 1: ny ignored; dims 0: (n_instances, 1) */
-    int32_t majorant;         /* DSMC_MAJORANT_EXACT or DSMC_MAJORANT_LEARNED */
+    int32_t majorant;         /* DSMC_MAJORANT_EXACT, _LEARNED or _DIAMETER */
     int32_t vr;               /* 1: importance-weight variance reduction */
     double length[2];         /* domain extents (dims >= 1) */
     double dt;                /* time step */
@@ -197,12 +203,14 @@ const char *dsmc_status_string(dsmc_status status);
  * ------------------------------------------------------------------ */
 
 /* For every cell (dims 0: instance) of the current state, write the six
- * FP32 input features of the learned majorant (device [n_cells][6]) and
- * the label log2 of the exact largest pairwise relative speed (device
- * [n_cells] float; -inf marks cells with fewer than two particles).
+ * FP32 input features of the learned majorant (device [n_cells][6]), the
+ * label log2 of the exact largest pairwise relative speed (device [n_cells]
+ * float; -inf marks cells with fewer than two particles) and, if bounds_dev
+ * is not NULL, log2 of the EXACT-mode bound (device [n_cells] float).
  * Features: log2(number density), u_x/sqrt(T), u_y/sqrt(T), log2(T),
- * P_xx/p - 1, P_xy/p, from FP64 moments of the cell.  Asynchronous. */
-dsmc_status dsmc_collect_features(dsmc_ctx *ctx, float *features_dev, float *labels_dev);
+ * P_xx/p - 1, P_xy/p, from FP64 moments of the cell.  Walled runs need one
+ * step first (cells are contiguous only after a sort).  Asynchronous. */
+dsmc_status dsmc_collect_features(dsmc_ctx *ctx, float *features_dev, float *labels_dev, float *bounds_dev);
 
 /* Forward pass of the 6-64-64-1 ReLU network in FP32 (params device
  * [DSMC_MLP_NPARAM] float, layout as in dsmc_set_majorant_model; x device

@@ -565,6 +565,11 @@ static int collide_cell(const orc_cfg *cfg, soa_t *s, const int64_t *list, int64
         if (used == 1) diag->learned_used++;
         else if (used == -1) diag->fallback++;
         else diag->learned_skip++;
+    } else if (cfg->majorant == 2) {
+        /* the true largest pair speed of the cell (brute force), with the same
+         * rounding margin as the bound */
+        double eps = IS_F32 ? 9.5367431640625e-07 : 8.8817841970012523e-16;
+        gmax = FN(orc_diameter)(s->cx, s->cy, s->cz, list, n) * (1.0 + eps);
     } else {
         gmax = FN(orc_exact_bound)(s->cx, s->cy, s->cz, list, n);
     }

@@ -84,7 +84,7 @@ def load():
         "dsmc_restore": [P, P, ctypes.c_size_t],
         "dsmc_profile_step": [P, P, I32, P, P, I32],
         "dsmc_destroy": [P],
-        "dsmc_collect_features": [P, P, P],
+        "dsmc_collect_features": [P, P, P, P],
         "dsmc_mlp_forward": [P, P, I64, P, P],
         "dsmc_mlp_loss_grad": [P, P, P, I64, D, P, P, P, P],
         "dsmc_mlp_adam": [P, P, P, P, I64, I64, D, D, D, D, P],

@@ -53,7 +53,7 @@ dsmc_status validate(const dsmc_config *c) {
     if (c->dims < 0 || c->dims > 2) return DSMC_EINVAL;
     if (c->real_bytes != 4 && c->real_bytes != 8) return DSMC_EINVAL;
     if (c->molecule != DSMC_HARD_SPHERE && c->molecule != DSMC_MAXWELL) return DSMC_EINVAL;
-    if (c->majorant != DSMC_MAJORANT_EXACT && c->majorant != DSMC_MAJORANT_LEARNED) return DSMC_EINVAL;
+    if (c->majorant < DSMC_MAJORANT_EXACT || c->majorant > DSMC_MAJORANT_DIAMETER) return DSMC_EINVAL;
     if (c->n_cells[0] < 1 || (c->dims == 2 && c->n_cells[1] < 1)) return DSMC_EINVAL;
     if (n_cells_of(*c) > (int64_t)1 << 30) return DSMC_EINVAL;
     if (c->n_particles < 0 || c->n_particles > (int64_t)0x7FFFFFFF) return DSMC_EINVAL;
@@ -171,6 +171,7 @@ CollideArgs<R> collide_args(dsmc_ctx *c, int buf) {
     a.FN = c->cfg.FN;
     a.molecule = c->cfg.molecule;
     a.cap = c->cap;
+    a.majorant = c->cfg.majorant;
     a.k0 = (uint32_t)(c->cfg.seed & 0xFFFFFFFFull);
     a.k1 = (uint32_t)(c->cfg.seed >> 32);
     a.sums = c->sums;
@@ -667,6 +668,24 @@ dsmc_status dsmc_profile_step(dsmc_ctx *c, float *ms_host, int32_t max_kernels, 
         names_host[names_len - 1] = 0;
     }
     return device_status(c);
+}
+
+dsmc_status dsmc_collect_features(dsmc_ctx *c, float *features, float *labels, float *bounds) {
+    if (!c || !features || !labels) return DSMC_EINVAL;
+    if (c->sticky != DSMC_OK) return c->sticky;
+    // cells of a walled run are contiguous only once a step has sorted them
+    unsigned long long next = 0;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipMemcpy(&next, &c->st->step_next, 8, hipMemcpyDeviceToHost));
+    if (c->cfg.dims >= 1 && next == 0) return DSMC_EINVAL;
+    if (c->cfg.real_bytes == 4)
+        hipLaunchKernelGGL(k_collect_features<float>, dim3((unsigned)c->ncell), dim3(64), 0, c->stream,
+                           collide_args<float>(c, c->cur), (int)c->ncell, features, labels, bounds);
+    else
+        hipLaunchKernelGGL(k_collect_features<double>, dim3((unsigned)c->ncell), dim3(64), 0, c->stream,
+                           collide_args<double>(c, c->cur), (int)c->ncell, features, labels, bounds);
+    HIP_TRY(hipGetLastError());
+    return DSMC_OK;
 }
 
 dsmc_status dsmc_destroy(dsmc_ctx *c) {

@@ -31,7 +31,7 @@ struct CollideArgs {
     const uint32_t *sched;         // block -> cell, or null for the identity
     const double *volume;          // per-cell volume, or null for Vuni
     double Vuni, dt, sigma, FN;
-    int molecule, cap;
+    int molecule, cap, majorant;
     uint32_t k0, k1;
     double *sums;                  // [ncell][26] running FP64 sums
     unsigned long long *counters;  // [ncell][2] candidates, accepted
@@ -126,6 +126,28 @@ __device__ double exact_bound(const View &v, uint32_t N, double &r_top) {
     r_top = sqrt(a1);
     const double eps = sizeof(R) == 4 ? 0x1.0p-20 : 0x1.0p-50;
     return (sqrt(a1) + sqrt(a2)) * (1.0 + eps);
+}
+
+// The largest pair speed of the cell by brute force (lane r takes rows
+// r, r + 64, ...), times the same rounding margin as the bound.
+template <typename R, typename View>
+__device__ double pair_diameter(const View &v, uint32_t N) {
+    const int lane = lane_id();
+    double best = 0.0;
+    for (uint32_t r = lane; r < N; r += 64) {
+        R x, y, z;
+        v.get(r, x, y, z);
+        for (uint32_t t = r + 1; t < N; ++t) {
+            R x2, y2, z2;
+            v.get(t, x2, y2, z2);
+            const double dx = (double)x - (double)x2, dy = (double)y - (double)y2, dz = (double)z - (double)z2;
+            const double g2 = (dx * dx + dy * dy) + dz * dz;
+            best = g2 > best ? g2 : best;
+        }
+    }
+    best = wave_max_t(best);
+    const double eps = sizeof(R) == 4 ? 0x1.0p-20 : 0x1.0p-50;
+    return sqrt(best) * (1.0 + eps);
 }
 
 // Uniform direction (Marsaglia 1972) from blocks 1, 2, ... of candidate k's
@@ -359,7 +381,8 @@ __device__ void process_cell(const CollideArgs<R> &a, const View &v, uint32_t ce
     if (N >= 2) {
         double rt;
         double gmax = 1.0;
-        if (a.molecule != DSMC_MAXWELL) gmax = exact_bound<R>(v, N, rt);
+        if (a.molecule != DSMC_MAXWELL)
+            gmax = a.majorant == DSMC_MAJORANT_DIAMETER ? pair_diameter<R>(v, N) : exact_bound<R>(v, N, rt);
         const double V = a.volume ? a.volume[cell] : a.Vuni;
         const double Nd = (double)N;
         double Mreal;

@@ -160,4 +160,46 @@ __global__ __launch_bounds__(64) void k_collide_big_learned(CollideArgs<R> a) {
     collide_big_body<R, VR, BYID, true>(a);
 }
 
+// Training data for the learned majorant: per cell, the six input features
+// and log2 of the exact largest pairwise relative speed (brute force over all
+// pairs, in double); -inf for cells with fewer than two particles.
+template <typename R>
+__global__ __launch_bounds__(64) void k_collect_features(CollideArgs<R> a, int ncell, float *feat, float *label,
+                                                         float *bound) {
+    const int lane = lane_id();
+    const uint32_t cell = blockIdx.x;
+    if ((int)cell >= ncell) return;
+    const uint32_t base = a.start[cell];
+    const uint32_t N = a.start[cell + 1] - base;
+    const GlobalView<R> v{a.s.cx + base, a.s.cy + base, a.s.cz + base, nullptr, nullptr, nullptr};
+    if (N < 2) {
+        if (lane < 6) feat[(size_t)cell * 6 + lane] = 0.0f;
+        if (lane == 0) label[cell] = -INFINITY;
+        if (lane == 0 && bound) bound[cell] = -INFINITY;
+        return;
+    }
+    const double V = a.volume ? a.volume[cell] : a.Vuni;
+    const Features F = cell_features<R>(v, N, a.FN, V);
+    double best = 0.0;
+    for (uint32_t r = lane; r < N; r += 64) {
+        R x, y, z;
+        v.get(r, x, y, z);
+        for (uint32_t t = r + 1; t < N; ++t) {
+            R x2, y2, z2;
+            v.get(t, x2, y2, z2);
+            const double dx = (double)x - (double)x2, dy = (double)y - (double)y2, dz = (double)z - (double)z2;
+            const double g2 = (dx * dx + dy * dy) + dz * dz;
+            best = g2 > best ? g2 : best;
+        }
+    }
+    best = wave_max_t(best);
+    if (lane < 6) feat[(size_t)cell * 6 + lane] = F.f[lane == 0 ? 0 : lane == 1 ? 1 : lane == 2 ? 2 : lane == 3 ? 3 : lane == 4 ? 4 : 5];
+    if (lane == 0) label[cell] = (float)log2(sqrt(best));
+    if (bound) {
+        double rt;
+        const double gb = exact_bound<R>(v, N, rt);
+        if (lane == 0) bound[cell] = (float)log2(gb);
+    }
+}
+
 }  // namespace dsmc

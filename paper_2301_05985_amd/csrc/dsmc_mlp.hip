@@ -1,14 +1,200 @@
-// dsmc_mlp.hip -- training-side kernels of the learned majorant (placeholder
-// entry points; filled in by the training kernels).
+// dsmc_mlp.hip -- training kernels of the learned collision majorant.
+//
+// Network 6 -> 64 -> 64 -> 1 with ReLU (parameter order W1[64][6], b1[64],
+// W2[64][64], b2[64], w3[64], b3), FP32 arithmetic, no matrix cores: the
+// network is tiny and a per-sample thread keeps its 64 hidden values in
+// registers while the weights sit in LDS and are read by broadcast.
+//
+// Training objective: mean expectile loss (Newey & Powell 1987)
+//   L = (1/n_valid) sum_s |tau - 1[r_s < 0]| r_s^2,  r = label - y,
+// rows with a non-finite label skipped.  The gradient is computed in two
+// passes: one thread per sample runs forward and backward and stores its
+// activations and deltas; then one thread per parameter sums its gradient
+// over the samples in ascending order (FP64 accumulation), so the result does
+// not depend on scheduling.  Adam (Kingma & Ba 2015) updates in place.
 #include <hip/hip_runtime.h>
+
+#include <cmath>
+
 #include "../../include/dsmc.h"
 
-extern "C" {
-dsmc_status dsmc_collect_features(dsmc_ctx *, float *, float *) { return DSMC_EINVAL; }
-dsmc_status dsmc_mlp_forward(const float *, const float *, int64_t, float *, void *) { return DSMC_EINVAL; }
-int64_t dsmc_mlp_scratch_floats(int64_t) { return 0; }
-dsmc_status dsmc_mlp_loss_grad(const float *, const float *, const float *, int64_t, double, float *, float *,
-                               float *, void *) { return DSMC_EINVAL; }
-dsmc_status dsmc_mlp_adam(float *, const float *, float *, float *, int64_t, int64_t, double, double, double,
-                          double, void *) { return DSMC_EINVAL; }
+namespace {
+
+constexpr int kIn = 6, kH = 64;
+constexpr int kOffW1 = 0, kOffB1 = kH * kIn, kOffW2 = kOffB1 + kH, kOffB2 = kOffW2 + kH * kH,
+              kOffW3 = kOffB2 + kH, kOffB3 = kOffW3 + kH, kNp = kOffB3 + 1;
+static_assert(kNp == DSMC_MLP_NPARAM, "parameter count");
+constexpr int kPerSample = 4 * kH + 4;  // h1, h2, d1, d2, e, valid (+pad)
+
+__device__ __forceinline__ void load_params(const float *P, float *s) {
+    for (int k = threadIdx.x; k < kNp; k += blockDim.x) s[k] = P[k];
+    __syncthreads();
 }
+
+__global__ __launch_bounds__(256) void k_mlp_forward(const float *P, const float *x, int64_t n, float *y) {
+    __shared__ float w[kNp];
+    load_params(P, w);
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    float in[kIn], h1[kH];
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) in[k] = x[s * kIn + k];
+#pragma unroll
+    for (int o = 0; o < kH; ++o) {
+        float a = w[kOffB1 + o];
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) a = fmaf(w[kOffW1 + o * kIn + k], in[k], a);
+        h1[o] = a > 0.0f ? a : 0.0f;
+    }
+    float out = w[kOffB3];
+    for (int o = 0; o < kH; ++o) {
+        float a = w[kOffB2 + o];
+#pragma unroll
+        for (int i = 0; i < kH; ++i) a = fmaf(w[kOffW2 + o * kH + i], h1[i], a);
+        const float h2 = a > 0.0f ? a : 0.0f;
+        out = fmaf(w[kOffW3 + o], h2, out);
+    }
+    y[s] = out;
+}
+
+// Forward + backward of one sample; stores h1, h2, dL/dz1, dL/dz2 (without
+// the 1/n_valid factor), e = dL/dy and the loss term.
+__global__ __launch_bounds__(256) void k_mlp_backward(const float *P, const float *x, const float *label,
+                                                      int64_t n, float tau, float *scr) {
+    __shared__ float w[kNp];
+    load_params(P, w);
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    float *rec = scr + s * kPerSample;
+    const float lab = label[s];
+    if (!isfinite(lab)) {
+        for (int k = 0; k < kPerSample; ++k) rec[k] = 0.0f;
+        return;
+    }
+    float in[kIn], h1[kH];
+    uint64_t z2pos = 0ull;  // bit o set when hidden unit o of layer 2 is active
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) in[k] = x[s * kIn + k];
+#pragma unroll
+    for (int o = 0; o < kH; ++o) {
+        float a = w[kOffB1 + o];
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) a = fmaf(w[kOffW1 + o * kIn + k], in[k], a);
+        h1[o] = a > 0.0f ? a : 0.0f;
+        rec[o] = h1[o];
+    }
+    float out = w[kOffB3];
+    for (int o = 0; o < kH; ++o) {
+        float a = w[kOffB2 + o];
+#pragma unroll
+        for (int i = 0; i < kH; ++i) a = fmaf(w[kOffW2 + o * kH + i], h1[i], a);
+        const float h2 = a > 0.0f ? a : 0.0f;
+        if (a > 0.0f) z2pos |= 1ull << o;
+        rec[kH + o] = h2;
+        out = fmaf(w[kOffW3 + o], h2, out);
+    }
+    const float r = lab - out;
+    const float wgt = r < 0.0f ? 1.0f - tau : tau;
+    const float e = -2.0f * wgt * r;  // dL/dy up to the 1/n_valid factor
+    float d2[kH];
+#pragma unroll
+    for (int o = 0; o < kH; ++o) {
+        d2[o] = ((z2pos >> o) & 1ull) ? e * w[kOffW3 + o] : 0.0f;
+        rec[3 * kH + o] = d2[o];
+    }
+    for (int i = 0; i < kH; ++i) {
+        float a = 0.0f;
+#pragma unroll
+        for (int o = 0; o < kH; ++o) a = fmaf(d2[o], w[kOffW2 + o * kH + i], a);
+        rec[2 * kH + i] = h1[i] > 0.0f ? a : 0.0f;
+    }
+    rec[4 * kH] = e;
+    rec[4 * kH + 1] = 1.0f;
+    rec[4 * kH + 2] = wgt * r * r;
+}
+
+// One thread per parameter (plus two for the loss and the valid count):
+// ascending-order FP64 sums over the samples.
+__global__ __launch_bounds__(256) void k_mlp_reduce(const float *x, int64_t n, const float *scr, float *grad,
+                                                    float *loss) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q > kNp + 1) return;
+    double acc = 0.0, valid = 0.0;
+    for (int64_t s = 0; s < n; ++s) {
+        const float *rec = scr + s * kPerSample;
+        double term;
+        if (q < kOffB1) {
+            const int o = q / kIn, k = q % kIn;
+            term = (double)rec[2 * kH + o] * (double)x[s * kIn + k];
+        } else if (q < kOffW2) {
+            term = rec[2 * kH + (q - kOffB1)];
+        } else if (q < kOffB2) {
+            const int o = (q - kOffW2) / kH, i = (q - kOffW2) % kH;
+            term = (double)rec[3 * kH + o] * (double)rec[i];
+        } else if (q < kOffW3) {
+            term = rec[3 * kH + (q - kOffB2)];
+        } else if (q < kOffB3) {
+            term = (double)rec[4 * kH] * (double)rec[kH + (q - kOffW3)];
+        } else if (q == kOffB3) {
+            term = rec[4 * kH];
+        } else {
+            term = rec[4 * kH + 2];  // loss term (q == kNp) / valid flag (q == kNp + 1)
+            if (q == kNp + 1) term = rec[4 * kH + 1];
+        }
+        acc += term;
+        valid += rec[4 * kH + 1];
+    }
+    const double inv = valid > 0.0 ? 1.0 / valid : 0.0;
+    if (q < kNp) grad[q] = (float)(acc * inv);
+    else if (q == kNp) loss[0] = (float)(acc * inv);
+}
+
+__global__ __launch_bounds__(256) void k_mlp_adam(float *p, const float *g, float *m, float *v, int64_t n,
+                                                  float lr, float b1, float b2, float eps, float c1, float c2) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const float gk = g[k];
+    const float mk = b1 * m[k] + (1.0f - b1) * gk;
+    const float vk = b2 * v[k] + (1.0f - b2) * (gk * gk);
+    m[k] = mk;
+    v[k] = vk;
+    p[k] = p[k] - lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+}
+
+}  // namespace
+
+extern "C" {
+
+dsmc_status dsmc_mlp_forward(const float *params, const float *x, int64_t n, float *y, void *stream) {
+    if (!params || !x || !y || n < 0) return DSMC_EINVAL;
+    if (n == 0) return DSMC_OK;
+    hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       params, x, n, y);
+    return hipGetLastError() == hipSuccess ? DSMC_OK : DSMC_EHIP;
+}
+
+int64_t dsmc_mlp_scratch_floats(int64_t n) { return n < 0 ? 0 : n * kPerSample; }
+
+dsmc_status dsmc_mlp_loss_grad(const float *params, const float *x, const float *label, int64_t n, double tau,
+                               float *grad, float *loss, float *scratch, void *stream) {
+    if (!params || !x || !label || !grad || !loss || !scratch || n <= 0 || !(tau > 0.0 && tau < 1.0))
+        return DSMC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_mlp_backward, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, params, x, label, n,
+                       (float)tau, scratch);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((unsigned)((kNp + 2 + 255) / 256)), dim3(256), 0, s, x, n, scratch,
+                       grad, loss);
+    return hipGetLastError() == hipSuccess ? DSMC_OK : DSMC_EHIP;
+}
+
+dsmc_status dsmc_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t n_param, int64_t t,
+                          double lr, double beta1, double beta2, double eps, void *stream) {
+    if (!params || !grad || !m || !v || n_param <= 0 || t < 1) return DSMC_EINVAL;
+    const double c1 = 1.0 - std::pow(beta1, (double)t), c2 = 1.0 - std::pow(beta2, (double)t);
+    hipLaunchKernelGGL(k_mlp_adam, dim3((unsigned)((n_param + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       params, grad, m, v, n_param, (float)lr, (float)beta1, (float)beta2, (float)eps, (float)c1,
+                       (float)c2);
+    return hipGetLastError() == hipSuccess ? DSMC_OK : DSMC_EHIP;
+}
+
+}  // extern "C"

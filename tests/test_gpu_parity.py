@@ -235,3 +235,13 @@ def test_too_many_wall_hits_is_reported(gpu):
     with pytest.raises(DsmcError) as e:
         s.sample()
     assert e.value.code == -5
+
+
+@pytest.mark.parametrize("real", ["f64", "f32"])
+def test_diameter_majorant_bit_exact(gpu, real):
+    # majorant = the largest pair speed of each cell (brute force)
+    _announce("diameter majorant %s" % real)
+    p, parts = _homog([2, 5, 64, 130, 700], dt=0.3)
+    p["majorant"] = 2
+    g, orc = _run(gpu, p, parts, 8, real, chunks=2)
+    _compare(g, orc, exact=True)
