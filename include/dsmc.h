@@ -92,7 +92,8 @@ typedef struct {
     const double *cell_volume;   /* host [n_cells] volumes, or NULL: uniform cell volume
                                     (dims 1: dx * 1 * 1, dims 2: dx * dy * 1, dims 0: 1) */
     const int64_t *inst_offset;  /* host [n_cells[0] + 1], dims == 0 only, ascending */
-    int32_t max_wall_hits;    /* wall interactions allowed per particle per step (0 -> 8) */
+    int32_t max_wall_hits;    /* wall interactions allowed per particle per step (0 -> 64; a
+                                 particle in a corner may bounce between two walls many times) */
     int32_t reserved;
 } dsmc_config;
 

@@ -158,7 +158,7 @@ def make_cfg(p):
     c.vr = int(p.get("vr", 0))
     c.majorant = int(p.get("majorant", 0))
     c.n_inst = p["n_cells"][0] if p["dims"] == 0 else 0
-    c.max_wall_hits = p.get("max_wall_hits", 8)
+    c.max_wall_hits = p.get("max_wall_hits", 64)
     c.Lx, c.Ly = p.get("length", (1.0, 1.0))
     c.dt, c.sigma, c.FN = p["dt"], p["sigma"], p["FN"]
     c.vr_T0 = p.get("vr_T0", 1.0)

@@ -126,7 +126,7 @@ def make_config(p, n_particles):
             c.wall_u[k][d] = p.get("wall_u", ((0.0, 0.0, 0.0),) * 4)[k][d]
     c.seed = int(p.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF
     c.n_particles = n_particles
-    c.max_wall_hits = p.get("max_wall_hits", 8)
+    c.max_wall_hits = p.get("max_wall_hits", 64)
     return c
 
 

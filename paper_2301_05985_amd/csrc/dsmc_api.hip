@@ -337,7 +337,7 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
     dsmc_ctx *c = new (std::nothrow) dsmc_ctx();
     if (!c) return DSMC_EINVAL;
     c->cfg = *cfg;
-    if (c->cfg.max_wall_hits == 0) c->cfg.max_wall_hits = 8;
+    if (c->cfg.max_wall_hits == 0) c->cfg.max_wall_hits = 64;
     c->cfg.cell_volume = nullptr;
     c->cfg.inst_offset = nullptr;
     c->stream = (hipStream_t)hip_stream;

@@ -30,7 +30,7 @@ def _base(**kw):
     p = dict(dims=0, n_cells=(1, 1), length=(1.0, 1.0), dt=0.05, sigma=1.0, FN=1.0,
              molecule=HARD_SPHERE, vr=0, vr_T0=1.0, vr_n0=0.0, wall_kind=(0, 0, 0, 0),
              wall_T=(1.0, 1.0, 1.0, 1.0), wall_u=((0.0, 0.0, 0.0),) * 4, seed=0,
-             majorant=0, real="f64", max_wall_hits=8)
+             majorant=0, real="f64", max_wall_hits=64)
     p.update(kw)
     return p
 
