@@ -202,22 +202,22 @@ struct Launcher {
     }
 };
 
-template <typename R, bool VR, bool BYID>
+template <typename R, bool VR, int D>
 void launch_collide(dsmc_ctx *c, Launcher &L, int buf) {
     CollideArgs<R> a = collide_args<R>(c, buf);
     const bool learned = a.mlp != nullptr && c->cfg.molecule == DSMC_HARD_SPHERE;
     L.mark(learned ? "collide_learned" : "collide");
     if (learned)
-        hipLaunchKernelGGL((k_collide_learned<R, VR, BYID>), dim3((unsigned)c->ncell), dim3(64), c->lds,
+        hipLaunchKernelGGL((k_collide_learned<R, VR, D>), dim3((unsigned)c->ncell), dim3(64), c->lds,
                            L.s, a);
     else
-        hipLaunchKernelGGL((k_collide<R, VR, BYID>), dim3((unsigned)c->ncell), dim3(64), c->lds, L.s, a);
+        hipLaunchKernelGGL((k_collide<R, VR, D>), dim3((unsigned)c->ncell), dim3(64), c->lds, L.s, a);
     if (c->any_big_possible) {
         L.mark("collide_big");
         if (learned)
-            hipLaunchKernelGGL((k_collide_big_learned<R, VR, BYID>), dim3(c->big_grid), dim3(64), 0, L.s, a);
+            hipLaunchKernelGGL((k_collide_big_learned<R, VR, D>), dim3(c->big_grid), dim3(64), 0, L.s, a);
         else
-            hipLaunchKernelGGL((k_collide_big<R, VR, BYID>), dim3(c->big_grid), dim3(64), 0, L.s, a);
+            hipLaunchKernelGGL((k_collide_big<R, VR, D>), dim3(c->big_grid), dim3(64), 0, L.s, a);
     }
 }
 
@@ -246,12 +246,16 @@ void enqueue_step_t(dsmc_ctx *c, Launcher &L, int src) {
     if (c->cfg.dims == 0) {
         L.mark("begin_step");
         hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(64), 0, L.s, c->st);
-        launch_collide<R, VR, false>(c, L, src);
+        launch_collide<R, VR, 0>(c, L, src);
         return;
     }
-    if (c->cfg.dims == 1) launch_sort<R, 1, VR>(c, L, src);
-    else launch_sort<R, 2, VR>(c, L, src);
-    launch_collide<R, VR, true>(c, L, src ^ 1);
+    if (c->cfg.dims == 1) {
+        launch_sort<R, 1, VR>(c, L, src);
+        launch_collide<R, VR, 1>(c, L, src ^ 1);
+    } else {
+        launch_sort<R, 2, VR>(c, L, src);
+        launch_collide<R, VR, 2>(c, L, src ^ 1);
+    }
 }
 
 // Enqueue one step reading buffer `src`; returns the buffer holding the result.

@@ -103,8 +103,11 @@ __device__ double exact_bound(const View &v, uint32_t N, double &r_top) {
         lo1 = fmin(lo1, b); hi1 = fmax(hi1, b);
         lo2 = fmin(lo2, c); hi2 = fmax(hi2, c);
     }
-    lo0 = wave_min_t(lo0); lo1 = wave_min_t(lo1); lo2 = wave_min_t(lo2);
-    hi0 = wave_max_t(hi0); hi1 = wave_max_t(hi1); hi2 = wave_max_t(hi2);
+    const auto mn = [](R a, R b) { return fmin(a, b); };
+    const auto mx = [](R a, R b) { return fmax(a, b); };
+    const R inf = (R)INFINITY;
+    lo0 = wave_reduce_dpp(lo0, inf, mn); lo1 = wave_reduce_dpp(lo1, inf, mn); lo2 = wave_reduce_dpp(lo2, inf, mn);
+    hi0 = wave_reduce_dpp(hi0, -inf, mx); hi1 = wave_reduce_dpp(hi1, -inf, mx); hi2 = wave_reduce_dpp(hi2, -inf, mx);
     const double m0 = 0.5 * ((double)hi0 + (double)lo0), m1 = 0.5 * ((double)hi1 + (double)lo1),
                  m2 = 0.5 * ((double)hi2 + (double)lo2);
     double a1 = 0.0, a2 = 0.0;  // largest, second largest r^2 of this lane
@@ -116,13 +119,19 @@ __device__ double exact_bound(const View &v, uint32_t N, double &r_top) {
         if (r2 > a1) { a2 = a1; a1 = r2; }
         else if (r2 > a2) { a2 = r2; }
     }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const double o1 = __shfl_xor(a1, off, 64), o2 = __shfl_xor(a2, off, 64);
-        const double n1 = fmax(a1, o1);
-        const double n2 = fmax(fmin(a1, o1), fmax(a2, o2));
-        a1 = n1; a2 = n2;
+    // top two over the wave with DPP moves of both values (identity 0, 0)
+#define DSMC_TOP2_STEP(ctrl)                                                \
+    {                                                                       \
+        const double o1 = dpp_f64(0.0, a1, ctrl), o2 = dpp_f64(0.0, a2, ctrl); \
+        const double n1 = fmax(a1, o1);                                     \
+        const double n2 = fmax(fmin(a1, o1), fmax(a2, o2));                 \
+        a1 = n1; a2 = n2;                                                   \
     }
+    DSMC_TOP2_STEP(0x111) DSMC_TOP2_STEP(0x112) DSMC_TOP2_STEP(0x114) DSMC_TOP2_STEP(0x118)
+    DSMC_TOP2_STEP(0x142) DSMC_TOP2_STEP(0x143)
+#undef DSMC_TOP2_STEP
+    a1 = read_lane63(a1);
+    a2 = read_lane63(a2);
     r_top = sqrt(a1);
     const double eps = sizeof(R) == 4 ? 0x1.0p-20 : 0x1.0p-50;
     return (sqrt(a1) + sqrt(a2)) * (1.0 + eps);

@@ -46,11 +46,59 @@ __device__ __forceinline__ void rank_pass(const CollideArgs<R> &a, uint32_t base
     }
 }
 
+// Cells of at most 256 particles: J slots per lane, ids and velocities loaded
+// in one round trip, ids shared through LDS, then ranked and placed.
+template <typename R, bool VR, int J>
+__device__ __forceinline__ void rank_single(const CollideArgs<R> &a, uint32_t base, uint32_t N, uint32_t n4,
+                                            uint32_t *ids, const uint4 *ids4, R *vx, R *vy, R *vz, R *w,
+                                            uint16_t *rank_of_slot) {
+    const uint32_t lane = (uint32_t)lane_id();
+    uint32_t me[J], rk[J];
+    R x[J], y[J], z[J], ww[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const uint32_t s = (uint32_t)j * 64 + lane;
+        me[j] = 0u;
+        rk[j] = 0u;
+        if (s < N) {
+            me[j] = a.s.id[base + s];
+            x[j] = a.s.cx[base + s]; y[j] = a.s.cy[base + s]; z[j] = a.s.cz[base + s];
+            if (VR) ww[j] = a.s.w[base + s];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const uint32_t s = (uint32_t)j * 64 + lane;
+        if (s < N) ids[s] = me[j];
+    }
+    if (lane < 4) ids[N + lane] = 0xFFFFFFFFu;  // padding never ranks below a real id
+    __syncthreads();
+    for (uint32_t t4 = 0; t4 < n4; ++t4) {
+        const uint4 q = ids4[t4];
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+            rk[j] += (uint32_t)(q.x < me[j]) + (uint32_t)(q.y < me[j]) + (uint32_t)(q.z < me[j]) +
+                     (uint32_t)(q.w < me[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const uint32_t s = (uint32_t)j * 64 + lane;
+        if (s < N) {
+            rank_of_slot[s] = (uint16_t)rk[j];
+            vx[rk[j]] = x[j]; vy[rk[j]] = y[j]; vz[rk[j]] = z[j];
+            if (VR) w[rk[j]] = ww[j];
+        }
+    }
+}
+
 // LDS kernel: one wave per cell.  BYID: the cell arrives in arbitrary order
 // from the counting sort and is ranked by particle id in LDS (canonical
 // order); otherwise (homogeneous instances) storage order is canonical.
-template <typename R, bool VR, bool BYID, bool LEARNED>
+// D is the run's dimension (0 for homogeneous instances); walled runs rank
+// by particle id.
+template <typename R, bool VR, int D, bool LEARNED>
 __device__ __forceinline__ void collide_lds_body(const CollideArgs<R> &a, unsigned char *smem) {
+    constexpr bool BYID = D > 0;
     const int lane = lane_id();
     const uint32_t cell = a.sched ? a.sched[blockIdx.x] : blockIdx.x;
     const uint32_t base = a.start[cell];
@@ -74,17 +122,26 @@ __device__ __forceinline__ void collide_lds_body(const CollideArgs<R> &a, unsign
         // the whole cell with 16-byte broadcast reads; up to four slots per
         // lane per pass (cells of up to 256 particles take one pass)
         uint32_t *ids = owner;  // the owner array is free until the ranks are known
-        for (uint32_t s = lane; s < N; s += 64) ids[s] = a.s.id[base + s];
-        if (lane < 4) ids[N + lane] = 0xFFFFFFFFu;  // padding never ranks below a real id
-        __syncthreads();
         const uint4 *ids4 = (const uint4 *)ids;
         const uint32_t n4 = (N + 3) / 4;
-        for (uint32_t s0 = 0; s0 < N; s0 += 256) {
-            const uint32_t left = N - s0;
-            if (left > 192) rank_pass<R, VR, 4>(a, base, s0, N, n4, ids, ids4, vx, vy, vz, w, rank_of_slot);
-            else if (left > 128) rank_pass<R, VR, 3>(a, base, s0, N, n4, ids, ids4, vx, vy, vz, w, rank_of_slot);
-            else if (left > 64) rank_pass<R, VR, 2>(a, base, s0, N, n4, ids, ids4, vx, vy, vz, w, rank_of_slot);
-            else rank_pass<R, VR, 1>(a, base, s0, N, n4, ids, ids4, vx, vy, vz, w, rank_of_slot);
+        if (N <= 256) {
+            // one pass: ids and velocities are fetched together before the
+            // ids are shared through LDS
+            if (N > 192) rank_single<R, VR, 4>(a, base, N, n4, ids, ids4, vx, vy, vz, w, rank_of_slot);
+            else if (N > 128) rank_single<R, VR, 3>(a, base, N, n4, ids, ids4, vx, vy, vz, w, rank_of_slot);
+            else if (N > 64) rank_single<R, VR, 2>(a, base, N, n4, ids, ids4, vx, vy, vz, w, rank_of_slot);
+            else rank_single<R, VR, 1>(a, base, N, n4, ids, ids4, vx, vy, vz, w, rank_of_slot);
+        } else {
+            for (uint32_t s = lane; s < N; s += 64) ids[s] = a.s.id[base + s];
+            if (lane < 4) ids[N + lane] = 0xFFFFFFFFu;  // padding never ranks below a real id
+            __syncthreads();
+            for (uint32_t s0 = 0; s0 < N; s0 += 256) {
+                const uint32_t left = N - s0;
+                if (left > 192) rank_pass<R, VR, 4>(a, base, s0, N, n4, ids, ids4, vx, vy, vz, w, rank_of_slot);
+                else if (left > 128) rank_pass<R, VR, 3>(a, base, s0, N, n4, ids, ids4, vx, vy, vz, w, rank_of_slot);
+                else if (left > 64) rank_pass<R, VR, 2>(a, base, s0, N, n4, ids, ids4, vx, vy, vz, w, rank_of_slot);
+                else rank_pass<R, VR, 1>(a, base, s0, N, n4, ids, ids4, vx, vy, vz, w, rank_of_slot);
+            }
         }
         __syncthreads();
     } else {
@@ -108,8 +165,9 @@ __device__ __forceinline__ void collide_lds_body(const CollideArgs<R> &a, unsign
 
 // Global-memory kernel for cells larger than the LDS capacity: works in
 // place through a rank -> slot permutation and a global owner array.
-template <typename R, bool VR, bool BYID, bool LEARNED>
+template <typename R, bool VR, int D, bool LEARNED>
 __device__ __forceinline__ void collide_big_body(const CollideArgs<R> &a) {
+    constexpr bool BYID = D > 0;
     const int lane = lane_id();
     const uint32_t step = (uint32_t)a.st->step_cur;
     const uint32_t nbig = a.st->big_count;
@@ -138,26 +196,26 @@ __device__ __forceinline__ void collide_big_body(const CollideArgs<R> &a) {
     }
 }
 
-template <typename R, bool VR, bool BYID>
+template <typename R, bool VR, int D>
 __global__ __launch_bounds__(64) void k_collide(CollideArgs<R> a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    collide_lds_body<R, VR, BYID, false>(a, smem);
+    collide_lds_body<R, VR, D, false>(a, smem);
 }
 
-template <typename R, bool VR, bool BYID>
+template <typename R, bool VR, int D>
 __global__ __launch_bounds__(64) void k_collide_big(CollideArgs<R> a) {
-    collide_big_body<R, VR, BYID, false>(a);
+    collide_big_body<R, VR, D, false>(a);
 }
 
-template <typename R, bool VR, bool BYID>
+template <typename R, bool VR, int D>
 __global__ __launch_bounds__(64) void k_collide_learned(CollideArgs<R> a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    collide_lds_body<R, VR, BYID, true>(a, smem);
+    collide_lds_body<R, VR, D, true>(a, smem);
 }
 
-template <typename R, bool VR, bool BYID>
+template <typename R, bool VR, int D>
 __global__ __launch_bounds__(64) void k_collide_big_learned(CollideArgs<R> a) {
-    collide_big_body<R, VR, BYID, true>(a);
+    collide_big_body<R, VR, D, true>(a);
 }
 
 // Training data for the learned majorant: per cell, the six input features

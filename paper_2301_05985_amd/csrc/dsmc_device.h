@@ -161,6 +161,54 @@ __device__ __forceinline__ double wave_sum_many(double (&v)[K]) {
     return r;
 }
 
+// DPP wave reductions (GFX9 data-parallel moves): row shifts by 1, 2, 4, 8
+// combine each row of 16 lanes into its lane 15, then the row broadcasts 15
+// and 31 carry rows into lane 63, whose value is read as a scalar.  These
+// are VALU moves, not LDS-crossbar permutes.  `id` is the identity of the
+// operation (lanes without a source keep it).
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t old, uint32_t v, int ctrl, int row_mask) {
+    switch (ctrl) {  // the DPP control must be a compile-time constant
+        case 0x111: return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, 0x111, 0xF, 0xF, false);
+        case 0x112: return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, 0x112, 0xF, 0xF, false);
+        case 0x114: return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, 0x114, 0xF, 0xF, false);
+        case 0x118: return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, 0x118, 0xF, 0xF, false);
+        case 0x142: return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, 0x142, 0xA, 0xF, false);
+        default:    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, 0x143, 0xC, 0xF, false);
+    }
+}
+__device__ __forceinline__ float dpp_f32(float old, float v, int ctrl) {
+    return __uint_as_float(dpp_u32(__float_as_uint(old), __float_as_uint(v), ctrl, 0));
+}
+__device__ __forceinline__ double dpp_f64(double old, double v, int ctrl) {
+    const uint64_t o = (uint64_t)__double_as_longlong(old), x = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = dpp_u32((uint32_t)o, (uint32_t)x, ctrl, 0);
+    const uint32_t hi = dpp_u32((uint32_t)(o >> 32), (uint32_t)(x >> 32), ctrl, 0);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ float dpp_any(float old, float v, int ctrl) { return dpp_f32(old, v, ctrl); }
+__device__ __forceinline__ double dpp_any(double old, double v, int ctrl) { return dpp_f64(old, v, ctrl); }
+
+__device__ __forceinline__ float read_lane63(float v) {
+    return __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)__float_as_uint(v), 63));
+}
+__device__ __forceinline__ double read_lane63(double v) {
+    const uint64_t x = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), 63);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+template <typename T, typename Op>
+__device__ __forceinline__ T wave_reduce_dpp(T v, T id, Op op) {
+    v = op(v, dpp_any(id, v, 0x111));
+    v = op(v, dpp_any(id, v, 0x112));
+    v = op(v, dpp_any(id, v, 0x114));
+    v = op(v, dpp_any(id, v, 0x118));
+    v = op(v, dpp_any(id, v, 0x142));
+    v = op(v, dpp_any(id, v, 0x143));
+    return read_lane63(v);
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_min_t(T v) {
 #pragma unroll
