@@ -181,8 +181,15 @@ def main():
         p2, parts2 = W.fourier(real="f32")
         sec.append(run_workload("fourier 200 cells x 200 (40,000), Kn=0.1, VR, FP32", p2, parts2, 2000, 100, torch))
         p3, parts3 = W.batched(real="f32")
-        sec.append(run_workload("batched 4096 cells, N uniform in [50,2000], exact majorant, FP32", p3, parts3,
-                                200, 20, torch))
+        # launch parameters of the collision step picked by the autotuner
+        # (grid vs persistent work queue; identical results either way)
+        from paper_2301_05985_amd import autotune
+        tlog = lambda s: print("[bench] " + s, file=sys.stderr, flush=True)
+        best3, times3 = autotune.tune(p3, parts3, steps=20, warmup=8, log=tlog)
+        r3 = run_workload("batched 4096 cells, N uniform in [50,2000], exact majorant, FP32",
+                          dict(p3, **best3), parts3, 200, 20, torch)
+        r3["launch"], r3["launch_candidates_ms_per_step"] = best3, times3
+        sec.append(r3)
         p3d = dict(p3, majorant=2)
         sec.append(run_workload("batched 4096 cells, largest-pair-speed majorant (O(N^2)), FP32", p3d, parts3,
                                 20, 2, torch))
@@ -191,7 +198,9 @@ def main():
         t0 = time.perf_counter()
         model = learned.train_model(log=lambda s: print("[bench] " + s, file=sys.stderr, flush=True))
         t_train = time.perf_counter() - t0
-        sim5 = learned.simulation_with_model(dict(p3, majorant=1), parts3, model)
+        p5 = dict(p3, majorant=1)
+        best5, times5 = autotune.tune(p5, parts3, steps=20, warmup=8, model=(model["bits"], model["delta"]), log=tlog)
+        sim5 = learned.simulation_with_model(dict(p5, **best5), parts3, model)
         ms5, wall5, cand5, acc5 = _timed_steps(sim5, torch, 200, 20)
         d5 = sim5.diagnostics()
         sim5.close()
@@ -204,6 +213,7 @@ def main():
                     "acceptance": acc5 / max(cand5, 1), "learned_used_frac": d5["learned_used"] / cells,
                     "fallback_frac": d5["fallback"] / cells, "skip_frac": d5["learned_skip"] / cells,
                     "delta": model["delta"], "train_samples": model["n_train"],
+                    "launch": best5, "launch_candidates_ms_per_step": times5,
                     "train_loss": model["loss_history"], "train_seconds": t_train})
         p1, parts1 = W.relaxation()
         sec.append(run_workload("relaxation 10,000 particles one cell FP64", p1, parts1, 200, 0, torch))

@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define DSMC_ABI_VERSION 1
+#define DSMC_ABI_VERSION 2
 #define DSMC_NSUM 26          /* FP64 running sums per cell (see dsmc_sample) */
 #define DSMC_MLP_NPARAM 4673  /* learned-majorant network 6-64-64-1 */
 
@@ -94,8 +94,21 @@ typedef struct {
     const int64_t *inst_offset;  /* host [n_cells[0] + 1], dims == 0 only, ascending */
     int32_t max_wall_hits;    /* wall interactions allowed per particle per step (0 -> 64; a
                                  particle in a corner may bounce between two walls many times) */
+    int32_t schedule;         /* homogeneous instances: DSMC_SCHEDULE_GRID or _PERSISTENT */
+    int32_t persistent_waves; /* waves of the persistent kernel (0 -> 8 per compute unit) */
     int32_t reserved;
+    int64_t chunk_work;       /* persistent kernel: consecutive small instances are handed out
+                                 together until their summed N^2 reaches this (0 -> one each) */
 } dsmc_config;
+
+/* How homogeneous instances are distributed over the GPU.  Both process the
+ * instances longest first (decreasing N, i.e. decreasing N^2 work) and give
+ * identical results; only the speed differs.
+ *   GRID        one workgroup (one wave) per instance, the hardware dispatcher
+ *               handing out instances in that order as slots free up;
+ *   PERSISTENT  a fixed grid of waves taking work units (one large instance,
+ *               or a run of small ones) from a device queue. */
+enum { DSMC_SCHEDULE_GRID = 0, DSMC_SCHEDULE_PERSISTENT = 1 };
 
 /* Structure-of-arrays particle state (device pointers).  Element type is
  * float (real_bytes 4) or double (real_bytes 8).  y is used only when

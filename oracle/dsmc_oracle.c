@@ -318,10 +318,13 @@ typedef struct {
 } soa_t;
 
 /* Move one particle for one time step with exact times of flight to the
- * walls it moves toward (Bird 1994, free molecular motion).  A hit snaps the
- * particle onto the wall, applies the wall's condition and continues with
- * the remaining time.  On a corner tie the x wall is taken first.  More than
- * max_wall_hits hits in one step is an error. */
+ * walls it moves toward (Bird 1994, free molecular motion).  The free end
+ * point x + c tau is computed first; if it lies in the closed box the particle
+ * moves there without meeting a wall.  Otherwise the times of flight decide
+ * which wall is met first; a hit snaps the particle onto the wall, applies
+ * the wall's condition and continues with the remaining time.  On a corner
+ * tie the x wall is taken first.  More than max_wall_hits hits in one step is
+ * an error. */
 static int stream_one(const orc_cfg *cfg, soa_t *s, int64_t p, uint32_t step, orc_diag *diag)
 {
     const REAL Lx = (REAL)cfg->Lx, Ly = (REAL)cfg->Ly;
@@ -331,6 +334,13 @@ static int stream_one(const orc_cfg *cfg, soa_t *s, int64_t p, uint32_t step, or
     uint32_t hits = 0;
     int rc = 0;
     for (;;) {
+        REAL xe = x + c[0] * tau;
+        REAL ye = (cfg->dims == 2) ? y + c[1] * tau : (REAL)0;
+        if (xe >= (REAL)0 && xe <= Lx && (cfg->dims < 2 || (ye >= (REAL)0 && ye <= Ly))) {
+            x = xe;
+            if (cfg->dims == 2) y = ye;
+            break;
+        }
         REAL tx = (REAL)INFINITY, ty = (REAL)INFINITY;
         if (c[0] > (REAL)0) tx = (Lx - x) / c[0];
         else if (c[0] < (REAL)0) tx = ((REAL)0 - x) / c[0];

@@ -1,0 +1,118 @@
+"""Launch-parameter autotuner for batched homogeneous instances.
+
+The collision step of many independent homogeneous cells can run as one
+workgroup per instance (``schedule=0``, grid launch in longest-first order)
+or as a persistent grid of ``persistent_waves`` single-wave workgroups that
+take work units from a device queue (``schedule=1``); a unit groups
+consecutive small instances of the longest-first order until their summed
+N^2 reaches ``chunk_work``.  The choice changes only the order in which
+instances are processed, never their arithmetic (every draw is keyed by
+instance, step and candidate), so all candidates give identical results and
+the tuner may pick purely on time.
+
+The tuner times each candidate on a scratch simulation built from a copy of
+the caller's initial state and caches the winner in a JSON file keyed by the
+GPU architecture and a signature of the workload (kind, precision, weights,
+majorant, and the instance-size histogram).
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+
+GRID = {"schedule": 0}
+CANDIDATES = [GRID] + [
+    {"schedule": 1, "persistent_waves": w, "chunk_work": c}
+    for w in (1024, 2048, 4096, 8192) for c in (0, 65536, 262144)
+]
+LAUNCH_KEYS = ("schedule", "persistent_waves", "chunk_work")
+
+
+def cache_path():
+    base = os.environ.get("DSMC_AUTOTUNE_CACHE")
+    if base:
+        return base
+    return os.path.join(os.path.expanduser("~"), ".cache", "dsmc_hip", "autotune.json")
+
+
+def signature(params):
+    """Key of a workload: everything that changes the collision kernel's cost."""
+    off = np.asarray(params["inst_offset"], dtype=np.int64)
+    n = np.diff(off)
+    hist = np.bincount(np.minimum(n // 64, 255), minlength=256)
+    h = hashlib.sha1(hist.astype(np.int64).tobytes()).hexdigest()[:16]
+    return "d%d_%s_vr%d_m%d_mol%d_k%d_n%d_%s" % (
+        params.get("dims", 0), params.get("real", "f64"), params.get("vr", 0),
+        params.get("majorant", 0), params.get("molecule", 0), len(n), int(off[-1]), h)
+
+
+def _arch():
+    import torch
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def _load_cache(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store_cache(path, table):
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def time_candidate(params, particles, cand, steps=8, warmup=8, model=None):
+    """Milliseconds per step of one launch candidate on a scratch simulation."""
+    import torch
+    from .binding import Simulation
+    sim = Simulation(dict(params, **cand), particles)
+    try:
+        if model is not None:
+            sim.set_majorant_model(*model)
+        sim.step(warmup)
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        sim.step(steps)
+        t1.record()
+        t1.synchronize()
+        return t0.elapsed_time(t1) / steps
+    finally:
+        sim.close()
+
+
+def tune(params, particles, candidates=None, steps=8, warmup=8, model=None, use_cache=True, log=None):
+    """Return (best launch parameters, {candidate label: ms per step}).
+
+    Walled workloads have a single schedule and return it untimed.
+    ``model`` is ``(bf16_weights, delta)`` for learned-majorant runs."""
+    if params.get("dims", 0) != 0:
+        return dict(GRID), {}
+    key = "%s/%s" % (_arch(), signature(params))
+    path = cache_path()
+    if use_cache:
+        hit = _load_cache(path).get(key)
+        if hit is not None:
+            return {k: hit["best"][k] for k in hit["best"] if k in LAUNCH_KEYS}, hit.get("times", {})
+    times = {}
+    best, best_t = None, float("inf")
+    for cand in candidates or CANDIDATES:
+        label = json.dumps(cand, sort_keys=True)
+        t = time_candidate(params, particles, cand, steps, warmup, model)
+        times[label] = t
+        if log:
+            log("autotune %s: %.4f ms/step" % (label, t))
+        if t < best_t:
+            best, best_t = dict(cand), t
+    if use_cache:
+        table = _load_cache(path)
+        table[key] = {"best": best, "times": times}
+        _store_cache(path, table)
+    return best, times

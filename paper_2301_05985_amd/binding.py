@@ -14,7 +14,7 @@ from . import build as _build
 
 NSUM = 26
 MLP_NPARAM = 4673
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 STATUS = {0: "DSMC_OK", -1: "DSMC_EINVAL", -2: "DSMC_ENOMEM", -3: "DSMC_EHIP",
           -4: "DSMC_ENONFINITE", -5: "DSMC_EWALLHITS", -6: "DSMC_ECAPACITY", -7: "DSMC_EABI"}
@@ -36,7 +36,8 @@ class Config(ctypes.Structure):
         ("wall_u", (ctypes.c_double * 3) * 4), ("seed", ctypes.c_uint64),
         ("n_particles", ctypes.c_int64), ("cell_volume", ctypes.c_void_p),
         ("inst_offset", ctypes.c_void_p), ("max_wall_hits", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("schedule", ctypes.c_int32), ("persistent_waves", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("chunk_work", ctypes.c_int64),
     ]
 
 
@@ -127,6 +128,9 @@ def make_config(p, n_particles):
     c.seed = int(p.get("seed", 0)) & 0xFFFFFFFFFFFFFFFF
     c.n_particles = n_particles
     c.max_wall_hits = p.get("max_wall_hits", 64)
+    c.schedule = int(p.get("schedule", 0))
+    c.persistent_waves = int(p.get("persistent_waves", 0))
+    c.chunk_work = int(p.get("chunk_work", 0))
     return c
 
 

@@ -37,7 +37,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t alt[7];  // x y cx cy cz w id of the second particle buffer
-    size_t count, offset, cursor, sums, counters, volume, state, big_list, perm, owner, sched, flags, done;
+    size_t count, offset, cursor, sums, counters, volume, state, big_list, perm, owner, sched, flags, done, units;
     size_t mlp, lattice;
     size_t total;
 };
@@ -79,6 +79,8 @@ dsmc_status validate(const dsmc_config *c) {
         for (int64_t i = 0; i < n_cells_of(*c); ++i)
             if (!(c->cell_volume[i] > 0)) return DSMC_EINVAL;
     if (c->max_wall_hits < 0) return DSMC_EINVAL;
+    if (c->schedule != DSMC_SCHEDULE_GRID && c->schedule != DSMC_SCHEDULE_PERSISTENT) return DSMC_EINVAL;
+    if (c->persistent_waves < 0 || c->chunk_work < 0) return DSMC_EINVAL;
     return DSMC_OK;
 }
 
@@ -105,6 +107,7 @@ Layout make_layout(const dsmc_config &c) {
     L.perm = take(n * 4);
     L.owner = take(n * 4);
     L.sched = take(nc * 4);
+    L.units = take(nc * 8);
     L.mlp = take(DSMC_MLP_NPARAM * 4);
     L.lattice = take(kLatticeSize * 8);
     L.total = off;
@@ -134,6 +137,9 @@ struct dsmc_ctx {
     bool any_big_possible = false;
     uint64_t *flags = nullptr;
     uint32_t *done = nullptr;
+    uint2 *units = nullptr;
+    uint32_t n_units = 0;
+    int persistent_grid = 0;
     uint32_t *count = nullptr, *offset = nullptr, *cursor = nullptr, *big_list = nullptr,
              *perm = nullptr, *owner = nullptr, *sched = nullptr;
     double *sums = nullptr, *volume = nullptr, *lattice = nullptr;
@@ -207,7 +213,14 @@ void launch_collide(dsmc_ctx *c, Launcher &L, int buf) {
     CollideArgs<R> a = collide_args<R>(c, buf);
     const bool learned = a.mlp != nullptr && c->cfg.molecule == DSMC_HARD_SPHERE;
     L.mark(learned ? "collide_learned" : "collide");
-    if (learned)
+    if (D == 0 && c->cfg.schedule == DSMC_SCHEDULE_PERSISTENT) {
+        if (learned)
+            hipLaunchKernelGGL((k_collide_persistent<R, VR, true>), dim3((unsigned)c->persistent_grid), dim3(64),
+                               c->lds, L.s, a, (const uint2 *)c->units, c->n_units);
+        else
+            hipLaunchKernelGGL((k_collide_persistent<R, VR, false>), dim3((unsigned)c->persistent_grid), dim3(64),
+                               c->lds, L.s, a, (const uint2 *)c->units, c->n_units);
+    } else if (learned)
         hipLaunchKernelGGL((k_collide_learned<R, VR, D>), dim3((unsigned)c->ncell), dim3(64), c->lds,
                            L.s, a);
     else
@@ -370,6 +383,7 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
     c->perm = (uint32_t *)(c->ws + L.perm);
     c->owner = (uint32_t *)(c->ws + L.owner);
     c->sched = (uint32_t *)(c->ws + L.sched);
+    c->units = (uint2 *)(c->ws + L.units);
     c->mlp = (float *)(c->ws + L.mlp);
     c->lattice = (double *)(c->ws + L.lattice);
 
@@ -406,6 +420,7 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
     const int cap_fit = (int)std::min<size_t>((kMaxLds - 64) / per, 65535) / 32 * 32;
     std::vector<uint32_t> start_host;
     std::vector<uint32_t> sched_host;
+    std::vector<uint2> units_host;
     if (cfg->dims == 0) {
         int64_t maxn = 0;
         start_host.resize(c->ncell + 1);
@@ -423,6 +438,26 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
         std::stable_sort(sched_host.begin(), sched_host.end(), [&](uint32_t a, uint32_t b) {
             return (cfg->inst_offset[a + 1] - cfg->inst_offset[a]) > (cfg->inst_offset[b + 1] - cfg->inst_offset[b]);
         });
+        // work units of the persistent kernel: runs of consecutive schedule
+        // entries whose summed N^2 reaches chunk_work (a large instance alone)
+        for (uint32_t k = 0; k < (uint32_t)c->ncell;) {
+            uint32_t cnt = 0;
+            int64_t work = 0;
+            do {
+                const int64_t nb = cfg->inst_offset[sched_host[k + cnt] + 1] - cfg->inst_offset[sched_host[k + cnt]];
+                work += nb * nb;
+                ++cnt;
+            } while (k + cnt < (uint32_t)c->ncell && work < cfg->chunk_work && cnt < 64);
+            units_host.push_back(make_uint2(k, cnt));
+            k += cnt;
+        }
+        c->n_units = (uint32_t)units_host.size();
+        int dev = 0, ncu = 256;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            hipDeviceProp_t prop;
+            if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ncu = prop.multiProcessorCount;
+        }
+        c->persistent_grid = cfg->persistent_waves > 0 ? cfg->persistent_waves : 8 * ncu;
     } else {
         const double mean = (double)c->n / (double)c->ncell;
         int want = (int)std::ceil(3.0 * mean + 64.0);
@@ -457,7 +492,8 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
     }
     if (cfg->dims == 0) {
         if (hipMemcpyAsync(c->offset, start_host.data(), start_host.size() * 4, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-            hipMemcpyAsync(c->sched, sched_host.data(), sched_host.size() * 4, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+            hipMemcpyAsync(c->sched, sched_host.data(), sched_host.size() * 4, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+            hipMemcpyAsync(c->units, units_host.data(), units_host.size() * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess)
             return fail(DSMC_EHIP);
     }
     {

@@ -97,10 +97,9 @@ __device__ __forceinline__ void rank_single(const CollideArgs<R> &a, uint32_t ba
 // D is the run's dimension (0 for homogeneous instances); walled runs rank
 // by particle id.
 template <typename R, bool VR, int D, bool LEARNED>
-__device__ __forceinline__ void collide_lds_body(const CollideArgs<R> &a, unsigned char *smem) {
+__device__ __forceinline__ void collide_lds_body(const CollideArgs<R> &a, unsigned char *smem, uint32_t cell) {
     constexpr bool BYID = D > 0;
     const int lane = lane_id();
-    const uint32_t cell = a.sched ? a.sched[blockIdx.x] : blockIdx.x;
     const uint32_t base = a.start[cell];
     const uint32_t N = a.start[cell + 1] - base;
     if (N > (uint32_t)a.cap) {
@@ -199,7 +198,7 @@ __device__ __forceinline__ void collide_big_body(const CollideArgs<R> &a) {
 template <typename R, bool VR, int D>
 __global__ __launch_bounds__(64) void k_collide(CollideArgs<R> a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    collide_lds_body<R, VR, D, false>(a, smem);
+    collide_lds_body<R, VR, D, false>(a, smem, a.sched ? a.sched[blockIdx.x] : blockIdx.x);
 }
 
 template <typename R, bool VR, int D>
@@ -210,12 +209,33 @@ __global__ __launch_bounds__(64) void k_collide_big(CollideArgs<R> a) {
 template <typename R, bool VR, int D>
 __global__ __launch_bounds__(64) void k_collide_learned(CollideArgs<R> a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    collide_lds_body<R, VR, D, true>(a, smem);
+    collide_lds_body<R, VR, D, true>(a, smem, a.sched ? a.sched[blockIdx.x] : blockIdx.x);
 }
 
 template <typename R, bool VR, int D>
 __global__ __launch_bounds__(64) void k_collide_big_learned(CollideArgs<R> a) {
     collide_big_body<R, VR, D, true>(a);
+}
+
+// Persistent collision kernel for homogeneous instances: a fixed grid of
+// waves takes work units from a device queue (reset by the step bookkeeping
+// kernel).  A unit is a run of consecutive entries of the longest-first
+// schedule: one large instance, or several small ones.  Every wave takes
+// units until the queue is exhausted, so the grid drains each step.
+template <typename R, bool VR, bool LEARNED>
+__global__ __launch_bounds__(64) void k_collide_persistent(CollideArgs<R> a, const uint2 *units, uint32_t n_units) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    for (;;) {
+        uint32_t u = 0;
+        if (lane_id() == 0) u = atomicAdd(&a.st->queue, 1u);
+        u = (uint32_t)__builtin_amdgcn_readfirstlane((int)u);
+        if (u >= n_units) break;
+        const uint2 w = units[u];
+        for (uint32_t k = 0; k < w.y; ++k) {
+            collide_lds_body<R, VR, 0, LEARNED>(a, smem, a.sched[w.x + k]);
+            __syncthreads();
+        }
+    }
 }
 
 // Training data for the learned majorant: per cell, the six input features

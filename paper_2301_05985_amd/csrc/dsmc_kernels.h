@@ -29,7 +29,9 @@ struct DevState {
     unsigned long long n_samples;   // sampled steps since the last reset
     unsigned int error;             // first device error (positive code), 0 = none
     unsigned int big_count;         // cells queued for the global-memory collision kernel
-    unsigned long long pad[4];
+    unsigned int queue;             // next work unit of the persistent collision kernel
+    unsigned int pad0;
+    unsigned long long pad[3];
     unsigned long long diag[kDiagStripes * kDiagPerStripe];
 };
 enum { kDiagOvershoot = 0, kDiagWallHits, kDiagLearned, kDiagFallback, kDiagSkip, kDiagVrNonfinite,
@@ -108,9 +110,11 @@ __device__ __forceinline__ T pick4(const T (&a)[4], int w) {
 }
 
 // ------------------------------------------------------------ free flight
-// Exact times of flight to the walls the particle moves toward; a hit snaps
-// the particle onto the wall, applies the wall condition and continues with
-// the remaining time; on a tie the x wall goes first.  Returns 0 or
+// The free end point x + c tau is tried first: inside the closed box the
+// particle simply moves there (no division).  Otherwise exact times of flight
+// to the walls the particle moves toward decide the wall met first; a hit
+// snaps the particle onto the wall, applies the wall condition and continues
+// with the remaining time; on a tie the x wall goes first.  Returns 0 or
 // DSMC_EWALLHITS.  The particle id is read only when a diffuse wall is hit.
 template <typename R, int D, bool WANT_W>
 __device__ __forceinline__ int fly(const Geo &g, R &x, R &y, R &cx, R &cy, R &cz, R &w,
@@ -122,6 +126,13 @@ __device__ __forceinline__ int fly(const Geo &g, R &x, R &y, R &cx, R &cy, R &cz
     uint32_t pid = 0;
     bool have_pid = false;
     for (;;) {
+        const R xe = x + cx * tau;
+        const R ye = D == 2 ? y + cy * tau : zero;
+        if (xe >= zero && xe <= Lx && (D < 2 || (ye >= zero && ye <= Ly))) {
+            x = xe;
+            if (D == 2) y = ye;
+            return 0;
+        }
         R tx = inf, ty = inf;
         if (cx > zero) tx = (Lx - x) / cx;
         else if (cx < zero) tx = (zero - x) / cx;
@@ -430,6 +441,7 @@ __global__ void k_begin_step(DevState *st) {
         st->step_next = st->step_next + 1;
         st->n_samples = st->n_samples + 1;
         st->big_count = 0;
+        st->queue = 0;
     }
 }
 

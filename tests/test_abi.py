@@ -59,6 +59,7 @@ def test_workspace_size_valid_configs(lib):
 @pytest.mark.parametrize("field,value,code", [
     ("abi_version", 99, -7), ("dims", 3, -1), ("real_bytes", 2, -1), ("dt", 0.0, -1),
     ("FN", -1.0, -1), ("molecule", 5, -1), ("majorant", 7, -1), ("n_particles", -5, -1),
+    ("schedule", 2, -1), ("persistent_waves", -1, -1), ("chunk_work", -3, -1),
 ])
 def test_workspace_size_rejects_invalid(lib, field, value, code):
     p, parts = W.cavity(nx=4, ny=4, per_cell=5)

@@ -1,0 +1,102 @@
+"""Launch schedules of the collision step for batched homogeneous instances:
+the grid launch and the persistent work-queue launch (any number of waves,
+any grouping of small instances into work units) give identical bits, with
+large instances routed through the global-memory kernel in both; the
+persistent launch matches the oracle bit for bit; the autotuner picks one of
+its candidates and caches it."""
+import json
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp_oracle as M
+from paper_2301_05985_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SCHEDULES = [
+    {"schedule": 1, "persistent_waves": 64, "chunk_work": 0},
+    {"schedule": 1, "persistent_waves": 1024, "chunk_work": 65536},
+    {"schedule": 1, "persistent_waves": 2048, "chunk_work": 262144},
+    {"schedule": 1, "persistent_waves": 8192, "chunk_work": 4 * 10 ** 6},
+]
+
+
+def _announce(name):
+    print("[gpu case] %s" % name, flush=True)
+
+
+def _net():
+    net = M.init_params(7) * 0.05
+    net[-1] = 2.9
+    return M.from_bf16(M.to_bf16(net.astype(np.float32)))
+
+
+def _run(p, parts, steps, model=None):
+    from paper_2301_05985_amd.binding import Simulation
+    sim = Simulation(p, parts)
+    if model is not None:
+        sim.set_majorant_model(M.to_bf16(model), 0.02)
+    sim.step(steps)
+    st = sim.particles()
+    sums, cnt, _ = sim.sample()
+    d = sim.diagnostics()
+    sim.close()
+    return st, sums, cnt, d
+
+
+@pytest.mark.parametrize("case", ["f32", "f64_vr", "learned"])
+def test_schedules_bit_identical(gpu, case):
+    # 600 instances, N uniform on [20, 6000]: dozens exceed the LDS capacity
+    # and go to the global-memory kernel; 13 steps (graphs of 8 plus a tail)
+    _announce("schedule invariance %s" % case)
+    real = "f32" if case != "f64_vr" else "f64"
+    p, parts = W.batched(n_inst=600, nmin=20, nmax=6000, real=real, seed=5)
+    model = None
+    if case == "f64_vr":
+        p = dict(p, vr=1)
+        parts = dict(parts, w=np.ones(len(parts["cx"])))
+    if case == "learned":
+        p = dict(p, majorant=1)
+        model = _net()
+    ref = _run(dict(p, schedule=0), parts, 13, model)
+    assert ref[3]["big_cells"] > 0
+    for sch in SCHEDULES:
+        got = _run(dict(p, **sch), parts, 13, model)
+        for k in ("cx", "cy", "cz", "w", "id"):
+            if ref[0][k] is None:
+                assert got[0][k] is None
+                continue
+            assert np.array_equal(got[0][k], ref[0][k], equal_nan=k != "id"), (sch, k)
+        assert np.array_equal(got[2], ref[2]), sch
+        assert np.allclose(got[1], ref[1], rtol=1e-12, atol=0, equal_nan=True), sch
+        for k in ("candidates", "accepted", "big_cells", "learned_used", "fallback"):
+            assert got[3][k] == ref[3][k], (sch, k)
+
+
+def test_persistent_matches_oracle(gpu):
+    _announce("persistent vs oracle")
+    p, parts = W.batched(n_inst=96, nmin=10, nmax=400, real="f32", seed=9)
+    p = dict(p, schedule=1, persistent_waves=40, chunk_work=20000)
+    st, _, cnt, _ = _run(p, parts, 9)
+    orc = oracle.Oracle(p, parts, np.float32)
+    orc.run(9)
+    for k in ("cx", "cy", "cz"):
+        assert np.array_equal(st[k], getattr(orc, k)), k
+    assert np.array_equal(cnt, orc.counters)
+
+
+def test_autotune_picks_and_caches(gpu, tmp_path, monkeypatch):
+    _announce("autotune")
+    from paper_2301_05985_amd import autotune
+    monkeypatch.setenv("DSMC_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    p, parts = W.batched(n_inst=512, nmin=50, nmax=2000, real="f32", seed=2)
+    cands = [autotune.GRID, SCHEDULES[1], SCHEDULES[2]]
+    best, times = autotune.tune(p, parts, candidates=cands, steps=8, warmup=8)
+    assert best in cands and len(times) == 3
+    assert all(t > 0 for t in times.values())
+    table = json.load(open(tmp_path / "tune.json"))
+    assert len(table) == 1
+    again, t2 = autotune.tune(p, parts, candidates=cands)
+    assert again == best and t2 == times
