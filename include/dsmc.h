@@ -97,8 +97,9 @@ typedef struct {
     int32_t schedule;         /* homogeneous instances: DSMC_SCHEDULE_GRID or _PERSISTENT */
     int32_t persistent_waves; /* waves of the persistent kernel (0 -> 8 per compute unit) */
     int32_t reserved;
-    int64_t chunk_work;       /* persistent kernel: consecutive small instances are handed out
-                                 together until their summed N^2 reaches this (0 -> one each) */
+    int64_t chunk_work;       /* persistent kernel: up to 64 consecutive instances of the
+                                 schedule form one work unit while they hold fewer than this
+                                 many particles (0 -> one instance per unit) */
 } dsmc_config;
 
 /* How homogeneous instances are distributed over the GPU.  Both process the
@@ -107,7 +108,9 @@ typedef struct {
  *   GRID        one workgroup (one wave) per instance, the hardware dispatcher
  *               handing out instances in that order as slots free up;
  *   PERSISTENT  a fixed grid of waves taking work units (one large instance,
- *               or a run of small ones) from a device queue. */
+ *               or a run of small ones) from eight device queues, one per XCD,
+ *               a wave moving on to the other queues once its own is empty.
+ * Walled runs (dims 1, 2) ignore the field and launch one wave per cell. */
 enum { DSMC_SCHEDULE_GRID = 0, DSMC_SCHEDULE_PERSISTENT = 1 };
 
 /* Structure-of-arrays particle state (device pointers).  Element type is

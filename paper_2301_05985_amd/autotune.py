@@ -3,9 +3,9 @@
 The collision step of many independent homogeneous cells can run as one
 workgroup per instance (``schedule=0``, grid launch in longest-first order)
 or as a persistent grid of ``persistent_waves`` single-wave workgroups that
-take work units from a device queue (``schedule=1``); a unit groups
-consecutive small instances of the longest-first order until their summed
-N^2 reaches ``chunk_work``.  The choice changes only the order in which
+take work units from per-XCD device queues (``schedule=1``); a unit groups
+consecutive small instances of the longest-first order while they hold
+fewer than ``chunk_work`` particles.  The choice changes only the order in which
 instances are processed, never their arithmetic (every draw is keyed by
 instance, step and candidate), so all candidates give identical results and
 the tuner may pick purely on time.
@@ -24,7 +24,7 @@ import numpy as np
 GRID = {"schedule": 0}
 CANDIDATES = [GRID] + [
     {"schedule": 1, "persistent_waves": w, "chunk_work": c}
-    for w in (1024, 2048, 4096, 8192) for c in (0, 65536, 262144)
+    for w in (1024, 2048, 4096) for c in (0, 256, 1024)
 ]
 LAUNCH_KEYS = ("schedule", "persistent_waves", "chunk_work")
 

@@ -438,14 +438,14 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
         std::stable_sort(sched_host.begin(), sched_host.end(), [&](uint32_t a, uint32_t b) {
             return (cfg->inst_offset[a + 1] - cfg->inst_offset[a]) > (cfg->inst_offset[b + 1] - cfg->inst_offset[b]);
         });
-        // work units of the persistent kernel: runs of consecutive schedule
-        // entries whose summed N^2 reaches chunk_work (a large instance alone)
+        // work units of the persistent kernel: runs of at most 64 consecutive
+        // schedule entries holding fewer than chunk_work particles before the
+        // last one is added (chunk_work 0: one instance per unit)
         for (uint32_t k = 0; k < (uint32_t)c->ncell;) {
             uint32_t cnt = 0;
             int64_t work = 0;
             do {
-                const int64_t nb = cfg->inst_offset[sched_host[k + cnt] + 1] - cfg->inst_offset[sched_host[k + cnt]];
-                work += nb * nb;
+                work += cfg->inst_offset[sched_host[k + cnt] + 1] - cfg->inst_offset[sched_host[k + cnt]];
                 ++cnt;
             } while (k + cnt < (uint32_t)c->ncell && work < cfg->chunk_work && cnt < 64);
             units_host.push_back(make_uint2(k, cnt));

@@ -218,22 +218,53 @@ __global__ __launch_bounds__(64) void k_collide_big_learned(CollideArgs<R> a) {
 }
 
 // Persistent collision kernel for homogeneous instances: a fixed grid of
-// waves takes work units from a device queue (reset by the step bookkeeping
-// kernel).  A unit is a run of consecutive entries of the longest-first
-// schedule: one large instance, or several small ones.  Every wave takes
-// units until the queue is exhausted, so the grid drains each step.
+// waves takes work units from eight device queues (reset by the step
+// bookkeeping kernel).  A unit is a run of consecutive entries of the
+// longest-first schedule: one large instance, or several small ones; unit u
+// belongs to queue u mod 8.  A wave starts on the queue of its XCD and, once
+// that queue is exhausted, moves on to the next ones, so every unit is taken
+// exactly once and the grid drains each step.  The claim of the next unit is
+// issued before the current unit is processed, so its latency overlaps the
+// current unit's loads.
 template <typename R, bool VR, bool LEARNED>
 __global__ __launch_bounds__(64) void k_collide_persistent(CollideArgs<R> a, const uint2 *units, uint32_t n_units) {
     extern __shared__ __align__(16) unsigned char smem[];
-    for (;;) {
-        uint32_t u = 0;
-        if (lane_id() == 0) u = atomicAdd(&a.st->queue, 1u);
-        u = (uint32_t)__builtin_amdgcn_readfirstlane((int)u);
-        if (u >= n_units) break;
+    uint32_t q = blockIdx.x % kQueues;
+    uint32_t left = kQueues;  // queues not yet found exhausted
+    uint32_t u = n_units;
+    // blocking claim: the next unit of queue q, moving on when q is exhausted
+    while (left > 0) {
+        uint32_t k = 0;
+        if (lane_id() == 0) k = atomicAdd(&a.st->queue[q * kQueueStride], 1u);
+        k = (uint32_t)__builtin_amdgcn_readfirstlane((int)k);
+        u = q + k * kQueues;
+        if (u < n_units) break;
+        q = (q + 1) % kQueues;
+        --left;
+        u = n_units;
+    }
+    while (u < n_units) {
         const uint2 w = units[u];
+        uint32_t pending = 0;
+        if (lane_id() == 0) pending = atomicAdd(&a.st->queue[q * kQueueStride], 1u);
         for (uint32_t k = 0; k < w.y; ++k) {
             collide_lds_body<R, VR, 0, LEARNED>(a, smem, a.sched[w.x + k]);
             __syncthreads();
+        }
+        u = q + (uint32_t)__builtin_amdgcn_readfirstlane((int)pending) * kQueues;
+        if (u < n_units) continue;
+        q = (q + 1) % kQueues;
+        --left;
+        u = n_units;
+        while (left > 0) {
+            uint32_t k = 0;
+            if (lane_id() == 0) k = atomicAdd(&a.st->queue[q * kQueueStride], 1u);
+            k = (uint32_t)__builtin_amdgcn_readfirstlane((int)k);
+            u = q + k * kQueues;
+            if (u < n_units) break;
+            q = (q + 1) % kQueues;
+            --left;
+            u = n_units;
         }
     }
 }

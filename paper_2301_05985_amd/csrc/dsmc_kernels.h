@@ -22,6 +22,10 @@ namespace dsmc {
 // address would serialize in a single L2 channel.  The host sums the stripes.
 constexpr int kDiagStripes = 1024;
 constexpr int kDiagPerStripe = 8;
+// One queue per XCD (workgroups are dealt to the eight XCDs round-robin), so
+// that the queue atomics of one step spread over eight addresses.
+constexpr int kQueues = 8;
+constexpr int kQueueStride = 32;
 
 struct DevState {
     unsigned long long step_next;   // index of the next step to stream
@@ -29,10 +33,12 @@ struct DevState {
     unsigned long long n_samples;   // sampled steps since the last reset
     unsigned int error;             // first device error (positive code), 0 = none
     unsigned int big_count;         // cells queued for the global-memory collision kernel
-    unsigned int queue;             // next work unit of the persistent collision kernel
-    unsigned int pad0;
+    unsigned int pad0[3];
     unsigned long long pad[3];
     unsigned long long diag[kDiagStripes * kDiagPerStripe];
+    // work-unit queues of the persistent collision kernel, one 128-byte line
+    // each: queue q hands out the units q, q + kQueues, q + 2 kQueues, ...
+    unsigned int queue[kQueues * kQueueStride];
 };
 enum { kDiagOvershoot = 0, kDiagWallHits, kDiagLearned, kDiagFallback, kDiagSkip, kDiagVrNonfinite,
        kDiagBig };
@@ -441,8 +447,8 @@ __global__ void k_begin_step(DevState *st) {
         st->step_next = st->step_next + 1;
         st->n_samples = st->n_samples + 1;
         st->big_count = 0;
-        st->queue = 0;
     }
+    if (threadIdx.x < kQueues) st->queue[threadIdx.x * kQueueStride] = 0;
 }
 
 }  // namespace dsmc

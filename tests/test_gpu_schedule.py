@@ -16,10 +16,11 @@ from paper_2301_05985_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 SCHEDULES = [
+    {"schedule": 1, "persistent_waves": 5, "chunk_work": 0},
     {"schedule": 1, "persistent_waves": 64, "chunk_work": 0},
-    {"schedule": 1, "persistent_waves": 1024, "chunk_work": 65536},
-    {"schedule": 1, "persistent_waves": 2048, "chunk_work": 262144},
-    {"schedule": 1, "persistent_waves": 8192, "chunk_work": 4 * 10 ** 6},
+    {"schedule": 1, "persistent_waves": 1024, "chunk_work": 256},
+    {"schedule": 1, "persistent_waves": 2048, "chunk_work": 4000},
+    {"schedule": 1, "persistent_waves": 8192, "chunk_work": 10 ** 6},
 ]
 
 
@@ -78,7 +79,7 @@ def test_schedules_bit_identical(gpu, case):
 def test_persistent_matches_oracle(gpu):
     _announce("persistent vs oracle")
     p, parts = W.batched(n_inst=96, nmin=10, nmax=400, real="f32", seed=9)
-    p = dict(p, schedule=1, persistent_waves=40, chunk_work=20000)
+    p = dict(p, schedule=1, persistent_waves=40, chunk_work=300)
     st, _, cnt, _ = _run(p, parts, 9)
     orc = oracle.Oracle(p, parts, np.float32)
     orc.run(9)
