@@ -116,9 +116,14 @@ enum { DSMC_SCHEDULE_GRID = 0, DSMC_SCHEDULE_PERSISTENT = 1 };
 /* Structure-of-arrays particle state (device pointers).  Element type is
  * float (real_bytes 4) or double (real_bytes 8).  y is used only when
  * dims == 2, x only when dims >= 1, w only when vr == 1 (may be NULL
- * otherwise).  id holds a unique persistent particle number < 2^32; within a
- * cell the canonical collision order is ascending id (dims >= 1) or storage
- * order (dims == 0). */
+ * otherwise).  id holds a unique persistent particle number < 2^32.
+ * Collision order inside a cell: storage order for dims == 0.  Walled runs
+ * (dims >= 1) keep the particles as one sequence grouped by cell: at set-up
+ * by the cell of the initial position with ascending id inside a cell, and
+ * after each step's free flight regrouped by the new cell with the relative
+ * order of the previous sequence kept (a stable counting sort); a cell's
+ * particles collide in sequence order.  The storage order of the buffers is
+ * that sequence. */
 typedef struct {
     void *x, *y, *cx, *cy, *cz, *w;
     uint32_t *id;
@@ -146,17 +151,19 @@ dsmc_status dsmc_workspace_size(const dsmc_config *cfg, size_t *bytes);
  * owned, n_particles each) and the workspace (device, >= workspace size,
  * 256-byte aligned), zero the running sums, and record the per-step HIP
  * graph on `hip_stream` (a hipStream_t; NULL = default stream).  For
- * dims == 0 the particle counts per instance come from inst_offset.  The
- * particle arrays are not read during this call except for dims == 0
- * scheduling, which uses only inst_offset.  No device allocation. */
+ * dims == 0 the particle counts per instance come from inst_offset.  For
+ * dims >= 1 the particles are rearranged in place into the initial sequence
+ * (grouped by cell, ascending id inside a cell; the workspace's second
+ * buffer is used in between).  No device allocation. */
 dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *particles, void *workspace,
                       size_t ws_bytes, void *hip_stream, dsmc_ctx **out);
 
 /* Enqueue n_steps time steps (asynchronous).  Each step runs, in order:
- * free flight with wall conditions and cell indexing (dims >= 1), the
- * counting sort into cells, NTC collisions in every cell with the majorant
- * chosen by cfg->majorant, the importance-weight update (vr == 1), and
- * accumulation of the cell moments into the running sums. */
+ * free flight with wall conditions, new cell and move code of every
+ * particle (dims >= 1), the scan of the new cells' counts, then per cell the
+ * gather of its particles into the new sequence (dims >= 1), NTC collisions
+ * with the majorant chosen by cfg->majorant, the importance-weight update
+ * (vr == 1), and accumulation of the cell moments into the running sums. */
 dsmc_status dsmc_step(dsmc_ctx *ctx, int32_t n_steps);
 
 /* Synchronise the stream and copy out the running sums (host
@@ -170,9 +177,9 @@ dsmc_status dsmc_step(dsmc_ctx *ctx, int32_t n_steps);
 dsmc_status dsmc_sample(dsmc_ctx *ctx, double *sums_host, uint64_t *counters_host,
                         uint64_t *n_samples, int32_t reset);
 
-/* Device pointers of the buffers that hold the current particle state (the
- * counting sort alternates between the caller's buffers and the workspace).
- * Valid until the next dsmc_step. */
+/* Device pointers of the buffers that hold the current particle state, in
+ * sequence order (walled runs alternate between the caller's buffers and
+ * the workspace).  Valid until the next dsmc_step. */
 dsmc_status dsmc_particles(dsmc_ctx *ctx, dsmc_soa *current);
 
 /* Synchronise and report diagnostics (host struct); returns the sticky
@@ -194,10 +201,10 @@ dsmc_status dsmc_set_majorant_model(dsmc_ctx *ctx, const uint16_t *bf16_weights_
                                     double delta);
 
 /* Checkpoint: with host_blob == NULL, *bytes receives the size needed;
- * otherwise the particle state, step index, running sums and counters are
- * copied into host_blob (synchronising).  Restore copies them back into the
- * context's buffers; a run restored at step s continues bit for bit like
- * the uninterrupted run. */
+ * otherwise the particle state (in sequence order), step index, running
+ * sums and counters are copied into host_blob (synchronising).  Restore
+ * copies them back into the context's buffers; a run restored at step s
+ * continues bit for bit like the uninterrupted run. */
 dsmc_status dsmc_checkpoint(dsmc_ctx *ctx, void *host_blob, size_t *bytes);
 dsmc_status dsmc_restore(dsmc_ctx *ctx, const void *host_blob, size_t bytes);
 
@@ -225,8 +232,8 @@ const char *dsmc_status_string(dsmc_status status);
  * float; -inf marks cells with fewer than two particles) and, if bounds_dev
  * is not NULL, log2 of the EXACT-mode bound (device [n_cells] float).
  * Features: log2(number density), u_x/sqrt(T), u_y/sqrt(T), log2(T),
- * P_xx/p - 1, P_xy/p, from FP64 moments of the cell.  Walled runs need one
- * step first (cells are contiguous only after a sort).  Asynchronous. */
+ * P_xx/p - 1, P_xy/p, from FP64 moments of the cell (walled runs: the
+ * particles currently grouped in the cell).  Asynchronous. */
 dsmc_status dsmc_collect_features(dsmc_ctx *ctx, float *features_dev, float *labels_dev, float *bounds_dev);
 
 /* Forward pass of the 6-64-64-1 ReLU network in FP32 (params device

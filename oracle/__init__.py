@@ -85,8 +85,11 @@ def lib():
         for sfx in ("_f64", "_f32"):
             f = getattr(_lib, "orc_run" + sfx)
             f.restype = ctypes.c_int
-            f.argtypes = [P, ctypes.c_int64, P, P, P, P, P, P, P, ctypes.c_int64, ctypes.c_int32,
+            f.argtypes = [P, ctypes.c_int64, P, P, P, P, P, P, P, P, ctypes.c_int64, ctypes.c_int32,
                           P, P, P, P]
+            g = getattr(_lib, "orc_initial_layout" + sfx)
+            g.restype = None
+            g.argtypes = [P, ctypes.c_int64, P, P, P, P]
             for name in ("orc_exact_bound", "orc_diameter"):
                 g = getattr(_lib, name + sfx)
                 g.restype = ctypes.c_double
@@ -175,7 +178,11 @@ def make_cfg(p):
 class Oracle:
     """Holds the particle state of one oracle run (numpy arrays, in place)."""
 
-    def __init__(self, params, particles, dtype=np.float64):
+    def __init__(self, params, particles, dtype=np.float64, layout=None):
+        """layout (walled runs): the particle sequence the next step starts
+        from, as indices into the given arrays; None takes the initial
+        sequence (grouped by cell, ascending id inside a cell), "storage" the
+        given storage order (a state read back in its own sequence)."""
         self.p = dict(params)
         self.dtype = np.dtype(dtype)
         self.sfx = _sfx(dtype)
@@ -215,12 +222,23 @@ class Oracle:
         self.counters = np.zeros((self.ncell, 2), dtype=np.uint64)
         self.diag = OrcDiag()
         self.step = 0
+        self.layout = None
+        if self.p["dims"] >= 1:
+            if layout is None:
+                self.layout = np.zeros(n, dtype=np.int64)
+                getattr(lib(), "orc_initial_layout" + self.sfx)(
+                    ctypes.byref(self.cfg), n, _ptr(self.x), _ptr(self.y), _ptr(self.id), _ptr(self.layout))
+            elif isinstance(layout, str) and layout == "storage":
+                self.layout = np.arange(n, dtype=np.int64)
+            else:
+                self.layout = np.ascontiguousarray(layout, dtype=np.int64).copy()
+                assert len(self.layout) == n
 
     def run(self, nsteps, learned_log=False):
         f = getattr(lib(), "orc_run" + self.sfx)
         log = np.zeros((nsteps, self.ncell), dtype=np.int32) if learned_log else None
         rc = f(ctypes.byref(self.cfg), self.n, _ptr(self.x), _ptr(self.y), _ptr(self.cx),
-               _ptr(self.cy), _ptr(self.cz), _ptr(self.w), _ptr(self.id), self.step, nsteps,
+               _ptr(self.cy), _ptr(self.cz), _ptr(self.w), _ptr(self.id), _ptr(self.layout), self.step, nsteps,
                _ptr(self.sums), _ptr(self.counters), ctypes.byref(self.diag), _ptr(log))
         self.step += nsteps
         if rc != 0:
@@ -247,6 +265,12 @@ class Oracle:
     def state(self):
         """Particle state sorted by id (positions, velocities, weights)."""
         o = np.argsort(self.id, kind="stable")
+        return {k: getattr(self, k)[o].copy() for k in ("x", "y", "cx", "cy", "cz", "w", "id")}
+
+    def sequence_state(self):
+        """Particle state in the current particle sequence (walled runs): the
+        order in which the next step groups the particles."""
+        o = self.layout if self.layout is not None else np.arange(self.n)
         return {k: getattr(self, k)[o].copy() for k in ("x", "y", "cx", "cy", "cz", "w", "id")}
 
 

@@ -668,12 +668,54 @@ static int sample_cell(const orc_cfg *cfg, const soa_t *s, const int64_t *list, 
     return vr_bad;
 }
 
+/* Group particles by cell in counting-sort fashion: the particles are taken
+ * in the order of seq[0..np-1] (seq NULL: storage order) and each cell's
+ * particles keep that relative order (a stable sort by cell).  Fills
+ * start[0..ncell] and list[0..np-1]; cellp and count are scratch. */
+static void stable_group(const orc_cfg *cfg, int64_t np, const REAL *x, const REAL *y, const int64_t *seq,
+                         int64_t ncell, int64_t *cellp, int64_t *count, int64_t *start, int64_t *list)
+{
+    memset(count, 0, sizeof(int64_t) * (size_t)(ncell + 1));
+    for (int64_t p = 0; p < np; ++p) { cellp[p] = cell_of(cfg, x[p], cfg->dims == 2 ? y[p] : 0); count[cellp[p]]++; }
+    start[0] = 0;
+    for (int64_t c = 0; c < ncell; ++c) start[c + 1] = start[c] + count[c];
+    memset(count, 0, sizeof(int64_t) * (size_t)(ncell + 1));
+    for (int64_t k = 0; k < np; ++k) {
+        int64_t p = seq ? seq[k] : k;
+        int64_t c = cellp[p];
+        list[start[c] + count[c]++] = p;
+    }
+}
+
+/* The particle sequence before the first step (reading of the canonical
+ * in-cell order): grouped by the cell of the initial position, cells in
+ * ascending index, ascending particle id inside each cell. */
+void FN(orc_initial_layout)(const orc_cfg *cfg, int64_t np, const REAL *x, const REAL *y, const uint32_t *id,
+                            int64_t *layout)
+{
+    int64_t ncell = (int64_t)cfg->nx * (cfg->dims == 2 ? cfg->ny : 1);
+    int64_t *count = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
+    int64_t *start = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
+    int64_t *cellp = (int64_t *)malloc(sizeof(int64_t) * (size_t)(np > 0 ? np : 1));
+    stable_group(cfg, np, x, y, NULL, ncell, cellp, count, start, layout);
+    g_sort_ids = id;
+    for (int64_t c = 0; c < ncell; ++c)
+        qsort(layout + start[c], (size_t)(start[c + 1] - start[c]), sizeof(int64_t), cmp_by_id);
+    free(count); free(start); free(cellp);
+}
+
 /* Run nsteps time steps starting at step index step0.  Particle arrays are
  * modified in place (storage order is never changed).  sums[n_cells][26] and
  * counters[n_cells][2] (candidates, accepted) are accumulated.  Per step:
- * stream -> group -> collide -> sample. */
+ * stream -> group -> collide -> sample.
+ *
+ * Walled runs (dims 1, 2) carry the particle sequence layout[0..np-1]
+ * (indices into the arrays) from step to step: after streaming, the new
+ * sequence is the stable grouping of the old one by new cell, and each
+ * cell's particles are collided in that order (the canonical in-cell order).
+ * The caller starts from orc_initial_layout. */
 int FN(orc_run)(const orc_cfg *cfg, int64_t np, REAL *x, REAL *y, REAL *cx, REAL *cy, REAL *cz,
-                REAL *w, const uint32_t *id, int64_t step0, int32_t nsteps, double *sums,
+                REAL *w, const uint32_t *id, int64_t *layout, int64_t step0, int32_t nsteps, double *sums,
                 uint64_t *counters, orc_diag *diag, int32_t *learned_log /* [nsteps][ncell] or NULL */)
 {
     soa_t s = {x, y, cx, cy, cz, w, id};
@@ -691,16 +733,9 @@ int FN(orc_run)(const orc_cfg *cfg, int64_t np, REAL *x, REAL *y, REAL *cx, REAL
             /* stream: each particle independently */
             for (int64_t p = 0; p < np && rc == 0; ++p) rc = stream_one(cfg, &s, p, step, diag);
             if (rc) break;
-            /* group: counting sort by cell, then ascending id inside each cell */
-            memset(count, 0, sizeof(int64_t) * (size_t)(ncell + 1));
-            for (int64_t p = 0; p < np; ++p) { cellp[p] = cell_of(cfg, x[p], cfg->dims == 2 ? y[p] : 0); count[cellp[p]]++; }
-            start[0] = 0;
-            for (int64_t c = 0; c < ncell; ++c) start[c + 1] = start[c] + count[c];
-            memset(count, 0, sizeof(int64_t) * (size_t)(ncell + 1));
-            for (int64_t p = 0; p < np; ++p) { int64_t c = cellp[p]; list[start[c] + count[c]++] = p; }
-            g_sort_ids = id;
-            for (int64_t c = 0; c < ncell; ++c)
-                qsort(list + start[c], (size_t)(start[c + 1] - start[c]), sizeof(int64_t), cmp_by_id);
+            /* group: stable counting sort of the current sequence by new cell */
+            stable_group(cfg, np, x, y, layout, ncell, cellp, count, start, list);
+            memcpy(layout, list, sizeof(int64_t) * (size_t)np);
         } else {
             /* homogeneous instances: contiguous ranges, storage order is canonical */
             for (int64_t c = 0; c <= ncell; ++c) start[c] = cfg->inst_offset[c];

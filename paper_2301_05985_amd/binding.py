@@ -242,6 +242,15 @@ class Simulation:
         o = np.argsort(out["id"], kind="stable")
         return {k: (v[o] if v is not None else None) for k, v in out.items()}
 
+    def sequence(self):
+        """Current particle state as numpy arrays in storage order, which for
+        walled runs is the particle sequence (grouped by cell)."""
+        t = self.raw_particles()
+        self.torch.cuda.synchronize(self.device)
+        out = {k: (v.cpu().numpy().copy() if v is not None else None) for k, v in t.items() if k != "id"}
+        out["id"] = t["id"].cpu().numpy().view(np.uint32).copy()
+        return out
+
     def raw_particles(self):
         """Current particle state in storage order (torch tensors on the device)."""
         torch = self.torch

@@ -37,7 +37,8 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t alt[7];  // x y cx cy cz w id of the second particle buffer
-    size_t count, offset, cursor, sums, counters, volume, state, big_list, perm, owner, sched, flags, done, units;
+    size_t count, offset, offset2, cursor, sums, counters, volume, state, big_list, perm, owner, sched, flags, done,
+        units, code, far_head, far_src, far_next;
     size_t mlp, lattice;
     size_t total;
 };
@@ -97,6 +98,11 @@ Layout make_layout(const dsmc_config &c) {
         L.cursor = take(nc * 4);
         L.flags = take(((nc + kScanTile - 1) / kScanTile) * 8);
         L.done = take(4);
+        L.offset2 = take((nc + 1) * 4);
+        L.code = take(n);
+        L.far_head = take(nc * 4);
+        L.far_src = take(n * 4);
+        L.far_next = take(n * 4);
     }
     L.offset = take((nc + 1) * 4);
     L.sums = take(nc * kNsum * 8);
@@ -142,6 +148,11 @@ struct dsmc_ctx {
     int persistent_grid = 0;
     uint32_t *count = nullptr, *offset = nullptr, *cursor = nullptr, *big_list = nullptr,
              *perm = nullptr, *owner = nullptr, *sched = nullptr;
+    // walled runs: cell ranges of each particle buffer (off[0] is `offset`),
+    // move codes and the far-mover lists of the streaming pass
+    uint32_t *off[2] = {nullptr, nullptr};
+    uint8_t *code = nullptr;
+    uint32_t *far_head = nullptr, *far_src = nullptr, *far_next = nullptr;
     double *sums = nullptr, *volume = nullptr, *lattice = nullptr;
     unsigned long long *counters = nullptr;
     float *mlp = nullptr;
@@ -164,12 +175,29 @@ Soa<R> soa_of(const Bufs &b) {
     return s;
 }
 
+// Collision arguments for a step reading buffer src and writing dst (the
+// same buffer for homogeneous instances, the other one for walled runs).
 template <typename R>
-CollideArgs<R> collide_args(dsmc_ctx *c, int buf) {
+CollideArgs<R> collide_args(dsmc_ctx *c, int src, int dst) {
     CollideArgs<R> a;
-    a.s = soa_of<R>(c->buf[buf]);
-    a.start = c->offset;
-    a.sched = c->cfg.dims == 0 ? c->sched : nullptr;
+    std::memset(&a, 0, sizeof(a));
+    a.s = soa_of<R>(c->buf[dst]);
+    a.sched = c->sched;
+    if (c->cfg.dims == 0) {
+        a.start = c->offset;
+    } else {
+        a.start = c->off[dst];
+        a.src = soa_of<R>(c->buf[src]);
+        a.src_start = c->off[src];
+        a.code = c->code;
+        a.far_head = c->far_head;
+        a.far_src = c->far_src;
+        a.far_next = c->far_next;
+        a.nx = c->geo.nx;
+        a.ny = c->geo.ny;
+        a.periodic_x = c->cfg.wall_kind[0] == DSMC_WALL_PERIODIC;
+        a.periodic_y = c->cfg.dims == 2 && c->cfg.wall_kind[2] == DSMC_WALL_PERIODIC;
+    }
     a.volume = c->cfg.cell_volume ? c->volume : nullptr;
     a.Vuni = c->Vuni;
     a.dt = c->cfg.dt;
@@ -209,8 +237,8 @@ struct Launcher {
 };
 
 template <typename R, bool VR, int D>
-void launch_collide(dsmc_ctx *c, Launcher &L, int buf) {
-    CollideArgs<R> a = collide_args<R>(c, buf);
+void launch_collide(dsmc_ctx *c, Launcher &L, int src) {
+    CollideArgs<R> a = collide_args<R>(c, src, D == 0 ? src : src ^ 1);
     const bool learned = a.mlp != nullptr && c->cfg.molecule == DSMC_HARD_SPHERE;
     L.mark(learned ? "collide_learned" : "collide");
     if (D == 0 && c->cfg.schedule == DSMC_SCHEDULE_PERSISTENT) {
@@ -234,23 +262,64 @@ void launch_collide(dsmc_ctx *c, Launcher &L, int buf) {
     }
 }
 
+// Streaming pass over buffer src and the scan of the new cells' counts into
+// the cell ranges of the other buffer.
 template <typename R, int D, bool VR>
-void launch_sort(dsmc_ctx *c, Launcher &L, int src) {
+void launch_stream(dsmc_ctx *c, Launcher &L, int src) {
     const int dst = src ^ 1;
     const unsigned grid = (unsigned)((c->n + 255) / 256);
-    const Soa<R> s = soa_of<R>(c->buf[src]), d = soa_of<R>(c->buf[dst]);
     if (c->n > 0) {
-        L.mark("stream_count");
-        hipLaunchKernelGGL((k_stream_count<R, D>), dim3(grid), dim3(256), 0, L.s, c->geo, s, (int64_t)c->n,
-                           c->count, c->st);
+        L.mark("stream");
+        hipLaunchKernelGGL((k_stream_code<R, D, VR>), dim3(grid), dim3(256), 0, L.s, c->geo,
+                           soa_of<R>(c->buf[src]), (int64_t)c->n, c->code, c->count, c->far_head, c->far_src,
+                           c->far_next, c->st);
     }
     L.mark("scan");
     hipLaunchKernelGGL(k_scan_lookback, dim3((unsigned)((c->ncell + kScanTile - 1) / kScanTile)), dim3(256), 0, L.s,
-                       c->count, c->offset, c->cursor, (int)c->ncell, c->flags, c->done, c->st);
-    if (c->n > 0) {
-        L.mark("stream_scatter");
-        hipLaunchKernelGGL((k_stream_scatter<R, D, VR>), dim3(grid), dim3(256), 0, L.s, c->geo, s, d,
-                           (int64_t)c->n, c->cursor, c->st);
+                       c->count, c->off[dst], c->cursor, (int)c->ncell, c->flags, c->done, c->st, 1);
+}
+
+// Cell ranges of buffer b from the cells of its current positions (set-up and
+// restore; the step bookkeeping is not advanced).
+template <typename R, int D>
+void launch_ranges(dsmc_ctx *c, hipStream_t s, int b) {
+    const unsigned grid = (unsigned)((c->n + 255) / 256);
+    if (c->n > 0)
+        hipLaunchKernelGGL((k_count_cells<R, D>), dim3(grid), dim3(256), 0, s, c->geo, soa_of<R>(c->buf[b]),
+                           (int64_t)c->n, c->count);
+    hipLaunchKernelGGL(k_scan_lookback, dim3((unsigned)((c->ncell + kScanTile - 1) / kScanTile)), dim3(256), 0, s,
+                       c->count, c->off[b], c->cursor, (int)c->ncell, c->flags, c->done, c->st, 0);
+}
+
+// Initial sequence in buffer 0: grouped by cell, ascending id inside a cell.
+template <typename R, int D, bool VR>
+void launch_initial_sequence(dsmc_ctx *c, hipStream_t s) {
+    launch_ranges<R, D>(c, s, 0);
+    if (c->n == 0) return;
+    const unsigned grid = (unsigned)((c->n + 255) / 256);
+    hipLaunchKernelGGL((k_place<R, D, VR>), dim3(grid), dim3(256), 0, s, c->geo, soa_of<R>(c->buf[0]),
+                       soa_of<R>(c->buf[1]), (int64_t)c->n, c->cursor, c->st);
+    hipLaunchKernelGGL((k_canonical<R, D, VR>), dim3((unsigned)c->ncell), dim3(64), 0, s, soa_of<R>(c->buf[1]),
+                       soa_of<R>(c->buf[0]), (const uint32_t *)c->off[0]);
+}
+
+template <typename R, int D>
+void dispatch_vr(dsmc_ctx *c, hipStream_t s, bool initial) {
+    if (initial) {
+        if (c->cfg.vr) launch_initial_sequence<R, D, true>(c, s);
+        else launch_initial_sequence<R, D, false>(c, s);
+    } else {
+        launch_ranges<R, D>(c, s, c->cur);
+    }
+}
+
+// Set-up (initial) or restore (ranges of the current buffer) of a walled run.
+void walled_setup(dsmc_ctx *c, bool initial) {
+    hipStream_t s = c->stream;
+    if (c->cfg.real_bytes == 4) {
+        if (c->cfg.dims == 1) dispatch_vr<float, 1>(c, s, initial); else dispatch_vr<float, 2>(c, s, initial);
+    } else {
+        if (c->cfg.dims == 1) dispatch_vr<double, 1>(c, s, initial); else dispatch_vr<double, 2>(c, s, initial);
     }
 }
 
@@ -263,11 +332,11 @@ void enqueue_step_t(dsmc_ctx *c, Launcher &L, int src) {
         return;
     }
     if (c->cfg.dims == 1) {
-        launch_sort<R, 1, VR>(c, L, src);
-        launch_collide<R, VR, 1>(c, L, src ^ 1);
+        launch_stream<R, 1, VR>(c, L, src);
+        launch_collide<R, VR, 1>(c, L, src);
     } else {
-        launch_sort<R, 2, VR>(c, L, src);
-        launch_collide<R, VR, 2>(c, L, src ^ 1);
+        launch_stream<R, 2, VR>(c, L, src);
+        launch_collide<R, VR, 2>(c, L, src);
     }
 }
 
@@ -371,10 +440,16 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
         c->cursor = (uint32_t *)(c->ws + L.cursor);
         c->flags = (uint64_t *)(c->ws + L.flags);
         c->done = (uint32_t *)(c->ws + L.done);
+        c->code = (uint8_t *)(c->ws + L.code);
+        c->far_head = (uint32_t *)(c->ws + L.far_head);
+        c->far_src = (uint32_t *)(c->ws + L.far_src);
+        c->far_next = (uint32_t *)(c->ws + L.far_next);
+        c->off[1] = (uint32_t *)(c->ws + L.offset2);
     } else {
         c->buf[1] = c->buf[0];
     }
     c->offset = (uint32_t *)(c->ws + L.offset);
+    c->off[0] = c->offset;
     c->sums = (double *)(c->ws + L.sums);
     c->counters = (unsigned long long *)(c->ws + L.counters);
     c->volume = (double *)(c->ws + L.volume);
@@ -414,9 +489,9 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
     else c->Vuni = 1.0;
 
     // LDS capacity per cell (one wave per cell)
-    // LDS per cell: velocities (+ weights), owner marks (+4 padding entries),
-    // rank of each slot (walled runs)
-    const size_t per = 3 * rb + (cfg->vr ? rb : 0) + 4 + (cfg->dims >= 1 ? 2 : 0);
+    // LDS per cell: velocities (+ weights), owner marks (+4 padding entries;
+    // in walled runs they first hold the gather's selection)
+    const size_t per = 3 * rb + (cfg->vr ? rb : 0) + 4;
     const int cap_fit = (int)std::min<size_t>((kMaxLds - 64) / per, 65535) / 32 * 32;
     std::vector<uint32_t> start_host;
     std::vector<uint32_t> sched_host;
@@ -466,6 +541,18 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
         const int64_t maxbig = c->n / (c->cap + 1);
         c->any_big_possible = maxbig > 0;
         c->big_grid = (int)std::max<int64_t>(1, std::min<int64_t>(maxbig, 256));
+        // XCD-aware order: workgroups are dealt to the eight XCDs in turn
+        // (block b on XCD b mod 8), so XCD x is given the x-th contiguous
+        // eighth of the cells and the neighbour cells a cell gathers from
+        // are mostly read through the same L2
+        sched_host.resize(c->ncell);
+        const int64_t per8 = (c->ncell + 7) / 8;
+        int64_t blk = 0;
+        for (int64_t k = 0; k < per8; ++k)
+            for (int64_t x = 0; x < 8; ++x) {
+                const int64_t cell = x * per8 + k;
+                if (cell < c->ncell) sched_host[blk++] = (uint32_t)cell;
+            }
     }
     c->lds = (size_t)c->cap * per + 16 + 16;
 
@@ -490,11 +577,17 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
         if (hipMemcpyAsync(c->volume, c->volume_host.data(), (size_t)c->ncell * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess)
             return fail(DSMC_EHIP);
     }
+    if (hipMemcpyAsync(c->sched, sched_host.data(), sched_host.size() * 4, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+        return fail(DSMC_EHIP);
     if (cfg->dims == 0) {
         if (hipMemcpyAsync(c->offset, start_host.data(), start_host.size() * 4, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-            hipMemcpyAsync(c->sched, sched_host.data(), sched_host.size() * 4, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
             hipMemcpyAsync(c->units, units_host.data(), units_host.size() * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess)
             return fail(DSMC_EHIP);
+    } else {
+        // empty far-mover lists, then the initial particle sequence
+        if (hipMemsetAsync(c->far_head, 0xFF, (size_t)c->ncell * 4, c->stream) != hipSuccess) return fail(DSMC_EHIP);
+        walled_setup(c, true);
+        if (hipGetLastError() != hipSuccess) return fail(DSMC_EHIP);
     }
     {
         std::vector<double> lat(kLatticeSize);
@@ -679,7 +772,14 @@ dsmc_status dsmc_restore(dsmc_ctx *c, const void *blob, size_t bytes) {
     HIP_TRY(hipMemcpy(c->counters, o, nc * 16, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(&c->st->step_next, &h.step_next, 8, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(&c->st->n_samples, &h.n_samples, 8, hipMemcpyHostToDevice));
-    return DSMC_OK;
+    if (c->cfg.dims >= 1) {
+        // the blob holds the particle sequence; its cell ranges follow from
+        // the positions
+        walled_setup(c, false);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    }
+    return device_status(c);
 }
 
 dsmc_status dsmc_profile_step(dsmc_ctx *c, float *ms_host, int32_t max_kernels, int32_t *n_kernels,
@@ -713,17 +813,15 @@ dsmc_status dsmc_profile_step(dsmc_ctx *c, float *ms_host, int32_t max_kernels, 
 dsmc_status dsmc_collect_features(dsmc_ctx *c, float *features, float *labels, float *bounds) {
     if (!c || !features || !labels) return DSMC_EINVAL;
     if (c->sticky != DSMC_OK) return c->sticky;
-    // cells of a walled run are contiguous only once a step has sorted them
-    unsigned long long next = 0;
+    // the current buffer holds the particle sequence grouped by cell (walled
+    // runs are grouped at set-up)
     HIP_TRY(hipStreamSynchronize(c->stream));
-    HIP_TRY(hipMemcpy(&next, &c->st->step_next, 8, hipMemcpyDeviceToHost));
-    if (c->cfg.dims >= 1 && next == 0) return DSMC_EINVAL;
     if (c->cfg.real_bytes == 4)
         hipLaunchKernelGGL(k_collect_features<float>, dim3((unsigned)c->ncell), dim3(64), 0, c->stream,
-                           collide_args<float>(c, c->cur), (int)c->ncell, features, labels, bounds);
+                           collide_args<float>(c, c->cur, c->cur), (int)c->ncell, features, labels, bounds);
     else
         hipLaunchKernelGGL(k_collect_features<double>, dim3((unsigned)c->ncell), dim3(64), 0, c->stream,
-                           collide_args<double>(c, c->cur), (int)c->ncell, features, labels, bounds);
+                           collide_args<double>(c, c->cur, c->cur), (int)c->ncell, features, labels, bounds);
     HIP_TRY(hipGetLastError());
     return DSMC_OK;
 }

@@ -29,6 +29,14 @@ struct CollideArgs {
     Soa<R> s;                      // particles grouped by cell (or instance storage)
     const uint32_t *start;         // [ncell + 1] first particle of each cell
     const uint32_t *sched;         // block -> cell, or null for the identity
+    // walled runs: s is written in the new sequence, gathered from src (the
+    // streamed particles in the previous sequence) by move code
+    Soa<R> src;
+    const uint32_t *src_start;     // [ncell + 1] cell ranges of src
+    const uint8_t *code;           // [n] move code of each src particle
+    uint32_t *far_head;            // [ncell] far-mover list heads, reset once read
+    const uint32_t *far_src, *far_next;
+    int nx, ny, periodic_x, periodic_y;
     const double *volume;          // per-cell volume, or null for Vuni
     double Vuni, dt, sigma, FN;
     int molecule, cap, majorant;

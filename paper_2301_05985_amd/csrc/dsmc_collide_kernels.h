@@ -7,98 +7,219 @@
 
 namespace dsmc {
 
-// One pass of the id ranking: J slots per lane (slots s0 + 64 j + lane),
-// each counted against every id of the cell with 16-byte broadcast reads;
-// the slot's particle is placed at its rank in the LDS arrays.
-template <typename R, bool VR, int J>
-__device__ __forceinline__ void rank_pass(const CollideArgs<R> &a, uint32_t base, uint32_t s0, uint32_t N,
-                                          uint32_t n4, const uint32_t *ids, const uint4 *ids4, R *vx, R *vy,
-                                          R *vz, R *w, uint16_t *rank_of_slot) {
-    const uint32_t lane = (uint32_t)lane_id();
-    uint32_t me[J], rk[J];
-    R x[J], y[J], z[J], ww[J];
+// ------------------------------------------------ gather of a walled cell
+// Cell t of the new sequence holds, in order, the particles of the previous
+// sequence whose new cell is t (a stable counting sort).  They come from the
+// cells around t: along each axis t - 1, t and t + 1 (wrapped when periodic,
+// dropped outside the grid), visited in ascending cell index, so that taking
+// in each source cell the particles whose move code leads to t, in position
+// order, yields them in ascending position.  Far movers (from farther away)
+// are taken from the cell's list and merged by position.
+
+// Distinct source coordinates of destination coordinate t along one axis,
+// ascending, with the move code step from each to t.
+struct AxisSources {
+    int n;
+    int c[3], d[3];
+};
+
+__device__ __forceinline__ AxisSources axis_sources(int t, int n, bool periodic) {
+    constexpr int kNone = 0x7FFFFFFF;
+    int a = t - 1, b = t + 1;
+    if (periodic) {
+        a = a < 0 ? a + n : a;
+        b = b >= n ? b - n : b;
+    } else {
+        a = a < 0 ? kNone : a;
+        b = b >= n ? kNone : b;
+    }
+    int v0 = a, v1 = t, v2 = b, tmp;
+    if (v0 > v1) { tmp = v0; v0 = v1; v1 = tmp; }
+    if (v1 > v2) { tmp = v1; v1 = v2; v2 = tmp; }
+    if (v0 > v1) { tmp = v0; v0 = v1; v1 = tmp; }
+    AxisSources r;
+    const int w1 = v1 > v0 ? v1 : v2;  // the next distinct value, if any
+    const bool h1 = w1 > v0 && w1 != kNone;
+    const bool h2 = h1 && v1 > v0 && v2 > v1 && v2 != kNone;
+    r.n = 1 + (h1 ? 1 : 0) + (h2 ? 1 : 0);
+    r.c[0] = v0;
+    r.c[1] = w1;
+    r.c[2] = v2;
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const uint32_t s = s0 + (uint32_t)j * 64 + lane;
-        me[j] = 0u;
-        rk[j] = 0u;
-        if (s < N) {
-            me[j] = ids[s];
-            x[j] = a.s.cx[base + s]; y[j] = a.s.cy[base + s]; z[j] = a.s.cz[base + s];
-            if (VR) ww[j] = a.s.w[base + s];
+    for (int k = 0; k < 3; ++k) r.d[k] = axis_move(r.c[k] == kNone ? t : r.c[k], t, n, periodic);
+    return r;
+}
+
+// Near movers of `cell`: source positions written to sel[0..) in ascending
+// order (at most N are written); returns how many were found.  The first
+// PRE x 64 codes of every source cell are loaded before any is consumed.
+template <typename R, int D>
+__device__ __forceinline__ uint32_t select_near(const CollideArgs<R> &a, uint32_t cell, uint32_t N, uint32_t *sel) {
+    constexpr int PRE = D == 1 ? 4 : 2;
+    constexpr int NS = D == 1 ? 3 : 9;
+    const int lane = lane_id();
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    const int tx = (int)(cell % (uint32_t)a.nx), ty = (int)(cell / (uint32_t)a.nx);
+    const AxisSources xs = axis_sources(tx, a.nx, a.periodic_x != 0);
+    AxisSources ys;
+    if (D == 2) {
+        ys = axis_sources(ty, a.ny, a.periodic_y != 0);
+    } else {
+        ys.n = 1;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { ys.c[k] = 0; ys.d[k] = 0; }
+    }
+    uint32_t b[NS], e[NS];
+    uint32_t req[NS];
+    uint32_t cd[NS][PRE];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const int iy = k / 3, ix = k % 3;
+        const bool ok = ix < xs.n && iy < ys.n;
+        const uint32_t src = ok ? (uint32_t)ys.c[iy] * (uint32_t)a.nx + (uint32_t)xs.c[ix] : 0u;
+        b[k] = ok ? a.src_start[src] : 0u;
+        e[k] = ok ? a.src_start[src + 1] : 0u;
+        req[k] = (uint32_t)((xs.d[ix] + 1) + 3 * (ys.d[iy] + 1));
+    }
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+#pragma unroll
+        for (int j = 0; j < PRE; ++j) {
+            const uint32_t i = b[k] + (uint32_t)(64 * j + lane);
+            cd[k][j] = i < e[k] ? (uint32_t)a.code[i] : (uint32_t)kFarMove;
+        }
+    uint32_t nsel = 0;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+#pragma unroll
+        for (int j = 0; j < PRE; ++j) {
+            const bool m = cd[k][j] == req[k];
+            const unsigned long long bal = __ballot(m);
+            if (m) {
+                const uint32_t pos = nsel + (uint32_t)__popcll(bal & lt);
+                if (pos < N) sel[pos] = b[k] + (uint32_t)(64 * j + lane);
+            }
+            nsel += (uint32_t)__popcll(bal);
+        }
+        // source cells longer than the preloaded part
+        for (uint32_t i0 = b[k] + 64 * PRE; i0 < e[k]; i0 += 64) {
+            const uint32_t i = i0 + (uint32_t)lane;
+            const bool m = i < e[k] && (uint32_t)a.code[i] == req[k];
+            const unsigned long long bal = __ballot(m);
+            if (m) {
+                const uint32_t pos = nsel + (uint32_t)__popcll(bal & lt);
+                if (pos < N) sel[pos] = i;
+            }
+            nsel += (uint32_t)__popcll(bal);
         }
     }
-    for (uint32_t t4 = 0; t4 < n4; ++t4) {
-        const uint4 q = ids4[t4];
+    return nsel;
+}
+
+// Far movers of `cell`: walked by lane 0 from the cell's list into
+// sel[n_near..N); the list head is reset for the next step.  Any mismatch
+// with the cell's count is reported, and sel is filled with valid positions.
+template <typename R>
+__device__ __forceinline__ void select_far(const CollideArgs<R> &a, uint32_t cell, uint32_t n_near, uint32_t N,
+                                           uint32_t *sel) {
+    if (lane_id() == 0) {
+        uint32_t k = a.far_head[cell], m = n_near;
+        while (k != kEmpty && m < N) {
+            sel[m++] = a.far_src[k];
+            k = a.far_next[k];
+        }
+        if (k != kEmpty || m != N) set_error(a.st, DSMC_ECAPACITY);
+        while (m < N) sel[m++] = 0u;
+        a.far_head[cell] = kEmpty;
+    }
+}
+
+// Position of source position q in the merged order: the number of smaller
+// entries of sel[0..N) (only cells with far movers need it).
+__device__ __forceinline__ uint32_t merged_rank(const uint32_t *sel, uint32_t N, uint32_t q) {
+    uint32_t r = 0;
+    for (uint32_t t = 0; t < N; ++t) r += sel[t] < q ? 1u : 0u;
+    return r;
+}
+
+// J elements per lane (e0 + 64 j + lane): every load issued before the first
+// store.  Positions, ids go straight to the new sequence; velocities and
+// weights to LDS at the element's rank.
+template <typename R, bool VR, int D, int J>
+__device__ __forceinline__ void gather_j(const CollideArgs<R> &a, uint32_t base, uint32_t e0, uint32_t N,
+                                         const uint32_t *sel, bool merge, R *vx, R *vy, R *vz, R *w) {
+    const uint32_t lane = (uint32_t)lane_id();
+    uint32_t q[J], r[J], id[J];
+    R x[J], y[J], c0[J], c1[J], c2[J], ww[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const uint32_t el = e0 + 64u * (uint32_t)j + lane;
+        q[j] = el < N ? sel[el] : 0u;
+        r[j] = el;
+    }
+    if (merge) {
 #pragma unroll
         for (int j = 0; j < J; ++j)
-            rk[j] += (uint32_t)(q.x < me[j]) + (uint32_t)(q.y < me[j]) + (uint32_t)(q.z < me[j]) +
-                     (uint32_t)(q.w < me[j]);
+            if (r[j] < N) r[j] = merged_rank(sel, N, q[j]);
     }
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-        const uint32_t s = s0 + (uint32_t)j * 64 + lane;
-        if (s < N) {
-            rank_of_slot[s] = (uint16_t)rk[j];
-            vx[rk[j]] = x[j]; vy[rk[j]] = y[j]; vz[rk[j]] = z[j];
-            if (VR) w[rk[j]] = ww[j];
+        if (e0 + 64u * (uint32_t)j + lane < N) {
+            x[j] = a.src.x[q[j]];
+            if (D == 2) y[j] = a.src.y[q[j]];
+            c0[j] = a.src.cx[q[j]]; c1[j] = a.src.cy[q[j]]; c2[j] = a.src.cz[q[j]];
+            if (VR) ww[j] = a.src.w[q[j]];
+            id[j] = a.src.id[q[j]];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        if (e0 + 64u * (uint32_t)j + lane < N) {
+            const uint32_t o = base + (r[j] < N ? r[j] : N - 1);
+            a.s.x[o] = x[j];
+            if (D == 2) a.s.y[o] = y[j];
+            a.s.id[o] = id[j];
+            const uint32_t rr = r[j] < N ? r[j] : N - 1;
+            if (vx) {
+                vx[rr] = c0[j]; vy[rr] = c1[j]; vz[rr] = c2[j];
+                if (VR) w[rr] = ww[j];
+            } else {
+                a.s.cx[o] = c0[j]; a.s.cy[o] = c1[j]; a.s.cz[o] = c2[j];
+                if (VR) a.s.w[o] = ww[j];
+            }
         }
     }
 }
 
-// Cells of at most 256 particles: J slots per lane, ids and velocities loaded
-// in one round trip, ids shared through LDS, then ranked and placed.
-template <typename R, bool VR, int J>
-__device__ __forceinline__ void rank_single(const CollideArgs<R> &a, uint32_t base, uint32_t N, uint32_t n4,
-                                            uint32_t *ids, const uint4 *ids4, R *vx, R *vy, R *vz, R *w,
-                                            uint16_t *rank_of_slot) {
-    const uint32_t lane = (uint32_t)lane_id();
-    uint32_t me[J], rk[J];
-    R x[J], y[J], z[J], ww[J];
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const uint32_t s = (uint32_t)j * 64 + lane;
-        me[j] = 0u;
-        rk[j] = 0u;
-        if (s < N) {
-            me[j] = a.s.id[base + s];
-            x[j] = a.s.cx[base + s]; y[j] = a.s.cy[base + s]; z[j] = a.s.cz[base + s];
-            if (VR) ww[j] = a.s.w[base + s];
-        }
+// Whole gather of a walled cell: selection into sel (LDS or global scratch
+// of at least N entries), then the particles into the new sequence at
+// `base` (velocities and weights into LDS when vx is given, else into the
+// new sequence too).
+template <typename R, bool VR, int D>
+__device__ __forceinline__ void gather_cell(const CollideArgs<R> &a, uint32_t cell, uint32_t base, uint32_t N,
+                                            uint32_t *sel, R *vx, R *vy, R *vz, R *w) {
+    uint32_t n_near = select_near<R, D>(a, cell, N, sel);
+    if (n_near > N) {
+        if (lane_id() == 0) set_error(a.st, DSMC_ECAPACITY);
+        n_near = N;
     }
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const uint32_t s = (uint32_t)j * 64 + lane;
-        if (s < N) ids[s] = me[j];
-    }
-    if (lane < 4) ids[N + lane] = 0xFFFFFFFFu;  // padding never ranks below a real id
+    const bool merge = n_near < N;
+    if (merge) select_far(a, cell, n_near, N, sel);
     __syncthreads();
-    for (uint32_t t4 = 0; t4 < n4; ++t4) {
-        const uint4 q = ids4[t4];
-#pragma unroll
-        for (int j = 0; j < J; ++j)
-            rk[j] += (uint32_t)(q.x < me[j]) + (uint32_t)(q.y < me[j]) + (uint32_t)(q.z < me[j]) +
-                     (uint32_t)(q.w < me[j]);
-    }
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const uint32_t s = (uint32_t)j * 64 + lane;
-        if (s < N) {
-            rank_of_slot[s] = (uint16_t)rk[j];
-            vx[rk[j]] = x[j]; vy[rk[j]] = y[j]; vz[rk[j]] = z[j];
-            if (VR) w[rk[j]] = ww[j];
-        }
-    }
+    uint32_t e0 = 0;
+    for (; e0 + 256 <= N; e0 += 256) gather_j<R, VR, D, 4>(a, base, e0, N, sel, merge, vx, vy, vz, w);
+    const uint32_t left = N - e0;
+    if (left > 192) gather_j<R, VR, D, 4>(a, base, e0, N, sel, merge, vx, vy, vz, w);
+    else if (left > 128) gather_j<R, VR, D, 3>(a, base, e0, N, sel, merge, vx, vy, vz, w);
+    else if (left > 64) gather_j<R, VR, D, 2>(a, base, e0, N, sel, merge, vx, vy, vz, w);
+    else if (left > 0) gather_j<R, VR, D, 1>(a, base, e0, N, sel, merge, vx, vy, vz, w);
 }
 
-// LDS kernel: one wave per cell.  BYID: the cell arrives in arbitrary order
-// from the counting sort and is ranked by particle id in LDS (canonical
-// order); otherwise (homogeneous instances) storage order is canonical.
-// D is the run's dimension (0 for homogeneous instances); walled runs rank
-// by particle id.
+// LDS kernel body: one wave per cell.  Homogeneous instances (D 0) collide
+// in place in storage order; walled cells (D 1, 2) are gathered into the new
+// sequence first.
 template <typename R, bool VR, int D, bool LEARNED>
 __device__ __forceinline__ void collide_lds_body(const CollideArgs<R> &a, unsigned char *smem, uint32_t cell) {
-    constexpr bool BYID = D > 0;
     const int lane = lane_id();
     const uint32_t base = a.start[cell];
     const uint32_t N = a.start[cell + 1] - base;
@@ -115,33 +236,8 @@ __device__ __forceinline__ void collide_lds_body(const CollideArgs<R> &a, unsign
     R *vx = (R *)smem, *vy = vx + cap, *vz = vy + cap;
     R *w = VR ? vz + cap : nullptr;
     uint32_t *owner = (uint32_t *)(VR ? w + cap : vz + cap);  // cap + 4 entries
-    uint16_t *rank_of_slot = (uint16_t *)(owner + cap + 4);
-    if (BYID) {
-        // canonical order: rank of each slot by particle id, counted against
-        // the whole cell with 16-byte broadcast reads; up to four slots per
-        // lane per pass (cells of up to 256 particles take one pass)
-        uint32_t *ids = owner;  // the owner array is free until the ranks are known
-        const uint4 *ids4 = (const uint4 *)ids;
-        const uint32_t n4 = (N + 3) / 4;
-        if (N <= 256) {
-            // one pass: ids and velocities are fetched together before the
-            // ids are shared through LDS
-            if (N > 192) rank_single<R, VR, 4>(a, base, N, n4, ids, ids4, vx, vy, vz, w, rank_of_slot);
-            else if (N > 128) rank_single<R, VR, 3>(a, base, N, n4, ids, ids4, vx, vy, vz, w, rank_of_slot);
-            else if (N > 64) rank_single<R, VR, 2>(a, base, N, n4, ids, ids4, vx, vy, vz, w, rank_of_slot);
-            else rank_single<R, VR, 1>(a, base, N, n4, ids, ids4, vx, vy, vz, w, rank_of_slot);
-        } else {
-            for (uint32_t s = lane; s < N; s += 64) ids[s] = a.s.id[base + s];
-            if (lane < 4) ids[N + lane] = 0xFFFFFFFFu;  // padding never ranks below a real id
-            __syncthreads();
-            for (uint32_t s0 = 0; s0 < N; s0 += 256) {
-                const uint32_t left = N - s0;
-                if (left > 192) rank_pass<R, VR, 4>(a, base, s0, N, n4, ids, ids4, vx, vy, vz, w, rank_of_slot);
-                else if (left > 128) rank_pass<R, VR, 3>(a, base, s0, N, n4, ids, ids4, vx, vy, vz, w, rank_of_slot);
-                else if (left > 64) rank_pass<R, VR, 2>(a, base, s0, N, n4, ids, ids4, vx, vy, vz, w, rank_of_slot);
-                else rank_pass<R, VR, 1>(a, base, s0, N, n4, ids, ids4, vx, vy, vz, w, rank_of_slot);
-            }
-        }
+    if (D > 0) {
+        gather_cell<R, VR, D>(a, cell, base, N, owner, vx, vy, vz, w);  // the owner array holds the selection
         __syncthreads();
     } else {
         for (uint32_t s = lane; s < N; s += 64) {
@@ -156,17 +252,16 @@ __device__ __forceinline__ void collide_lds_body(const CollideArgs<R> &a, unsign
     else process_cell<R, VR>(a, view, cell, N, step, pf);
     __syncthreads();
     for (uint32_t s = lane; s < N; s += 64) {
-        const uint32_t r = BYID ? (uint32_t)rank_of_slot[s] : s;
-        a.s.cx[base + s] = vx[r]; a.s.cy[base + s] = vy[r]; a.s.cz[base + s] = vz[r];
-        if (VR) a.s.w[base + s] = w[r];
+        a.s.cx[base + s] = vx[s]; a.s.cy[base + s] = vy[s]; a.s.cz[base + s] = vz[s];
+        if (VR) a.s.w[base + s] = w[s];
     }
 }
 
-// Global-memory kernel for cells larger than the LDS capacity: works in
-// place through a rank -> slot permutation and a global owner array.
+// Global-memory kernel for cells larger than the LDS capacity: walled cells
+// are gathered into the new sequence (selection in a global scratch array),
+// then every cell is operated on in place.
 template <typename R, bool VR, int D, bool LEARNED>
 __device__ __forceinline__ void collide_big_body(const CollideArgs<R> &a) {
-    constexpr bool BYID = D > 0;
     const int lane = lane_id();
     const uint32_t step = (uint32_t)a.st->step_cur;
     const uint32_t nbig = a.st->big_count;
@@ -174,17 +269,13 @@ __device__ __forceinline__ void collide_big_body(const CollideArgs<R> &a) {
         const uint32_t cell = a.big_list[q];
         const uint32_t base = a.start[cell];
         const uint32_t N = a.start[cell + 1] - base;
-        uint32_t *perm = BYID ? a.perm_g + base : nullptr;
-        if (BYID) {
-            for (uint32_t s = lane; s < N; s += 64) {
-                const uint32_t me = a.s.id[base + s];
-                uint32_t rank = 0;
-                for (uint32_t t = 0; t < N; ++t) rank += a.s.id[base + t] < me ? 1u : 0u;
-                perm[rank] = s;
-            }
+        if (D > 0) {
+            gather_cell<R, VR, D>(a, cell, base, N, a.perm_g + base, (R *)nullptr, (R *)nullptr, (R *)nullptr,
+                                  (R *)nullptr);
+            __syncthreads();
         }
         const GlobalView<R> view{a.s.cx + base, a.s.cy + base, a.s.cz + base,
-                                 VR ? a.s.w + base : nullptr, perm, a.owner_g + base};
+                                 VR ? a.s.w + base : nullptr, nullptr, a.owner_g + base};
         for (uint32_t r = lane; r < N; r += 64) view.clear_own(r);
         __syncthreads();
         const CellPrefetch pf = prefetch_cell<R, VR>(a, cell);

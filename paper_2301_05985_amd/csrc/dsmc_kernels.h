@@ -33,7 +33,8 @@ struct DevState {
     unsigned long long n_samples;   // sampled steps since the last reset
     unsigned int error;             // first device error (positive code), 0 = none
     unsigned int big_count;         // cells queued for the global-memory collision kernel
-    unsigned int pad0[3];
+    unsigned int far_count;         // entries of this step's far-mover list
+    unsigned int pad0[2];
     unsigned long long pad[3];
     unsigned long long diag[kDiagStripes * kDiagPerStripe];
     // work-unit queues of the persistent collision kernel, one 128-byte line
@@ -122,13 +123,17 @@ __device__ __forceinline__ T pick4(const T (&a)[4], int w) {
 // snaps the particle onto the wall, applies the wall condition and continues
 // with the remaining time; on a tie the x wall goes first.  Returns 0 or
 // DSMC_EWALLHITS.  The particle id is read only when a diffuse wall is hit.
+// cz is only written (at diffuse walls); w is read from wsrc[p] at the
+// first diffuse hit.  diffuse reports whether one happened.
 template <typename R, int D, bool WANT_W>
 __device__ __forceinline__ int fly(const Geo &g, R &x, R &y, R &cx, R &cy, R &cz, R &w,
-                                   const uint32_t *ids, int64_t p, uint32_t step, uint32_t &hits) {
+                                   const uint32_t *ids, const R *wsrc, int64_t p, uint32_t step, uint32_t &hits,
+                                   bool &diffuse) {
     const R Lx = (R)g.Lx, Ly = (R)g.Ly, zero = (R)0;
     const R inf = (R)INFINITY;
     R tau = (R)g.dt;
     hits = 0;
+    diffuse = false;
     uint32_t pid = 0;
     bool have_pid = false;
     for (;;) {
@@ -168,7 +173,12 @@ __device__ __forceinline__ int fly(const Geo &g, R &x, R &y, R &cx, R &cy, R &cz
         } else if (kind == DSMC_WALL_SPECULAR) {
             if (xwall) cx = -cx; else cy = -cy;
         } else {
-            if (!have_pid) { pid = ids[p]; have_pid = true; }
+            if (!have_pid) {
+                pid = ids[p];
+                have_pid = true;
+                if (WANT_W) w = wsrc[p];
+            }
+            diffuse = true;
             R dn, d1, d2;
             const double Tw = pick4(g.Tw, wall);
             wall_draw((R)Tw, hits, pid, step, g.k0, g.k1, dn, d1, d2);
@@ -185,159 +195,142 @@ __device__ __forceinline__ int fly(const Geo &g, R &x, R &y, R &cx, R &cy, R &cz
     }
 }
 
-// Cell index floor(x nx / Lx) clamped to [0, nx-1], in double; 2-D cells are
-// numbered iy * nx + ix.
-__device__ __forceinline__ uint32_t cell_index(const Geo &g, double x, double y) {
+// Cell coordinates floor(x nx / Lx), floor(y ny / Ly), each clamped to the
+// grid, in double; 2-D cells are numbered iy * nx + ix.
+__device__ __forceinline__ void cell_coords(const Geo &g, double x, double y, int &ix, int &iy) {
     const double fx = floor(x * g.invx);
-    const int ix = !(fx >= 0.0) ? 0 : (fx > (double)(g.nx - 1) ? g.nx - 1 : (int)fx);
-    if (g.dims < 2) return (uint32_t)ix;
-    const double fy = floor(y * g.invy);
-    const int iy = !(fy >= 0.0) ? 0 : (fy > (double)(g.ny - 1) ? g.ny - 1 : (int)fy);
+    ix = !(fx >= 0.0) ? 0 : (fx > (double)(g.nx - 1) ? g.nx - 1 : (int)fx);
+    iy = 0;
+    if (g.dims == 2) {
+        const double fy = floor(y * g.invy);
+        iy = !(fy >= 0.0) ? 0 : (fy > (double)(g.ny - 1) ? g.ny - 1 : (int)fy);
+    }
+}
+__device__ __forceinline__ uint32_t cell_index(const Geo &g, double x, double y) {
+    int ix, iy;
+    cell_coords(g, x, y, ix, iy);
     return (uint32_t)iy * (uint32_t)g.nx + (uint32_t)ix;
 }
 
-// Pass 1 of the counting sort: fly, index, count.  Reads x, (y), cx, cy only
-// (16 B per particle in FP32 2-D) -- the post-flight state is recomputed by
-// pass 2 instead of being written and re-read.
-template <typename R, int D>
-__global__ __launch_bounds__(256) void k_stream_count(Geo g, Soa<R> s, int64_t n, uint32_t *count,
-                                                      DevState *st) {
+// ------------------------------------------------------------ move codes
+// The particle sequence is regrouped every step by a stable counting sort on
+// the new cell.  Streaming records, per particle, how its cell changed: along
+// each axis a step of -1, 0 or +1 cells (across a periodic boundary the
+// wrapped neighbour counts as one step), coded (dx + 1) + 3 (dy + 1); a
+// particle that moved further is a far mover, linked into a per-cell list.
+// The collision kernel of cell t then finds its particles in the (at most
+// nine) neighbouring cells of the previous sequence from the codes alone.
+constexpr uint8_t kFarMove = 0xFF;
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+
+__device__ __forceinline__ int axis_move(int from, int to, int n, bool periodic) {
+    const int d = to - from;
+    if (d >= -1 && d <= 1) return d;
+    if (periodic && d == n - 1) return -1;
+    if (periodic && d == 1 - n) return 1;
+    return 2;
+}
+
+__device__ __forceinline__ uint8_t move_code(const Geo &g, int fx, int fy, int tx, int ty) {
+    const int dx = axis_move(fx, tx, g.nx, g.kind[0] == DSMC_WALL_PERIODIC);
+    const int dy = g.dims == 2 ? axis_move(fy, ty, g.ny, g.kind[2] == DSMC_WALL_PERIODIC) : 0;
+    if (dx == 2 || dy == 2) return kFarMove;
+    return (uint8_t)((dx + 1) + 3 * (dy + 1));
+}
+
+// Streaming pass, in sequence order and in place: free flight, the new cell
+// counted, the move code written (far movers linked into their new cell's
+// list), and the velocity and weight stored back only for the particles that
+// met a wall.  Reads x, (y), cx, cy; writes x, (y) and one code byte.
+template <typename R, int D, bool VR>
+__global__ __launch_bounds__(256) void k_stream_code(Geo g, Soa<R> s, int64_t n, uint8_t *code, uint32_t *count,
+                                                     uint32_t *far_head, uint32_t *far_src, uint32_t *far_next,
+                                                     DevState *st) {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool act = p < n;
     const uint32_t step = (uint32_t)st->step_next;
-    uint32_t cell = 0;
+    uint32_t cell = 0, hits = 0;
     if (act) {
         R x = s.x[p], y = D == 2 ? s.y[p] : (R)0, cx = s.cx[p], cy = s.cy[p], cz = (R)0, w = (R)0;
-        uint32_t hits;
-        const int rc = fly<R, D, false>(g, x, y, cx, cy, cz, w, s.id, p, step, hits);
+        int fx, fy, tx, ty;
+        cell_coords(g, (double)x, D == 2 ? (double)y : 0.0, fx, fy);
+        bool diffuse;
+        const int rc = fly<R, D, VR>(g, x, y, cx, cy, cz, w, s.id, s.w, p, step, hits, diffuse);
         if (rc) set_error(st, rc);
-        cell = cell_index(g, (double)x, D == 2 ? (double)y : 0.0);
+        cell_coords(g, (double)x, D == 2 ? (double)y : 0.0, tx, ty);
+        cell = (uint32_t)ty * (uint32_t)g.nx + (uint32_t)tx;
+        s.x[p] = x;
+        if (D == 2) s.y[p] = y;
+        if (hits) {
+            s.cx[p] = cx;
+            s.cy[p] = cy;
+            if (diffuse) {
+                s.cz[p] = cz;
+                if (VR) s.w[p] = w;
+            }
+        }
+        const uint8_t mc = move_code(g, fx, fy, tx, ty);
+        code[p] = mc;
+        if (mc == kFarMove) {
+            const uint32_t k = atomicAdd(&st->far_count, 1u);
+            far_src[k] = (uint32_t)p;
+            far_next[k] = atomicExch(&far_head[cell], k);
+        }
     }
     wave_aggregated_add(count, cell, act);
-}
-
-// Pass 2: fly again (same bits), claim a slot in the cell's range and write
-// the whole particle to the other buffer.  Order inside a cell is arbitrary;
-// the collision kernel restores the canonical order.
-template <typename R, int D, bool VR>
-__global__ __launch_bounds__(256) void k_stream_scatter(Geo g, Soa<R> src, Soa<R> dst, int64_t n,
-                                                        uint32_t *cursor, DevState *st) {
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool act = p < n;
-    const uint32_t step = (uint32_t)st->step_cur;
-    uint32_t cell = 0, hits = 0, pid = 0;
-    R x = 0, y = 0, cx = 0, cy = 0, cz = 0, w = 0;
-    if (act) {
-        x = src.x[p];
-        if (D == 2) y = src.y[p];
-        cx = src.cx[p]; cy = src.cy[p]; cz = src.cz[p];
-        if (VR) w = src.w[p];
-        pid = src.id[p];
-        const int rc = fly<R, D, VR>(g, x, y, cx, cy, cz, w, src.id, p, step, hits);
-        if (rc) set_error(st, rc);
-        cell = cell_index(g, (double)x, D == 2 ? (double)y : 0.0);
-    }
-    const uint32_t slot = wave_aggregated_inc(cursor, cell, act);
-    if (act && (int64_t)slot >= n) {
-        // both passes compute the same cell by construction; never write
-        // outside the buffer if they ever disagree
-        set_error(st, DSMC_ECAPACITY);
-        return;
-    }
-    if (act) {
-        dst.x[slot] = x;
-        if (D == 2) dst.y[slot] = y;
-        dst.cx[slot] = cx; dst.cy[slot] = cy; dst.cz[slot] = cz;
-        if (VR) dst.w[slot] = w;
-        dst.id[slot] = pid;
-    }
     const uint32_t hsum = wave_sum_u32(hits);
     if (lane_id() == 0 && hsum) diag_add(st, kDiagWallHits, (unsigned long long)hsum);
 }
 
-// Exclusive scan of the per-cell counts in one workgroup of 1024 threads,
-// writing offsets and cursors and clearing the counts for the next step;
-// thread 0 also advances the step bookkeeping.  Each thread owns a
-// contiguous chunk; when the cell count is a multiple of 4 and at most
-// 65,536 the chunk is moved with 16-byte loads and stores, all issued before
-// the first is consumed.
-__global__ __launch_bounds__(1024) void k_scan(uint32_t *count, uint32_t *offset, uint32_t *cursor,
-                                               int ncell, DevState *st) {
-    __shared__ uint32_t wave_tot[16];
-    const int t = threadIdx.x, lane = lane_id(), wv = t >> 6;
-    const bool vec = (ncell % 4) == 0 && ncell <= 65536;
-    constexpr int kV = 16;  // uint4 per thread in the vector path
-    uint4 q[kV];
-    int b, e;
-    uint32_t local = 0;
-    if (vec) {
-        const int n4 = ncell / 4;
-        const int per4 = (n4 + 1023) / 1024;
-        b = t * per4;
-        e = min(b + per4, n4);
-        const uint4 *c4 = (const uint4 *)count;
-#pragma unroll
-        for (int k = 0; k < kV; ++k) q[k] = (b + k < e) ? c4[b + k] : make_uint4(0, 0, 0, 0);
-#pragma unroll
-        for (int k = 0; k < kV; ++k) local += (q[k].x + q[k].y) + (q[k].z + q[k].w);
-    } else {
-        const int per = (ncell + 1023) / 1024;
-        b = t * per;
-        e = min(b + per, ncell);
-        for (int i = b; i < e; ++i) local += count[i];
+// Set-up of the initial sequence (grouped by the cell of the initial
+// position, ascending particle id inside a cell): count the cells of the
+// current positions, place every particle in its cell's range (arbitrary
+// order), then rank each cell by id.
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_count_cells(Geo g, Soa<R> s, int64_t n, uint32_t *count) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool act = p < n;
+    uint32_t cell = 0;
+    if (act) cell = cell_index(g, (double)s.x[p], D == 2 ? (double)s.y[p] : 0.0);
+    wave_aggregated_add(count, cell, act);
+}
+
+template <typename R, int D, bool VR>
+__global__ __launch_bounds__(256) void k_place(Geo g, Soa<R> src, Soa<R> dst, int64_t n, uint32_t *cursor,
+                                               DevState *st) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool act = p < n;
+    uint32_t cell = 0;
+    if (act) cell = cell_index(g, (double)src.x[p], D == 2 ? (double)src.y[p] : 0.0);
+    const uint32_t slot = wave_aggregated_inc(cursor, cell, act);
+    if (act && (int64_t)slot >= n) {
+        set_error(st, DSMC_ECAPACITY);
+        return;
     }
-    // block-wide exclusive scan of the chunk totals
-    uint32_t inc = local;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t v = __shfl_up(inc, off, 64);
-        if (lane >= off) inc += v;
+    if (act) {
+        dst.x[slot] = src.x[p];
+        if (D == 2) dst.y[slot] = src.y[p];
+        dst.cx[slot] = src.cx[p]; dst.cy[slot] = src.cy[p]; dst.cz[slot] = src.cz[p];
+        if (VR) dst.w[slot] = src.w[p];
+        dst.id[slot] = src.id[p];
     }
-    if (lane == 63) wave_tot[wv] = inc;
-    __syncthreads();
-    if (wv == 0) {
-        const uint32_t v = lane < 16 ? wave_tot[lane] : 0u;
-        uint32_t s = v;
-#pragma unroll
-        for (int off = 1; off < 16; off <<= 1) {
-            const uint32_t u = __shfl_up(s, off, 64);
-            if (lane >= off) s += u;
-        }
-        if (lane < 16) wave_tot[lane] = s - v;
-    }
-    __syncthreads();
-    uint32_t run = wave_tot[wv] + inc - local;
-    if (vec) {
-        uint4 *o4 = (uint4 *)offset, *u4 = (uint4 *)cursor, *c4 = (uint4 *)count;
-#pragma unroll
-        for (int k = 0; k < kV; ++k) {
-            if (b + k < e) {
-                uint4 r;
-                r.x = run; run += q[k].x;
-                r.y = run; run += q[k].y;
-                r.z = run; run += q[k].z;
-                r.w = run; run += q[k].w;
-                o4[b + k] = r;
-                u4[b + k] = r;
-                c4[b + k] = make_uint4(0, 0, 0, 0);
-            }
-        }
-        if (e == ncell / 4 && b < e) offset[ncell] = run;
-    } else {
-        for (int i = b; i < e; ++i) {
-            const uint32_t c = count[i];
-            offset[i] = run;
-            cursor[i] = run;
-            count[i] = 0;
-            run += c;
-        }
-        if (e == ncell && b < e) offset[ncell] = run;
-    }
-    if (t == 0) {
-        st->step_cur = st->step_next;
-        st->step_next = st->step_next + 1;
-        st->n_samples = st->n_samples + 1;
-        st->big_count = 0;
+}
+
+template <typename R, int D, bool VR>
+__global__ __launch_bounds__(64) void k_canonical(Soa<R> src, Soa<R> dst, const uint32_t *start) {
+    const uint32_t cell = blockIdx.x;
+    const uint32_t base = start[cell], N = start[cell + 1] - base;
+    for (uint32_t q = lane_id(); q < N; q += 64) {
+        const uint32_t me = src.id[base + q];
+        uint32_t r = 0;
+        for (uint32_t t = 0; t < N; ++t) r += src.id[base + t] < me ? 1u : 0u;
+        if (r >= N) r = N - 1;  // ids are distinct; never write outside the cell
+        const uint32_t o = base + r;
+        dst.x[o] = src.x[base + q];
+        if (D == 2) dst.y[o] = src.y[base + q];
+        dst.cx[o] = src.cx[base + q]; dst.cy[o] = src.cy[base + q]; dst.cz[o] = src.cz[base + q];
+        if (VR) dst.w[o] = src.w[base + q];
+        dst.id[o] = me;
     }
 }
 
@@ -348,14 +341,15 @@ __global__ __launch_bounds__(1024) void k_scan(uint32_t *count, uint32_t *offset
 // found by walking back over earlier tiles' flags.  Workgroups are dispatched
 // in index order, so every tile it waits on is resident or finished; the walk
 // still gives up (and reports an error) after a bounded number of polls.  The
-// last workgroup to finish clears the flags for the next launch and advances
-// the step bookkeeping.
+// last workgroup to finish clears the flags for the next launch and, when
+// `advance` is set (every step; not at set-up), advances the step
+// bookkeeping.
 constexpr int kScanTile = 1024;
 constexpr uint64_t kFlagAgg = 1ull << 32, kFlagInc = 2ull << 32;
 
 __global__ __launch_bounds__(256) void k_scan_lookback(uint32_t *count, uint32_t *offset, uint32_t *cursor,
                                                        int ncell, uint64_t *flags, uint32_t *done,
-                                                       DevState *st) {
+                                                       DevState *st, int advance) {
     __shared__ uint32_t wave_tot[4];
     __shared__ uint32_t tile_prefix;
     __shared__ bool last;
@@ -432,10 +426,13 @@ __global__ __launch_bounds__(256) void k_scan_lookback(uint32_t *count, uint32_t
             __hip_atomic_store(&flags[k], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (t == 0) {
             *done = 0u;
-            st->step_cur = st->step_next;
-            st->step_next = st->step_next + 1;
-            st->n_samples = st->n_samples + 1;
-            st->big_count = 0;
+            if (advance) {
+                st->step_cur = st->step_next;
+                st->step_next = st->step_next + 1;
+                st->n_samples = st->n_samples + 1;
+                st->big_count = 0;
+                st->far_count = 0;
+            }
         }
     }
 }

@@ -52,12 +52,12 @@ def test_cavity_full_size_sampled_cells_and_every_flight(gpu):
     p, parts = W.cavity(Kn=0.01, real="f32")
     sim = Simulation(p, parts)
     sim.step(1)
-    s1 = sim.particles()
+    s1 = sim.sequence()  # the oracle continues from the GPU's particle sequence
     sim.sample(reset=True)
     rng = np.random.default_rng(11)
     cells = np.unique(rng.choice(65536, 64, replace=False))
     cells = np.unique(np.concatenate([cells, [0, 255, 65280, 65535]]))  # the four corner cells
-    orc = oracle.Oracle(p, s1, np.float32)
+    orc = oracle.Oracle(p, s1, np.float32, layout="storage")
     orc.step = 1
     orc.run_sampled(cells)
     sim.step(1)
@@ -65,6 +65,7 @@ def test_cavity_full_size_sampled_cells_and_every_flight(gpu):
     _, cnt, _ = sim.sample()
     o = orc.state()
     assert np.array_equal(s2["id"], o["id"])
+    assert np.array_equal(sim.sequence()["id"], orc.sequence_state()["id"])
     # every particle's flight (walls included): identical except for the last
     # bits of particles that hit a diffuse wall (device vs host log/cos/sin)
     for k in ("x", "y"):

@@ -38,14 +38,19 @@ def _run(gpu_unused, p, parts, steps, real, chunks=1):
         orc.run(per)
     sums, cnt, ns = sim.sample()
     st = sim.particles()
+    seq = sim.sequence()["id"]
     diag = sim.diagnostics()
     sim.close()
-    return dict(sums=sums, cnt=cnt, ns=ns, st=st, diag=diag), orc
+    return dict(sums=sums, cnt=cnt, ns=ns, st=st, diag=diag, seq=seq), orc
 
 
 def _compare(g, orc, exact, rtol=1e-12, fields=("x", "y", "cx", "cy", "cz", "w"), dims=None):
     o = orc.state()
     assert np.array_equal(g["st"]["id"], o["id"])
+    if orc.layout is not None:
+        # walled runs: the GPU's storage order is the oracle's particle sequence
+        assert np.array_equal(g["seq"], orc.sequence_state()["id"]), "particle sequence differs"
+    assert g["diag"]["status"] == 0, g["diag"]
     assert np.array_equal(g["cnt"], orc.counters), "per-cell candidate/accepted counts differ"
     for k in fields:
         a, b = g["st"][k], o[k]
@@ -156,8 +161,8 @@ def test_cavity_diffuse_lid_vr_f64(gpu):
 
 
 def test_cavity_big_cell_global_path_f64(gpu):
-    # one crowded cell above the LDS capacity in a walled run (id ranking in
-    # global memory)
+    # one crowded cell above the LDS capacity in a walled run (gathered and
+    # collided in global memory)
     _announce("cavity big cell f64")
     p, parts = W.cavity(nx=4, ny=4, per_cell=40, Kn=0.05, real="f64", dt=1e-4)
     rng = np.random.default_rng(5)
@@ -170,6 +175,44 @@ def test_cavity_big_cell_global_path_f64(gpu):
     g, orc = _run(gpu, p, parts, 4, "f64")
     assert g["diag"]["big_cells"] > 0
     _compare(g, orc, exact=False, rtol=1e-12)
+
+
+@pytest.mark.parametrize("case", ["periodic_2x3", "periodic_1x1", "specular_far", "fourier_periodic_2",
+                                  "big_cell_far"])
+def test_far_movers_and_small_periodic_grids(gpu, case):
+    # steps long enough that many particles cross several cells (far-mover
+    # lists), periodic grids so small that neighbours coincide, and a crowded
+    # cell gathered in global memory while particles jump across the box
+    _announce("far movers %s" % case)
+    spec = (W.WALL_SPECULAR,) * 4
+    if case == "periodic_2x3":
+        p, parts = W.cavity(nx=2, ny=3, per_cell=30, Kn=0.05, real="f64", dt=0.4)
+        p["wall_kind"] = (W.WALL_PERIODIC,) * 4
+    elif case == "periodic_1x1":
+        p, parts = W.cavity(nx=1, ny=1, per_cell=60, Kn=0.05, real="f64", dt=0.4)
+        p["wall_kind"] = (W.WALL_PERIODIC,) * 4
+    elif case == "specular_far":
+        p, parts = W.cavity(nx=7, ny=5, per_cell=20, Kn=0.05, real="f64", dt=0.25)
+        p["wall_kind"] = spec
+    elif case == "fourier_periodic_2":
+        p, parts = W.fourier(n_cells=2, per_cell=50, Kn=0.05, real="f64", dt=0.3)
+        p["wall_kind"] = (W.WALL_PERIODIC, W.WALL_PERIODIC, 0, 0)
+    else:
+        p, parts = W.cavity(nx=4, ny=4, per_cell=30, Kn=0.05, real="f64", dt=0.2)
+        p["wall_kind"] = spec
+        rng = np.random.default_rng(8)
+        extra = 1200
+        n0 = len(parts["cx"])
+        add = dict(x=rng.random(extra) * 0.2 + 0.02, y=rng.random(extra) * 0.2 + 0.02,
+                   cx=rng.standard_normal(extra), cy=rng.standard_normal(extra), cz=rng.standard_normal(extra),
+                   w=np.ones(extra), id=np.arange(n0, n0 + extra, dtype=np.uint32))
+        parts = {k: np.concatenate([parts[k], add[k]]) for k in add}
+    parts = W.shuffle_storage(parts, seed=4)
+    g, orc = _run(gpu, p, parts, 6, "f64", chunks=2)
+    assert orc.counters[:, 1].sum() > 20
+    if case == "big_cell_far":
+        assert g["diag"]["big_cells"] > 0
+    _compare(g, orc, exact=True)
 
 
 def test_relaxation_full_size_f64(gpu):

@@ -353,9 +353,10 @@ def test_hard_sphere_relaxes_to_the_maxwellian():
 
 
 def test_results_do_not_depend_on_storage_order():
-    # canonical order inside a cell is ascending particle id, and every draw is
-    # keyed by (step, cell, candidate) or (step, particle, hit): permuting the
-    # storage order must give the same bits per particle
+    # the initial sequence orders each cell by particle id, later sequences
+    # follow from it by stable grouping, and every draw is keyed by (step,
+    # cell, candidate) or (step, particle, hit): permuting the storage order
+    # must give the same bits per particle
     p, parts = W.cavity(nx=4, ny=4, per_cell=12, Kn=0.05, steps=6, real="f64")
     a = oracle.Oracle(p, parts)
     b = oracle.Oracle(p, W.shuffle_storage(parts, seed=3))
@@ -373,8 +374,8 @@ def test_checkpoint_resume_is_bit_exact():
     a.run(10)
     b = oracle.Oracle(p, parts)
     b.run(5)
-    snap = b.state()
-    c = oracle.Oracle(p, snap)
+    snap = b.sequence_state()
+    c = oracle.Oracle(p, snap, layout="storage")
     c.step = 5
     c.run(5)
     sa, sc = a.state(), c.state()
@@ -448,3 +449,39 @@ def test_vr_weight_divergence_is_a_diagnostic_not_an_error():
     o.run(400)
     assert np.isfinite(o.sums[:, :13]).all()
     assert o.diag.vr_nonfinite > 0
+
+
+def _cells_np(p, x, y):
+    nx = p["n_cells"][0]
+    ix = np.clip(np.floor(np.asarray(x, dtype=np.float64) * nx), 0, nx - 1).astype(np.int64)
+    if p["dims"] < 2:
+        return ix
+    ny = p["n_cells"][1]
+    iy = np.clip(np.floor(np.asarray(y, dtype=np.float64) * ny), 0, ny - 1).astype(np.int64)
+    return iy * nx + ix
+
+
+@pytest.mark.parametrize("kind", ["cavity", "fourier"])
+def test_particle_sequence_is_a_stable_grouping_by_cell(kind):
+    # the initial sequence is (cell, id) in lexicographic order; after every
+    # step the sequence is the previous one regrouped by the new cells with
+    # the relative order kept (checked against numpy's stable argsort)
+    if kind == "cavity":
+        p, parts = W.cavity(nx=6, ny=5, per_cell=20, Kn=0.05, steps=4, real="f64", dt=0.05)
+    else:
+        p, parts = W.fourier(n_cells=7, per_cell=25, Kn=0.05, steps=4, real="f64", dt=0.02)
+    parts = W.shuffle_storage(parts, seed=5)
+    o = oracle.Oracle(p, parts)
+    cell0 = _cells_np(p, o.x, o.y)
+    want = np.lexsort((o.id, cell0))
+    assert np.array_equal(o.layout, want)
+    moved = 0
+    for _ in range(4):
+        prev = o.layout.copy()
+        c_prev = _cells_np(p, o.x, o.y)
+        o.run(1)
+        c_new = _cells_np(p, o.x, o.y)
+        moved += int((c_prev != c_new).sum())
+        want = prev[np.argsort(c_new[prev], kind="stable")]
+        assert np.array_equal(o.layout, want)
+    assert moved > 20
