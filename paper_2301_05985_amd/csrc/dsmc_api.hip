@@ -30,6 +30,7 @@ using namespace dsmc;
 namespace {
 
 constexpr int kGraphSteps = 8;  // steps recorded per graph (even: the sort ping-pongs)
+constexpr unsigned kWallGrid = 256;  // workgroups of the wall-flight kernel (grid-stride)
 constexpr size_t kAlign = 256;
 constexpr size_t kMaxLds = 64 * 1024;
 
@@ -38,7 +39,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
     size_t alt[7];  // x y cx cy cz w id of the second particle buffer
     size_t count, offset, offset2, cursor, sums, counters, volume, state, big_list, perm, owner, sched, flags, done,
-        units, code, far_head, far_src, far_next;
+        units, code, far_head, far_src, far_next, wall_list;
     size_t mlp, lattice;
     size_t total;
 };
@@ -103,6 +104,7 @@ Layout make_layout(const dsmc_config &c) {
         L.far_head = take(nc * 4);
         L.far_src = take(n * 4);
         L.far_next = take(n * 4);
+        L.wall_list = take(n * 4);
     }
     L.offset = take((nc + 1) * 4);
     L.sums = take(nc * kNsum * 8);
@@ -152,7 +154,7 @@ struct dsmc_ctx {
     // move codes and the far-mover lists of the streaming pass
     uint32_t *off[2] = {nullptr, nullptr};
     uint8_t *code = nullptr;
-    uint32_t *far_head = nullptr, *far_src = nullptr, *far_next = nullptr;
+    uint32_t *far_head = nullptr, *far_src = nullptr, *far_next = nullptr, *wall_list = nullptr;
     double *sums = nullptr, *volume = nullptr, *lattice = nullptr;
     unsigned long long *counters = nullptr;
     float *mlp = nullptr;
@@ -267,12 +269,16 @@ void launch_collide(dsmc_ctx *c, Launcher &L, int src) {
 template <typename R, int D, bool VR>
 void launch_stream(dsmc_ctx *c, Launcher &L, int src) {
     const int dst = src ^ 1;
-    const unsigned grid = (unsigned)((c->n + 255) / 256);
+    constexpr int P = 2;  // particles per thread of the streaming kernel
+    const unsigned grid = (unsigned)((c->n + 256 * P - 1) / (256 * P));
     if (c->n > 0) {
+        const Soa<R> s = soa_of<R>(c->buf[src]);
         L.mark("stream");
-        hipLaunchKernelGGL((k_stream_code<R, D, VR>), dim3(grid), dim3(256), 0, L.s, c->geo,
-                           soa_of<R>(c->buf[src]), (int64_t)c->n, c->code, c->count, c->far_head, c->far_src,
-                           c->far_next, c->st);
+        hipLaunchKernelGGL((k_stream_code<R, D, P>), dim3(grid), dim3(256), 0, L.s, c->geo, s, (int64_t)c->n,
+                           c->code, c->count, c->far_head, c->far_src, c->far_next, c->wall_list, c->st);
+        L.mark("stream_walls");
+        hipLaunchKernelGGL((k_stream_walls<R, D, VR>), dim3(kWallGrid), dim3(256), 0, L.s, c->geo, s, c->code,
+                           c->count, c->far_head, c->far_src, c->far_next, (const uint32_t *)c->wall_list, c->st);
     }
     L.mark("scan");
     hipLaunchKernelGGL(k_scan_lookback, dim3((unsigned)((c->ncell + kScanTile - 1) / kScanTile)), dim3(256), 0, L.s,
@@ -444,6 +450,7 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
         c->far_head = (uint32_t *)(c->ws + L.far_head);
         c->far_src = (uint32_t *)(c->ws + L.far_src);
         c->far_next = (uint32_t *)(c->ws + L.far_next);
+        c->wall_list = (uint32_t *)(c->ws + L.wall_list);
         c->off[1] = (uint32_t *)(c->ws + L.offset2);
     } else {
         c->buf[1] = c->buf[0];

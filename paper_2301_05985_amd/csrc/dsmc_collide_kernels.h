@@ -69,16 +69,22 @@ __device__ __forceinline__ uint32_t select_near(const CollideArgs<R> &a, uint32_
 #pragma unroll
         for (int k = 0; k < 3; ++k) { ys.c[k] = 0; ys.d[k] = 0; }
     }
+    if (N == 0) return 0;  // nothing lands here (and the sequence may be empty)
     uint32_t b[NS], e[NS];
     uint32_t req[NS];
     uint32_t cd[NS][PRE];
+    // every load below is issued unconditionally from an in-bounds address
+    // (positions past a source range are clamped to the last particle) and
+    // masked afterwards: no branches around the loads
+    const uint32_t last = a.src_start[(uint32_t)a.nx * (uint32_t)(D == 2 ? a.ny : 1)] - 1u;
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
         const int iy = k / 3, ix = k % 3;
         const bool ok = ix < xs.n && iy < ys.n;
         const uint32_t src = ok ? (uint32_t)ys.c[iy] * (uint32_t)a.nx + (uint32_t)xs.c[ix] : 0u;
-        b[k] = ok ? a.src_start[src] : 0u;
-        e[k] = ok ? a.src_start[src + 1] : 0u;
+        const uint32_t lb = a.src_start[src], le = a.src_start[src + 1];
+        b[k] = ok ? lb : 0u;
+        e[k] = ok ? le : 0u;
         req[k] = (uint32_t)((xs.d[ix] + 1) + 3 * (ys.d[iy] + 1));
     }
 #pragma unroll
@@ -86,7 +92,8 @@ __device__ __forceinline__ uint32_t select_near(const CollideArgs<R> &a, uint32_
 #pragma unroll
         for (int j = 0; j < PRE; ++j) {
             const uint32_t i = b[k] + (uint32_t)(64 * j + lane);
-            cd[k][j] = i < e[k] ? (uint32_t)a.code[i] : (uint32_t)kFarMove;
+            const uint32_t v = (uint32_t)a.code[i < e[k] ? i : last];
+            cd[k][j] = i < e[k] ? v : (uint32_t)kFarMove;
         }
     uint32_t nsel = 0;
 #pragma unroll
@@ -286,8 +293,10 @@ __device__ __forceinline__ void collide_big_body(const CollideArgs<R> &a) {
     }
 }
 
+// At least five waves per SIMD: the register budget that the LDS footprint
+// of a typical walled cell with weights also allows.
 template <typename R, bool VR, int D>
-__global__ __launch_bounds__(64) void k_collide(CollideArgs<R> a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_collide(CollideArgs<R> a) {
     extern __shared__ __align__(16) unsigned char smem[];
     collide_lds_body<R, VR, D, false>(a, smem, a.sched ? a.sched[blockIdx.x] : blockIdx.x);
 }

@@ -34,7 +34,8 @@ struct DevState {
     unsigned int error;             // first device error (positive code), 0 = none
     unsigned int big_count;         // cells queued for the global-memory collision kernel
     unsigned int far_count;         // entries of this step's far-mover list
-    unsigned int pad0[2];
+    unsigned int wall_count;        // entries of this step's wall list
+    unsigned int pad0;
     unsigned long long pad[3];
     unsigned long long diag[kDiagStripes * kDiagPerStripe];
     // work-unit queues of the persistent collision kernel, one 128-byte line
@@ -238,27 +239,100 @@ __device__ __forceinline__ uint8_t move_code(const Geo &g, int fx, int fy, int t
     return (uint8_t)((dx + 1) + 3 * (dy + 1));
 }
 
-// Streaming pass, in sequence order and in place: free flight, the new cell
-// counted, the move code written (far movers linked into their new cell's
-// list), and the velocity and weight stored back only for the particles that
-// met a wall.  Reads x, (y), cx, cy; writes x, (y) and one code byte.
-template <typename R, int D, bool VR>
+// Streaming, in sequence order and in place, in two kernels.  The first
+// takes every particle whose free end point x + c dt lies inside the closed
+// box (the rule the flight itself applies first): it writes the new position
+// and the move code and counts the new cell; P particles per thread, all
+// loads issued first.  Particles that would leave the box go to a list that
+// the second kernel flies exactly, wall conditions included, and finishes in
+// the same way.  Keeping the rare wall path out of the first kernel keeps
+// its register use, and so the number of loads in flight, at the level of a
+// plain streaming kernel.
+template <typename R, int D>
+__device__ __forceinline__ void finish_move(const Geo &g, int64_t p, int fx, int fy, R x, R y, uint8_t *code,
+                                            uint32_t *far_head, uint32_t *far_src, uint32_t *far_next,
+                                            DevState *st, uint32_t &cell) {
+    int tx, ty;
+    cell_coords(g, (double)x, D == 2 ? (double)y : 0.0, tx, ty);
+    cell = (uint32_t)ty * (uint32_t)g.nx + (uint32_t)tx;
+    const uint8_t mc = move_code(g, fx, fy, tx, ty);
+    code[p] = mc;
+    if (mc == kFarMove) {
+        const uint32_t k = atomicAdd(&st->far_count, 1u);
+        far_src[k] = (uint32_t)p;
+        far_next[k] = atomicExch(&far_head[cell], k);
+    }
+}
+
+template <typename R, int D, int P>
 __global__ __launch_bounds__(256) void k_stream_code(Geo g, Soa<R> s, int64_t n, uint8_t *code, uint32_t *count,
                                                      uint32_t *far_head, uint32_t *far_src, uint32_t *far_next,
-                                                     DevState *st) {
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool act = p < n;
+                                                     uint32_t *wall_list, DevState *st) {
+    const int64_t p0 = (int64_t)blockIdx.x * (256 * P) + threadIdx.x;
+    const R tau = (R)g.dt, Lx = (R)g.Lx, Ly = (R)g.Ly, zero = (R)0;
+    R x[P], y[P], cx[P], cy[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const int64_t p = p0 + 256 * k;
+        if (p < n) {
+            x[k] = s.x[p];
+            y[k] = D == 2 ? s.y[p] : zero;
+            cx[k] = s.cx[p];
+            cy[k] = D == 2 ? s.cy[p] : zero;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const int64_t p = p0 + 256 * k;
+        const bool act = p < n;
+        bool inside = false;
+        uint32_t cell = 0;
+        if (act) {
+            const R xe = x[k] + cx[k] * tau;
+            const R ye = D == 2 ? y[k] + cy[k] * tau : zero;
+            inside = xe >= zero && xe <= Lx && (D < 2 || (ye >= zero && ye <= Ly));
+            if (inside) {
+                int fx, fy;
+                cell_coords(g, (double)x[k], D == 2 ? (double)y[k] : 0.0, fx, fy);
+                s.x[p] = xe;
+                if (D == 2) s.y[p] = ye;
+                finish_move<R, D>(g, p, fx, fy, xe, ye, code, far_head, far_src, far_next, st, cell);
+            }
+        }
+        wave_aggregated_add(count, cell, act && inside);
+        // particles that meet a wall: one list slot each, one atomic per wave
+        const bool wall = act && !inside;
+        const unsigned long long bal = __ballot(wall);
+        if (bal) {
+            const int lane = lane_id();
+            const int leader = __ffsll((long long)bal) - 1;
+            uint32_t b0 = 0;
+            if (lane == leader) b0 = atomicAdd(&st->wall_count, (uint32_t)__popcll(bal));
+            b0 = (uint32_t)__shfl((int)b0, leader, 64);
+            if (wall) wall_list[b0 + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull))] = (uint32_t)p;
+        }
+    }
+}
+
+// The particles of the wall list: exact flight with wall conditions from
+// their unmodified state, then the same finish as in the first kernel.
+// Grid-stride over the list length of this step.
+template <typename R, int D, bool VR>
+__global__ __launch_bounds__(256) void k_stream_walls(Geo g, Soa<R> s, uint8_t *code, uint32_t *count,
+                                                      uint32_t *far_head, uint32_t *far_src, uint32_t *far_next,
+                                                      const uint32_t *wall_list, DevState *st) {
+    const uint32_t nw = st->wall_count;
     const uint32_t step = (uint32_t)st->step_next;
-    uint32_t cell = 0, hits = 0;
-    if (act) {
+    uint32_t hsum = 0;
+    for (uint32_t t = blockIdx.x * 256 + threadIdx.x; t < nw; t += gridDim.x * 256) {
+        const int64_t p = wall_list[t];
         R x = s.x[p], y = D == 2 ? s.y[p] : (R)0, cx = s.cx[p], cy = s.cy[p], cz = (R)0, w = (R)0;
-        int fx, fy, tx, ty;
+        int fx, fy;
         cell_coords(g, (double)x, D == 2 ? (double)y : 0.0, fx, fy);
+        uint32_t hits;
         bool diffuse;
         const int rc = fly<R, D, VR>(g, x, y, cx, cy, cz, w, s.id, s.w, p, step, hits, diffuse);
         if (rc) set_error(st, rc);
-        cell_coords(g, (double)x, D == 2 ? (double)y : 0.0, tx, ty);
-        cell = (uint32_t)ty * (uint32_t)g.nx + (uint32_t)tx;
         s.x[p] = x;
         if (D == 2) s.y[p] = y;
         if (hits) {
@@ -269,16 +343,12 @@ __global__ __launch_bounds__(256) void k_stream_code(Geo g, Soa<R> s, int64_t n,
                 if (VR) s.w[p] = w;
             }
         }
-        const uint8_t mc = move_code(g, fx, fy, tx, ty);
-        code[p] = mc;
-        if (mc == kFarMove) {
-            const uint32_t k = atomicAdd(&st->far_count, 1u);
-            far_src[k] = (uint32_t)p;
-            far_next[k] = atomicExch(&far_head[cell], k);
-        }
+        uint32_t cell;
+        finish_move<R, D>(g, p, fx, fy, x, y, code, far_head, far_src, far_next, st, cell);
+        atomicAdd(&count[cell], 1u);
+        hsum += hits;
     }
-    wave_aggregated_add(count, cell, act);
-    const uint32_t hsum = wave_sum_u32(hits);
+    hsum = wave_sum_u32(hsum);
     if (lane_id() == 0 && hsum) diag_add(st, kDiagWallHits, (unsigned long long)hsum);
 }
 
@@ -432,6 +502,7 @@ __global__ __launch_bounds__(256) void k_scan_lookback(uint32_t *count, uint32_t
                 st->n_samples = st->n_samples + 1;
                 st->big_count = 0;
                 st->far_count = 0;
+                st->wall_count = 0;
             }
         }
     }
