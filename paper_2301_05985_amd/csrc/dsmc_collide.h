@@ -169,18 +169,21 @@ __device__ double pair_diameter(const View &v, uint32_t N) {
 
 // Uniform direction (Marsaglia 1972) from blocks 1, 2, ... of candidate k's
 // PAIR stream; one attempt per block in double, two in float.  Lanes with
-// `pending` set iterate until success (at most 64 blocks, then (0,0,1)).
+// `pending` set iterate until success (at most 64 blocks, then (0,0,1)) and
+// receive the direction; the other lanes keep their values.
 template <typename R>
 __device__ __forceinline__ void direction(bool pending, uint32_t k, uint32_t cell, uint32_t step,
                                           uint32_t k0, uint32_t k1, R &nx, R &ny, R &nz) {
-    nx = (R)0; ny = (R)0; nz = (R)1;
+    if (!__ballot(pending)) return;
+    R tx = (R)0, ty = (R)0, tz = (R)1;
+    bool want = pending;
     for (uint32_t blk = 1; blk <= 64; ++blk) {
-        if (!__ballot(pending)) break;
-        if (pending) {
+        if (!__ballot(want)) break;
+        if (want) {
             const u32x4 r = draw(k, kTagPair, blk, cell, step, k0, k1);
 #pragma unroll
             for (int a = 0; a < (sizeof(R) == 4 ? 2 : 1); ++a) {
-                if (!pending) break;
+                if (!want) break;
                 R u, v;
                 if (sizeof(R) == 4) {
                     u = (R)2 * (R)unif24(r.v[2 * a]) - (R)1;
@@ -192,48 +195,59 @@ __device__ __forceinline__ void direction(bool pending, uint32_t k, uint32_t cel
                 const R s = u * u + v * v;
                 if (s < (R)1 && s > (R)0) {
                     const R h = sqrt((R)1 - s);
-                    nx = ((R)2 * u) * h;
-                    ny = ((R)2 * v) * h;
-                    nz = (R)1 - (R)2 * s;
-                    pending = false;
+                    tx = ((R)2 * u) * h;
+                    ty = ((R)2 * v) * h;
+                    tz = (R)1 - (R)2 * s;
+                    want = false;
                 }
             }
         }
+    }
+    if (pending) {
+        nx = tx;
+        ny = ty;
+        nz = tz;
     }
 }
 
 // The NTC candidate loop of one cell in conflict-free wave batches.
 //
-// Velocities: only accepted candidates write them, so a batch ends at the
-// first candidate that reads a particle an earlier accepted candidate of the
-// batch has changed.  Importance weights: every candidate writes them; the
-// committed candidates of a batch replay their weight updates in order, in
-// sub-batches that end at the first candidate touching a particle whose
-// weight an earlier pending candidate updates.  Both chains give exactly the
-// sequential result, and separating them keeps the (expensive) velocity
-// batches long when weights are carried.
+// The wave holds a window of 64 consecutive candidates, candidate k on lane
+// k mod 64.  Velocities: only accepted candidates write them, so the window
+// commits every candidate before the first one that reads a particle an
+// earlier accepted candidate of the window has changed (marks: atomic min of
+// the candidate index); committed lanes then take the candidate 64 later
+// while the others keep theirs, so each candidate's random draws (pair,
+// acceptance number, scattering direction -- functions of the candidate
+// index only) are computed once however often it waits.  Importance weights:
+// every candidate writes them; the committed candidates replay their weight
+// updates in candidate order, in sub-batches that end at the first candidate
+// touching a particle whose weight an earlier pending candidate updates.
+// Both chains give exactly the sequential result.
 template <typename R, bool VR, typename View>
 __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uint32_t cell,
                          uint32_t step, uint32_t k0, uint32_t k1, int molecule, uint32_t &n_acc,
                          uint32_t &n_over) {
-    const int lane = lane_id();
-    const uint32_t ulane = (uint32_t)lane;
+    const uint32_t ulane = (uint32_t)lane_id();
     const R gm = (R)gmax;
     const R gm2 = gm * gm;
     uint32_t kb = 0, acc = 0, over = 0;
+    uint32_t k = ulane;  // candidate held by this lane; k in [kb, kb + 64)
+    bool fresh = true;   // its draws are still to be computed
+    uint32_t i = 0, j = 0;
+    R U = (R)0, nx = (R)0, ny = (R)0, nz = (R)1;
     while (kb < M) {
-        const uint32_t B = min(64u, M - kb);
-        const bool act = ulane < B;
-        const uint32_t k = kb + ulane;
-        uint32_t i = 0, j = 0;
-        R U = (R)0;
-        if (act) {
+        const bool act = k < M;
+        const bool draw_now = act && fresh;
+        if (draw_now) {
             const u32x4 r = draw(k, kTagPair, 0, cell, step, k0, k1);
             i = scale_index(r.v[0], N);
             j = scale_index(r.v[1], N - 1);
             j += (j >= i) ? 1u : 0u;
             U = sizeof(R) == 4 ? (R)unif24(r.v[2]) : (R)unif53(r.v[2], r.v[3]);
         }
+        direction<R>(draw_now, k, cell, step, k0, k1, nx, ny, nz);
+        fresh = fresh && !act;
         R ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0, g2 = 0;
         bool accept = false;
         if (act) {
@@ -250,22 +264,23 @@ __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uin
         }
         const bool writer = act && accept;
         if (writer) {
-            atomicMin(v.own(i), ulane);
-            atomicMin(v.own(j), ulane);
+            atomicMin(v.own(i), k);
+            atomicMin(v.own(j), k);
         }
         __syncthreads();
-        const bool bad = act && (v.read_own(i) < ulane || v.read_own(j) < ulane);
-        const unsigned long long badm = __ballot(bad);
-        const uint32_t P = badm ? (uint32_t)(__ffsll((long long)badm) - 1) : B;
-        const bool commit = act && ulane < P;
+        const bool bad = act && (v.read_own(i) < k || v.read_own(j) < k);
+        // first candidate that must wait; the window ends there (or at its
+        // last candidate)
+        const uint32_t wend = M - kb > 64u ? kb + 64u : M;
+        uint32_t kend = wave_min_u32(bad ? k : 0xFFFFFFFFu);
+        kend = kend < wend ? kend : wend;
+        const bool commit = act && k < kend;
         __syncthreads();
         if (writer) {
             v.clear_own(i);
             v.clear_own(j);
         }
         const bool coll = commit && accept;
-        R nx, ny, nz;
-        direction<R>(coll, k, cell, step, k0, k1, nx, ny, nz);
         if (coll) {
             const R g = sqrt(g2);
             const R hg = (R)0.5 * g;
@@ -282,24 +297,24 @@ __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uin
             // W_i W_j; rejected -> W_i (1 - p W_j) / (1 - p), p = g / g_max
             double p = 1.0;
             if (commit && !accept && molecule != DSMC_MAXWELL) p = sqrt((double)g2) / gmax;
-            uint32_t q0 = 0;
+            uint32_t q0 = kb;
             __syncthreads();
-            while (q0 < P) {
-                const bool pend = commit && ulane >= q0;
+            while (q0 < kend) {
+                const bool pend = commit && k >= q0;
                 if (pend) {
-                    atomicMin(v.own(i), ulane);
-                    atomicMin(v.own(j), ulane);
+                    atomicMin(v.own(i), k);
+                    atomicMin(v.own(j), k);
                 }
                 __syncthreads();
-                const bool wbad = pend && (v.read_own(i) < ulane || v.read_own(j) < ulane);
-                const unsigned long long wm = __ballot(wbad);
-                const uint32_t Q = wm ? (uint32_t)(__ffsll((long long)wm) - 1) : P;
+                const bool wbad = pend && (v.read_own(i) < k || v.read_own(j) < k);
+                uint32_t Q = wave_min_u32(wbad ? k : 0xFFFFFFFFu);
+                Q = Q < kend ? Q : kend;
                 __syncthreads();
                 if (pend) {
                     v.clear_own(i);
                     v.clear_own(j);
                 }
-                if (pend && ulane < Q) {
+                if (pend && k < Q) {
                     const double wa = (double)v.getw(i), wb = (double)v.getw(j);
                     if (accept) {
                         const double ab = wa * wb;
@@ -318,7 +333,12 @@ __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uin
             }
         }
         __syncthreads();
-        kb += P;
+        // committed lanes move on to the candidate 64 later
+        if (commit) {
+            k += 64;
+            fresh = true;
+        }
+        kb = kend;
     }
     n_acc = acc;
     n_over = wave_sum_u32(over);

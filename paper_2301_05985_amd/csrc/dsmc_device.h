@@ -185,9 +185,13 @@ __device__ __forceinline__ double dpp_f64(double old, double v, int ctrl) {
     const uint32_t hi = dpp_u32((uint32_t)(o >> 32), (uint32_t)(x >> 32), ctrl, 0);
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
+__device__ __forceinline__ uint32_t dpp_any(uint32_t old, uint32_t v, int ctrl) { return dpp_u32(old, v, ctrl, 0); }
 __device__ __forceinline__ float dpp_any(float old, float v, int ctrl) { return dpp_f32(old, v, ctrl); }
 __device__ __forceinline__ double dpp_any(double old, double v, int ctrl) { return dpp_f64(old, v, ctrl); }
 
+__device__ __forceinline__ uint32_t read_lane63(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
 __device__ __forceinline__ float read_lane63(float v) {
     return __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)__float_as_uint(v), 63));
 }
@@ -207,6 +211,11 @@ __device__ __forceinline__ T wave_reduce_dpp(T v, T id, Op op) {
     v = op(v, dpp_any(id, v, 0x142));
     v = op(v, dpp_any(id, v, 0x143));
     return read_lane63(v);
+}
+
+// Wave minimum of an unsigned value (uniform result).
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+    return wave_reduce_dpp(v, 0xFFFFFFFFu, [](uint32_t a, uint32_t b) { return a < b ? a : b; });
 }
 
 template <typename T>
