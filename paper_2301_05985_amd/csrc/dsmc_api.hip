@@ -269,7 +269,7 @@ void launch_collide(dsmc_ctx *c, Launcher &L, int src) {
 template <typename R, int D, bool VR>
 void launch_stream(dsmc_ctx *c, Launcher &L, int src) {
     const int dst = src ^ 1;
-    constexpr int P = 2;  // particles per thread of the streaming kernel
+    constexpr int P = 4;  // particles per thread of the streaming kernel
     const unsigned grid = (unsigned)((c->n + 256 * P - 1) / (256 * P));
     if (c->n > 0) {
         const Soa<R> s = soa_of<R>(c->buf[src]);

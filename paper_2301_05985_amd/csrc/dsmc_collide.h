@@ -212,18 +212,76 @@ __device__ __forceinline__ void direction(bool pending, uint32_t k, uint32_t cel
 
 // The NTC candidate loop of one cell in conflict-free wave batches.
 //
-// The wave holds a window of 64 consecutive candidates, candidate k on lane
-// k mod 64.  Velocities: only accepted candidates write them, so the window
-// commits every candidate before the first one that reads a particle an
-// earlier accepted candidate of the window has changed (marks: atomic min of
-// the candidate index); committed lanes then take the candidate 64 later
-// while the others keep theirs, so each candidate's random draws (pair,
-// acceptance number, scattering direction -- functions of the candidate
-// index only) are computed once however often it waits.  Importance weights:
-// every candidate writes them; the committed candidates replay their weight
-// updates in candidate order, in sub-batches that end at the first candidate
+// The wave holds a window of up to 64 consecutive candidates, candidate k on
+// lane k mod 64.  Velocities: only accepted candidates write them, so the
+// window commits every candidate before the first one that reads a particle
+// an earlier accepted candidate of the window has changed (marks: atomic min
+// of the candidate index).  A candidate's random draws (pair, acceptance
+// number, scattering direction) are functions of its index only and are
+// computed once, however often it waits.
+//
+// Without weights, committed lanes take the candidate 64 later at once (the
+// window rolls).  With importance weights every candidate writes the weights
+// of its pair, and the weights never feed back into the velocity decisions:
+// the window stays inside one generation of 64 candidates (64 g .. 64 g + 63)
+// until all of them are committed, then the generation's weight updates are
+// replayed in candidate order, in sub-batches that end at the first candidate
 // touching a particle whose weight an earlier pending candidate updates.
-// Both chains give exactly the sequential result.
+// Both give exactly the sequential result.
+
+// Velocity window over the live candidates (k in [kb, wend)); returns the
+// first uncommitted candidate and sets `commit` and `accept` per lane.
+template <typename R, typename View>
+__device__ __forceinline__ uint32_t velocity_window(const View &v, bool live, uint32_t k, uint32_t kb, uint32_t wend,
+                                                    uint32_t i, uint32_t j, R U, R nx, R ny, R nz, R gm, R gm2,
+                                                    int molecule, bool &commit, bool &accept, R &g2_out,
+                                                    uint32_t &acc, uint32_t &over) {
+    R ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0, g2 = 0;
+    accept = false;
+    if (live) {
+        v.get(i, ax, ay, az);
+        v.get(j, bx, by, bz);
+        const R dx = ax - bx, dy = ay - by, dz = az - bz;
+        g2 = (dx * dx + dy * dy) + dz * dz;
+        if (molecule == DSMC_MAXWELL) {
+            accept = true;
+        } else {
+            const R a = U * gm;
+            accept = (a * a) < g2;
+        }
+    }
+    const bool writer = live && accept;
+    if (writer) {
+        atomicMin(v.own(i), k);
+        atomicMin(v.own(j), k);
+    }
+    __syncthreads();
+    const bool bad = live && (v.read_own(i) < k || v.read_own(j) < k);
+    // first candidate that must wait; the window ends there (or at wend)
+    uint32_t kend = wave_min_u32(bad ? k : 0xFFFFFFFFu);
+    kend = kend < wend ? kend : wend;
+    commit = live && k < kend;
+    __syncthreads();
+    if (writer) {
+        v.clear_own(i);
+        v.clear_own(j);
+    }
+    const bool coll = commit && accept;
+    if (coll) {
+        const R g = sqrt(g2);
+        const R hg = (R)0.5 * g;
+        const R mx = (R)0.5 * (ax + bx), my = (R)0.5 * (ay + by), mz = (R)0.5 * (az + bz);
+        const R tx = hg * nx, ty = hg * ny, tz = hg * nz;
+        v.put(i, mx + tx, my + ty, mz + tz);
+        v.put(j, mx - tx, my - ty, mz - tz);
+    }
+    if (molecule != DSMC_MAXWELL && commit && g2 > gm2) over++;
+    acc += (uint32_t)__popcll(__ballot(coll));
+    g2_out = g2;
+    __syncthreads();
+    return kend;
+}
+
 template <typename R, bool VR, typename View>
 __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uint32_t cell,
                          uint32_t step, uint32_t k0, uint32_t k1, int molecule, uint32_t &n_acc,
@@ -234,8 +292,12 @@ __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uin
     uint32_t kb = 0, acc = 0, over = 0;
     uint32_t k = ulane;  // candidate held by this lane; k in [kb, kb + 64)
     bool fresh = true;   // its draws are still to be computed
+    bool done = false;   // committed, waiting for the end of its generation (weights)
+    bool acc_k = false;  // committed candidate's acceptance (weights)
+    double p = 1.0;      // and its g / g_max (weights, rejected candidates)
     uint32_t i = 0, j = 0;
     R U = (R)0, nx = (R)0, ny = (R)0, nz = (R)1;
+    uint32_t g0 = 0;     // first candidate of the current generation (weights)
     while (kb < M) {
         const bool act = k < M;
         const bool draw_now = act && fresh;
@@ -248,97 +310,71 @@ __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uin
         }
         direction<R>(draw_now, k, cell, step, k0, k1, nx, ny, nz);
         fresh = fresh && !act;
-        R ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0, g2 = 0;
-        bool accept = false;
-        if (act) {
-            v.get(i, ax, ay, az);
-            v.get(j, bx, by, bz);
-            const R dx = ax - bx, dy = ay - by, dz = az - bz;
-            g2 = (dx * dx + dy * dy) + dz * dz;
-            if (molecule == DSMC_MAXWELL) {
-                accept = true;
-            } else {
-                const R a = U * gm;
-                accept = (a * a) < g2;
+        const uint32_t gend = M - g0 > 64u ? g0 + 64u : M;
+        const uint32_t wend = VR ? gend : (M - kb > 64u ? kb + 64u : M);
+        bool commit, accept;
+        R g2;
+        const uint32_t kend = velocity_window<R>(v, act && !done, k, kb, wend, i, j, U, nx, ny, nz, gm, gm2,
+                                                 molecule, commit, accept, g2, acc, over);
+        kb = kend;
+        if (!VR) {
+            // committed lanes move on to the candidate 64 later
+            if (commit) {
+                k += 64;
+                fresh = true;
             }
+            continue;
         }
-        const bool writer = act && accept;
-        if (writer) {
-            atomicMin(v.own(i), k);
-            atomicMin(v.own(j), k);
+        if (commit) {
+            done = true;
+            acc_k = accept;
+            p = (!accept && molecule != DSMC_MAXWELL) ? sqrt((double)g2) / gmax : 1.0;
         }
-        __syncthreads();
-        const bool bad = act && (v.read_own(i) < k || v.read_own(j) < k);
-        // first candidate that must wait; the window ends there (or at its
-        // last candidate)
-        const uint32_t wend = M - kb > 64u ? kb + 64u : M;
-        uint32_t kend = wave_min_u32(bad ? k : 0xFFFFFFFFu);
-        kend = kend < wend ? kend : wend;
-        const bool commit = act && k < kend;
-        __syncthreads();
-        if (writer) {
-            v.clear_own(i);
-            v.clear_own(j);
-        }
-        const bool coll = commit && accept;
-        if (coll) {
-            const R g = sqrt(g2);
-            const R hg = (R)0.5 * g;
-            const R mx = (R)0.5 * (ax + bx), my = (R)0.5 * (ay + by), mz = (R)0.5 * (az + bz);
-            const R tx = hg * nx, ty = hg * ny, tz = hg * nz;
-            v.put(i, mx + tx, my + ty, mz + tz);
-            v.put(j, mx - tx, my - ty, mz - tz);
-        }
-        if (molecule != DSMC_MAXWELL && commit && g2 > gm2) over++;
-        acc += (uint32_t)__popcll(__ballot(coll));
-        if (VR) {
-            // importance weights (Al-Mohssen & Hadjiconstantinou 2010) of the
-            // committed candidates, in candidate order: accepted -> both
-            // W_i W_j; rejected -> W_i (1 - p W_j) / (1 - p), p = g / g_max
-            double p = 1.0;
-            if (commit && !accept && molecule != DSMC_MAXWELL) p = sqrt((double)g2) / gmax;
-            uint32_t q0 = kb;
+        if (kb < gend) continue;
+        // generation complete: importance weights (Al-Mohssen & Hadjiconstantinou
+        // 2010) of its candidates, in candidate order: accepted -> both W_i W_j;
+        // rejected -> W_i (1 - p W_j) / (1 - p), p = g / g_max
+        const bool mine = act && k < gend;  // this lane's candidate belongs to the generation
+        uint32_t q0 = g0;
+        while (q0 < gend) {
+            const bool pend = mine && k >= q0;
+            if (pend) {
+                atomicMin(v.own(i), k);
+                atomicMin(v.own(j), k);
+            }
             __syncthreads();
-            while (q0 < kend) {
-                const bool pend = commit && k >= q0;
-                if (pend) {
-                    atomicMin(v.own(i), k);
-                    atomicMin(v.own(j), k);
-                }
-                __syncthreads();
-                const bool wbad = pend && (v.read_own(i) < k || v.read_own(j) < k);
-                uint32_t Q = wave_min_u32(wbad ? k : 0xFFFFFFFFu);
-                Q = Q < kend ? Q : kend;
-                __syncthreads();
-                if (pend) {
-                    v.clear_own(i);
-                    v.clear_own(j);
-                }
-                if (pend && k < Q) {
-                    const double wa = (double)v.getw(i), wb = (double)v.getw(j);
-                    if (accept) {
-                        const double ab = wa * wb;
-                        v.putw(i, (R)ab);
-                        v.putw(j, (R)ab);
-                    } else {
-                        const double q = 1.0 - p;
-                        if (q > 0.0) {
-                            v.putw(i, (R)((wa * (1.0 - p * wb)) / q));
-                            v.putw(j, (R)((wb * (1.0 - p * wa)) / q));
-                        }
+            const bool wbad = pend && (v.read_own(i) < k || v.read_own(j) < k);
+            uint32_t Q = wave_min_u32(wbad ? k : 0xFFFFFFFFu);
+            Q = Q < gend ? Q : gend;
+            __syncthreads();
+            if (pend) {
+                v.clear_own(i);
+                v.clear_own(j);
+            }
+            if (pend && k < Q) {
+                const double wa = (double)v.getw(i), wb = (double)v.getw(j);
+                if (acc_k) {
+                    const double ab = wa * wb;
+                    v.putw(i, (R)ab);
+                    v.putw(j, (R)ab);
+                } else {
+                    const double q = 1.0 - p;
+                    if (q > 0.0) {
+                        v.putw(i, (R)((wa * (1.0 - p * wb)) / q));
+                        v.putw(j, (R)((wb * (1.0 - p * wa)) / q));
                     }
                 }
-                __syncthreads();
-                q0 = Q;
             }
+            __syncthreads();
+            q0 = Q;
         }
-        __syncthreads();
-        // committed lanes move on to the candidate 64 later
-        if (commit) {
+        // next generation
+        if (mine) {
             k += 64;
             fresh = true;
+            done = false;
         }
-        kb = kend;
+        g0 = gend;
     }
     n_acc = acc;
     n_over = wave_sum_u32(over);
