@@ -23,7 +23,7 @@ NSUM = 26
 MLP_NPARAM = 64 * 6 + 64 + 64 * 64 + 64 + 64 + 1  # 4673
 
 WALL_DIFFUSE, WALL_SPECULAR, WALL_PERIODIC = 0, 1, 2
-HARD_SPHERE, MAXWELL = 0, 1
+HARD_SPHERE, MAXWELL, VHS = 0, 1, 2
 
 
 def build(force=False):
@@ -64,6 +64,7 @@ class OrcCfg(ctypes.Structure):
         ("cell_ids", ctypes.c_void_p),
         ("only_cells", ctypes.c_void_p),
         ("n_only", ctypes.c_int64),
+        ("omega", ctypes.c_double),
     ]
 
 
@@ -125,6 +126,8 @@ def lib():
                 g.argtypes = [P, ctypes.c_double, ctypes.c_double]
             else:
                 g.argtypes = [P, ctypes.c_float, ctypes.c_float]
+        _lib.orc_vhs_pow.restype = ctypes.c_double
+        _lib.orc_vhs_pow.argtypes = [ctypes.c_double, ctypes.c_double]
         _lib.orc_philox4x32_10.restype = None
         _lib.orc_philox4x32_10.argtypes = [P, P, P]
     return _lib
@@ -172,6 +175,7 @@ def make_cfg(p):
             c.wall_u[3 * k + d] = p.get("wall_u", ((0, 0, 0),) * 4)[k][d]
     c.key[0], c.key[1] = seed_key(p.get("seed", 0))
     c.mlp_delta = p.get("mlp_delta", 0.0)
+    c.omega = float(p.get("omega", 0.5))
     return c
 
 
@@ -387,3 +391,8 @@ def estimators(sums, n_samples, FN, V, vr=False, vr_n0=None, vr_T0=None):
         q = 0.5 * n[:, None] * (m3 - 2.0 * np.einsum("ne,nde->nd", u, full)
                                 - u * c2m[:, None] + 2.0 * u * uu[:, None])
     return {"n": n, "u": u, "T": T, "P": P, "q": q}
+
+
+def vhs_pow(x, a):
+    """x^a as the VHS acceptance computes it (fixed operation sequence)."""
+    return lib().orc_vhs_pow(float(x), float(a))

@@ -123,6 +123,7 @@ typedef struct {
     const int64_t *cell_ids;            /* dims == 0: random-stream id of each instance, or NULL (= index) */
     const int64_t *only_cells;          /* if not NULL: collide and sample only these cells ... */
     int64_t n_only;                     /* ... (sorted ascending, n_only of them) */
+    double omega;                       /* molecule 2 (VHS): viscosity index in [0.5, 1] */
 } orc_cfg;
 
 typedef struct {
@@ -552,6 +553,53 @@ static int cmp_by_id(const void *a, const void *b)
     return ia < ib ? -1 : (ia > ib ? 1 : 0);
 }
 
+/* ------------------------------------------------------------ VHS power */
+/* x^a for x >= 0, 0 <= a <= 1, as 2^(a log2 x), in a fixed sequence of IEEE
+ * double operations (no library transcendental), so that a decision taken
+ * on it is identical wherever the same sequence runs.
+ *   log2: x = m 2^e with m in [sqrt(1/2), sqrt(2)); ln m = 2 atanh(s),
+ *         s = (m - 1)/(m + 1), |s| < 0.1716, by its odd series through s^27
+ *         (Horner in s^2); log2 x = e + ln m / ln 2.
+ *   exp2: y = n + f, n = floor(y), f in [0, 1); 2^f = e^(f ln 2) by its
+ *         Taylor series through degree 18 (Horner); scaled by 2^n exactly. */
+static const double VHS_LN2 = 0.69314718055994530942;
+static const double VHS_INV_LN2 = 1.44269504088896340736;
+static double vhs_log2(double x)
+{
+    int e;
+    double m = frexp(x, &e); /* m in [0.5, 1) */
+    if (m < 0.70710678118654752440) {
+        m = m * 2.0;
+        e = e - 1;
+    }
+    double sv = (m - 1.0) / (m + 1.0);
+    double s2 = sv * sv;
+    double t = 1.0 / 27.0;
+    for (int k = 25; k >= 1; k -= 2) t = t * s2 + 1.0 / (double)k;
+    double lnm = (2.0 * sv) * t;
+    return (double)e + lnm * VHS_INV_LN2;
+}
+static double vhs_exp2(double y)
+{
+    double n = floor(y);
+    double f = (y - n) * VHS_LN2;
+    double t = 1.0;
+    for (int k = 18; k >= 1; --k) t = 1.0 + (f * t) / (double)k;
+    return ldexp(t, (int)n);
+}
+static double vhs_pow(double x, double a)
+{
+    if (a == 0.0) return 1.0;
+    if (!(x > 0.0)) return 0.0;
+    if (x == 1.0) return 1.0;
+    double y = a * vhs_log2(x);
+    if (y < -1000.0) return 0.0;
+    return vhs_exp2(y);
+}
+#ifdef ORC_PRIMARY
+double orc_vhs_pow(double x, double a) { return vhs_pow(x, a); }
+#endif
+
 /* NTC collisions in one cell (Bird 1994), with the cell's particles listed in
  * canonical order (list[0..n-1]).  Candidate count
  * M = floor(1/2 N (N-1) F_N sigma g_max dt / V + U0); candidate k draws the
@@ -586,6 +634,10 @@ static int collide_cell(const orc_cfg *cfg, soa_t *s, const int64_t *list, int64
     double Mreal;
     if (cfg->molecule == 1)
         Mreal = (((((0.5 * (double)n) * (double)(n - 1)) * cfg->FN) * cfg->sigma) * cfg->dt) / V;
+    else if (cfg->molecule == 2)
+        /* VHS: (sigma_T g)_max = sigma g_max^(2 - 2 omega) */
+        Mreal = ((((((0.5 * (double)n) * (double)(n - 1)) * cfg->FN) * cfg->sigma) *
+                  vhs_pow(gmax * gmax, 1.0 - cfg->omega)) * cfg->dt) / V;
     else
         Mreal = ((((((0.5 * (double)n) * (double)(n - 1)) * cfg->FN) * cfg->sigma) * gmax) * cfg->dt) / V;
     uint32_t r[4];
@@ -612,6 +664,13 @@ static int collide_cell(const orc_cfg *cfg, soa_t *s, const int64_t *list, int64
         if (cfg->molecule == 1) {
             accept = 1;
             p = 1.0;
+        } else if (cfg->molecule == 2) {
+            /* VHS: accept with probability (g / g_max)^(2 - 2 omega),
+             * i.e. iff U < (g^2 / g_max^2)^(1 - omega), in double */
+            double U = IS_F32 ? (double)u24(r[2]) : u53(r[2], r[3]);
+            p = vhs_pow((double)g2 / (gmax * gmax), 1.0 - cfg->omega);
+            accept = U < p;
+            if (g2 > gm * gm) diag->overshoot++;
         } else {
             REAL U = IS_F32 ? (REAL)u24(r[2]) : (REAL)u53(r[2], r[3]);
             REAL a = U * gm;

@@ -485,3 +485,88 @@ def test_particle_sequence_is_a_stable_grouping_by_cell(kind):
         want = prev[np.argsort(c_new[prev], kind="stable")]
         assert np.array_equal(o.layout, want)
     assert moved > 20
+
+
+# ------------------------------------------------------ VHS molecules
+def test_vhs_power_matches_the_power_function():
+    # the fixed-sequence x^a of the VHS acceptance against numpy's power, and
+    # its exact special values
+    rng = np.random.default_rng(21)
+    x = np.concatenate([rng.random(3000), 10.0 ** rng.uniform(-300, 0, 1000), [1e-308, 0.5, 0.999999, 1.2]])
+    a = rng.uniform(0.0, 1.0, len(x))
+    got = np.array([oracle.vhs_pow(u, v) for u, v in zip(x, a)])
+    want = np.power(x, a)
+    # 2^(a log2 x): the exponent's own rounding (~ulp(|y|)) is the error floor
+    y = np.abs(a * np.log2(x))
+    assert (np.abs(got - want) / want / (8.0 + y)).max() < 2e-16
+    for u in (0.3, 1e-10, 0.999):
+        tol = 2e-16 * (8.0 + abs(math.log2(u)))
+        assert oracle.vhs_pow(u, 0.0) == 1.0
+        assert abs(oracle.vhs_pow(u, 1.0) / u - 1) < tol
+        assert abs(oracle.vhs_pow(u, 0.5) / math.sqrt(u) - 1) < tol
+    for v in (0.0, 0.19, 0.5, 1.0):
+        assert oracle.vhs_pow(1.0, v) == 1.0
+    assert oracle.vhs_pow(0.0, 0.3) == 0.0
+
+
+@pytest.mark.parametrize("real", ["f64", "f32"])
+def test_vhs_at_omega_one_is_maxwell_molecules_bit_for_bit(real):
+    # omega = 1: sigma_T g is constant, (g / g_max)^0 = 1 accepts every
+    # candidate and the majorant factor is 1, exactly the Maxwell-molecule run
+    dtype = np.float64 if real == "f64" else np.float32
+    p, parts = W.bkw(N=400, n_inst=6, dt=0.05, seed=3, real=real)
+    a = oracle.Oracle(p, parts, dtype)
+    b = oracle.Oracle(dict(p, molecule=W.VHS, omega=1.0), parts, dtype)
+    a.run(12)
+    b.run(12)
+    for k in ("cx", "cy", "cz"):
+        assert np.array_equal(getattr(a, k), getattr(b, k)), k
+    assert np.array_equal(a.counters, b.counters)
+
+
+def test_vhs_acceptance_rate_matches_exact_pair_mean():
+    # VHS (omega = 0.81, argon-like): a candidate is accepted with probability
+    # (g / g_max)^(2 - 2 omega), so E[accepted] = E[M] mean_pairs(g^(2-2w)) /
+    # g_max^(2-2w), with M_real = 1/2 N (N-1) sigma g_max^(2-2w) dt
+    N, n_inst, dt, om = 120, 3000, 0.004, 0.81
+    rng = np.random.default_rng(13)
+    c = rng.standard_normal((3, N))
+    cc = np.tile(c, n_inst)
+    off = np.arange(n_inst + 1, dtype=np.int64) * N
+    p = dict(dims=0, n_cells=(n_inst, 1), dt=dt, sigma=1.0, FN=1.0, molecule=W.VHS, omega=om, seed=6,
+             inst_offset=off, cell_volume=np.ones(n_inst))
+    o = oracle.Oracle(p, dict(cx=cc[0], cy=cc[1], cz=cc[2]))
+    o.run(1)
+    d = c[:, :, None] - c[:, None, :]
+    g = np.sqrt((d ** 2).sum(0))
+    e = 2.0 - 2.0 * om
+    gbar = (g[~np.eye(N, dtype=bool)] ** e).mean()
+    gmax = oracle.exact_bound(*c)
+    Mreal = 0.5 * N * (N - 1) * dt * gmax ** e
+    cand = o.counters[:, 0].astype(float)
+    acc = o.counters[:, 1].astype(float)
+    assert abs(cand.mean() - Mreal) < 5 * 0.5 / math.sqrt(n_inst)
+    pacc = gbar / gmax ** e
+    se = math.sqrt((Mreal * pacc * (1 - pacc) + 0.25 * pacc * pacc) / n_inst)
+    assert abs(acc.mean() - Mreal * pacc) < 5 * se
+    # a softer cross-section accepts more often than hard spheres would
+    assert pacc > (g[~np.eye(N, dtype=bool)]).mean() / gmax
+
+
+def test_vhs_relaxes_to_the_maxwellian_and_conserves():
+    p, parts = W.relaxation(N=6000, steps=300)
+    p = dict(p, molecule=W.VHS, omega=0.81)
+    o = oracle.Oracle(p, parts)
+    c0 = np.stack([o.cx, o.cy, o.cz])
+    P0, E0 = c0.sum(1), (c0 ** 2).sum()
+    o.run(300)
+    c = np.stack([o.cx, o.cy, o.cz])
+    assert np.abs(c.sum(1) - P0).max() < 1e-9 * len(o.cx)
+    assert abs((c ** 2).sum() / E0 - 1) < 1e-12
+    u = c.mean(1)
+    cc = c - u[:, None]
+    T = (cc ** 2).sum(0).mean() / 3
+    kx = (cc[0] ** 4).mean() / (cc[0] ** 2).mean() ** 2
+    assert abs(kx - 3.0) < 0.25  # started at 2.04 (bimodal)
+    for d in range(3):
+        assert stats.kstest(cc[d] / math.sqrt(T), "norm").pvalue > 1e-3
