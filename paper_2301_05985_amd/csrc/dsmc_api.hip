@@ -54,7 +54,9 @@ dsmc_status validate(const dsmc_config *c) {
     if (c->abi_version != DSMC_ABI_VERSION) return DSMC_EABI;
     if (c->dims < 0 || c->dims > 2) return DSMC_EINVAL;
     if (c->real_bytes != 4 && c->real_bytes != 8) return DSMC_EINVAL;
-    if (c->molecule != DSMC_HARD_SPHERE && c->molecule != DSMC_MAXWELL) return DSMC_EINVAL;
+    if (c->molecule != DSMC_HARD_SPHERE && c->molecule != DSMC_MAXWELL && c->molecule != DSMC_VHS)
+        return DSMC_EINVAL;
+    if (c->molecule == DSMC_VHS && !(c->omega >= 0.5 && c->omega <= 1.0)) return DSMC_EINVAL;
     if (c->majorant < DSMC_MAJORANT_EXACT || c->majorant > DSMC_MAJORANT_DIAMETER) return DSMC_EINVAL;
     if (c->n_cells[0] < 1 || (c->dims == 2 && c->n_cells[1] < 1)) return DSMC_EINVAL;
     if (n_cells_of(*c) > (int64_t)1 << 30) return DSMC_EINVAL;
@@ -206,6 +208,7 @@ CollideArgs<R> collide_args(dsmc_ctx *c, int src, int dst) {
     a.sigma = c->cfg.sigma;
     a.FN = c->cfg.FN;
     a.molecule = c->cfg.molecule;
+    a.omega1 = 1.0 - c->cfg.omega;
     a.cap = c->cap;
     a.majorant = c->cfg.majorant;
     a.k0 = (uint32_t)(c->cfg.seed & 0xFFFFFFFFull);
@@ -241,7 +244,7 @@ struct Launcher {
 template <typename R, bool VR, int D>
 void launch_collide(dsmc_ctx *c, Launcher &L, int src) {
     CollideArgs<R> a = collide_args<R>(c, src, D == 0 ? src : src ^ 1);
-    const bool learned = a.mlp != nullptr && c->cfg.molecule == DSMC_HARD_SPHERE;
+    const bool learned = a.mlp != nullptr && c->cfg.molecule != DSMC_MAXWELL;
     L.mark(learned ? "collide_learned" : "collide");
     if (D == 0 && c->cfg.schedule == DSMC_SCHEDULE_PERSISTENT) {
         if (learned)

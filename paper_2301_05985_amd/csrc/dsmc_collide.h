@@ -39,6 +39,7 @@ struct CollideArgs {
     int nx, ny, periodic_x, periodic_y;
     const double *volume;          // per-cell volume, or null for Vuni
     double Vuni, dt, sigma, FN;
+    double omega1;                 // VHS: 1 - omega
     int molecule, cap, majorant;
     uint32_t k0, k1;
     double *sums;                  // [ncell][26] running FP64 sums
@@ -234,10 +235,12 @@ __device__ __forceinline__ void direction(bool pending, uint32_t k, uint32_t cel
 template <typename R, typename View>
 __device__ __forceinline__ uint32_t velocity_window(const View &v, bool live, uint32_t k, uint32_t kb, uint32_t wend,
                                                     uint32_t i, uint32_t j, R U, R nx, R ny, R nz, R gm, R gm2,
-                                                    int molecule, bool &commit, bool &accept, R &g2_out,
-                                                    uint32_t &acc, uint32_t &over) {
+                                                    double gmax2, double om1, int molecule, bool &commit,
+                                                    bool &accept, R &g2_out, double &pacc, uint32_t &acc,
+                                                    uint32_t &over) {
     R ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0, g2 = 0;
     accept = false;
+    pacc = 1.0;
     if (live) {
         v.get(i, ax, ay, az);
         v.get(j, bx, by, bz);
@@ -245,6 +248,10 @@ __device__ __forceinline__ uint32_t velocity_window(const View &v, bool live, ui
         g2 = (dx * dx + dy * dy) + dz * dz;
         if (molecule == DSMC_MAXWELL) {
             accept = true;
+        } else if (molecule == DSMC_VHS) {
+            // accept with probability (g / g_max)^(2 - 2 omega), in double
+            pacc = vhs_pow((double)g2 / gmax2, om1);
+            accept = (double)U < pacc;
         } else {
             const R a = U * gm;
             accept = (a * a) < g2;
@@ -284,11 +291,12 @@ __device__ __forceinline__ uint32_t velocity_window(const View &v, bool live, ui
 
 template <typename R, bool VR, typename View>
 __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uint32_t cell,
-                         uint32_t step, uint32_t k0, uint32_t k1, int molecule, uint32_t &n_acc,
+                         uint32_t step, uint32_t k0, uint32_t k1, int molecule, double om1, uint32_t &n_acc,
                          uint32_t &n_over) {
     const uint32_t ulane = (uint32_t)lane_id();
     const R gm = (R)gmax;
     const R gm2 = gm * gm;
+    const double gmax2 = gmax * gmax;
     uint32_t kb = 0, acc = 0, over = 0;
     uint32_t k = ulane;  // candidate held by this lane; k in [kb, kb + 64)
     bool fresh = true;   // its draws are still to be computed
@@ -314,8 +322,9 @@ __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uin
         const uint32_t wend = VR ? gend : (M - kb > 64u ? kb + 64u : M);
         bool commit, accept;
         R g2;
+        double pacc;
         const uint32_t kend = velocity_window<R>(v, act && !done, k, kb, wend, i, j, U, nx, ny, nz, gm, gm2,
-                                                 molecule, commit, accept, g2, acc, over);
+                                                 gmax2, om1, molecule, commit, accept, g2, pacc, acc, over);
         kb = kend;
         if (!VR) {
             // committed lanes move on to the candidate 64 later
@@ -328,7 +337,9 @@ __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uin
         if (commit) {
             done = true;
             acc_k = accept;
-            p = (!accept && molecule != DSMC_MAXWELL) ? sqrt((double)g2) / gmax : 1.0;
+            p = (!accept && molecule != DSMC_MAXWELL)
+                    ? (molecule == DSMC_VHS ? pacc : sqrt((double)g2) / gmax)
+                    : 1.0;
         }
         if (kb < gend) continue;
         // generation complete: importance weights (Al-Mohssen & Hadjiconstantinou
@@ -444,6 +455,18 @@ __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cel
     }
 }
 
+// Real-valued NTC candidate count 1/2 N (N-1) F_N (sigma g)_max dt / V, in
+// this left-to-right order: (sigma g)_max = sigma g_max (hard spheres),
+// sigma (Maxwell molecules, sigma g constant) or sigma g_max^(2 - 2 omega)
+// (variable hard spheres).
+template <typename R>
+__device__ __forceinline__ double candidates_real(const CollideArgs<R> &a, double Nd, double gmax, double V) {
+    if (a.molecule == DSMC_MAXWELL) return (((((0.5 * Nd) * (Nd - 1.0)) * a.FN) * a.sigma) * a.dt) / V;
+    if (a.molecule == DSMC_VHS)
+        return ((((((0.5 * Nd) * (Nd - 1.0)) * a.FN) * a.sigma) * vhs_pow(gmax * gmax, a.omega1)) * a.dt) / V;
+    return ((((((0.5 * Nd) * (Nd - 1.0)) * a.FN) * a.sigma) * gmax) * a.dt) / V;
+}
+
 // Majorant, candidate count, NTC loop and sampling of one cell; the view
 // already holds the cell in canonical order.
 template <typename R, bool VR, typename View>
@@ -458,11 +481,7 @@ __device__ void process_cell(const CollideArgs<R> &a, const View &v, uint32_t ce
             gmax = a.majorant == DSMC_MAJORANT_DIAMETER ? pair_diameter<R>(v, N) : exact_bound<R>(v, N, rt);
         const double V = a.volume ? a.volume[cell] : a.Vuni;
         const double Nd = (double)N;
-        double Mreal;
-        if (a.molecule == DSMC_MAXWELL)
-            Mreal = (((((0.5 * Nd) * (Nd - 1.0)) * a.FN) * a.sigma) * a.dt) / V;
-        else
-            Mreal = ((((((0.5 * Nd) * (Nd - 1.0)) * a.FN) * a.sigma) * gmax) * a.dt) / V;
+        const double Mreal = candidates_real<R>(a, Nd, gmax, V);
         const u32x4 r = draw(0, kTagNcand, 0, cell, step, a.k0, a.k1);
         double Mf = floor(Mreal + unif53(r.v[0], r.v[1]));
         if (!(Mf >= 0.0)) Mf = 0.0;
@@ -471,7 +490,7 @@ __device__ void process_cell(const CollideArgs<R> &a, const View &v, uint32_t ce
             Mf = 0.0;
         }
         M = (uint32_t)Mf;
-        ntc_loop<R, VR>(v, N, gmax, M, cell, step, a.k0, a.k1, a.molecule, acc, over);
+        ntc_loop<R, VR>(v, N, gmax, M, cell, step, a.k0, a.k1, a.molecule, a.omega1, acc, over);
     }
     sample_cell<R, VR>(a, v, cell, N, M, acc, over, pf);
 }

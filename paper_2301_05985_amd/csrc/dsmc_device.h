@@ -53,6 +53,45 @@ __device__ __forceinline__ double unif53(uint32_t a, uint32_t b) {
 }
 __device__ __forceinline__ float unif24(uint32_t a) { return (float)(a >> 8) * 0x1.0p-24f; }
 
+// x^a for x >= 0, 0 <= a <= 1, as 2^(a log2 x) in a fixed sequence of IEEE
+// double operations (the variable-hard-sphere acceptance takes a decision on
+// it, so the sequence is part of the method's definition here).
+//   log2: x = m 2^e, m in [sqrt(1/2), sqrt(2)); ln m = 2 atanh(s) with
+//         s = (m - 1)/(m + 1) by its odd series through s^27 (Horner in s^2).
+//   exp2: y = n + f, n = floor(y); 2^f = e^(f ln 2) by its Taylor series
+//         through degree 18 (Horner); scaled by 2^n exactly.
+__device__ __forceinline__ double vhs_log2(double x) {
+    int e;
+    double m = frexp(x, &e);
+    if (m < 0.70710678118654752440) {
+        m = m * 2.0;
+        e = e - 1;
+    }
+    const double sv = (m - 1.0) / (m + 1.0);
+    const double s2 = sv * sv;
+    double t = 1.0 / 27.0;
+#pragma unroll
+    for (int k = 25; k >= 1; k -= 2) t = t * s2 + 1.0 / (double)k;
+    const double lnm = (2.0 * sv) * t;
+    return (double)e + lnm * 1.44269504088896340736;
+}
+__device__ __forceinline__ double vhs_exp2(double y) {
+    const double n = floor(y);
+    const double f = (y - n) * 0.69314718055994530942;
+    double t = 1.0;
+#pragma unroll
+    for (int k = 18; k >= 1; --k) t = 1.0 + (f * t) / (double)k;
+    return ldexp(t, (int)n);
+}
+__device__ __forceinline__ double vhs_pow(double x, double a) {
+    if (a == 0.0) return 1.0;
+    if (!(x > 0.0)) return 0.0;
+    if (x == 1.0) return 1.0;
+    const double y = a * vhs_log2(x);
+    if (y < -1000.0) return 0.0;
+    return vhs_exp2(y);
+}
+
 // Index in [0, n) from a 32-bit word by multiply-shift (no rejection).
 __device__ __forceinline__ uint32_t scale_index(uint32_t r, uint32_t n) { return __umulhi(r, n); }
 

@@ -171,7 +171,7 @@ __device__ void process_cell_learned(const CollideArgs<R> &a, const View &v, uin
             diag_add(a.st, slot, 1ull);
         }
         const double Nd = (double)N;
-        const double Mreal = ((((((0.5 * Nd) * (Nd - 1.0)) * a.FN) * a.sigma) * gmax) * a.dt) / V;
+        const double Mreal = candidates_real<R>(a, Nd, gmax, V);
         const u32x4 r = draw(0, kTagNcand, 0, cell, step, a.k0, a.k1);
         double Mf = floor(Mreal + unif53(r.v[0], r.v[1]));
         if (!(Mf >= 0.0)) Mf = 0.0;
@@ -180,7 +180,7 @@ __device__ void process_cell_learned(const CollideArgs<R> &a, const View &v, uin
             Mf = 0.0;
         }
         M = (uint32_t)Mf;
-        ntc_loop<R, VR>(v, N, gmax, M, cell, step, a.k0, a.k1, a.molecule, acc, over);
+        ntc_loop<R, VR>(v, N, gmax, M, cell, step, a.k0, a.k1, a.molecule, a.omega1, acc, over);
     }
     sample_cell<R, VR>(a, v, cell, N, M, acc, over, pf);
 }

@@ -82,3 +82,10 @@ def test_rejects_unpaired_periodic_wall_and_bad_offsets(lib):
     assert _ws(lib, cfg)[0] == -1
     cfg.inst_offset = None
     assert _ws(lib, cfg)[0] == -1
+
+
+def test_vhs_needs_a_viscosity_index_in_range(lib):
+    p, parts = W.cavity(nx=4, ny=4, per_cell=5)
+    for omega, code in ((0.81, 0), (0.5, 0), (1.0, 0), (0.3, -1), (1.2, -1)):
+        cfg = binding.make_config(dict(p, molecule=W.VHS, omega=omega), len(parts["cx"]))
+        assert _ws(lib, cfg)[0] == code, omega

@@ -215,6 +215,34 @@ def test_far_movers_and_small_periodic_grids(gpu, case):
     _compare(g, orc, exact=True)
 
 
+@pytest.mark.parametrize("real", ["f64", "f32"])
+def test_vhs_homogeneous_bit_exact(gpu, real):
+    # variable hard spheres (omega = 0.81): the acceptance decision rests on
+    # the fixed-sequence power, evaluated identically on both sides
+    _announce("vhs homogeneous %s" % real)
+    p, parts = _homog([2, 40, 300, 900, 64, 65, 1100], dt=0.2)
+    p = dict(p, molecule=W.VHS, omega=0.81)
+    g, orc = _run(gpu, p, parts, 10, real, chunks=2)
+    assert orc.counters[:, 1].sum() > 200
+    _compare(g, orc, exact=True)
+
+
+@pytest.mark.parametrize("case", ["cavity_specular", "fourier_diffuse_vr"])
+def test_vhs_walled(gpu, case):
+    _announce("vhs walled %s" % case)
+    if case == "cavity_specular":
+        p, parts = W.cavity(nx=12, ny=10, per_cell=25, Kn=0.01, real="f64", dt=0.01)
+        p["wall_kind"] = (W.WALL_PERIODIC, W.WALL_PERIODIC, W.WALL_SPECULAR, W.WALL_SPECULAR)
+        exact = True
+    else:
+        p, parts = W.fourier(n_cells=20, per_cell=50, Kn=0.05, dt=2e-3, real="f64")
+        exact = False
+    p = dict(p, molecule=W.VHS, omega=0.74)
+    g, orc = _run(gpu, p, parts, 10, "f64", chunks=2)
+    assert orc.counters[:, 1].sum() > 100
+    _compare(g, orc, exact=exact, rtol=1e-12)
+
+
 def test_relaxation_full_size_f64(gpu):
     # relaxation workload at its full size: 10,000 particles in one cell,
     # FP64, 200 steps, bit-exact against the oracle
