@@ -267,6 +267,13 @@ def main():
                     "delta": model["delta"], "train_samples": model["n_train"],
                     "launch": best5, "launch_candidates_ms_per_step": times5,
                     "train_loss": model["loss_history"], "train_seconds": t_train})
+        p6 = dict(p3, molecule=W.VHS, omega=0.81)
+        sec.append(run_workload("batched 4096 cells, variable hard spheres (omega 0.81), exact majorant, FP32",
+                                dict(p6, **best3), parts3, 200, 20, torch))
+        p7, parts7 = W.cavity(Kn=args.kn, real="f32")
+        p7 = dict(p7, molecule=W.VHS, omega=0.74)
+        sec.append(run_workload("cavity 256x256 x 100, variable hard spheres (omega 0.74), VR, FP32", p7, parts7,
+                                100, 10, torch))
         p1, parts1 = W.relaxation()
         sec.append(run_workload("relaxation 10,000 particles one cell FP64", p1, parts1, 200, 0, torch))
         line["secondary"] = sec
