@@ -408,9 +408,10 @@ __global__ __launch_bounds__(64) void k_canonical(Soa<R> src, Soa<R> dst, const 
 // look-back scan (Merrill & Garland 2016): each workgroup of 256 threads
 // scans a tile of 1024 cells, publishes its tile total (flag AGG) and, once
 // its prefix is known, its inclusive prefix (flag INC); a tile's prefix is
-// found by walking back over earlier tiles' flags.  Workgroups are dispatched
-// in index order, so every tile it waits on is resident or finished; the walk
-// still gives up (and reports an error) after a bounded number of polls.  The
+// found by walking back over earlier tiles' flags, 64 at a time (one per
+// lane of the first wave).  Workgroups are dispatched in index order, so
+// every tile it waits on is resident or finished; the walk still gives up
+// (and reports an error) after a bounded number of polls.  The
 // last workgroup to finish clears the flags for the next launch and, when
 // `advance` is set (every step; not at set-up), advances the step
 // bookkeeping.
@@ -446,25 +447,47 @@ __global__ __launch_bounds__(256) void k_scan_lookback(uint32_t *count, uint32_t
     const uint32_t w0 = wave_tot[0], w1 = wave_tot[1], w2 = wave_tot[2], w3 = wave_tot[3];
     const uint32_t tile_total = (w0 + w1) + (w2 + w3);
     const uint32_t wave_excl = wv == 0 ? 0u : (wv == 1 ? w0 : (wv == 2 ? w0 + w1 : (w0 + w1) + w2));
-    if (t == 0) {
+    if (wv == 0) {
+        // wave-wide look-back: lane l inspects tile j - l, 64 predecessors per
+        // round; the window is summed up to the nearest inclusive prefix once
+        // every tile before it has published its total
         uint32_t prefix = 0;
         if (tile == 0) {
-            __hip_atomic_store(&flags[0], kFlagInc | (uint64_t)tile_total, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0)
+                __hip_atomic_store(&flags[0], kFlagInc | (uint64_t)tile_total, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            __hip_atomic_store(&flags[tile], kFlagAgg | (uint64_t)tile_total, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0)
+                __hip_atomic_store(&flags[tile], kFlagAgg | (uint64_t)tile_total, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
             int j = tile - 1;
             uint32_t polls = 0;
             while (j >= 0) {
-                const uint64_t f = __hip_atomic_load(&flags[j], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                if (f & kFlagInc) { prefix += (uint32_t)f; break; }
-                if (f & kFlagAgg) { prefix += (uint32_t)f; --j; continue; }
-                if (++polls > (1u << 24)) { set_error(st, DSMC_EHIP); break; }
-                __builtin_amdgcn_s_sleep(1);
+                const int idx = j - lane;
+                // before tile 0: an inclusive prefix of zero ends the window
+                const uint64_t f = idx >= 0 ? __hip_atomic_load(&flags[idx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)
+                                            : kFlagInc;
+                const unsigned long long incm = __ballot((f & kFlagInc) != 0);
+                const int first = incm ? __ffsll((long long)incm) - 1 : 64;
+                const unsigned long long need = first >= 63 ? ~0ull : ((1ull << (first + 1)) - 1ull);
+                const unsigned long long waiting = __ballot((f & (kFlagInc | kFlagAgg)) == 0) & need;
+                if (waiting) {
+                    if (++polls > (1u << 24)) {
+                        if (lane == 0) set_error(st, DSMC_EHIP);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                prefix += wave_sum_u32(lane <= first ? (uint32_t)f : 0u);
+                if (first < 64) break;
+                j -= 64;
             }
-            __hip_atomic_store(&flags[tile], kFlagInc | (uint64_t)(prefix + tile_total), __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0)
+                __hip_atomic_store(&flags[tile], kFlagInc | (uint64_t)(prefix + tile_total), __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         }
-        tile_prefix = prefix;
+        if (lane == 0) tile_prefix = prefix;
     }
     __syncthreads();
     uint32_t run = tile_prefix + wave_excl + inc - local;
