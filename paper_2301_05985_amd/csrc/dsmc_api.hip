@@ -564,7 +564,8 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
                 if (cell < c->ncell) sched_host[blk++] = (uint32_t)cell;
             }
     }
-    c->lds = (size_t)c->cap * per + 16 + 16;
+    // (at least the transpose area of the moment reduction: 13 x 66 doubles)
+    c->lds = std::max<size_t>((size_t)c->cap * per + 16 + 16, (size_t)13 * 66 * 8);
 
     // graphs are recorded on a private stream (capture is not allowed on
     // the legacy default stream the caller may use)

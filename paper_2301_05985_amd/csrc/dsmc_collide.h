@@ -58,6 +58,7 @@ constexpr int kNsum = 26;
 // Cell staged in LDS (index = canonical rank).
 template <typename R>
 struct LdsView {
+    static constexpr bool kInLds = true;
     R *vx, *vy, *vz, *w;
     uint32_t *owner;
     __device__ __forceinline__ void get(uint32_t r, R &a, R &b, R &c) const { a = vx[r]; b = vy[r]; c = vz[r]; }
@@ -72,6 +73,7 @@ struct LdsView {
 // Cell operated on in place in global memory, through a rank -> slot map.
 template <typename R>
 struct GlobalView {
+    static constexpr bool kInLds = false;
     R *cx, *cy, *cz, *w;
     const uint32_t *perm;  // rank -> slot inside the cell, or null for the identity
     uint32_t *owner;
@@ -393,7 +395,7 @@ __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uin
 
 // The cell's running sums and counters, read at the start of the cell's work
 // so that the final read-modify-write does not wait on memory.  Lane L owns
-// sum index L >> 1 (with weights) or L >> 2 (without); lane 0 the counters.
+// sum index L (L < 26 with weights, L < 13 without); lane 0 the counters.
 struct CellPrefetch {
     double sum;
     unsigned long long cand, acc;
@@ -402,10 +404,8 @@ struct CellPrefetch {
 template <typename R, bool VR>
 __device__ __forceinline__ CellPrefetch prefetch_cell(const CollideArgs<R> &a, uint32_t cell) {
     const int lane = lane_id();
-    const uint32_t idx = (uint32_t)lane >> (VR ? 1 : 2);
-    const bool writer = (lane & (VR ? 1 : 3)) == 0 && idx < (uint32_t)(VR ? kNsum : 13);
     CellPrefetch pf{0.0, 0ull, 0ull};
-    if (writer) pf.sum = a.sums[(size_t)cell * kNsum + idx];
+    if (lane < (VR ? kNsum : 13)) pf.sum = a.sums[(size_t)cell * kNsum + lane];
     if (lane == 0) {
         pf.cand = a.counters[2 * (size_t)cell];
         pf.acc = a.counters[2 * (size_t)cell + 1];
@@ -414,10 +414,17 @@ __device__ __forceinline__ CellPrefetch prefetch_cell(const CollideArgs<R> &a, u
 }
 
 // FP64 moment sums of the post-collision state of one cell, added to the
-// running sums; per-cell counters and diagnostics.
+// running sums; per-cell counters and diagnostics.  Each lane accumulates
+// the moments of its particles; the 13 (26 with weights) sums are then
+// reduced over the wave.  A cell in global memory reduces by shuffles
+// (recursive halving).  A cell staged in LDS writes its velocities and
+// weights back to the particle arrays at wb_base during the accumulation,
+// and then uses its LDS area (`red`, at least 13 x 66 doubles) for a
+// transpose: every lane stores its partial sums as a column and lanes 0..12
+// add up one row each.
 template <typename R, bool VR, typename View>
 __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cell, uint32_t N, uint32_t M,
-                            uint32_t acc, uint32_t over, const CellPrefetch &pf) {
+                            uint32_t acc, uint32_t over, const CellPrefetch &pf, double *red, uint32_t wb_base) {
     const int lane = lane_id();
     constexpr int K = VR ? 32 : 16;  // 26 or 13 sums, padded to a power of two
     double q[K];
@@ -426,6 +433,12 @@ __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cel
     for (uint32_t r = lane; r < N; r += 64) {
         R x, y, z;
         v.get(r, x, y, z);
+        R w = (R)1;
+        if (VR) w = v.getw(r);
+        if (View::kInLds) {
+            a.s.cx[wb_base + r] = x; a.s.cy[wb_base + r] = y; a.s.cz[wb_base + r] = z;
+            if (VR) a.s.w[wb_base + r] = w;
+        }
         const double vx = (double)x, vy = (double)y, vz = (double)z;
         const double c2 = (vx * vx + vy * vy) + vz * vz;
         const double t[13] = {1.0, vx, vy, vz, vx * vx, vy * vy, vz * vz, vx * vy, vx * vz, vy * vz,
@@ -433,15 +446,47 @@ __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cel
 #pragma unroll
         for (int u = 0; u < 13; ++u) q[u] += t[u];
         if (VR) {
-            const double f = 1.0 - (double)v.getw(r);
+            const double f = 1.0 - (double)w;
 #pragma unroll
             for (int u = 0; u < 13; ++u) q[(13 + u) % K] += f * t[u];
         }
     }
-    // lane L ends up with the total of sum index L >> (VR ? 1 : 2)
-    const double tot = wave_sum_many<K>(q);
-    const uint32_t idx = (uint32_t)lane >> (VR ? 1 : 2);
-    const bool writer = (lane & (VR ? 1 : 3)) == 0 && idx < (uint32_t)(VR ? kNsum : 13);
+    // lane L ends up with the total of sum index L
+    double tot = 0.0;
+    if constexpr (View::kInLds) {
+        constexpr int RS = 66;  // row stride (doubles): 16-byte rows, distinct banks for rows 0..12
+        double second = 0.0;
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < (VR ? 2 : 1); ++h) {
+#pragma unroll
+            for (int u = 0; u < 13; ++u) red[u * RS + lane] = q[13 * h + u];
+            __syncthreads();
+            if (lane < 13) {
+                const double2 *row = (const double2 *)(red + lane * RS);
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll 4
+                for (int l = 0; l < 32; l += 2) {
+                    const double2 e0 = row[l], e1 = row[l + 1];
+                    s0 += e0.x; s1 += e0.y; s2 += e1.x; s3 += e1.y;
+                }
+                const double t = (s0 + s1) + (s2 + s3);
+                if (h == 0) tot = t;
+                else second = t;
+            }
+            __syncthreads();
+        }
+        if (VR) {
+            const double moved = __shfl(second, lane >= 13 ? lane - 13 : 0, 64);
+            if (lane >= 13 && lane < 26) tot = moved;
+        }
+    } else {
+        (void)red;
+        const double t = wave_sum_many<K>(q);  // lane L: total of index L >> (VR ? 1 : 2)
+        tot = __shfl(t, (lane << (VR ? 1 : 2)) & 63, 64);
+    }
+    const uint32_t idx = (uint32_t)lane;
+    const bool writer = idx < (uint32_t)(VR ? kNsum : 13);
     const bool nonfinite = writer && !isfinite(tot);
     const bool bad_plain = __ballot(nonfinite && idx < 13) != 0ull;
     const bool bad_vr = __ballot(nonfinite && idx >= 13) != 0ull;
@@ -471,7 +516,7 @@ __device__ __forceinline__ double candidates_real(const CollideArgs<R> &a, doubl
 // already holds the cell in canonical order.
 template <typename R, bool VR, typename View>
 __device__ void process_cell(const CollideArgs<R> &a, const View &v, uint32_t cell, uint32_t N,
-                             uint32_t step, const CellPrefetch &pf) {
+                             uint32_t step, const CellPrefetch &pf, double *red = nullptr, uint32_t wb_base = 0) {
     const int lane = lane_id();
     uint32_t M = 0, acc = 0, over = 0;
     if (N >= 2) {
@@ -492,7 +537,7 @@ __device__ void process_cell(const CollideArgs<R> &a, const View &v, uint32_t ce
         M = (uint32_t)Mf;
         ntc_loop<R, VR>(v, N, gmax, M, cell, step, a.k0, a.k1, a.molecule, a.omega1, acc, over);
     }
-    sample_cell<R, VR>(a, v, cell, N, M, acc, over, pf);
+    sample_cell<R, VR>(a, v, cell, N, M, acc, over, pf, red, wb_base);
 }
 
 }  // namespace dsmc

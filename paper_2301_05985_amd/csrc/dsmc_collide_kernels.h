@@ -255,13 +255,11 @@ __device__ __forceinline__ void collide_lds_body(const CollideArgs<R> &a, unsign
     for (uint32_t r = lane; r < N; r += 64) owner[r] = 0xFFFFFFFFu;
     __syncthreads();
     const LdsView<R> view{vx, vy, vz, w, owner};
-    if (LEARNED) process_cell_learned<R, VR>(a, view, cell, N, step, pf);
-    else process_cell<R, VR>(a, view, cell, N, step, pf);
+    // the sampling writes the cell back and reduces its sums through the
+    // cell's LDS area
+    if (LEARNED) process_cell_learned<R, VR>(a, view, cell, N, step, pf, (double *)smem, base);
+    else process_cell<R, VR>(a, view, cell, N, step, pf, (double *)smem, base);
     __syncthreads();
-    for (uint32_t s = lane; s < N; s += 64) {
-        a.s.cx[base + s] = vx[s]; a.s.cy[base + s] = vy[s]; a.s.cz[base + s] = vz[s];
-        if (VR) a.s.w[base + s] = w[s];
-    }
 }
 
 // Global-memory kernel for cells larger than the LDS capacity: walled cells

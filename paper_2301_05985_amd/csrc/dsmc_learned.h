@@ -159,7 +159,8 @@ __device__ double learned_majorant(const CollideArgs<R> &a, const View &v, uint3
 // Same as process_cell, with the learned majorant.
 template <typename R, bool VR, typename View>
 __device__ void process_cell_learned(const CollideArgs<R> &a, const View &v, uint32_t cell, uint32_t N,
-                                     uint32_t step, const CellPrefetch &pf) {
+                                     uint32_t step, const CellPrefetch &pf, double *red = nullptr,
+                                     uint32_t wb_base = 0) {
     const int lane = lane_id();
     uint32_t M = 0, acc = 0, over = 0;
     if (N >= 2) {
@@ -182,7 +183,7 @@ __device__ void process_cell_learned(const CollideArgs<R> &a, const View &v, uin
         M = (uint32_t)Mf;
         ntc_loop<R, VR>(v, N, gmax, M, cell, step, a.k0, a.k1, a.molecule, a.omega1, acc, over);
     }
-    sample_cell<R, VR>(a, v, cell, N, M, acc, over, pf);
+    sample_cell<R, VR>(a, v, cell, N, M, acc, over, pf, red, wb_base);
 }
 
 }  // namespace dsmc
