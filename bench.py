@@ -5,8 +5,8 @@ Default (no flags): the 2-D lid-driven cavity at its full size -- 256 x 256
 cells, 100 particles per cell (6,553,600 particles), Kn = 0.01, diffuse walls,
 importance weights, FP32 state with FP64 moment sums -- W untimed warm-up
 steps, then exactly K timed steps (one step = free flight with walls, the
-two-pass counting sort, per-cell majorant + NTC collisions + weight update,
-moment sampling).  Rank 0 prints one JSON line.
+stable regrouping by cell, per-cell majorant + NTC collisions + weight
+update, moment sampling).  Rank 0 prints one JSON line.
 
 Also reported in the same line: per-kernel durations measured live with HIP
 events on the run's stream (roofline of the dominant kernel), the CPU oracle

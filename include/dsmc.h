@@ -148,9 +148,10 @@ typedef struct {
     uint64_t big_cells;       /* cell-steps processed by the global-memory collision kernel */
 } dsmc_diag;
 
-/* Bytes of device workspace the configuration needs (alternate particle
- * buffer for the counting sort, per-cell offsets, FP64 running sums,
- * counters, scratch).  EINVAL on an invalid configuration. */
+/* Bytes of device workspace the configuration needs (second particle
+ * buffer of the regrouping, per-cell ranges, move codes and far-mover lists,
+ * FP64 running sums, counters, scratch).  EINVAL on an invalid
+ * configuration. */
 dsmc_status dsmc_workspace_size(const dsmc_config *cfg, size_t *bytes);
 
 /* Validate the configuration, bind the particle buffers (device, caller

@@ -1,16 +1,17 @@
 // dsmc_kernels.h -- the per-step kernels of the DSMC hot path on gfx950.
 //
-// One time step (Bird 1994, direct simulation Monte Carlo):
-//   k_stream_count    free flight with wall conditions, cell index, per-cell
-//                     counts (counting sort, pass 1)            [grid over particles]
-//   k_scan            exclusive scan of the counts, step bookkeeping [one workgroup]
-//   k_stream_scatter  the same flight recomputed, particles written to their
-//                     cell's range of the other buffer (pass 2)  [grid over particles]
-//   k_collide         per cell: stage the cell in LDS in canonical (ascending
-//                     id) order, exact majorant, NTC candidates in
-//                     conflict-free wave batches, importance weights, FP64
-//                     moment sums, write back                     [one wave per cell]
-// Homogeneous instances (dims == 0) skip the first three and run k_begin_step.
+// One time step (Bird 1994, direct simulation Monte Carlo), walled runs:
+//   k_stream_code     free flight of the particles that stay in the box, new
+//                     cell counted, one move-code byte each; the others go
+//                     to the wall list                       [grid over particles]
+//   k_stream_walls    exact flight with wall conditions of the wall list
+//   k_scan_lookback   exclusive scan of the counts into the new cell ranges,
+//                     step bookkeeping                   [decoupled look-back]
+//   k_collide         per cell (dsmc_collide_kernels.h): gather the cell's
+//                     particles from the previous sequence by move code,
+//                     majorant, NTC candidates in conflict-free wave batches,
+//                     importance weights, FP64 moment sums [one wave per cell]
+// Homogeneous instances (dims == 0) run k_begin_step and k_collide only.
 #pragma once
 #include "dsmc_device.h"
 #include "../../include/dsmc.h"

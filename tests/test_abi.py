@@ -89,3 +89,17 @@ def test_vhs_needs_a_viscosity_index_in_range(lib):
     for omega, code in ((0.81, 0), (0.5, 0), (1.0, 0), (0.3, -1), (1.2, -1)):
         cfg = binding.make_config(dict(p, molecule=W.VHS, omega=omega), len(parts["cx"]))
         assert _ws(lib, cfg)[0] == code, omega
+
+
+def test_autotune_signature_separates_workloads():
+    # the cache key changes with everything that changes the collision cost
+    from paper_2301_05985_amd import autotune
+    p, _ = W.batched(n_inst=64, nmin=10, nmax=200)
+    sig = autotune.signature(p)
+    assert sig == autotune.signature(dict(p))
+    assert sig != autotune.signature(dict(p, vr=1))
+    assert sig != autotune.signature(dict(p, majorant=1))
+    assert sig != autotune.signature(dict(p, real="f64"))
+    q, _ = W.batched(n_inst=64, nmin=10, nmax=200, seed=1)
+    assert sig != autotune.signature(q)  # other instance sizes
+    assert all(c["schedule"] in (0, 1) for c in autotune.CANDIDATES)
