@@ -129,7 +129,8 @@ enum { DSMC_SCHEDULE_GRID = 0, DSMC_SCHEDULE_PERSISTENT = 1 };
  * after each step's free flight regrouped by the new cell with the relative
  * order of the previous sequence kept (a stable counting sort); a cell's
  * particles collide in sequence order.  The storage order of the buffers is
- * that sequence. */
+ * that sequence.  Every non-NULL pointer must be 16-byte aligned (any
+ * hipMalloc or torch allocation is); dsmc_init returns EINVAL otherwise. */
 typedef struct {
     void *x, *y, *cx, *cy, *cz, *w;
     uint32_t *id;
@@ -215,11 +216,13 @@ dsmc_status dsmc_set_majorant_model(dsmc_ctx *ctx, const uint16_t *bf16_weights_
 dsmc_status dsmc_checkpoint(dsmc_ctx *ctx, void *host_blob, size_t *bytes);
 dsmc_status dsmc_restore(dsmc_ctx *ctx, const void *host_blob, size_t bytes);
 
-/* Run one step with every kernel launched separately and timed with HIP
- * events on the context's stream; ms_host receives up to max_kernels
- * per-kernel durations (milliseconds) in launch order, *n_kernels their
- * number and names_host (may be NULL) a '\n'-separated list of kernel names
- * (at most names_len bytes).  Synchronising.  Used for roofline reports. */
+/* Run two steps: the first untimed (it keeps the GPU busy while the second
+ * is enqueued, so that no launch waits on the host), the second with every
+ * kernel launched separately and timed with HIP events on the context's
+ * stream; ms_host receives up to max_kernels per-kernel durations
+ * (milliseconds) of the second step in launch order, *n_kernels their number
+ * and names_host (may be NULL) a '\n'-separated list of kernel names (at
+ * most names_len bytes).  Synchronising.  Used for roofline reports. */
 dsmc_status dsmc_profile_step(dsmc_ctx *ctx, float *ms_host, int32_t max_kernels,
                               int32_t *n_kernels, char *names_host, int32_t names_len);
 

@@ -272,12 +272,11 @@ void launch_collide(dsmc_ctx *c, Launcher &L, int src) {
 template <typename R, int D, bool VR>
 void launch_stream(dsmc_ctx *c, Launcher &L, int src) {
     const int dst = src ^ 1;
-    constexpr int P = 4;  // particles per thread of the streaming kernel
-    const unsigned grid = (unsigned)((c->n + 256 * P - 1) / (256 * P));
+    const unsigned grid = (unsigned)((c->n + 1023) / 1024);  // 4 particles per thread
     if (c->n > 0) {
         const Soa<R> s = soa_of<R>(c->buf[src]);
         L.mark("stream");
-        hipLaunchKernelGGL((k_stream_code<R, D, P>), dim3(grid), dim3(256), 0, L.s, c->geo, s, (int64_t)c->n,
+        hipLaunchKernelGGL((k_stream_code<R, D>), dim3(grid), dim3(256), 0, L.s, c->geo, s, (int64_t)c->n,
                            c->code, c->count, c->far_head, c->far_src, c->far_next, c->wall_list, c->st);
         L.mark("stream_walls");
         hipLaunchKernelGGL((k_stream_walls<R, D, VR>), dim3(kWallGrid), dim3(256), 0, L.s, c->geo, s, c->code,
@@ -426,6 +425,10 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
     if (cfg->n_particles > 0 && cfg->dims >= 1 && !p->x) return DSMC_EINVAL;
     if (cfg->n_particles > 0 && cfg->dims == 2 && !p->y) return DSMC_EINVAL;
     if (cfg->n_particles > 0 && cfg->vr && !p->w) return DSMC_EINVAL;
+    // the streaming kernel moves four particles per vector access
+    for (const void *q : {(const void *)p->x, (const void *)p->y, (const void *)p->cx, (const void *)p->cy,
+                          (const void *)p->cz, (const void *)p->w, (const void *)p->id})
+        if (((uintptr_t)q % 16) != 0) return DSMC_EINVAL;
     const Layout L = make_layout(*cfg);
     if (ws_bytes < L.total) return DSMC_ENOMEM;
 
@@ -799,6 +802,8 @@ dsmc_status dsmc_profile_step(dsmc_ctx *c, float *ms_host, int32_t max_kernels, 
     if (c->sticky != DSMC_OK) return c->sticky;
     std::vector<hipEvent_t> ev;
     std::vector<const char *> names;
+    Launcher lead{c->stream, nullptr, nullptr};
+    c->cur = enqueue_step(c, lead, c->cur);
     Launcher L{c->stream, &ev, &names};
     c->cur = enqueue_step(c, L, c->cur);
     L.mark("end");

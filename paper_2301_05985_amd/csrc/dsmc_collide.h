@@ -171,46 +171,127 @@ __device__ double pair_diameter(const View &v, uint32_t N) {
 }
 
 // Uniform direction (Marsaglia 1972) from blocks 1, 2, ... of candidate k's
-// PAIR stream; one attempt per block in double, two in float.  Lanes with
-// `pending` set iterate until success (at most 64 blocks, then (0,0,1)) and
-// receive the direction; the other lanes keep their values.
+// PAIR stream; one attempt per block in double (u from words 0-1, v from
+// words 2-3), two in float (words 0, 1, then words 2, 3).  The first
+// successful attempt gives the direction; after 64 blocks without one it is
+// (0, 0, 1).
 template <typename R>
-__device__ __forceinline__ void direction(bool pending, uint32_t k, uint32_t cell, uint32_t step,
+__device__ __forceinline__ bool marsaglia_block(const u32x4 &r, R &tx, R &ty, R &tz) {
+#pragma unroll
+    for (int a = 0; a < (sizeof(R) == 4 ? 2 : 1); ++a) {
+        R u, v;
+        if (sizeof(R) == 4) {
+            u = (R)2 * (R)unif24(r.v[2 * a]) - (R)1;
+            v = (R)2 * (R)unif24(r.v[2 * a + 1]) - (R)1;
+        } else {
+            u = (R)2 * (R)unif53(r.v[0], r.v[1]) - (R)1;
+            v = (R)2 * (R)unif53(r.v[2], r.v[3]) - (R)1;
+        }
+        const R s = u * u + v * v;
+        if (s < (R)1 && s > (R)0) {
+            const R h = sqrt((R)1 - s);
+            tx = ((R)2 * u) * h;
+            ty = ((R)2 * v) * h;
+            tz = (R)1 - (R)2 * s;
+            return true;
+        }
+    }
+    return false;
+}
+
+// Lanes with `pending` set try blocks first, first + 1, ... (first may differ
+// between lanes; blocks before it are known to have failed) and receive the
+// direction; the other lanes keep their values.
+template <typename R>
+__device__ __forceinline__ void direction(bool pending, uint32_t first, uint32_t k, uint32_t cell, uint32_t step,
                                           uint32_t k0, uint32_t k1, R &nx, R &ny, R &nz) {
     if (!__ballot(pending)) return;
     R tx = (R)0, ty = (R)0, tz = (R)1;
     bool want = pending;
-    for (uint32_t blk = 1; blk <= 64; ++blk) {
+    for (uint32_t it = 0; it < 64; ++it) {
+        const uint32_t blk = first + it;
+        if (want && blk > 64) want = false;  // no success in 64 blocks: (0, 0, 1)
         if (!__ballot(want)) break;
-        if (want) {
-            const u32x4 r = draw(k, kTagPair, blk, cell, step, k0, k1);
-#pragma unroll
-            for (int a = 0; a < (sizeof(R) == 4 ? 2 : 1); ++a) {
-                if (!want) break;
-                R u, v;
-                if (sizeof(R) == 4) {
-                    u = (R)2 * (R)unif24(r.v[2 * a]) - (R)1;
-                    v = (R)2 * (R)unif24(r.v[2 * a + 1]) - (R)1;
-                } else {
-                    u = (R)2 * (R)unif53(r.v[0], r.v[1]) - (R)1;
-                    v = (R)2 * (R)unif53(r.v[2], r.v[3]) - (R)1;
-                }
-                const R s = u * u + v * v;
-                if (s < (R)1 && s > (R)0) {
-                    const R h = sqrt((R)1 - s);
-                    tx = ((R)2 * u) * h;
-                    ty = ((R)2 * v) * h;
-                    tz = (R)1 - (R)2 * s;
-                    want = false;
-                }
-            }
-        }
+        if (want && marsaglia_block<R>(draw(k, kTagPair, blk, cell, step, k0, k1), tx, ty, tz)) want = false;
     }
     if (pending) {
         nx = tx;
         ny = ty;
         nz = tz;
     }
+}
+
+// Random draws of the fresh candidates (lanes with `fresh` set): the pair
+// (i, j) and acceptance number U from block 0 of the candidate's PAIR
+// stream, the scattering direction from blocks 1, 2, ...
+//
+// The fresh candidates of a window are consecutive, kf .. kf + m - 1, on a
+// cyclic run of lanes (candidate k lives on lane k mod 64).  With m <= 32 the
+// whole wave computes blocks for them at once: lane b m + t computes block b
+// of candidate kf + t (and its direction attempts when b >= 1), so one pass
+// yields block 0 and the first 64 / m - 1 direction blocks of every
+// candidate; each candidate's lane then collects block 0 and the first
+// successful direction block by lane shuffles.  Candidates whose computed
+// blocks all fail continue one block at a time.  Same draws, same order of
+// attempts: the result equals the per-candidate definition.
+template <typename R>
+__device__ __forceinline__ void draw_candidates(bool fresh, uint32_t k, uint32_t N, uint32_t cell, uint32_t step,
+                                                uint32_t k0, uint32_t k1, uint32_t &i, uint32_t &j, R &U, R &nx,
+                                                R &ny, R &nz) {
+    const unsigned long long fm = __ballot(fresh);
+    if (!fm) return;
+    const uint32_t m = (uint32_t)__popcll(fm);
+    // first lane of the run: fresh, with its predecessor not fresh
+    const unsigned long long starts = fm & ~((fm << 1) | (fm >> 63));
+    if (m > 32 || __popcll(starts) != 1) {
+        if (fresh) {
+            const u32x4 r = draw(k, kTagPair, 0, cell, step, k0, k1);
+            i = scale_index(r.v[0], N);
+            j = scale_index(r.v[1], N - 1);
+            j += (j >= i) ? 1u : 0u;
+            U = sizeof(R) == 4 ? (R)unif24(r.v[2]) : (R)unif53(r.v[2], r.v[3]);
+        }
+        direction<R>(fresh, 1u, k, cell, step, k0, k1, nx, ny, nz);
+        return;
+    }
+    const uint32_t lane = (uint32_t)lane_id();
+    const int l0 = __ffsll((long long)starts) - 1;
+    const uint32_t kf = (uint32_t)__builtin_amdgcn_readlane((int)k, l0);
+    // x / m as (x * ceil(2^16 / m)) >> 16, exact for x < 64 and m <= 64
+    const uint32_t inv = (65536u + m - 1u) / m;
+    const uint32_t b = (lane * inv) >> 16;
+    const uint32_t t = lane - b * m;
+    const u32x4 r = draw(kf + t, kTagPair, b, cell, step, k0, k1);
+    R tx = (R)0, ty = (R)0, tz = (R)1;
+    const bool ok = b >= 1u && marsaglia_block<R>(r, tx, ty, tz);
+    const uint32_t own = fresh ? k - kf : 0u;  // this lane's candidate offset
+    const uint32_t w0 = (uint32_t)__shfl((int)r.v[0], (int)own, 64);
+    const uint32_t w1 = (uint32_t)__shfl((int)r.v[1], (int)own, 64);
+    const uint32_t w2 = (uint32_t)__shfl((int)r.v[2], (int)own, 64);
+    const uint32_t w3 = sizeof(R) == 8 ? (uint32_t)__shfl((int)r.v[3], (int)own, 64) : 0u;
+    if (fresh) {
+        i = scale_index(w0, N);
+        j = scale_index(w1, N - 1);
+        j += (j >= i) ? 1u : 0u;
+        U = sizeof(R) == 4 ? (R)unif24(w2) : (R)unif53(w2, w3);
+    }
+    bool want = fresh;
+    for (uint32_t blk = 1; blk < 64; ++blk) {
+        const uint32_t src = blk * m + own;
+        const bool avail = want && src < 64u;
+        if (!__ballot(avail)) break;
+        const int s = (int)(src & 63u);
+        const int okb = __shfl((int)ok, s, 64);
+        const R ax = __shfl(tx, s, 64), ay = __shfl(ty, s, 64), az = __shfl(tz, s, 64);
+        if (avail && okb) {
+            nx = ax;
+            ny = ay;
+            nz = az;
+            want = false;
+        }
+    }
+    // blocks 1 .. (63 - own) / m were computed for this candidate
+    direction<R>(want, (((63u - own) * inv) >> 16) + 1u, k, cell, step, k0, k1, nx, ny, nz);
 }
 
 // The NTC candidate loop of one cell in conflict-free wave batches.
@@ -228,9 +309,9 @@ __device__ __forceinline__ void direction(bool pending, uint32_t k, uint32_t cel
 // of its pair, and the weights never feed back into the velocity decisions:
 // the window stays inside one generation of 64 candidates (64 g .. 64 g + 63)
 // until all of them are committed, then the generation's weight updates are
-// replayed in candidate order, in sub-batches that end at the first candidate
-// touching a particle whose weight an earlier pending candidate updates.
-// Both give exactly the sequential result.
+// replayed in rounds: a round applies every pending candidate that no
+// earlier pending candidate shares a particle with.  Both give exactly the
+// sequential result.
 
 // Velocity window over the live candidates (k in [kb, wend)); returns the
 // first uncommitted candidate and sets `commit` and `accept` per lane.
@@ -311,14 +392,7 @@ __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uin
     while (kb < M) {
         const bool act = k < M;
         const bool draw_now = act && fresh;
-        if (draw_now) {
-            const u32x4 r = draw(k, kTagPair, 0, cell, step, k0, k1);
-            i = scale_index(r.v[0], N);
-            j = scale_index(r.v[1], N - 1);
-            j += (j >= i) ? 1u : 0u;
-            U = sizeof(R) == 4 ? (R)unif24(r.v[2]) : (R)unif53(r.v[2], r.v[3]);
-        }
-        direction<R>(draw_now, k, cell, step, k0, k1, nx, ny, nz);
+        draw_candidates<R>(draw_now, k, N, cell, step, k0, k1, i, j, U, nx, ny, nz);
         fresh = fresh && !act;
         const uint32_t gend = M - g0 > 64u ? g0 + 64u : M;
         const uint32_t wend = VR ? gend : (M - kb > 64u ? kb + 64u : M);
@@ -348,23 +422,23 @@ __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uin
         // 2010) of its candidates, in candidate order: accepted -> both W_i W_j;
         // rejected -> W_i (1 - p W_j) / (1 - p), p = g / g_max
         const bool mine = act && k < gend;  // this lane's candidate belongs to the generation
-        uint32_t q0 = g0;
-        while (q0 < gend) {
-            const bool pend = mine && k >= q0;
+        bool pend = mine;
+        while (__ballot(pend)) {
+            // a pending candidate is ready when no earlier pending candidate
+            // touches its particles; ready candidates touch disjoint pairs and
+            // every particle sees its updates in candidate order
             if (pend) {
                 atomicMin(v.own(i), k);
                 atomicMin(v.own(j), k);
             }
             __syncthreads();
-            const bool wbad = pend && (v.read_own(i) < k || v.read_own(j) < k);
-            uint32_t Q = wave_min_u32(wbad ? k : 0xFFFFFFFFu);
-            Q = Q < gend ? Q : gend;
+            const bool ready = pend && v.read_own(i) == k && v.read_own(j) == k;
             __syncthreads();
             if (pend) {
                 v.clear_own(i);
                 v.clear_own(j);
             }
-            if (pend && k < Q) {
+            if (ready) {
                 const double wa = (double)v.getw(i), wb = (double)v.getw(j);
                 if (acc_k) {
                     const double ab = wa * wb;
@@ -378,8 +452,8 @@ __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uin
                     }
                 }
             }
+            pend = pend && !ready;
             __syncthreads();
-            q0 = Q;
         }
         // next generation
         if (mine) {
@@ -393,19 +467,31 @@ __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uin
     n_over = wave_sum_u32(over);
 }
 
+// The running sum a lane owns in the moment reduction, or -1.  Cells in
+// global memory: lane L owns sum L.  Cells staged in LDS: the four lanes of
+// quad r add up row r (moment r) together, and lane 4 r + h keeps the total
+// of set h (h = 0 plain, 1 weighted): sum 13 h + r.
+template <bool IN_LDS, bool VR>
+__device__ __forceinline__ int owned_sum(int lane) {
+    if (!IN_LDS) return lane < (VR ? kNsum : 13) ? lane : -1;
+    const int r = lane >> 2, h = lane & 3;
+    return (r < 13 && h < (VR ? 2 : 1)) ? 13 * h + r : -1;
+}
+
 // The cell's running sums and counters, read at the start of the cell's work
-// so that the final read-modify-write does not wait on memory.  Lane L owns
-// sum index L (L < 26 with weights, L < 13 without); lane 0 the counters.
+// so that the final read-modify-write does not wait on memory: each lane the
+// sum it owns, lane 0 the counters.
 struct CellPrefetch {
     double sum;
     unsigned long long cand, acc;
 };
 
-template <typename R, bool VR>
+template <typename R, bool VR, bool IN_LDS>
 __device__ __forceinline__ CellPrefetch prefetch_cell(const CollideArgs<R> &a, uint32_t cell) {
     const int lane = lane_id();
     CellPrefetch pf{0.0, 0ull, 0ull};
-    if (lane < (VR ? kNsum : 13)) pf.sum = a.sums[(size_t)cell * kNsum + lane];
+    const int idx = owned_sum<IN_LDS, VR>(lane);
+    if (idx >= 0) pf.sum = a.sums[(size_t)cell * kNsum + idx];
     if (lane == 0) {
         pf.cand = a.counters[2 * (size_t)cell];
         pf.acc = a.counters[2 * (size_t)cell + 1];
@@ -420,8 +506,9 @@ __device__ __forceinline__ CellPrefetch prefetch_cell(const CollideArgs<R> &a, u
 // (recursive halving).  A cell staged in LDS writes its velocities and
 // weights back to the particle arrays at wb_base during the accumulation,
 // and then uses its LDS area (`red`, at least 13 x 66 doubles) for a
-// transpose: every lane stores its partial sums as a column and lanes 0..12
-// add up one row each.
+// transpose, once per set of 13 sums: every lane stores its partial sums as
+// a column, the four lanes of quad r add up a quarter of row r each
+// (interleaved 16-byte columns) and the quad combines its four parts.
 template <typename R, bool VR, typename View>
 __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cell, uint32_t N, uint32_t M,
                             uint32_t acc, uint32_t over, const CellPrefetch &pf, double *red, uint32_t wb_base) {
@@ -451,42 +538,41 @@ __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cel
             for (int u = 0; u < 13; ++u) q[(13 + u) % K] += f * t[u];
         }
     }
-    // lane L ends up with the total of sum index L
+    // each lane ends up with the total of the sum it owns
     double tot = 0.0;
     if constexpr (View::kInLds) {
-        constexpr int RS = 66;  // row stride (doubles): 16-byte rows, distinct banks for rows 0..12
-        double second = 0.0;
+        constexpr int RS = 66;  // row stride (doubles): 16-byte aligned rows
+        const int row = lane >> 2, part = lane & 3;
         __syncthreads();
 #pragma unroll
         for (int h = 0; h < (VR ? 2 : 1); ++h) {
 #pragma unroll
             for (int u = 0; u < 13; ++u) red[u * RS + lane] = q[13 * h + u];
             __syncthreads();
-            if (lane < 13) {
-                const double2 *row = (const double2 *)(red + lane * RS);
-                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-#pragma unroll 4
-                for (int l = 0; l < 32; l += 2) {
-                    const double2 e0 = row[l], e1 = row[l + 1];
-                    s0 += e0.x; s1 += e0.y; s2 += e1.x; s3 += e1.y;
+            double t = 0.0;
+            if (row < 13) {
+                const double2 *rp = (const double2 *)(red + row * RS);
+                double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const double2 e = rp[4 * c + part];
+                    s0 += e.x;
+                    s1 += e.y;
                 }
-                const double t = (s0 + s1) + (s2 + s3);
-                if (h == 0) tot = t;
-                else second = t;
+                t = s0 + s1;
             }
+            t = quad_sum_f64(t);
+            if (part == h) tot = t;
             __syncthreads();
-        }
-        if (VR) {
-            const double moved = __shfl(second, lane >= 13 ? lane - 13 : 0, 64);
-            if (lane >= 13 && lane < 26) tot = moved;
         }
     } else {
         (void)red;
         const double t = wave_sum_many<K>(q);  // lane L: total of index L >> (VR ? 1 : 2)
         tot = __shfl(t, (lane << (VR ? 1 : 2)) & 63, 64);
     }
-    const uint32_t idx = (uint32_t)lane;
-    const bool writer = idx < (uint32_t)(VR ? kNsum : 13);
+    const int owned = owned_sum<View::kInLds, VR>(lane);
+    const uint32_t idx = (uint32_t)owned;
+    const bool writer = owned >= 0;
     const bool nonfinite = writer && !isfinite(tot);
     const bool bad_plain = __ballot(nonfinite && idx < 13) != 0ull;
     const bool bad_vr = __ballot(nonfinite && idx >= 13) != 0ull;

@@ -238,7 +238,7 @@ __device__ __forceinline__ void collide_lds_body(const CollideArgs<R> &a, unsign
         return;
     }
     const uint32_t step = (uint32_t)a.st->step_cur;
-    const CellPrefetch pf = prefetch_cell<R, VR>(a, cell);
+    const CellPrefetch pf = prefetch_cell<R, VR, true>(a, cell);
     const int cap = a.cap;
     R *vx = (R *)smem, *vy = vx + cap, *vz = vy + cap;
     R *w = VR ? vz + cap : nullptr;
@@ -283,7 +283,7 @@ __device__ __forceinline__ void collide_big_body(const CollideArgs<R> &a) {
                                  VR ? a.s.w + base : nullptr, nullptr, a.owner_g + base};
         for (uint32_t r = lane; r < N; r += 64) view.clear_own(r);
         __syncthreads();
-        const CellPrefetch pf = prefetch_cell<R, VR>(a, cell);
+        const CellPrefetch pf = prefetch_cell<R, VR, false>(a, cell);
         if (LEARNED) process_cell_learned<R, VR>(a, view, cell, N, step, pf);
         else process_cell<R, VR>(a, view, cell, N, step, pf);
         if (lane == 0) diag_add(a.st, kDiagBig, 1ull);

@@ -224,6 +224,20 @@ __device__ __forceinline__ double dpp_f64(double old, double v, int ctrl) {
     const uint32_t hi = dpp_u32((uint32_t)(o >> 32), (uint32_t)(x >> 32), ctrl, 0);
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
+// Value of another lane of the same quad (DPP quad permutation CTRL; every
+// source lane is valid, so no identity is needed).
+template <int CTRL>
+__device__ __forceinline__ double quad_perm_f64(double v) {
+    const uint64_t x = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, CTRL, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+// Sum over the four lanes of each quad, the same in all four.
+__device__ __forceinline__ double quad_sum_f64(double v) {
+    v += quad_perm_f64<0xB1>(v);  // lanes (0,1)(2,3) swapped
+    return v + quad_perm_f64<0x4E>(v);  // pairs swapped
+}
 __device__ __forceinline__ uint32_t dpp_any(uint32_t old, uint32_t v, int ctrl) { return dpp_u32(old, v, ctrl, 0); }
 __device__ __forceinline__ float dpp_any(float old, float v, int ctrl) { return dpp_f32(old, v, ctrl); }
 __device__ __forceinline__ double dpp_any(double old, double v, int ctrl) { return dpp_f64(old, v, ctrl); }

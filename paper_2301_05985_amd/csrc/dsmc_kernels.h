@@ -198,15 +198,15 @@ __device__ __forceinline__ int fly(const Geo &g, R &x, R &y, R &cx, R &cy, R &cz
 }
 
 // Cell coordinates floor(x nx / Lx), floor(y ny / Ly), each clamped to the
-// grid, in double; 2-D cells are numbered iy * nx + ix.
+// grid (NaN to 0), in double; 2-D cells are numbered iy * nx + ix.  The
+// product is clamped to [0, n - 1] first (max returns 0 for NaN), where
+// truncation equals floor.
+__device__ __forceinline__ int cell_coord(double t, int n) {
+    return (int)fmin(fmax(t, 0.0), (double)(n - 1));
+}
 __device__ __forceinline__ void cell_coords(const Geo &g, double x, double y, int &ix, int &iy) {
-    const double fx = floor(x * g.invx);
-    ix = !(fx >= 0.0) ? 0 : (fx > (double)(g.nx - 1) ? g.nx - 1 : (int)fx);
-    iy = 0;
-    if (g.dims == 2) {
-        const double fy = floor(y * g.invy);
-        iy = !(fy >= 0.0) ? 0 : (fy > (double)(g.ny - 1) ? g.ny - 1 : (int)fy);
-    }
+    ix = cell_coord(x * g.invx, g.nx);
+    iy = g.dims == 2 ? cell_coord(y * g.invy, g.ny) : 0;
 }
 __device__ __forceinline__ uint32_t cell_index(const Geo &g, double x, double y) {
     int ix, iy;
@@ -243,12 +243,11 @@ __device__ __forceinline__ uint8_t move_code(const Geo &g, int fx, int fy, int t
 // Streaming, in sequence order and in place, in two kernels.  The first
 // takes every particle whose free end point x + c dt lies inside the closed
 // box (the rule the flight itself applies first): it writes the new position
-// and the move code and counts the new cell; P particles per thread, all
-// loads issued first.  Particles that would leave the box go to a list that
-// the second kernel flies exactly, wall conditions included, and finishes in
-// the same way.  Keeping the rare wall path out of the first kernel keeps
-// its register use, and so the number of loads in flight, at the level of a
-// plain streaming kernel.
+// and the move code and counts the new cell.  Particles that would leave the
+// box go to a list that the second kernel flies exactly, wall conditions
+// included, and finishes in the same way.  Keeping the rare wall path out of
+// the first kernel keeps its register use, and so the number of loads in
+// flight, at the level of a plain streaming kernel.
 template <typename R, int D>
 __device__ __forceinline__ void finish_move(const Geo &g, int64_t p, int fx, int fy, R x, R y, uint8_t *code,
                                             uint32_t *far_head, uint32_t *far_src, uint32_t *far_next,
@@ -265,44 +264,132 @@ __device__ __forceinline__ void finish_move(const Geo &g, int64_t p, int fx, int
     }
 }
 
-template <typename R, int D, int P>
+template <typename R>
+__device__ __forceinline__ void load4(const R *p, R (&v)[4]) {
+    if constexpr (sizeof(R) == 4) {
+        const float4 t = *(const float4 *)p;
+        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    } else {
+        const double2 a = ((const double2 *)p)[0], b = ((const double2 *)p)[1];
+        v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+    }
+}
+template <typename R>
+__device__ __forceinline__ void store4(R *p, const R (&v)[4]) {
+    if constexpr (sizeof(R) == 4) {
+        *(float4 *)p = make_float4(v[0], v[1], v[2], v[3]);
+    } else {
+        ((double2 *)p)[0] = make_double2(v[0], v[1]);
+        ((double2 *)p)[1] = make_double2(v[2], v[3]);
+    }
+}
+
+// Workgroup of 256 threads, 4 consecutive particles per thread (vector loads
+// and stores; one 32-bit store of the four move codes).  New-cell counts go
+// to 2048 LDS bins covering the cells base .. base + 2047, base one row and
+// one cell before the old cell of the workgroup's first particle: the
+// sequence is grouped by cell, so the workgroup's particles come from a few
+// consecutive cells and, apart from far movers and wrapped periodic moves,
+// land within one row of them.  The bins are added to the global counts
+// once per workgroup; cells outside the window are counted directly.
+constexpr int kStreamBins = 2048;
+
+template <typename R, int D>
 __global__ __launch_bounds__(256) void k_stream_code(Geo g, Soa<R> s, int64_t n, uint8_t *code, uint32_t *count,
                                                      uint32_t *far_head, uint32_t *far_src, uint32_t *far_next,
                                                      uint32_t *wall_list, DevState *st) {
-    const int64_t p0 = (int64_t)blockIdx.x * (256 * P) + threadIdx.x;
+    __shared__ uint4 bins4[kStreamBins / 4];
+    __shared__ uint32_t base_sh;
+    uint32_t *bins = (uint32_t *)bins4;
+    const uint32_t tid = threadIdx.x;
+    const int64_t p0 = (int64_t)blockIdx.x * 1024 + 4 * tid;  // first particle of this thread
+    const int64_t left = n - p0;
+    const int nv = left >= 4 ? 4 : (left > 0 ? (int)left : 0);
+    bins4[tid] = make_uint4(0u, 0u, 0u, 0u);
+    bins4[tid + 256] = make_uint4(0u, 0u, 0u, 0u);
     const R tau = (R)g.dt, Lx = (R)g.Lx, Ly = (R)g.Ly, zero = (R)0;
-    R x[P], y[P], cx[P], cy[P];
-#pragma unroll
-    for (int k = 0; k < P; ++k) {
-        const int64_t p = p0 + 256 * k;
-        if (p < n) {
-            x[k] = s.x[p];
-            y[k] = D == 2 ? s.y[p] : zero;
-            cx[k] = s.cx[p];
-            cy[k] = D == 2 ? s.cy[p] : zero;
+    R x[4], y[4], cx[4], cy[4];
+    if (nv == 4) {
+        load4(s.x + p0, x);
+        load4(s.cx + p0, cx);
+        if (D == 2) {
+            load4(s.y + p0, y);
+            load4(s.cy + p0, cy);
         }
-    }
+    } else {
 #pragma unroll
-    for (int k = 0; k < P; ++k) {
-        const int64_t p = p0 + 256 * k;
-        const bool act = p < n;
-        bool inside = false;
-        uint32_t cell = 0;
-        if (act) {
-            const R xe = x[k] + cx[k] * tau;
-            const R ye = D == 2 ? y[k] + cy[k] * tau : zero;
-            inside = xe >= zero && xe <= Lx && (D < 2 || (ye >= zero && ye <= Ly));
-            if (inside) {
-                int fx, fy;
-                cell_coords(g, (double)x[k], D == 2 ? (double)y[k] : 0.0, fx, fy);
-                s.x[p] = xe;
-                if (D == 2) s.y[p] = ye;
-                finish_move<R, D>(g, p, fx, fy, xe, ye, code, far_head, far_src, far_next, st, cell);
+        for (int k = 0; k < 4; ++k) {
+            const bool a = k < nv;
+            x[k] = a ? s.x[p0 + k] : zero;
+            cx[k] = a ? s.cx[p0 + k] : zero;
+            if (D == 2) {
+                y[k] = a ? s.y[p0 + k] : zero;
+                cy[k] = a ? s.cy[p0 + k] : zero;
             }
         }
-        wave_aggregated_add(count, cell, act && inside);
+    }
+    if (D < 2) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) { y[k] = zero; cy[k] = zero; }
+    }
+    uint32_t cell[4];
+    bool in[4];
+    uint32_t codes = 0;
+    int fx0 = 0, fy0 = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const R xe = x[k] + cx[k] * tau;
+        const R ye = D == 2 ? y[k] + cy[k] * tau : zero;
+        in[k] = k < nv && xe >= zero && xe <= Lx && (D < 2 || (ye >= zero && ye <= Ly));
+        int fx, fy;
+        cell_coords(g, (double)x[k], D == 2 ? (double)y[k] : 0.0, fx, fy);
+        if (k == 0) {
+            fx0 = fx;
+            fy0 = fy;
+        }
+        uint32_t mc = kFarMove;  // particles of the wall list get theirs from the second kernel
+        cell[k] = 0;
+        if (in[k]) {
+            int tx, ty;
+            cell_coords(g, (double)xe, D == 2 ? (double)ye : 0.0, tx, ty);
+            cell[k] = (uint32_t)ty * (uint32_t)g.nx + (uint32_t)tx;
+            mc = move_code(g, fx, fy, tx, ty);
+            x[k] = xe;
+            y[k] = ye;
+            if (mc == kFarMove) {
+                const uint32_t q = atomicAdd(&st->far_count, 1u);
+                far_src[q] = (uint32_t)(p0 + k);
+                far_next[q] = atomicExch(&far_head[cell[k]], q);
+            }
+        }
+        codes |= mc << (8 * k);
+    }
+    // particles of the wall list keep their stored position and velocity
+    if (nv == 4) {
+        store4(s.x + p0, x);
+        if (D == 2) store4(s.y + p0, y);
+        *(uint32_t *)(code + p0) = codes;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (k < nv) {
+                s.x[p0 + k] = x[k];
+                if (D == 2) s.y[p0 + k] = y[k];
+                code[p0 + k] = (uint8_t)(codes >> (8 * k));
+            }
+    }
+    if (tid == 0) base_sh = (uint32_t)fy0 * (uint32_t)g.nx + (uint32_t)fx0 - (D == 2 ? (uint32_t)g.nx : 0u) - 1u;
+    __syncthreads();
+    const uint32_t base = base_sh;  // modulo 2^32: cell - base is the bin
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (in[k]) {
+            const uint32_t b = cell[k] - base;
+            if (b < (uint32_t)kStreamBins) atomicAdd(&bins[b], 1u);
+            else atomicAdd(&count[cell[k]], 1u);
+        }
         // particles that meet a wall: one list slot each, one atomic per wave
-        const bool wall = act && !inside;
+        const bool wall = k < nv && !in[k];
         const unsigned long long bal = __ballot(wall);
         if (bal) {
             const int lane = lane_id();
@@ -310,8 +397,18 @@ __global__ __launch_bounds__(256) void k_stream_code(Geo g, Soa<R> s, int64_t n,
             uint32_t b0 = 0;
             if (lane == leader) b0 = atomicAdd(&st->wall_count, (uint32_t)__popcll(bal));
             b0 = (uint32_t)__shfl((int)b0, leader, 64);
-            if (wall) wall_list[b0 + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull))] = (uint32_t)p;
+            if (wall) wall_list[b0 + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull))] = (uint32_t)(p0 + k);
         }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const uint4 c = bins4[tid + 256 * h];
+        const uint32_t b = base + 4u * (tid + 256u * h);
+        if (c.x) atomicAdd(&count[b], c.x);
+        if (c.y) atomicAdd(&count[b + 1u], c.y);
+        if (c.z) atomicAdd(&count[b + 2u], c.z);
+        if (c.w) atomicAdd(&count[b + 3u], c.w);
     }
 }
 

@@ -103,3 +103,20 @@ def test_autotune_signature_separates_workloads():
     q, _ = W.batched(n_inst=64, nmin=10, nmax=200, seed=1)
     assert sig != autotune.signature(q)  # other instance sizes
     assert all(c["schedule"] in (0, 1) for c in autotune.CANDIDATES)
+
+
+def test_init_rejects_misaligned_particle_arrays(lib):
+    # validation happens before any device call: the addresses below are
+    # never dereferenced
+    p, parts = W.cavity(nx=4, ny=4, per_cell=5, real="f32")
+    n = len(parts["cx"])
+    cfg = binding.make_config(p, n)
+    ctx = ctypes.c_void_p()
+    fake = 1 << 40
+    names = ("x", "y", "cx", "cy", "cz", "w", "id")
+    for field in ("x", "y", "cx", "cy", "cz", "id"):
+        soa = binding.Soa(*(fake + k * (1 << 20) + (4 if f == field else 0) for k, f in enumerate(names)))
+        rc = lib.dsmc_init(ctypes.byref(cfg), ctypes.byref(soa), ctypes.c_void_p(fake + (1 << 30)),
+                           ctypes.c_size_t(1 << 40), None, ctypes.byref(ctx))
+        assert rc == -1, field
+        assert not ctx.value

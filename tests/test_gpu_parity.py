@@ -285,10 +285,10 @@ def test_repeatable_and_direct_launch_matches_graph(gpu):
     for mode in ("graph", "graph", "direct"):
         s = Simulation(p, parts)
         if mode == "graph":
-            s.step(9)
+            s.step(10)
         else:
-            for _ in range(9):
-                s.profile_step()
+            for _ in range(5):
+                s.profile_step()  # an untimed step, then a step of separate timed launches
         runs.append(s.particles())
         s.close()
     for k in ("x", "y", "cx", "cy", "cz", "w"):
