@@ -101,26 +101,72 @@ struct GlobalView {
 // r_p = |c_p - m|, bound = (r_(1) + r_(2)) (1 + eps) >= |c_i - c_j| for every
 // pair (triangle inequality); computed in double from max/min and top-two
 // reductions, so the value does not depend on the order of the particles.
+//
+// In float the box extremes are reduced as unsigned keys that order like
+// the values (sign-magnitude to offset binary: negative values inverted,
+// positive ones with the top bit set; -0 sorts below +0, which changes no
+// midpoint), so every reduction step is one DPP-fused integer min; maxima
+// are minima of the inverted keys.  The top two r^2 (non-negative doubles,
+// whose bit patterns order like their values) are found as the wave maximum
+// of the high words, then of the low words among the lanes holding that
+// high word; the second one the same way over every lane's largest value,
+// except its second largest on the first lane holding the maximum.
+__device__ __forceinline__ uint32_t order_key(float f) {
+    const uint32_t b = __float_as_uint(f);
+    return b ^ ((uint32_t)((int32_t)b >> 31) | 0x80000000u);
+}
+__device__ __forceinline__ float from_order_key(uint32_t k) {
+    return __uint_as_float((k & 0x80000000u) ? (k ^ 0x80000000u) : ~k);
+}
+
+// Wave maximum of non-negative doubles (exact, as 64-bit patterns).
+__device__ __forceinline__ double wave_max_nonneg(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t hi = (uint32_t)(b >> 32), lo = (uint32_t)b;
+    const uint32_t hmax = ~wave_min_u32(~hi);
+    const uint32_t lmax = ~wave_min_u32(hi == hmax ? ~lo : 0xFFFFFFFFu);
+    return __longlong_as_double((long long)(((uint64_t)hmax << 32) | lmax));
+}
+
 template <typename R, typename View>
 __device__ double exact_bound(const View &v, uint32_t N, double &r_top) {
     const int lane = lane_id();
-    // box extremes: min and max are exact in the working precision
-    R lo0 = (R)INFINITY, lo1 = (R)INFINITY, lo2 = (R)INFINITY;
-    R hi0 = -(R)INFINITY, hi1 = -(R)INFINITY, hi2 = -(R)INFINITY;
-    for (uint32_t r = lane; r < N; r += 64) {
-        R a, b, c;
-        v.get(r, a, b, c);
-        lo0 = fmin(lo0, a); hi0 = fmax(hi0, a);
-        lo1 = fmin(lo1, b); hi1 = fmax(hi1, b);
-        lo2 = fmin(lo2, c); hi2 = fmax(hi2, c);
+    double m0, m1, m2;
+    if constexpr (sizeof(R) == 4) {
+        uint32_t lo0 = ~0u, lo1 = ~0u, lo2 = ~0u, nh0 = ~0u, nh1 = ~0u, nh2 = ~0u;  // min keys, min inverted keys
+        for (uint32_t r = lane; r < N; r += 64) {
+            R a, b, c;
+            v.get(r, a, b, c);
+            const uint32_t ka = order_key(a), kb = order_key(b), kc = order_key(c);
+            lo0 = min(lo0, ka); nh0 = min(nh0, ~ka);
+            lo1 = min(lo1, kb); nh1 = min(nh1, ~kb);
+            lo2 = min(lo2, kc); nh2 = min(nh2, ~kc);
+        }
+        lo0 = wave_min_u32(lo0); lo1 = wave_min_u32(lo1); lo2 = wave_min_u32(lo2);
+        nh0 = wave_min_u32(nh0); nh1 = wave_min_u32(nh1); nh2 = wave_min_u32(nh2);
+        m0 = 0.5 * ((double)from_order_key(~nh0) + (double)from_order_key(lo0));
+        m1 = 0.5 * ((double)from_order_key(~nh1) + (double)from_order_key(lo1));
+        m2 = 0.5 * ((double)from_order_key(~nh2) + (double)from_order_key(lo2));
+    } else {
+        // box extremes: min and max are exact in the working precision
+        R lo0 = (R)INFINITY, lo1 = (R)INFINITY, lo2 = (R)INFINITY;
+        R hi0 = -(R)INFINITY, hi1 = -(R)INFINITY, hi2 = -(R)INFINITY;
+        for (uint32_t r = lane; r < N; r += 64) {
+            R a, b, c;
+            v.get(r, a, b, c);
+            lo0 = fmin(lo0, a); hi0 = fmax(hi0, a);
+            lo1 = fmin(lo1, b); hi1 = fmax(hi1, b);
+            lo2 = fmin(lo2, c); hi2 = fmax(hi2, c);
+        }
+        const auto mn = [](R a, R b) { return fmin(a, b); };
+        const auto mx = [](R a, R b) { return fmax(a, b); };
+        const R inf = (R)INFINITY;
+        lo0 = wave_reduce_dpp(lo0, inf, mn); lo1 = wave_reduce_dpp(lo1, inf, mn); lo2 = wave_reduce_dpp(lo2, inf, mn);
+        hi0 = wave_reduce_dpp(hi0, -inf, mx); hi1 = wave_reduce_dpp(hi1, -inf, mx); hi2 = wave_reduce_dpp(hi2, -inf, mx);
+        m0 = 0.5 * ((double)hi0 + (double)lo0);
+        m1 = 0.5 * ((double)hi1 + (double)lo1);
+        m2 = 0.5 * ((double)hi2 + (double)lo2);
     }
-    const auto mn = [](R a, R b) { return fmin(a, b); };
-    const auto mx = [](R a, R b) { return fmax(a, b); };
-    const R inf = (R)INFINITY;
-    lo0 = wave_reduce_dpp(lo0, inf, mn); lo1 = wave_reduce_dpp(lo1, inf, mn); lo2 = wave_reduce_dpp(lo2, inf, mn);
-    hi0 = wave_reduce_dpp(hi0, -inf, mx); hi1 = wave_reduce_dpp(hi1, -inf, mx); hi2 = wave_reduce_dpp(hi2, -inf, mx);
-    const double m0 = 0.5 * ((double)hi0 + (double)lo0), m1 = 0.5 * ((double)hi1 + (double)lo1),
-                 m2 = 0.5 * ((double)hi2 + (double)lo2);
     double a1 = 0.0, a2 = 0.0;  // largest, second largest r^2 of this lane
     for (uint32_t r = lane; r < N; r += 64) {
         R a, b, c;
@@ -130,22 +176,13 @@ __device__ double exact_bound(const View &v, uint32_t N, double &r_top) {
         if (r2 > a1) { a2 = a1; a1 = r2; }
         else if (r2 > a2) { a2 = r2; }
     }
-    // top two over the wave with DPP moves of both values (identity 0, 0)
-#define DSMC_TOP2_STEP(ctrl)                                                \
-    {                                                                       \
-        const double o1 = dpp_f64(0.0, a1, ctrl), o2 = dpp_f64(0.0, a2, ctrl); \
-        const double n1 = fmax(a1, o1);                                     \
-        const double n2 = fmax(fmin(a1, o1), fmax(a2, o2));                 \
-        a1 = n1; a2 = n2;                                                   \
-    }
-    DSMC_TOP2_STEP(0x111) DSMC_TOP2_STEP(0x112) DSMC_TOP2_STEP(0x114) DSMC_TOP2_STEP(0x118)
-    DSMC_TOP2_STEP(0x142) DSMC_TOP2_STEP(0x143)
-#undef DSMC_TOP2_STEP
-    a1 = read_lane63(a1);
-    a2 = read_lane63(a2);
-    r_top = sqrt(a1);
+    const double t1 = wave_max_nonneg(a1);
+    const unsigned long long at = __ballot(a1 == t1);
+    const bool first = lane == __ffsll((long long)at) - 1;
+    const double t2 = wave_max_nonneg(first ? a2 : a1);
+    r_top = sqrt(t1);
     const double eps = sizeof(R) == 4 ? 0x1.0p-20 : 0x1.0p-50;
-    return (sqrt(a1) + sqrt(a2)) * (1.0 + eps);
+    return (sqrt(t1) + sqrt(t2)) * (1.0 + eps);
 }
 
 // The largest pair speed of the cell by brute force (lane r takes rows
@@ -517,6 +554,8 @@ __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cel
     double q[K];
 #pragma unroll
     for (int t = 0; t < K; ++t) q[t] = 0.0;
+    // products are added with fused multiply-adds (the sums are compared
+    // with a tolerance; the particle state is what must match exactly)
     for (uint32_t r = lane; r < N; r += 64) {
         R x, y, z;
         v.get(r, x, y, z);
@@ -527,15 +566,19 @@ __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cel
             if (VR) a.s.w[wb_base + r] = w;
         }
         const double vx = (double)x, vy = (double)y, vz = (double)z;
-        const double c2 = (vx * vx + vy * vy) + vz * vz;
-        const double t[13] = {1.0, vx, vy, vz, vx * vx, vy * vy, vz * vz, vx * vy, vx * vz, vy * vz,
-                              vx * c2, vy * c2, vz * c2};
-#pragma unroll
-        for (int u = 0; u < 13; ++u) q[u] += t[u];
+        const double xx = vx * vx, yy = vy * vy, zz = vz * vz;
+        const double c2 = (xx + yy) + zz;
+        q[0] += 1.0; q[1] += vx; q[2] += vy; q[3] += vz;
+        q[4] += xx; q[5] += yy; q[6] += zz;
+        q[7] = fma(vx, vy, q[7]); q[8] = fma(vx, vz, q[8]); q[9] = fma(vy, vz, q[9]);
+        q[10] = fma(vx, c2, q[10]); q[11] = fma(vy, c2, q[11]); q[12] = fma(vz, c2, q[12]);
         if (VR) {
             const double f = 1.0 - (double)w;
-#pragma unroll
-            for (int u = 0; u < 13; ++u) q[(13 + u) % K] += f * t[u];
+            const double fx = f * vx, fy = f * vy, fz = f * vz;
+            q[13] += f; q[14] += fx; q[15] += fy; q[16] += fz;
+            q[17] = fma(fx, vx, q[17]); q[18] = fma(fy, vy, q[18]); q[19] = fma(fz, vz, q[19]);
+            q[20] = fma(fx, vy, q[20]); q[21] = fma(fx, vz, q[21]); q[22] = fma(fy, vz, q[22]);
+            q[23] = fma(fx, c2, q[23]); q[24] = fma(fy, c2, q[24]); q[25] = fma(fz, c2, q[25]);
         }
     }
     // each lane ends up with the total of the sum it owns

@@ -31,6 +31,10 @@ __device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
         c3 = lo_a;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
+        // the round keys are recomputed (two scalar adds) rather than kept:
+        // hoisted out of the callers' loops they would hold 20 scalar
+        // registers for the whole kernel
+        asm volatile("" : "+s"(k0), "+s"(k1));
     }
     u32x4 o;
     o.v[0] = c0; o.v[1] = c1; o.v[2] = c2; o.v[3] = c3;
