@@ -39,7 +39,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
     size_t alt[7];  // x y cx cy cz w id of the second particle buffer
     size_t count, offset, offset2, cursor, sums, counters, volume, state, big_list, perm, owner, sched, flags, done,
-        units, code, far_head, far_src, far_next, wall_list;
+        units, code, far_head, far_src, far_next, wall_list, mcount, movers;
     size_t mlp, lattice;
     size_t total;
 };
@@ -107,6 +107,8 @@ Layout make_layout(const dsmc_config &c) {
         L.far_src = take(n * 4);
         L.far_next = take(n * 4);
         L.wall_list = take(n * 4);
+        L.mcount = take(nc * 4);
+        L.movers = take(nc * kMoverSlots * 4);
     }
     L.offset = take((nc + 1) * 4);
     L.sums = take(nc * kNsum * 8);
@@ -157,6 +159,7 @@ struct dsmc_ctx {
     uint32_t *off[2] = {nullptr, nullptr};
     uint8_t *code = nullptr;
     uint32_t *far_head = nullptr, *far_src = nullptr, *far_next = nullptr, *wall_list = nullptr;
+    uint32_t *mcount = nullptr, *movers = nullptr;
     double *sums = nullptr, *volume = nullptr, *lattice = nullptr;
     unsigned long long *counters = nullptr;
     float *mlp = nullptr;
@@ -179,6 +182,17 @@ Soa<R> soa_of(const Bufs &b) {
     return s;
 }
 
+Regroup regroup_of(const dsmc_ctx *c) {
+    Regroup r;
+    r.code = c->code;
+    r.mcount = c->mcount;
+    r.movers = c->movers;
+    r.far_head = c->far_head;
+    r.far_src = c->far_src;
+    r.far_next = c->far_next;
+    return r;
+}
+
 // Collision arguments for a step reading buffer src and writing dst (the
 // same buffer for homogeneous instances, the other one for walled runs).
 template <typename R>
@@ -193,14 +207,7 @@ CollideArgs<R> collide_args(dsmc_ctx *c, int src, int dst) {
         a.start = c->off[dst];
         a.src = soa_of<R>(c->buf[src]);
         a.src_start = c->off[src];
-        a.code = c->code;
-        a.far_head = c->far_head;
-        a.far_src = c->far_src;
-        a.far_next = c->far_next;
-        a.nx = c->geo.nx;
-        a.ny = c->geo.ny;
-        a.periodic_x = c->cfg.wall_kind[0] == DSMC_WALL_PERIODIC;
-        a.periodic_y = c->cfg.dims == 2 && c->cfg.wall_kind[2] == DSMC_WALL_PERIODIC;
+        a.rg = regroup_of(c);
     }
     a.volume = c->cfg.cell_volume ? c->volume : nullptr;
     a.Vuni = c->Vuni;
@@ -277,10 +284,10 @@ void launch_stream(dsmc_ctx *c, Launcher &L, int src) {
         const Soa<R> s = soa_of<R>(c->buf[src]);
         L.mark("stream");
         hipLaunchKernelGGL((k_stream_code<R, D>), dim3(grid), dim3(256), 0, L.s, c->geo, s, (int64_t)c->n,
-                           c->code, c->count, c->far_head, c->far_src, c->far_next, c->wall_list, c->st);
+                           regroup_of(c), c->count, c->wall_list, c->st);
         L.mark("stream_walls");
-        hipLaunchKernelGGL((k_stream_walls<R, D, VR>), dim3(kWallGrid), dim3(256), 0, L.s, c->geo, s, c->code,
-                           c->count, c->far_head, c->far_src, c->far_next, (const uint32_t *)c->wall_list, c->st);
+        hipLaunchKernelGGL((k_stream_walls<R, D, VR>), dim3(kWallGrid), dim3(256), 0, L.s, c->geo, s, regroup_of(c),
+                           c->count, (const uint32_t *)c->wall_list, c->st);
     }
     L.mark("scan");
     hipLaunchKernelGGL(k_scan_lookback, dim3((unsigned)((c->ncell + kScanTile - 1) / kScanTile)), dim3(256), 0, L.s,
@@ -457,6 +464,8 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
         c->far_src = (uint32_t *)(c->ws + L.far_src);
         c->far_next = (uint32_t *)(c->ws + L.far_next);
         c->wall_list = (uint32_t *)(c->ws + L.wall_list);
+        c->mcount = (uint32_t *)(c->ws + L.mcount);
+        c->movers = (uint32_t *)(c->ws + L.movers);
         c->off[1] = (uint32_t *)(c->ws + L.offset2);
     } else {
         c->buf[1] = c->buf[0];
@@ -599,7 +608,9 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
             return fail(DSMC_EHIP);
     } else {
         // empty far-mover lists, then the initial particle sequence
-        if (hipMemsetAsync(c->far_head, 0xFF, (size_t)c->ncell * 4, c->stream) != hipSuccess) return fail(DSMC_EHIP);
+        if (hipMemsetAsync(c->far_head, 0xFF, (size_t)c->ncell * 4, c->stream) != hipSuccess ||
+            hipMemsetAsync(c->mcount, 0, (size_t)c->ncell * 4, c->stream) != hipSuccess)
+            return fail(DSMC_EHIP);
         walled_setup(c, true);
         if (hipGetLastError() != hipSuccess) return fail(DSMC_EHIP);
     }

@@ -30,13 +30,11 @@ struct CollideArgs {
     const uint32_t *start;         // [ncell + 1] first particle of each cell
     const uint32_t *sched;         // block -> cell, or null for the identity
     // walled runs: s is written in the new sequence, gathered from src (the
-    // streamed particles in the previous sequence) by move code
+    // streamed particles in the previous sequence): each cell's stays and
+    // movers (the regrouping lists, reset once read)
     Soa<R> src;
     const uint32_t *src_start;     // [ncell + 1] cell ranges of src
-    const uint8_t *code;           // [n] move code of each src particle
-    uint32_t *far_head;            // [ncell] far-mover list heads, reset once read
-    const uint32_t *far_src, *far_next;
-    int nx, ny, periodic_x, periodic_y;
+    Regroup rg;
     const double *volume;          // per-cell volume, or null for Vuni
     double Vuni, dt, sigma, FN;
     double omega1;                 // VHS: 1 - omega

@@ -9,136 +9,116 @@ namespace dsmc {
 
 // ------------------------------------------------ gather of a walled cell
 // Cell t of the new sequence holds, in order, the particles of the previous
-// sequence whose new cell is t (a stable counting sort).  They come from the
-// cells around t: along each axis t - 1, t and t + 1 (wrapped when periodic,
-// dropped outside the grid), visited in ascending cell index, so that taking
-// in each source cell the particles whose move code leads to t, in position
-// order, yields them in ascending position.  Far movers (from farther away)
-// are taken from the cell's list and merged by position.
+// sequence whose new cell is t (a stable counting sort).  In ascending
+// position these are the movers from cells before t, the particles that
+// stayed in t (found from t's own range of code bytes), and the movers from
+// cells after t: the movers, listed by the streaming pass in no particular
+// order, are sorted across the wave and split at t's range.  Overflow movers
+// (beyond the slot list, rare) are appended and the whole selection is then
+// merged by position.
 
-// Distinct source coordinates of destination coordinate t along one axis,
-// ascending, with the move code step from each to t.
-struct AxisSources {
-    int n;
-    int c[3], d[3];
-};
-
-__device__ __forceinline__ AxisSources axis_sources(int t, int n, bool periodic) {
-    constexpr int kNone = 0x7FFFFFFF;
-    int a = t - 1, b = t + 1;
-    if (periodic) {
-        a = a < 0 ? a + n : a;
-        b = b >= n ? b - n : b;
-    } else {
-        a = a < 0 ? kNone : a;
-        b = b >= n ? kNone : b;
-    }
-    int v0 = a, v1 = t, v2 = b, tmp;
-    if (v0 > v1) { tmp = v0; v0 = v1; v1 = tmp; }
-    if (v1 > v2) { tmp = v1; v1 = v2; v2 = tmp; }
-    if (v0 > v1) { tmp = v0; v0 = v1; v1 = tmp; }
-    AxisSources r;
-    const int w1 = v1 > v0 ? v1 : v2;  // the next distinct value, if any
-    const bool h1 = w1 > v0 && w1 != kNone;
-    const bool h2 = h1 && v1 > v0 && v2 > v1 && v2 != kNone;
-    r.n = 1 + (h1 ? 1 : 0) + (h2 ? 1 : 0);
-    r.c[0] = v0;
-    r.c[1] = w1;
-    r.c[2] = v2;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) r.d[k] = axis_move(r.c[k] == kNone ? t : r.c[k], t, n, periodic);
-    return r;
+// Lane v ^ J of a 64-lane value (J a power of two).
+template <int J>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
+    if constexpr (J == 1) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+    else if constexpr (J == 2) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
+    else if constexpr (J < 32) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, (J << 10) | 0x1F);
+    else return (uint32_t)__shfl_xor((int)v, 32, 64);
 }
 
-// Near movers of `cell`: source positions written to sel[0..) in ascending
-// order (at most N are written); returns how many were found.  The first
-// PRE x 64 codes of every source cell are loaded before any is consumed.
-template <typename R, int D>
-__device__ __forceinline__ uint32_t select_near(const CollideArgs<R> &a, uint32_t cell, uint32_t N, uint32_t *sel) {
-    constexpr int PRE = D == 1 ? 4 : 2;
-    constexpr int NS = D == 1 ? 3 : 9;
-    const int lane = lane_id();
-    const unsigned long long lt = (1ull << lane) - 1ull;
-    const int tx = (int)(cell % (uint32_t)a.nx), ty = (int)(cell / (uint32_t)a.nx);
-    const AxisSources xs = axis_sources(tx, a.nx, a.periodic_x != 0);
-    AxisSources ys;
-    if (D == 2) {
-        ys = axis_sources(ty, a.ny, a.periodic_y != 0);
-    } else {
-        ys.n = 1;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) { ys.c[k] = 0; ys.d[k] = 0; }
-    }
-    if (N == 0) return 0;  // nothing lands here (and the sequence may be empty)
-    uint32_t b[NS], e[NS];
-    uint32_t req[NS];
-    uint32_t cd[NS][PRE];
-    // every load below is issued unconditionally from an in-bounds address
-    // (positions past a source range are clamped to the last particle) and
-    // masked afterwards: no branches around the loads
-    const uint32_t last = a.src_start[(uint32_t)a.nx * (uint32_t)(D == 2 ? a.ny : 1)] - 1u;
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-        const int iy = k / 3, ix = k % 3;
-        const bool ok = ix < xs.n && iy < ys.n;
-        const uint32_t src = ok ? (uint32_t)ys.c[iy] * (uint32_t)a.nx + (uint32_t)xs.c[ix] : 0u;
-        const uint32_t lb = a.src_start[src], le = a.src_start[src + 1];
-        b[k] = ok ? lb : 0u;
-        e[k] = ok ? le : 0u;
-        req[k] = (uint32_t)((xs.d[ix] + 1) + 3 * (ys.d[iy] + 1));
-    }
-#pragma unroll
-    for (int k = 0; k < NS; ++k)
-#pragma unroll
-        for (int j = 0; j < PRE; ++j) {
-            const uint32_t i = b[k] + (uint32_t)(64 * j + lane);
-            const uint32_t v = (uint32_t)a.code[i < e[k] ? i : last];
-            cd[k][j] = i < e[k] ? v : (uint32_t)kFarMove;
-        }
-    uint32_t nsel = 0;
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-#pragma unroll
-        for (int j = 0; j < PRE; ++j) {
-            const bool m = cd[k][j] == req[k];
-            const unsigned long long bal = __ballot(m);
-            if (m) {
-                const uint32_t pos = nsel + (uint32_t)__popcll(bal & lt);
-                if (pos < N) sel[pos] = b[k] + (uint32_t)(64 * j + lane);
-            }
-            nsel += (uint32_t)__popcll(bal);
-        }
-        // source cells longer than the preloaded part
-        for (uint32_t i0 = b[k] + 64 * PRE; i0 < e[k]; i0 += 64) {
-            const uint32_t i = i0 + (uint32_t)lane;
-            const bool m = i < e[k] && (uint32_t)a.code[i] == req[k];
-            const unsigned long long bal = __ballot(m);
-            if (m) {
-                const uint32_t pos = nsel + (uint32_t)__popcll(bal & lt);
-                if (pos < N) sel[pos] = i;
-            }
-            nsel += (uint32_t)__popcll(bal);
-        }
-    }
-    return nsel;
+// One compare-exchange stage of a bitonic sort (block size K, distance J):
+// ascending blocks keep the minimum on the lower lane.
+template <int K, int J>
+__device__ __forceinline__ uint32_t bitonic_stage(uint32_t v, uint32_t lane) {
+    const uint32_t o = xor_lane<J>(v);
+    const bool keep_min = ((lane & J) == 0) == ((lane & K) == 0 || K == 64);
+    const uint32_t lo = v < o ? v : o, hi = v < o ? o : v;
+    return keep_min ? lo : hi;
+}
+template <int K, int J>
+__device__ __forceinline__ uint32_t bitonic_merge(uint32_t v, uint32_t lane) {
+    v = bitonic_stage<K, J>(v, lane);
+    if constexpr (J > 1) v = bitonic_merge<K, J / 2>(v, lane);
+    return v;
+}
+// Ascending sort of one value per lane over the first W lanes (W 32 or 64).
+template <int W>
+__device__ __forceinline__ uint32_t bitonic_sort(uint32_t v, uint32_t lane) {
+    v = bitonic_merge<2, 1>(v, lane);
+    v = bitonic_merge<4, 2>(v, lane);
+    v = bitonic_merge<8, 4>(v, lane);
+    v = bitonic_merge<16, 8>(v, lane);
+    v = bitonic_merge<(W == 32 ? 64 : 32), 16>(v, lane);  // W 32: the last stage, ascending
+    if constexpr (W == 64) v = bitonic_merge<64, 32>(v, lane);
+    return v;
 }
 
-// Far movers of `cell`: walked by lane 0 from the cell's list into
-// sel[n_near..N); the list head is reset for the next step.  Any mismatch
-// with the cell's count is reported, and sel is filled with valid positions.
+// Selection of `cell`: source positions written to sel[0..N) (sel holds at
+// least N entries); returns whether they must still be merged by position
+// (overflow movers).  Any mismatch with the cell's count is reported, and sel
+// is filled with valid positions.
 template <typename R>
-__device__ __forceinline__ void select_far(const CollideArgs<R> &a, uint32_t cell, uint32_t n_near, uint32_t N,
-                                           uint32_t *sel) {
-    if (lane_id() == 0) {
-        uint32_t k = a.far_head[cell], m = n_near;
-        while (k != kEmpty && m < N) {
-            sel[m++] = a.far_src[k];
-            k = a.far_next[k];
-        }
-        if (k != kEmpty || m != N) set_error(a.st, DSMC_ECAPACITY);
-        while (m < N) sel[m++] = 0u;
-        a.far_head[cell] = kEmpty;
+__device__ __forceinline__ bool select_cell(const CollideArgs<R> &a, uint32_t cell, uint32_t N, uint32_t *sel) {
+    const uint32_t lane = (uint32_t)lane_id();
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    if (N == 0) return false;  // nothing lands here (and the sequence may be empty)
+    const uint32_t b = a.src_start[cell], e = a.src_start[cell + 1];
+    const uint32_t mc = a.rg.mcount[cell];
+    const uint32_t nm = mc < kMoverSlots ? mc : kMoverSlots;
+    uint32_t v = lane < nm ? a.rg.movers[(size_t)cell * kMoverSlots + lane] : 0xFFFFFFFFu;
+    // the codes of the cell's own range, the first two chunks loaded at once
+    // every load below is issued from an in-bounds address (the sequence is
+    // not empty) and masked afterwards
+    const uint32_t last = e > b ? e - 1u : (b > 0u ? b - 1u : 0u);
+    const uint32_t i0 = b + lane, i1 = b + 64u + lane;
+    const uint8_t c0 = a.rg.code[i0 < e ? i0 : last], c1 = a.rg.code[i1 < e ? i1 : last];
+    v = nm > 32 ? bitonic_sort<64>(v, lane) : bitonic_sort<32>(v, lane);
+    const uint32_t nlow = (uint32_t)__popcll(__ballot(lane < nm && v < b));
+    uint32_t nstay = 0;
+    {
+        const bool m = i0 < e && c0 == kStay;
+        const unsigned long long bal = __ballot(m);
+        const uint32_t pos = nlow + (uint32_t)__popcll(bal & lt);
+        if (m && pos < N) sel[pos] = i0;
+        nstay += (uint32_t)__popcll(bal);
     }
+    {
+        const bool m = i1 < e && c1 == kStay;
+        const unsigned long long bal = __ballot(m);
+        const uint32_t pos = nlow + nstay + (uint32_t)__popcll(bal & lt);
+        if (m && pos < N) sel[pos] = i1;
+        nstay += (uint32_t)__popcll(bal);
+    }
+    for (uint32_t c = b + 128u; c < e; c += 64u) {
+        const uint32_t i = c + lane;
+        const bool m = i < e && a.rg.code[i] == kStay;
+        const unsigned long long bal = __ballot(m);
+        const uint32_t pos = nlow + nstay + (uint32_t)__popcll(bal & lt);
+        if (m && pos < N) sel[pos] = i;
+        nstay += (uint32_t)__popcll(bal);
+    }
+    if (lane < nm) {
+        const uint32_t pos = lane < nlow ? lane : lane + nstay;
+        if (pos < N) sel[pos] = v;
+    }
+    const bool merge = mc > kMoverSlots;
+    if (lane == 0) {
+        uint32_t m = nstay + nm;
+        if (merge) {
+            // overflow movers from the list, merged by position afterwards
+            uint32_t q = a.rg.far_head[cell];
+            while (q != kEmpty && m < N) {
+                sel[m++] = a.rg.far_src[q];
+                q = a.rg.far_next[q];
+            }
+            if (q != kEmpty) set_error(a.st, DSMC_ECAPACITY);
+            a.rg.far_head[cell] = kEmpty;
+        }
+        if (m != N) set_error(a.st, DSMC_ECAPACITY);
+        while (m < N) sel[m++] = b;  // valid positions only
+        if (mc) a.rg.mcount[cell] = 0u;
+    }
+    return merge;
 }
 
 // Position of source position q in the merged order: the number of smaller
@@ -205,13 +185,7 @@ __device__ __forceinline__ void gather_j(const CollideArgs<R> &a, uint32_t base,
 template <typename R, bool VR, int D>
 __device__ __forceinline__ void gather_cell(const CollideArgs<R> &a, uint32_t cell, uint32_t base, uint32_t N,
                                             uint32_t *sel, R *vx, R *vy, R *vz, R *w) {
-    uint32_t n_near = select_near<R, D>(a, cell, N, sel);
-    if (n_near > N) {
-        if (lane_id() == 0) set_error(a.st, DSMC_ECAPACITY);
-        n_near = N;
-    }
-    const bool merge = n_near < N;
-    if (merge) select_far(a, cell, n_near, N, sel);
+    const bool merge = select_cell(a, cell, N, sel);
     __syncthreads();
     uint32_t e0 = 0;
     for (; e0 + 256 <= N; e0 += 256) gather_j<R, VR, D, 4>(a, base, e0, N, sel, merge, vx, vy, vz, w);

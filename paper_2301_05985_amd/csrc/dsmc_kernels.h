@@ -214,54 +214,57 @@ __device__ __forceinline__ uint32_t cell_index(const Geo &g, double x, double y)
     return (uint32_t)iy * (uint32_t)g.nx + (uint32_t)ix;
 }
 
-// ------------------------------------------------------------ move codes
+// ------------------------------------------------------------ regrouping
 // The particle sequence is regrouped every step by a stable counting sort on
-// the new cell.  Streaming records, per particle, how its cell changed: along
-// each axis a step of -1, 0 or +1 cells (across a periodic boundary the
-// wrapped neighbour counts as one step), coded (dx + 1) + 3 (dy + 1); a
-// particle that moved further is a far mover, linked into a per-cell list.
-// The collision kernel of cell t then finds its particles in the (at most
-// nine) neighbouring cells of the previous sequence from the codes alone.
-constexpr uint8_t kFarMove = 0xFF;
+// the new cell.  Streaming marks each particle that stays in its cell
+// (code byte kStay) and appends the position of each particle that changes
+// cell (a mover) to a list of its new cell: kMoverSlots slots per cell, the
+// rest (rare) linked into a per-cell overflow list.  The collision wave of
+// cell t then has, in ascending position, the movers from cells before t,
+// the particles that stayed in t, and the movers from cells after t: the
+// stays are found from t's own codes, the movers by sorting t's short list.
+constexpr uint8_t kStay = 1;
+constexpr uint8_t kMoved = 0;
+constexpr uint32_t kMoverSlots = 64;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 
-__device__ __forceinline__ int axis_move(int from, int to, int n, bool periodic) {
-    const int d = to - from;
-    if (d >= -1 && d <= 1) return d;
-    if (periodic && d == n - 1) return -1;
-    if (periodic && d == 1 - n) return 1;
-    return 2;
-}
+struct Regroup {
+    uint8_t *code;        // [n] kStay or kMoved per position of the streamed sequence
+    uint32_t *mcount;     // [ncell] movers into each cell this step (reset by the collision wave)
+    uint32_t *movers;     // [ncell][kMoverSlots] their positions, in no particular order
+    uint32_t *far_head;   // [ncell] overflow list heads (reset by the collision wave)
+    uint32_t *far_src, *far_next;
+};
 
-__device__ __forceinline__ uint8_t move_code(const Geo &g, int fx, int fy, int tx, int ty) {
-    const int dx = axis_move(fx, tx, g.nx, g.kind[0] == DSMC_WALL_PERIODIC);
-    const int dy = g.dims == 2 ? axis_move(fy, ty, g.ny, g.kind[2] == DSMC_WALL_PERIODIC) : 0;
-    if (dx == 2 || dy == 2) return kFarMove;
-    return (uint8_t)((dx + 1) + 3 * (dy + 1));
+__device__ __forceinline__ void push_mover(const Regroup &rg, uint32_t p, uint32_t cell, uint32_t slot,
+                                           DevState *st) {
+    if (slot < kMoverSlots) {
+        rg.movers[(size_t)cell * kMoverSlots + slot] = p;
+    } else {
+        const uint32_t q = atomicAdd(&st->far_count, 1u);
+        rg.far_src[q] = p;
+        rg.far_next[q] = atomicExch(&rg.far_head[cell], q);
+    }
 }
 
 // Streaming, in sequence order and in place, in two kernels.  The first
 // takes every particle whose free end point x + c dt lies inside the closed
 // box (the rule the flight itself applies first): it writes the new position
-// and the move code and counts the new cell.  Particles that would leave the
-// box go to a list that the second kernel flies exactly, wall conditions
-// included, and finishes in the same way.  Keeping the rare wall path out of
-// the first kernel keeps its register use, and so the number of loads in
-// flight, at the level of a plain streaming kernel.
+// and the code byte, counts the new cell and lists the movers.  Particles
+// that would leave the box go to a list that the second kernel flies
+// exactly, wall conditions included, and finishes in the same way.  Keeping
+// the rare wall path out of the first kernel keeps its register use, and so
+// the number of loads in flight, at the level of a plain streaming kernel.
 template <typename R, int D>
-__device__ __forceinline__ void finish_move(const Geo &g, int64_t p, int fx, int fy, R x, R y, uint8_t *code,
-                                            uint32_t *far_head, uint32_t *far_src, uint32_t *far_next,
-                                            DevState *st, uint32_t &cell) {
+__device__ __forceinline__ void finish_move(const Geo &g, int64_t p, int fx, int fy, R x, R y, const Regroup &rg,
+                                            uint32_t *count, DevState *st) {
     int tx, ty;
     cell_coords(g, (double)x, D == 2 ? (double)y : 0.0, tx, ty);
-    cell = (uint32_t)ty * (uint32_t)g.nx + (uint32_t)tx;
-    const uint8_t mc = move_code(g, fx, fy, tx, ty);
-    code[p] = mc;
-    if (mc == kFarMove) {
-        const uint32_t k = atomicAdd(&st->far_count, 1u);
-        far_src[k] = (uint32_t)p;
-        far_next[k] = atomicExch(&far_head[cell], k);
-    }
+    const uint32_t cell = (uint32_t)ty * (uint32_t)g.nx + (uint32_t)tx;
+    const bool stay = tx == fx && ty == fy;
+    rg.code[p] = stay ? kStay : kMoved;
+    atomicAdd(&count[cell], 1u);
+    if (!stay) push_mover(rg, (uint32_t)p, cell, atomicAdd(&rg.mcount[cell], 1u), st);
 }
 
 template <typename R>
@@ -285,28 +288,32 @@ __device__ __forceinline__ void store4(R *p, const R (&v)[4]) {
 }
 
 // Workgroup of 256 threads, 4 consecutive particles per thread (vector loads
-// and stores; one 32-bit store of the four move codes).  New-cell counts go
-// to 2048 LDS bins covering the cells base .. base + 2047, base one row and
-// one cell before the old cell of the workgroup's first particle: the
-// sequence is grouped by cell, so the workgroup's particles come from a few
-// consecutive cells and, apart from far movers and wrapped periodic moves,
-// land within one row of them.  The bins are added to the global counts
-// once per workgroup; cells outside the window are counted directly.
+// and stores; one 32-bit store of the four code bytes).  New-cell counts and
+// mover counts go to LDS bins covering the cells base .. base + 2047, base
+// one row and one cell before the old cell of the workgroup's first
+// particle: the sequence is grouped by cell, so the workgroup's particles
+// come from a few consecutive cells and, apart from far and wrapped moves,
+// land within one row of them.  Each bin is added to the global counters
+// once per workgroup (the mover count returning the bin's first slot);
+// cells outside the window are counted directly.
 constexpr int kStreamBins = 2048;
 
 template <typename R, int D>
-__global__ __launch_bounds__(256) void k_stream_code(Geo g, Soa<R> s, int64_t n, uint8_t *code, uint32_t *count,
-                                                     uint32_t *far_head, uint32_t *far_src, uint32_t *far_next,
+__global__ __launch_bounds__(256) void k_stream_code(Geo g, Soa<R> s, int64_t n, Regroup rg, uint32_t *count,
                                                      uint32_t *wall_list, DevState *st) {
-    __shared__ uint4 bins4[kStreamBins / 4];
+    __shared__ uint4 bins4[kStreamBins / 4];   // new-cell counts
+    __shared__ uint4 mbins4[kStreamBins / 4];  // movers per new cell, then their first slot
     __shared__ uint32_t base_sh;
-    uint32_t *bins = (uint32_t *)bins4;
+    uint32_t *bins = (uint32_t *)bins4, *mbins = (uint32_t *)mbins4;
     const uint32_t tid = threadIdx.x;
     const int64_t p0 = (int64_t)blockIdx.x * 1024 + 4 * tid;  // first particle of this thread
     const int64_t left = n - p0;
     const int nv = left >= 4 ? 4 : (left > 0 ? (int)left : 0);
-    bins4[tid] = make_uint4(0u, 0u, 0u, 0u);
-    bins4[tid + 256] = make_uint4(0u, 0u, 0u, 0u);
+    const uint4 zero4 = make_uint4(0u, 0u, 0u, 0u);
+    bins4[tid] = zero4;
+    bins4[tid + 256] = zero4;
+    mbins4[tid] = zero4;
+    mbins4[tid + 256] = zero4;
     const R tau = (R)g.dt, Lx = (R)g.Lx, Ly = (R)g.Ly, zero = (R)0;
     R x[4], y[4], cx[4], cy[4];
     if (nv == 4) {
@@ -333,7 +340,7 @@ __global__ __launch_bounds__(256) void k_stream_code(Geo g, Soa<R> s, int64_t n,
         for (int k = 0; k < 4; ++k) { y[k] = zero; cy[k] = zero; }
     }
     uint32_t cell[4];
-    bool in[4];
+    bool in[4], stay[4];
     uint32_t codes = 0;
     int fx0 = 0, fy0 = 0;
 #pragma unroll
@@ -347,46 +354,47 @@ __global__ __launch_bounds__(256) void k_stream_code(Geo g, Soa<R> s, int64_t n,
             fx0 = fx;
             fy0 = fy;
         }
-        uint32_t mc = kFarMove;  // particles of the wall list get theirs from the second kernel
-        cell[k] = 0;
+        int tx, ty;
+        cell_coords(g, (double)xe, D == 2 ? (double)ye : 0.0, tx, ty);
+        cell[k] = (uint32_t)ty * (uint32_t)g.nx + (uint32_t)tx;
+        stay[k] = tx == fx && ty == fy;
         if (in[k]) {
-            int tx, ty;
-            cell_coords(g, (double)xe, D == 2 ? (double)ye : 0.0, tx, ty);
-            cell[k] = (uint32_t)ty * (uint32_t)g.nx + (uint32_t)tx;
-            mc = move_code(g, fx, fy, tx, ty);
             x[k] = xe;
             y[k] = ye;
-            if (mc == kFarMove) {
-                const uint32_t q = atomicAdd(&st->far_count, 1u);
-                far_src[q] = (uint32_t)(p0 + k);
-                far_next[q] = atomicExch(&far_head[cell[k]], q);
-            }
         }
-        codes |= mc << (8 * k);
+        // particles of the wall list get their code from the second kernel
+        codes |= (uint32_t)(in[k] && stay[k] ? kStay : kMoved) << (8 * k);
     }
     // particles of the wall list keep their stored position and velocity
     if (nv == 4) {
         store4(s.x + p0, x);
         if (D == 2) store4(s.y + p0, y);
-        *(uint32_t *)(code + p0) = codes;
+        *(uint32_t *)(rg.code + p0) = codes;
     } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k)
             if (k < nv) {
                 s.x[p0 + k] = x[k];
                 if (D == 2) s.y[p0 + k] = y[k];
-                code[p0 + k] = (uint8_t)(codes >> (8 * k));
+                rg.code[p0 + k] = (uint8_t)(codes >> (8 * k));
             }
     }
     if (tid == 0) base_sh = (uint32_t)fy0 * (uint32_t)g.nx + (uint32_t)fx0 - (D == 2 ? (uint32_t)g.nx : 0u) - 1u;
     __syncthreads();
     const uint32_t base = base_sh;  // modulo 2^32: cell - base is the bin
+    uint32_t local[4];              // slot of each mover inside its bin
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
+        local[k] = 0;
         if (in[k]) {
             const uint32_t b = cell[k] - base;
-            if (b < (uint32_t)kStreamBins) atomicAdd(&bins[b], 1u);
-            else atomicAdd(&count[cell[k]], 1u);
+            if (b < (uint32_t)kStreamBins) {
+                atomicAdd(&bins[b], 1u);
+                if (!stay[k]) local[k] = atomicAdd(&mbins[b], 1u);
+            } else {
+                atomicAdd(&count[cell[k]], 1u);
+                if (!stay[k]) push_mover(rg, (uint32_t)(p0 + k), cell[k], atomicAdd(&rg.mcount[cell[k]], 1u), st);
+            }
         }
         // particles that meet a wall: one list slot each, one atomic per wave
         const bool wall = k < nv && !in[k];
@@ -404,11 +412,24 @@ __global__ __launch_bounds__(256) void k_stream_code(Geo g, Soa<R> s, int64_t n,
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const uint4 c = bins4[tid + 256 * h];
+        uint4 m = mbins4[tid + 256 * h];
         const uint32_t b = base + 4u * (tid + 256u * h);
         if (c.x) atomicAdd(&count[b], c.x);
         if (c.y) atomicAdd(&count[b + 1u], c.y);
         if (c.z) atomicAdd(&count[b + 2u], c.z);
         if (c.w) atomicAdd(&count[b + 3u], c.w);
+        if (m.x) m.x = atomicAdd(&rg.mcount[b], m.x);
+        if (m.y) m.y = atomicAdd(&rg.mcount[b + 1u], m.y);
+        if (m.z) m.z = atomicAdd(&rg.mcount[b + 2u], m.z);
+        if (m.w) m.w = atomicAdd(&rg.mcount[b + 3u], m.w);
+        mbins4[tid + 256 * h] = m;  // first slot of each bin (a zero base is a base too)
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t b = cell[k] - base;
+        if (in[k] && !stay[k] && b < (uint32_t)kStreamBins)
+            push_mover(rg, (uint32_t)(p0 + k), cell[k], mbins[b] + local[k], st);
     }
 }
 
@@ -416,8 +437,7 @@ __global__ __launch_bounds__(256) void k_stream_code(Geo g, Soa<R> s, int64_t n,
 // their unmodified state, then the same finish as in the first kernel.
 // Grid-stride over the list length of this step.
 template <typename R, int D, bool VR>
-__global__ __launch_bounds__(256) void k_stream_walls(Geo g, Soa<R> s, uint8_t *code, uint32_t *count,
-                                                      uint32_t *far_head, uint32_t *far_src, uint32_t *far_next,
+__global__ __launch_bounds__(256) void k_stream_walls(Geo g, Soa<R> s, Regroup rg, uint32_t *count,
                                                       const uint32_t *wall_list, DevState *st) {
     const uint32_t nw = st->wall_count;
     const uint32_t step = (uint32_t)st->step_next;
@@ -441,9 +461,7 @@ __global__ __launch_bounds__(256) void k_stream_walls(Geo g, Soa<R> s, uint8_t *
                 if (VR) s.w[p] = w;
             }
         }
-        uint32_t cell;
-        finish_move<R, D>(g, p, fx, fy, x, y, code, far_head, far_src, far_next, st, cell);
-        atomicAdd(&count[cell], 1u);
+        finish_move<R, D>(g, p, fx, fy, x, y, rg, count, st);
         hsum += hits;
     }
     hsum = wave_sum_u32(hsum);
