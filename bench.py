@@ -30,11 +30,11 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 METRIC = "accepted collisions/s + particle-steps/s on 1 MI355X; learned vs exact majorant"
 
 # algorithmic bytes per particle and launch, FP32 2-D with weights, 100
-# particles per cell (see DESIGN.md)
+# particles per cell
 ALGO_BYTES = {
-    "stream": 25.0,    # read x, y, cx, cy; write x, y and one move-code byte
+    "stream": 25.0,    # read x, y, cx, cy; write x, y and one code byte
     # gather-collide: read the 28 B state (x, y, cx, cy, cz, w, id) and one
-    # move-code byte, write the 28 B state into the new sequence, read and
+    # code byte, write the 28 B state into the new sequence, read and
     # write the cell's 26 FP64 running sums (416 B per cell of 100)
     "collide": 28.0 + 1.0 + 28.0 + 4.16,
 }

@@ -150,7 +150,7 @@ typedef struct {
 } dsmc_diag;
 
 /* Bytes of device workspace the configuration needs (second particle
- * buffer of the regrouping, per-cell ranges, move codes and far-mover lists,
+ * buffer of the regrouping, per-cell ranges, code bytes and mover lists,
  * FP64 running sums, counters, scratch).  EINVAL on an invalid
  * configuration. */
 dsmc_status dsmc_workspace_size(const dsmc_config *cfg, size_t *bytes);
@@ -167,7 +167,7 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *particles, void *w
                       size_t ws_bytes, void *hip_stream, dsmc_ctx **out);
 
 /* Enqueue n_steps time steps (asynchronous).  Each step runs, in order:
- * free flight with wall conditions, new cell and move code of every
+ * free flight with wall conditions, new cell and code byte of every
  * particle (dims >= 1), the scan of the new cells' counts, then per cell the
  * gather of its particles into the new sequence (dims >= 1), NTC collisions
  * with the majorant chosen by cfg->majorant, the importance-weight update
