@@ -53,16 +53,26 @@ struct CollideArgs {
 
 constexpr int kNsum = 26;
 
-// Cell staged in LDS (index = canonical rank).
+// One particle of a cell staged in LDS: velocity and weight side by side,
+// so that a particle is read with one 16-byte access (two in double).
+template <typename R>
+struct alignas(16) Vel4 {
+    R x, y, z, w;
+};
+
+// Cell staged in LDS (index = rank in the cell's collision order).
 template <typename R>
 struct LdsView {
     static constexpr bool kInLds = true;
-    R *vx, *vy, *vz, *w;
+    Vel4<R> *p;
     uint32_t *owner;
-    __device__ __forceinline__ void get(uint32_t r, R &a, R &b, R &c) const { a = vx[r]; b = vy[r]; c = vz[r]; }
-    __device__ __forceinline__ void put(uint32_t r, R a, R b, R c) const { vx[r] = a; vy[r] = b; vz[r] = c; }
-    __device__ __forceinline__ R getw(uint32_t r) const { return w[r]; }
-    __device__ __forceinline__ void putw(uint32_t r, R v) const { w[r] = v; }
+    __device__ __forceinline__ void get(uint32_t r, R &a, R &b, R &c) const {
+        const Vel4<R> t = p[r];
+        a = t.x; b = t.y; c = t.z;
+    }
+    __device__ __forceinline__ void put(uint32_t r, R a, R b, R c) const { p[r].x = a; p[r].y = b; p[r].z = c; }
+    __device__ __forceinline__ R getw(uint32_t r) const { return p[r].w; }
+    __device__ __forceinline__ void putw(uint32_t r, R v) const { p[r].w = v; }
     __device__ __forceinline__ uint32_t *own(uint32_t r) const { return &owner[r]; }
     __device__ __forceinline__ uint32_t read_own(uint32_t r) const { return owner[r]; }
     __device__ __forceinline__ void clear_own(uint32_t r) const { owner[r] = 0xFFFFFFFFu; }
@@ -551,32 +561,50 @@ __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cel
     constexpr int K = VR ? 32 : 16;  // 26 or 13 sums, padded to a power of two
     double q[K];
 #pragma unroll
-    for (int t = 0; t < K; ++t) q[t] = 0.0;
-    // products are added with fused multiply-adds (the sums are compared
-    // with a tolerance; the particle state is what must match exactly)
-    for (uint32_t r = lane; r < N; r += 64) {
-        R x, y, z;
-        v.get(r, x, y, z);
-        R w = (R)1;
-        if (VR) w = v.getw(r);
-        if (View::kInLds) {
-            a.s.cx[wb_base + r] = x; a.s.cy[wb_base + r] = y; a.s.cz[wb_base + r] = z;
-            if (VR) a.s.w[wb_base + r] = w;
+    for (int t = VR ? 26 : 13; t < K; ++t) q[t] = 0.0;  // padding
+    // the lane's first particle sets the sums (a lane without one sets
+    // zeros), the others are added; products are added with fused
+    // multiply-adds (the sums are compared with a tolerance; the particle
+    // state is what must match exactly)
+    for (uint32_t r = lane; r < N || r == (uint32_t)lane; r += 64) {
+        const bool has = r < N;
+        R x = (R)0, y = (R)0, z = (R)0, w = (R)1;
+        if (has) {
+            v.get(r, x, y, z);
+            if (VR) w = v.getw(r);
+            if (View::kInLds) {
+                a.s.cx[wb_base + r] = x; a.s.cy[wb_base + r] = y; a.s.cz[wb_base + r] = z;
+                if (VR) a.s.w[wb_base + r] = w;
+            }
         }
         const double vx = (double)x, vy = (double)y, vz = (double)z;
         const double xx = vx * vx, yy = vy * vy, zz = vz * vz;
         const double c2 = (xx + yy) + zz;
-        q[0] += 1.0; q[1] += vx; q[2] += vy; q[3] += vz;
-        q[4] += xx; q[5] += yy; q[6] += zz;
-        q[7] = fma(vx, vy, q[7]); q[8] = fma(vx, vz, q[8]); q[9] = fma(vy, vz, q[9]);
-        q[10] = fma(vx, c2, q[10]); q[11] = fma(vy, c2, q[11]); q[12] = fma(vz, c2, q[12]);
+        if (r == (uint32_t)lane) {
+            q[0] = has ? 1.0 : 0.0; q[1] = vx; q[2] = vy; q[3] = vz;
+            q[4] = xx; q[5] = yy; q[6] = zz;
+            q[7] = vx * vy; q[8] = vx * vz; q[9] = vy * vz;
+            q[10] = vx * c2; q[11] = vy * c2; q[12] = vz * c2;
+        } else {
+            q[0] += 1.0; q[1] += vx; q[2] += vy; q[3] += vz;
+            q[4] += xx; q[5] += yy; q[6] += zz;
+            q[7] = fma(vx, vy, q[7]); q[8] = fma(vx, vz, q[8]); q[9] = fma(vy, vz, q[9]);
+            q[10] = fma(vx, c2, q[10]); q[11] = fma(vy, c2, q[11]); q[12] = fma(vz, c2, q[12]);
+        }
         if (VR) {
             const double f = 1.0 - (double)w;
             const double fx = f * vx, fy = f * vy, fz = f * vz;
-            q[13] += f; q[14] += fx; q[15] += fy; q[16] += fz;
-            q[17] = fma(fx, vx, q[17]); q[18] = fma(fy, vy, q[18]); q[19] = fma(fz, vz, q[19]);
-            q[20] = fma(fx, vy, q[20]); q[21] = fma(fx, vz, q[21]); q[22] = fma(fy, vz, q[22]);
-            q[23] = fma(fx, c2, q[23]); q[24] = fma(fy, c2, q[24]); q[25] = fma(fz, c2, q[25]);
+            if (r == (uint32_t)lane) {
+                q[13] = f; q[14] = fx; q[15] = fy; q[16] = fz;
+                q[17] = fx * vx; q[18] = fy * vy; q[19] = fz * vz;
+                q[20] = fx * vy; q[21] = fx * vz; q[22] = fy * vz;
+                q[23] = fx * c2; q[24] = fy * c2; q[25] = fz * c2;
+            } else {
+                q[13] += f; q[14] += fx; q[15] += fy; q[16] += fz;
+                q[17] = fma(fx, vx, q[17]); q[18] = fma(fy, vy, q[18]); q[19] = fma(fz, vz, q[19]);
+                q[20] = fma(fx, vy, q[20]); q[21] = fma(fx, vz, q[21]); q[22] = fma(fy, vz, q[22]);
+                q[23] = fma(fx, c2, q[23]); q[24] = fma(fy, c2, q[24]); q[25] = fma(fz, c2, q[25]);
+            }
         }
     }
     // each lane ends up with the total of the sum it owns

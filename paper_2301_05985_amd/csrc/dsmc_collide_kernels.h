@@ -134,7 +134,7 @@ __device__ __forceinline__ uint32_t merged_rank(const uint32_t *sel, uint32_t N,
 // weights to LDS at the element's rank.
 template <typename R, bool VR, int D, int J>
 __device__ __forceinline__ void gather_j(const CollideArgs<R> &a, uint32_t base, uint32_t e0, uint32_t N,
-                                         const uint32_t *sel, bool merge, R *vx, R *vy, R *vz, R *w) {
+                                         const uint32_t *sel, bool merge, Vel4<R> *vel) {
     const uint32_t lane = (uint32_t)lane_id();
     uint32_t q[J], r[J], id[J];
     R x[J], y[J], c0[J], c1[J], c2[J], ww[J];
@@ -167,9 +167,8 @@ __device__ __forceinline__ void gather_j(const CollideArgs<R> &a, uint32_t base,
             if (D == 2) a.s.y[o] = y[j];
             a.s.id[o] = id[j];
             const uint32_t rr = r[j] < N ? r[j] : N - 1;
-            if (vx) {
-                vx[rr] = c0[j]; vy[rr] = c1[j]; vz[rr] = c2[j];
-                if (VR) w[rr] = ww[j];
+            if (vel) {
+                vel[rr] = Vel4<R>{c0[j], c1[j], c2[j], VR ? ww[j] : (R)1};
             } else {
                 a.s.cx[o] = c0[j]; a.s.cy[o] = c1[j]; a.s.cz[o] = c2[j];
                 if (VR) a.s.w[o] = ww[j];
@@ -180,20 +179,20 @@ __device__ __forceinline__ void gather_j(const CollideArgs<R> &a, uint32_t base,
 
 // Whole gather of a walled cell: selection into sel (LDS or global scratch
 // of at least N entries), then the particles into the new sequence at
-// `base` (velocities and weights into LDS when vx is given, else into the
+// `base` (velocities and weights into LDS when vel is given, else into the
 // new sequence too).
 template <typename R, bool VR, int D>
 __device__ __forceinline__ void gather_cell(const CollideArgs<R> &a, uint32_t cell, uint32_t base, uint32_t N,
-                                            uint32_t *sel, R *vx, R *vy, R *vz, R *w) {
+                                            uint32_t *sel, Vel4<R> *vel) {
     const bool merge = select_cell(a, cell, N, sel);
     __syncthreads();
     uint32_t e0 = 0;
-    for (; e0 + 256 <= N; e0 += 256) gather_j<R, VR, D, 4>(a, base, e0, N, sel, merge, vx, vy, vz, w);
+    for (; e0 + 256 <= N; e0 += 256) gather_j<R, VR, D, 4>(a, base, e0, N, sel, merge, vel);
     const uint32_t left = N - e0;
-    if (left > 192) gather_j<R, VR, D, 4>(a, base, e0, N, sel, merge, vx, vy, vz, w);
-    else if (left > 128) gather_j<R, VR, D, 3>(a, base, e0, N, sel, merge, vx, vy, vz, w);
-    else if (left > 64) gather_j<R, VR, D, 2>(a, base, e0, N, sel, merge, vx, vy, vz, w);
-    else if (left > 0) gather_j<R, VR, D, 1>(a, base, e0, N, sel, merge, vx, vy, vz, w);
+    if (left > 192) gather_j<R, VR, D, 4>(a, base, e0, N, sel, merge, vel);
+    else if (left > 128) gather_j<R, VR, D, 3>(a, base, e0, N, sel, merge, vel);
+    else if (left > 64) gather_j<R, VR, D, 2>(a, base, e0, N, sel, merge, vel);
+    else if (left > 0) gather_j<R, VR, D, 1>(a, base, e0, N, sel, merge, vel);
 }
 
 // LDS kernel body: one wave per cell.  Homogeneous instances (D 0) collide
@@ -214,21 +213,18 @@ __device__ __forceinline__ void collide_lds_body(const CollideArgs<R> &a, unsign
     const uint32_t step = (uint32_t)a.st->step_cur;
     const CellPrefetch pf = prefetch_cell<R, VR, true>(a, cell);
     const int cap = a.cap;
-    R *vx = (R *)smem, *vy = vx + cap, *vz = vy + cap;
-    R *w = VR ? vz + cap : nullptr;
-    uint32_t *owner = (uint32_t *)(VR ? w + cap : vz + cap);  // cap + 4 entries
+    Vel4<R> *vel = (Vel4<R> *)smem;
+    uint32_t *owner = (uint32_t *)(vel + cap);  // cap + 4 entries
     if (D > 0) {
-        gather_cell<R, VR, D>(a, cell, base, N, owner, vx, vy, vz, w);  // the owner array holds the selection
+        gather_cell<R, VR, D>(a, cell, base, N, owner, vel);  // the owner array holds the selection
         __syncthreads();
     } else {
-        for (uint32_t s = lane; s < N; s += 64) {
-            vx[s] = a.s.cx[base + s]; vy[s] = a.s.cy[base + s]; vz[s] = a.s.cz[base + s];
-            if (VR) w[s] = a.s.w[base + s];
-        }
+        for (uint32_t s = lane; s < N; s += 64)
+            vel[s] = Vel4<R>{a.s.cx[base + s], a.s.cy[base + s], a.s.cz[base + s], VR ? a.s.w[base + s] : (R)1};
     }
     for (uint32_t r = lane; r < N; r += 64) owner[r] = 0xFFFFFFFFu;
     __syncthreads();
-    const LdsView<R> view{vx, vy, vz, w, owner};
+    const LdsView<R> view{vel, owner};
     // the sampling writes the cell back and reduces its sums through the
     // cell's LDS area
     if (LEARNED) process_cell_learned<R, VR>(a, view, cell, N, step, pf, (double *)smem, base);
@@ -249,8 +245,7 @@ __device__ __forceinline__ void collide_big_body(const CollideArgs<R> &a) {
         const uint32_t base = a.start[cell];
         const uint32_t N = a.start[cell + 1] - base;
         if (D > 0) {
-            gather_cell<R, VR, D>(a, cell, base, N, a.perm_g + base, (R *)nullptr, (R *)nullptr, (R *)nullptr,
-                                  (R *)nullptr);
+            gather_cell<R, VR, D>(a, cell, base, N, a.perm_g + base, (Vel4<R> *)nullptr);
             __syncthreads();
         }
         const GlobalView<R> view{a.s.cx + base, a.s.cy + base, a.s.cz + base,
