@@ -155,7 +155,7 @@ struct dsmc_ctx {
     uint32_t *count = nullptr, *offset = nullptr, *cursor = nullptr, *big_list = nullptr,
              *perm = nullptr, *owner = nullptr, *sched = nullptr;
     // walled runs: cell ranges of each particle buffer (off[0] is `offset`),
-    // move codes and the far-mover lists of the streaming pass
+    // code bytes, mover lists and overflow lists of the streaming pass
     uint32_t *off[2] = {nullptr, nullptr};
     uint8_t *code = nullptr;
     uint32_t *far_head = nullptr, *far_src = nullptr, *far_next = nullptr, *wall_list = nullptr;
@@ -608,7 +608,7 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
             hipMemcpyAsync(c->units, units_host.data(), units_host.size() * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess)
             return fail(DSMC_EHIP);
     } else {
-        // empty far-mover lists, then the initial particle sequence
+        // empty mover and overflow lists, then the initial particle sequence
         if (hipMemsetAsync(c->far_head, 0xFF, (size_t)c->ncell * 4, c->stream) != hipSuccess ||
             hipMemsetAsync(c->mcount, 0, (size_t)c->ncell * 4, c->stream) != hipSuccess)
             return fail(DSMC_EHIP);

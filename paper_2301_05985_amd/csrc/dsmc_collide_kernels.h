@@ -122,7 +122,7 @@ __device__ __forceinline__ bool select_cell(const CollideArgs<R> &a, uint32_t ce
 }
 
 // Position of source position q in the merged order: the number of smaller
-// entries of sel[0..N) (only cells with far movers need it).
+// entries of sel[0..N) (only cells with overflow movers need it).
 __device__ __forceinline__ uint32_t merged_rank(const uint32_t *sel, uint32_t N, uint32_t q) {
     uint32_t r = 0;
     for (uint32_t t = 0; t < N; ++t) r += sel[t] < q ? 1u : 0u;

@@ -2,13 +2,13 @@
 //
 // One time step (Bird 1994, direct simulation Monte Carlo), walled runs:
 //   k_stream_code     free flight of the particles that stay in the box, new
-//                     cell counted, one move-code byte each; the others go
+//                     cell counted, one code byte each, movers listed; the others go
 //                     to the wall list                       [grid over particles]
 //   k_stream_walls    exact flight with wall conditions of the wall list
 //   k_scan_lookback   exclusive scan of the counts into the new cell ranges,
 //                     step bookkeeping                   [decoupled look-back]
 //   k_collide         per cell (dsmc_collide_kernels.h): gather the cell's
-//                     particles from the previous sequence by move code,
+//                     particles from the previous sequence (stays and movers),
 //                     majorant, NTC candidates in conflict-free wave batches,
 //                     importance weights, FP64 moment sums [one wave per cell]
 // Homogeneous instances (dims == 0) run k_begin_step and k_collide only.
@@ -34,7 +34,7 @@ struct DevState {
     unsigned long long n_samples;   // sampled steps since the last reset
     unsigned int error;             // first device error (positive code), 0 = none
     unsigned int big_count;         // cells queued for the global-memory collision kernel
-    unsigned int far_count;         // entries of this step's far-mover list
+    unsigned int far_count;         // entries of this step's overflow mover list
     unsigned int wall_count;        // entries of this step's wall list
     unsigned int pad0;
     unsigned long long pad[3];

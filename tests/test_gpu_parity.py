@@ -180,9 +180,10 @@ def test_cavity_big_cell_global_path_f64(gpu):
 @pytest.mark.parametrize("case", ["periodic_2x3", "periodic_1x1", "specular_far", "fourier_periodic_2",
                                   "big_cell_far"])
 def test_far_movers_and_small_periodic_grids(gpu, case):
-    # steps long enough that many particles cross several cells (far-mover
-    # lists), periodic grids so small that neighbours coincide, and a crowded
-    # cell gathered in global memory while particles jump across the box
+    # steps long enough that many particles cross several cells (more than
+    # 64 movers into one cell: the overflow lists), periodic grids so small
+    # that neighbours coincide, and a crowded cell gathered in global memory
+    # while particles jump across the box
     _announce("far movers %s" % case)
     spec = (W.WALL_SPECULAR,) * 4
     if case == "periodic_2x3":
