@@ -88,6 +88,16 @@ dsmc_status validate(const dsmc_config *c) {
     return DSMC_OK;
 }
 
+// Mover slots per cell: the mean cell population rounded up to a power of
+// two, between 64 and 256 (the whole cell moving in one step still fits).
+uint32_t mover_slots(const dsmc_config &c) {
+    const int64_t nc = n_cells_of(c);
+    const double mean = nc > 0 ? (double)c.n_particles / (double)nc : 0.0;
+    uint32_t s = 64;
+    while ((double)s < mean && s < kMaxMoverSlots) s *= 2;
+    return s;
+}
+
 Layout make_layout(const dsmc_config &c) {
     Layout L;
     std::memset(&L, 0, sizeof(L));
@@ -108,7 +118,7 @@ Layout make_layout(const dsmc_config &c) {
         L.far_next = take(n * 4);
         L.wall_list = take(n * 4);
         L.mcount = take(nc * 4);
-        L.movers = take(nc * kMoverSlots * 4);
+        L.movers = take(nc * mover_slots(c) * 4);
     }
     L.offset = take((nc + 1) * 4);
     L.sums = take(nc * kNsum * 8);
@@ -190,6 +200,7 @@ Regroup regroup_of(const dsmc_ctx *c) {
     r.far_head = c->far_head;
     r.far_src = c->far_src;
     r.far_next = c->far_next;
+    r.slots = mover_slots(c->cfg);
     return r;
 }
 

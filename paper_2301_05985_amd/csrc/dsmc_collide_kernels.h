@@ -53,6 +53,41 @@ __device__ __forceinline__ uint32_t bitonic_sort(uint32_t v, uint32_t lane) {
     return v;
 }
 
+// Ascending sort of C values per lane (element lane + 64 r in register r,
+// 64 C elements): the same bitonic network, with the stages of distance 64
+// and more exchanging registers within a lane.
+template <int C, int K, int J>
+__device__ __forceinline__ void bitonic_stage_regs(uint32_t (&v)[4], uint32_t lane) {
+#pragma unroll
+    for (int r = 0; r < C; ++r) {
+        const bool asc = ((lane + 64u * (uint32_t)r) & (uint32_t)K) == 0u;
+        if constexpr (J >= 64) {
+            constexpr int R = J / 64;
+            if ((r & R) == 0) {
+                const uint32_t a = v[r], b = v[r | R];
+                const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+                v[r] = asc ? lo : hi;
+                v[r | R] = asc ? hi : lo;
+            }
+        } else {
+            const uint32_t o = xor_lane<J>(v[r]);
+            const bool keep_min = ((lane & (uint32_t)J) == 0u) == asc;
+            const uint32_t lo = v[r] < o ? v[r] : o, hi = v[r] < o ? o : v[r];
+            v[r] = keep_min ? lo : hi;
+        }
+    }
+}
+template <int C, int K, int J>
+__device__ __forceinline__ void bitonic_merge_regs(uint32_t (&v)[4], uint32_t lane) {
+    bitonic_stage_regs<C, K, J>(v, lane);
+    if constexpr (J > 1) bitonic_merge_regs<C, K, J / 2>(v, lane);
+}
+template <int C, int K>
+__device__ __forceinline__ void bitonic_sort_regs(uint32_t (&v)[4], uint32_t lane) {
+    if constexpr (K > 2) bitonic_sort_regs<C, K / 2>(v, lane);
+    bitonic_merge_regs<C, K, K / 2>(v, lane);
+}
+
 // Selection of `cell`: source positions written to sel[0..N) (sel holds at
 // least N entries); returns whether they must still be merged by position
 // (overflow movers).  Any mismatch with the cell's count is reported, and sel
@@ -64,16 +99,33 @@ __device__ __forceinline__ bool select_cell(const CollideArgs<R> &a, uint32_t ce
     if (N == 0) return false;  // nothing lands here (and the sequence may be empty)
     const uint32_t b = a.src_start[cell], e = a.src_start[cell + 1];
     const uint32_t mc = a.rg.mcount[cell];
-    const uint32_t nm = mc < kMoverSlots ? mc : kMoverSlots;
-    uint32_t v = lane < nm ? a.rg.movers[(size_t)cell * kMoverSlots + lane] : 0xFFFFFFFFu;
+    const uint32_t K = a.rg.slots;
+    const uint32_t nm = mc < K ? mc : K;
+    const uint32_t *ml = a.rg.movers + (size_t)cell * K;
+    uint32_t v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint32_t el = lane + 64u * (uint32_t)r;
+        v[r] = 0xFFFFFFFFu;
+        if (r == 0 || nm > 64u * (uint32_t)r) v[r] = el < nm ? ml[el] : 0xFFFFFFFFu;  // uniform test
+    }
     // the codes of the cell's own range, the first two chunks loaded at once
     // every load below is issued from an in-bounds address (the sequence is
     // not empty) and masked afterwards
     const uint32_t last = e > b ? e - 1u : (b > 0u ? b - 1u : 0u);
     const uint32_t i0 = b + lane, i1 = b + 64u + lane;
     const uint8_t c0 = a.rg.code[i0 < e ? i0 : last], c1 = a.rg.code[i1 < e ? i1 : last];
-    v = nm > 32 ? bitonic_sort<64>(v, lane) : bitonic_sort<32>(v, lane);
-    const uint32_t nlow = (uint32_t)__popcll(__ballot(lane < nm && v < b));
+    if (nm <= 32) v[0] = bitonic_sort<32>(v[0], lane);
+    else if (nm <= 64) v[0] = bitonic_sort<64>(v[0], lane);
+    else if (nm <= 128) bitonic_sort_regs<2, 128>(v, lane);
+    else bitonic_sort_regs<4, 256>(v, lane);
+    uint32_t nlow = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        if (r > 0 && nm <= 64u * (uint32_t)r) break;
+        const uint32_t el = lane + 64u * (uint32_t)r;
+        nlow += (uint32_t)__popcll(__ballot(el < nm && v[r] < b));
+    }
     uint32_t nstay = 0;
     {
         const bool m = i0 < e && c0 == kStay;
@@ -97,11 +149,16 @@ __device__ __forceinline__ bool select_cell(const CollideArgs<R> &a, uint32_t ce
         if (m && pos < N) sel[pos] = i;
         nstay += (uint32_t)__popcll(bal);
     }
-    if (lane < nm) {
-        const uint32_t pos = lane < nlow ? lane : lane + nstay;
-        if (pos < N) sel[pos] = v;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        if (r > 0 && nm <= 64u * (uint32_t)r) break;
+        const uint32_t el = lane + 64u * (uint32_t)r;
+        if (el < nm) {
+            const uint32_t pos = el < nlow ? el : el + nstay;
+            if (pos < N) sel[pos] = v[r];
+        }
     }
-    const bool merge = mc > kMoverSlots;
+    const bool merge = mc > K;
     if (lane == 0) {
         uint32_t m = nstay + nm;
         if (merge) {
@@ -115,7 +172,7 @@ __device__ __forceinline__ bool select_cell(const CollideArgs<R> &a, uint32_t ce
             a.rg.far_head[cell] = kEmpty;
         }
         if (m != N) set_error(a.st, DSMC_ECAPACITY);
-        while (m < N) sel[m++] = b;  // valid positions only
+        while (m < N) sel[m++] = last;  // valid positions only (b itself may be the end of the sequence)
         if (mc) a.rg.mcount[cell] = 0u;
     }
     return merge;

@@ -218,28 +218,29 @@ __device__ __forceinline__ uint32_t cell_index(const Geo &g, double x, double y)
 // The particle sequence is regrouped every step by a stable counting sort on
 // the new cell.  Streaming marks each particle that stays in its cell
 // (code byte kStay) and appends the position of each particle that changes
-// cell (a mover) to a list of its new cell: kMoverSlots slots per cell, the
+// cell (a mover) to a list of its new cell: 64, 128 or 256 slots per cell, the
 // rest (rare) linked into a per-cell overflow list.  The collision wave of
 // cell t then has, in ascending position, the movers from cells before t,
 // the particles that stayed in t, and the movers from cells after t: the
 // stays are found from t's own codes, the movers by sorting t's short list.
 constexpr uint8_t kStay = 1;
 constexpr uint8_t kMoved = 0;
-constexpr uint32_t kMoverSlots = 64;
+constexpr uint32_t kMaxMoverSlots = 256;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 
 struct Regroup {
     uint8_t *code;        // [n] kStay or kMoved per position of the streamed sequence
     uint32_t *mcount;     // [ncell] movers into each cell this step (reset by the collision wave)
-    uint32_t *movers;     // [ncell][kMoverSlots] their positions, in no particular order
+    uint32_t *movers;     // [ncell][slots] their positions, in no particular order
     uint32_t *far_head;   // [ncell] overflow list heads (reset by the collision wave)
     uint32_t *far_src, *far_next;
+    uint32_t slots;       // mover slots per cell: 64, 128 or 256
 };
 
 __device__ __forceinline__ void push_mover(const Regroup &rg, uint32_t p, uint32_t cell, uint32_t slot,
                                            DevState *st) {
-    if (slot < kMoverSlots) {
-        rg.movers[(size_t)cell * kMoverSlots + slot] = p;
+    if (slot < rg.slots) {
+        rg.movers[(size_t)cell * rg.slots + slot] = p;
     } else {
         const uint32_t q = atomicAdd(&st->far_count, 1u);
         rg.far_src[q] = p;

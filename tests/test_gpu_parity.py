@@ -216,6 +216,37 @@ def test_far_movers_and_small_periodic_grids(gpu, case):
     _compare(g, orc, exact=True)
 
 
+def _max_movers_first_step(p, parts):
+    """Largest number of particles that enter one cell from other cells in
+    the first step (oracle flight, cells by position)."""
+    orc = oracle.Oracle(dict(p, real="f64"), parts, np.float64)
+    nx, ny = p["n_cells"]
+
+    def cells(st):
+        ix = np.minimum(np.floor(st["x"] * nx), nx - 1).astype(np.int64)
+        iy = np.minimum(np.floor(st["y"] * ny), ny - 1).astype(np.int64)
+        return iy * nx + ix
+
+    c0 = cells(orc.state())
+    orc.run(1)
+    c1 = cells(orc.state())
+    moved = c1 != c0
+    return int(np.bincount(c1[moved], minlength=nx * ny).max())
+
+
+@pytest.mark.parametrize("per_cell,dt,lo", [(100, 0.08, 64), (200, 0.15, 128)])
+def test_many_movers_per_cell(gpu, per_cell, dt, lo):
+    # more than 64 (128) particles enter a cell in one step: mover lists of
+    # 128 (256) slots per cell and their sort over two (four) values per lane
+    _announce("many movers %d" % per_cell)
+    p, parts = W.cavity(nx=6, ny=6, per_cell=per_cell, Kn=0.05, real="f64", dt=dt)
+    p["wall_kind"] = (W.WALL_SPECULAR,) * 4
+    parts = W.shuffle_storage(parts, seed=5)
+    assert _max_movers_first_step(p, parts) > lo
+    g, orc = _run(gpu, p, parts, 4, "f64", chunks=2)
+    _compare(g, orc, exact=True)
+
+
 @pytest.mark.parametrize("real", ["f64", "f32"])
 def test_vhs_homogeneous_bit_exact(gpu, real):
     # variable hard spheres (omega = 0.81): the acceptance decision rests on
