@@ -274,6 +274,12 @@ def main():
         p7 = dict(p7, molecule=W.VHS, omega=0.74)
         sec.append(run_workload("cavity 256x256 x 100, variable hard spheres (omega 0.74), VR, FP32", p7, parts7,
                                 100, 10, torch))
+        # the rest of the cavity's Knudsen sweep
+        for kn in (0.1, 1.0):
+            if kn == args.kn:
+                continue
+            pk, partsk = W.cavity(Kn=kn, real="f32")
+            sec.append(run_workload("cavity 256x256 x 100, Kn=%g, VR, FP32" % kn, pk, partsk, 100, 10, torch))
         p1, parts1 = W.relaxation()
         sec.append(run_workload("relaxation 10,000 particles one cell FP64", p1, parts1, 200, 0, torch))
         line["secondary"] = sec
