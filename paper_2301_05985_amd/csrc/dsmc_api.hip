@@ -30,7 +30,8 @@ using namespace dsmc;
 namespace {
 
 constexpr int kGraphSteps = 8;  // steps recorded per graph (even: the sort ping-pongs)
-constexpr unsigned kWallGrid = 256;  // workgroups of the wall-flight kernel (grid-stride)
+constexpr unsigned kWallGrid = 256;
+constexpr uint32_t kWideMin = 512;  // homogeneous instances above this size run on a workgroup of waves  // workgroups of the wall-flight kernel (grid-stride)
 constexpr size_t kAlign = 256;
 constexpr size_t kMaxLds = 64 * 1024;
 
@@ -162,6 +163,12 @@ struct dsmc_ctx {
     uint2 *units = nullptr;
     uint32_t n_units = 0;
     int persistent_grid = 0;
+    // homogeneous instances, grid launch: the largest ones (more than
+    // kWideMin particles, a prefix of the longest-first order) run on
+    // workgroups of kWideThreads threads, the rest on single waves
+    uint32_t nwide = 0;
+    int cap_small = 0;
+    size_t lds_wide = 0, lds_small = 0;
     uint32_t *count = nullptr, *offset = nullptr, *cursor = nullptr, *big_list = nullptr,
              *perm = nullptr, *owner = nullptr, *sched = nullptr;
     // walled runs: cell ranges of each particle buffer (off[0] is `offset`),
@@ -271,6 +278,15 @@ void launch_collide(dsmc_ctx *c, Launcher &L, int src) {
         else
             hipLaunchKernelGGL((k_collide_persistent<R, VR, false>), dim3((unsigned)c->persistent_grid), dim3(64),
                                c->lds, L.s, a, (const uint2 *)c->units, c->n_units);
+    } else if (D == 0 && !learned && c->nwide > 0) {
+        hipLaunchKernelGGL((k_collide_wide<R, VR>), dim3(c->nwide), dim3(kWideThreads), c->lds_wide, L.s, a);
+        if ((int64_t)c->nwide < c->ncell) {
+            CollideArgs<R> as = a;
+            as.sched = c->sched + c->nwide;
+            as.cap = c->cap_small;
+            hipLaunchKernelGGL((k_collide<R, VR, D>), dim3((unsigned)(c->ncell - c->nwide)), dim3(64), c->lds_small,
+                               L.s, as);
+        }
     } else if (learned)
         hipLaunchKernelGGL((k_collide_learned<R, VR, D>), dim3((unsigned)c->ncell), dim3(64), c->lds,
                            L.s, a);
@@ -561,6 +577,23 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
             k += cnt;
         }
         c->n_units = (uint32_t)units_host.size();
+        // wide instances: the prefix of the longest-first order above kWideMin
+        if (cfg->schedule == DSMC_SCHEDULE_GRID) {
+            uint32_t nw = 0;
+            while (nw < (uint32_t)c->ncell &&
+                   cfg->inst_offset[sched_host[nw] + 1] - cfg->inst_offset[sched_host[nw]] > (int64_t)kWideMin)
+                ++nw;
+            const size_t lw = std::max<size_t>((size_t)c->cap * per + 16 + 16 + sizeof(GroupScratch),
+                                               (size_t)13 * 66 * 8);
+            if (nw > 0 && lw <= kMaxLds) {
+                c->nwide = nw;
+                c->lds_wide = lw;
+                const int64_t nsmall = nw < (uint32_t)c->ncell
+                    ? cfg->inst_offset[sched_host[nw] + 1] - cfg->inst_offset[sched_host[nw]] : 0;
+                c->cap_small = (int)std::min<int64_t>(std::max<int64_t>((nsmall + 31) / 32 * 32, 32), cap_fit);
+                c->lds_small = std::max<size_t>((size_t)c->cap_small * per + 16 + 16, (size_t)13 * 66 * 8);
+            }
+        }
         int dev = 0, ncu = 256;
         if (hipGetDevice(&dev) == hipSuccess) {
             hipDeviceProp_t prop;

@@ -53,6 +53,53 @@ struct CollideArgs {
 
 constexpr int kNsum = 26;
 
+// A cell is processed by T threads: one wave (T = 64), or a workgroup of
+// T / 64 waves for large homogeneous instances.  Wave-level results of a
+// workgroup are combined through a small LDS area after a barrier, every
+// thread combining the waves in the same order.
+constexpr int kWideThreads = 256;
+struct GroupScratch {
+    uint32_t u[kWideThreads / 64][8];
+    double d[kWideThreads / 64][32];
+};
+template <int T>
+__device__ __forceinline__ void grp_put(GroupScratch *gs, int slot, uint32_t v) {
+    if constexpr (T > 64) {
+        if (lane_id() == 0) gs->u[threadIdx.x >> 6][slot] = v;
+    }
+}
+template <int T>
+__device__ __forceinline__ void grp_putd(GroupScratch *gs, int slot, double v) {
+    if constexpr (T > 64) {
+        if (lane_id() == 0) gs->d[threadIdx.x >> 6][slot] = v;
+    }
+}
+template <int T>
+__device__ __forceinline__ uint32_t grp_min(const GroupScratch *gs, int slot, uint32_t v) {
+    if constexpr (T > 64) {
+        uint32_t r = gs->u[0][slot];
+#pragma unroll
+        for (int w = 1; w < T / 64; ++w) r = r < gs->u[w][slot] ? r : gs->u[w][slot];
+        return r;
+    }
+    return v;
+}
+template <int T>
+__device__ __forceinline__ uint32_t grp_sum(const GroupScratch *gs, int slot, uint32_t v) {
+    if constexpr (T > 64) {
+        uint32_t r = gs->u[0][slot];
+#pragma unroll
+        for (int w = 1; w < T / 64; ++w) r += gs->u[w][slot];
+        return r;
+    }
+    return v;
+}
+// a barrier only between the waves of a workgroup (one wave needs none)
+template <int T>
+__device__ __forceinline__ void grp_sync() {
+    if constexpr (T > 64) __syncthreads();
+}
+
 // One particle of a cell staged in LDS: velocity and weight side by side,
 // so that a particle is read with one 16-byte access (two in double).
 template <typename R>
@@ -136,13 +183,13 @@ __device__ __forceinline__ double wave_max_nonneg(double v) {
     return __longlong_as_double((long long)(((uint64_t)hmax << 32) | lmax));
 }
 
-template <typename R, typename View>
-__device__ double exact_bound(const View &v, uint32_t N, double &r_top) {
-    const int lane = lane_id();
+template <typename R, typename View, int T = 64>
+__device__ double exact_bound(const View &v, uint32_t N, double &r_top, GroupScratch *gs = nullptr) {
+    const uint32_t tid = threadIdx.x;
     double m0, m1, m2;
     if constexpr (sizeof(R) == 4) {
         uint32_t lo0 = ~0u, lo1 = ~0u, lo2 = ~0u, nh0 = ~0u, nh1 = ~0u, nh2 = ~0u;  // min keys, min inverted keys
-        for (uint32_t r = lane; r < N; r += 64) {
+        for (uint32_t r = tid; r < N; r += T) {
             R a, b, c;
             v.get(r, a, b, c);
             const uint32_t ka = order_key(a), kb = order_key(b), kc = order_key(c);
@@ -152,6 +199,11 @@ __device__ double exact_bound(const View &v, uint32_t N, double &r_top) {
         }
         lo0 = wave_min_u32(lo0); lo1 = wave_min_u32(lo1); lo2 = wave_min_u32(lo2);
         nh0 = wave_min_u32(nh0); nh1 = wave_min_u32(nh1); nh2 = wave_min_u32(nh2);
+        grp_put<T>(gs, 0, lo0); grp_put<T>(gs, 1, lo1); grp_put<T>(gs, 2, lo2);
+        grp_put<T>(gs, 3, nh0); grp_put<T>(gs, 4, nh1); grp_put<T>(gs, 5, nh2);
+        grp_sync<T>();
+        lo0 = grp_min<T>(gs, 0, lo0); lo1 = grp_min<T>(gs, 1, lo1); lo2 = grp_min<T>(gs, 2, lo2);
+        nh0 = grp_min<T>(gs, 3, nh0); nh1 = grp_min<T>(gs, 4, nh1); nh2 = grp_min<T>(gs, 5, nh2);
         m0 = 0.5 * ((double)from_order_key(~nh0) + (double)from_order_key(lo0));
         m1 = 0.5 * ((double)from_order_key(~nh1) + (double)from_order_key(lo1));
         m2 = 0.5 * ((double)from_order_key(~nh2) + (double)from_order_key(lo2));
@@ -159,7 +211,7 @@ __device__ double exact_bound(const View &v, uint32_t N, double &r_top) {
         // box extremes: min and max are exact in the working precision
         R lo0 = (R)INFINITY, lo1 = (R)INFINITY, lo2 = (R)INFINITY;
         R hi0 = -(R)INFINITY, hi1 = -(R)INFINITY, hi2 = -(R)INFINITY;
-        for (uint32_t r = lane; r < N; r += 64) {
+        for (uint32_t r = tid; r < N; r += T) {
             R a, b, c;
             v.get(r, a, b, c);
             lo0 = fmin(lo0, a); hi0 = fmax(hi0, a);
@@ -171,12 +223,22 @@ __device__ double exact_bound(const View &v, uint32_t N, double &r_top) {
         const R inf = (R)INFINITY;
         lo0 = wave_reduce_dpp(lo0, inf, mn); lo1 = wave_reduce_dpp(lo1, inf, mn); lo2 = wave_reduce_dpp(lo2, inf, mn);
         hi0 = wave_reduce_dpp(hi0, -inf, mx); hi1 = wave_reduce_dpp(hi1, -inf, mx); hi2 = wave_reduce_dpp(hi2, -inf, mx);
+        if constexpr (T > 64) {
+            grp_putd<T>(gs, 0, (double)lo0); grp_putd<T>(gs, 1, (double)lo1); grp_putd<T>(gs, 2, (double)lo2);
+            grp_putd<T>(gs, 3, (double)hi0); grp_putd<T>(gs, 4, (double)hi1); grp_putd<T>(gs, 5, (double)hi2);
+            __syncthreads();
+#pragma unroll
+            for (int w = 0; w < T / 64; ++w) {
+                lo0 = fmin(lo0, (R)gs->d[w][0]); lo1 = fmin(lo1, (R)gs->d[w][1]); lo2 = fmin(lo2, (R)gs->d[w][2]);
+                hi0 = fmax(hi0, (R)gs->d[w][3]); hi1 = fmax(hi1, (R)gs->d[w][4]); hi2 = fmax(hi2, (R)gs->d[w][5]);
+            }
+        }
         m0 = 0.5 * ((double)hi0 + (double)lo0);
         m1 = 0.5 * ((double)hi1 + (double)lo1);
         m2 = 0.5 * ((double)hi2 + (double)lo2);
     }
     double a1 = 0.0, a2 = 0.0;  // largest, second largest r^2 of this lane
-    for (uint32_t r = lane; r < N; r += 64) {
+    for (uint32_t r = tid; r < N; r += T) {
         R a, b, c;
         v.get(r, a, b, c);
         const double dx = (double)a - m0, dy = (double)b - m1, dz = (double)c - m2;
@@ -184,10 +246,28 @@ __device__ double exact_bound(const View &v, uint32_t N, double &r_top) {
         if (r2 > a1) { a2 = a1; a1 = r2; }
         else if (r2 > a2) { a2 = r2; }
     }
-    const double t1 = wave_max_nonneg(a1);
+    double t1 = wave_max_nonneg(a1);
     const unsigned long long at = __ballot(a1 == t1);
-    const bool first = lane == __ffsll((long long)at) - 1;
-    const double t2 = wave_max_nonneg(first ? a2 : a1);
+    const bool first = lane_id() == __ffsll((long long)at) - 1;
+    double t2 = wave_max_nonneg(first ? a2 : a1);
+    if constexpr (T > 64) {
+        // top two of the waves' top twos
+        grp_putd<T>(gs, 6, t1);
+        grp_putd<T>(gs, 7, t2);
+        __syncthreads();
+        t1 = gs->d[0][6];
+        int aw = 0;
+#pragma unroll
+        for (int w = 1; w < T / 64; ++w)
+            if (gs->d[w][6] > t1) { t1 = gs->d[w][6]; aw = w; }
+        t2 = 0.0;
+#pragma unroll
+        for (int w = 0; w < T / 64; ++w) {
+            if (w != aw) t2 = fmax(t2, gs->d[w][6]);
+            t2 = fmax(t2, gs->d[w][7]);
+        }
+        __syncthreads();  // the scratch is reused
+    }
     r_top = sqrt(t1);
     const double eps = sizeof(R) == 4 ? 0x1.0p-20 : 0x1.0p-50;
     return (sqrt(t1) + sqrt(t2)) * (1.0 + eps);
@@ -195,11 +275,10 @@ __device__ double exact_bound(const View &v, uint32_t N, double &r_top) {
 
 // The largest pair speed of the cell by brute force (lane r takes rows
 // r, r + 64, ...), times the same rounding margin as the bound.
-template <typename R, typename View>
-__device__ double pair_diameter(const View &v, uint32_t N) {
-    const int lane = lane_id();
+template <typename R, typename View, int T = 64>
+__device__ double pair_diameter(const View &v, uint32_t N, GroupScratch *gs = nullptr) {
     double best = 0.0;
-    for (uint32_t r = lane; r < N; r += 64) {
+    for (uint32_t r = threadIdx.x; r < N; r += T) {
         R x, y, z;
         v.get(r, x, y, z);
         for (uint32_t t = r + 1; t < N; ++t) {
@@ -211,6 +290,13 @@ __device__ double pair_diameter(const View &v, uint32_t N) {
         }
     }
     best = wave_max_t(best);
+    if constexpr (T > 64) {
+        grp_putd<T>(gs, 0, best);
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < T / 64; ++w) best = fmax(best, gs->d[w][0]);
+        __syncthreads();  // the scratch is reused
+    }
     const double eps = sizeof(R) == 4 ? 0x1.0p-20 : 0x1.0p-50;
     return sqrt(best) * (1.0 + eps);
 }
@@ -360,12 +446,12 @@ __device__ __forceinline__ void draw_candidates(bool fresh, uint32_t k, uint32_t
 
 // Velocity window over the live candidates (k in [kb, wend)); returns the
 // first uncommitted candidate and sets `commit` and `accept` per lane.
-template <typename R, typename View>
+template <typename R, typename View, int T>
 __device__ __forceinline__ uint32_t velocity_window(const View &v, bool live, uint32_t k, uint32_t kb, uint32_t wend,
                                                     uint32_t i, uint32_t j, R U, R nx, R ny, R nz, R gm, R gm2,
                                                     double gmax2, double om1, int molecule, bool &commit,
                                                     bool &accept, R &g2_out, double &pacc, uint32_t &acc,
-                                                    uint32_t &over) {
+                                                    uint32_t &over, GroupScratch *gs) {
     R ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0, g2 = 0;
     accept = false;
     pacc = 1.0;
@@ -394,9 +480,11 @@ __device__ __forceinline__ uint32_t velocity_window(const View &v, bool live, ui
     const bool bad = live && (v.read_own(i) < k || v.read_own(j) < k);
     // first candidate that must wait; the window ends there (or at wend)
     uint32_t kend = wave_min_u32(bad ? k : 0xFFFFFFFFu);
+    grp_put<T>(gs, 0, kend);
+    __syncthreads();
+    kend = grp_min<T>(gs, 0, kend);
     kend = kend < wend ? kend : wend;
     commit = live && k < kend;
-    __syncthreads();
     if (writer) {
         v.clear_own(i);
         v.clear_own(j);
@@ -417,16 +505,16 @@ __device__ __forceinline__ uint32_t velocity_window(const View &v, bool live, ui
     return kend;
 }
 
-template <typename R, bool VR, typename View>
+template <typename R, bool VR, typename View, int T = 64>
 __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uint32_t cell,
                          uint32_t step, uint32_t k0, uint32_t k1, int molecule, double om1, uint32_t &n_acc,
-                         uint32_t &n_over) {
-    const uint32_t ulane = (uint32_t)lane_id();
+                         uint32_t &n_over, GroupScratch *gs = nullptr) {
+    constexpr uint32_t W = (uint32_t)T;  // candidates per window (one per thread)
     const R gm = (R)gmax;
     const R gm2 = gm * gm;
     const double gmax2 = gmax * gmax;
     uint32_t kb = 0, acc = 0, over = 0;
-    uint32_t k = ulane;  // candidate held by this lane; k in [kb, kb + 64)
+    uint32_t k = threadIdx.x;  // candidate held by this thread; k in [kb, kb + W)
     bool fresh = true;   // its draws are still to be computed
     bool done = false;   // committed, waiting for the end of its generation (weights)
     bool acc_k = false;  // committed candidate's acceptance (weights)
@@ -437,20 +525,32 @@ __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uin
     while (kb < M) {
         const bool act = k < M;
         const bool draw_now = act && fresh;
-        draw_candidates<R>(draw_now, k, N, cell, step, k0, k1, i, j, U, nx, ny, nz);
+        if constexpr (T == 64) {
+            draw_candidates<R>(draw_now, k, N, cell, step, k0, k1, i, j, U, nx, ny, nz);
+        } else {
+            if (draw_now) {
+                const u32x4 r = draw(k, kTagPair, 0, cell, step, k0, k1);
+                i = scale_index(r.v[0], N);
+                j = scale_index(r.v[1], N - 1);
+                j += (j >= i) ? 1u : 0u;
+                U = sizeof(R) == 4 ? (R)unif24(r.v[2]) : (R)unif53(r.v[2], r.v[3]);
+            }
+            direction<R>(draw_now, 1u, k, cell, step, k0, k1, nx, ny, nz);
+        }
         fresh = fresh && !act;
-        const uint32_t gend = M - g0 > 64u ? g0 + 64u : M;
-        const uint32_t wend = VR ? gend : (M - kb > 64u ? kb + 64u : M);
+        const uint32_t gend = M - g0 > W ? g0 + W : M;
+        const uint32_t wend = VR ? gend : (M - kb > W ? kb + W : M);
         bool commit, accept;
         R g2;
         double pacc;
-        const uint32_t kend = velocity_window<R>(v, act && !done, k, kb, wend, i, j, U, nx, ny, nz, gm, gm2,
-                                                 gmax2, om1, molecule, commit, accept, g2, pacc, acc, over);
+        const uint32_t kend = velocity_window<R, View, T>(v, act && !done, k, kb, wend, i, j, U, nx, ny, nz, gm, gm2,
+                                                          gmax2, om1, molecule, commit, accept, g2, pacc, acc, over,
+                                                          gs);
         kb = kend;
         if (!VR) {
-            // committed lanes move on to the candidate 64 later
+            // committed threads move on to the candidate W later
             if (commit) {
-                k += 64;
+                k += W;
                 fresh = true;
             }
             continue;
@@ -468,7 +568,14 @@ __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uin
         // rejected -> W_i (1 - p W_j) / (1 - p), p = g / g_max
         const bool mine = act && k < gend;  // this lane's candidate belongs to the generation
         bool pend = mine;
-        while (__ballot(pend)) {
+        for (;;) {
+            bool any = __ballot(pend) != 0ull;
+            if constexpr (T > 64) {
+                grp_put<T>(gs, 1, any ? 1u : 0u);
+                __syncthreads();
+                any = grp_sum<T>(gs, 1, 0u) != 0u;
+            }
+            if (!any) break;
             // a pending candidate is ready when no earlier pending candidate
             // touches its particles; ready candidates touch disjoint pairs and
             // every particle sees its updates in candidate order
@@ -502,14 +609,20 @@ __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uin
         }
         // next generation
         if (mine) {
-            k += 64;
+            k += W;
             fresh = true;
             done = false;
         }
         g0 = gend;
     }
-    n_acc = acc;
-    n_over = wave_sum_u32(over);
+    // acc counts this wave's lanes; the workgroup adds its waves
+    over = wave_sum_u32(over);
+    grp_put<T>(gs, 2, acc);
+    grp_put<T>(gs, 3, over);
+    grp_sync<T>();
+    n_acc = grp_sum<T>(gs, 2, acc);
+    n_over = grp_sum<T>(gs, 3, over);
+    grp_sync<T>();
 }
 
 // The running sum a lane owns in the moment reduction, or -1.  Cells in
@@ -554,10 +667,12 @@ __device__ __forceinline__ CellPrefetch prefetch_cell(const CollideArgs<R> &a, u
 // transpose, once per set of 13 sums: every lane stores its partial sums as
 // a column, the four lanes of quad r add up a quarter of row r each
 // (interleaved 16-byte columns) and the quad combines its four parts.
-template <typename R, bool VR, typename View>
+template <typename R, bool VR, typename View, int T = 64>
 __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cell, uint32_t N, uint32_t M,
-                            uint32_t acc, uint32_t over, const CellPrefetch &pf, double *red, uint32_t wb_base) {
+                            uint32_t acc, uint32_t over, const CellPrefetch &pf, double *red, uint32_t wb_base,
+                            GroupScratch *gs = nullptr) {
     const int lane = lane_id();
+    const uint32_t tid = threadIdx.x;
     constexpr int K = VR ? 32 : 16;  // 26 or 13 sums, padded to a power of two
     double q[K];
 #pragma unroll
@@ -566,7 +681,7 @@ __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cel
     // zeros), the others are added; products are added with fused
     // multiply-adds (the sums are compared with a tolerance; the particle
     // state is what must match exactly)
-    for (uint32_t r = lane; r < N || r == (uint32_t)lane; r += 64) {
+    for (uint32_t r = tid; r < N || r == tid; r += T) {
         const bool has = r < N;
         R x = (R)0, y = (R)0, z = (R)0, w = (R)1;
         if (has) {
@@ -580,7 +695,7 @@ __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cel
         const double vx = (double)x, vy = (double)y, vz = (double)z;
         const double xx = vx * vx, yy = vy * vy, zz = vz * vz;
         const double c2 = (xx + yy) + zz;
-        if (r == (uint32_t)lane) {
+        if (r == tid) {
             q[0] = has ? 1.0 : 0.0; q[1] = vx; q[2] = vy; q[3] = vz;
             q[4] = xx; q[5] = yy; q[6] = zz;
             q[7] = vx * vy; q[8] = vx * vz; q[9] = vy * vz;
@@ -594,7 +709,7 @@ __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cel
         if (VR) {
             const double f = 1.0 - (double)w;
             const double fx = f * vx, fy = f * vy, fz = f * vz;
-            if (r == (uint32_t)lane) {
+            if (r == tid) {
                 q[13] = f; q[14] = fx; q[15] = fy; q[16] = fz;
                 q[17] = fx * vx; q[18] = fy * vy; q[19] = fz * vz;
                 q[20] = fx * vy; q[21] = fx * vz; q[22] = fy * vz;
@@ -609,7 +724,18 @@ __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cel
     }
     // each lane ends up with the total of the sum it owns
     double tot = 0.0;
-    if constexpr (View::kInLds) {
+    if constexpr (T > 64) {
+        // per wave by recursive halving, then the waves in a fixed order:
+        // thread t < 26 (13) owns sum t
+        (void)red;
+        const double t = wave_sum_many<K>(q);  // lane L: total of index L >> (VR ? 1 : 2)
+        if ((lane & (VR ? 1 : 3)) == 0) gs->d[tid >> 6][lane >> (VR ? 1 : 2)] = t;
+        __syncthreads();
+        if (tid < (uint32_t)(VR ? kNsum : 13)) {
+#pragma unroll
+            for (int w = 0; w < T / 64; ++w) tot += gs->d[w][tid];
+        }
+    } else if constexpr (View::kInLds) {
         constexpr int RS = 66;  // row stride (doubles): 16-byte aligned rows
         const int row = lane >> 2, part = lane & 3;
         __syncthreads();
@@ -639,14 +765,14 @@ __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cel
         const double t = wave_sum_many<K>(q);  // lane L: total of index L >> (VR ? 1 : 2)
         tot = __shfl(t, (lane << (VR ? 1 : 2)) & 63, 64);
     }
-    const int owned = owned_sum<View::kInLds, VR>(lane);
+    const int owned = owned_sum<View::kInLds && T == 64, VR>((int)tid);
     const uint32_t idx = (uint32_t)owned;
     const bool writer = owned >= 0;
     const bool nonfinite = writer && !isfinite(tot);
     const bool bad_plain = __ballot(nonfinite && idx < 13) != 0ull;
     const bool bad_vr = __ballot(nonfinite && idx >= 13) != 0ull;
     if (writer) a.sums[(size_t)cell * kNsum + idx] = pf.sum + tot;
-    if (lane == 0) {
+    if (tid == 0) {
         a.counters[2 * (size_t)cell] = pf.cand + M;
         a.counters[2 * (size_t)cell + 1] = pf.acc + acc;
         if (over) diag_add(a.st, kDiagOvershoot, (unsigned long long)over);
@@ -669,16 +795,17 @@ __device__ __forceinline__ double candidates_real(const CollideArgs<R> &a, doubl
 
 // Majorant, candidate count, NTC loop and sampling of one cell; the view
 // already holds the cell in canonical order.
-template <typename R, bool VR, typename View>
+template <typename R, bool VR, typename View, int T = 64>
 __device__ void process_cell(const CollideArgs<R> &a, const View &v, uint32_t cell, uint32_t N,
-                             uint32_t step, const CellPrefetch &pf, double *red = nullptr, uint32_t wb_base = 0) {
-    const int lane = lane_id();
+                             uint32_t step, const CellPrefetch &pf, double *red = nullptr, uint32_t wb_base = 0,
+                             GroupScratch *gs = nullptr) {
     uint32_t M = 0, acc = 0, over = 0;
     if (N >= 2) {
         double rt;
         double gmax = 1.0;
         if (a.molecule != DSMC_MAXWELL)
-            gmax = a.majorant == DSMC_MAJORANT_DIAMETER ? pair_diameter<R>(v, N) : exact_bound<R>(v, N, rt);
+            gmax = a.majorant == DSMC_MAJORANT_DIAMETER ? pair_diameter<R, View, T>(v, N, gs)
+                                                        : exact_bound<R, View, T>(v, N, rt, gs);
         const double V = a.volume ? a.volume[cell] : a.Vuni;
         const double Nd = (double)N;
         const double Mreal = candidates_real<R>(a, Nd, gmax, V);
@@ -686,13 +813,13 @@ __device__ void process_cell(const CollideArgs<R> &a, const View &v, uint32_t ce
         double Mf = floor(Mreal + unif53(r.v[0], r.v[1]));
         if (!(Mf >= 0.0)) Mf = 0.0;
         if (Mf > 2147483647.0) {
-            if (lane == 0) set_error(a.st, DSMC_ECAPACITY);
+            if (threadIdx.x == 0) set_error(a.st, DSMC_ECAPACITY);
             Mf = 0.0;
         }
         M = (uint32_t)Mf;
-        ntc_loop<R, VR>(v, N, gmax, M, cell, step, a.k0, a.k1, a.molecule, a.omega1, acc, over);
+        ntc_loop<R, VR, View, T>(v, N, gmax, M, cell, step, a.k0, a.k1, a.molecule, a.omega1, acc, over, gs);
     }
-    sample_cell<R, VR>(a, v, cell, N, M, acc, over, pf, red, wb_base);
+    sample_cell<R, VR, View, T>(a, v, cell, N, M, acc, over, pf, red, wb_base, gs);
 }
 
 }  // namespace dsmc

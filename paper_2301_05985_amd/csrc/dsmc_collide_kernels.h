@@ -276,8 +276,23 @@ __device__ __forceinline__ void collide_lds_body(const CollideArgs<R> &a, unsign
         gather_cell<R, VR, D>(a, cell, base, N, owner, vel);  // the owner array holds the selection
         __syncthreads();
     } else {
-        for (uint32_t s = lane; s < N; s += 64)
-            vel[s] = Vel4<R>{a.s.cx[base + s], a.s.cy[base + s], a.s.cz[base + s], VR ? a.s.w[base + s] : (R)1};
+        // staged four rows of 64 at a time: all their loads are in flight
+        // before the first LDS store
+        for (uint32_t s0 = 0; s0 < N; s0 += 256) {
+            Vel4<R> t[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t s = s0 + 64u * (uint32_t)j + (uint32_t)lane;
+                if (s < N)
+                    t[j] = Vel4<R>{a.s.cx[base + s], a.s.cy[base + s], a.s.cz[base + s],
+                                   VR ? a.s.w[base + s] : (R)1};
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t s = s0 + 64u * (uint32_t)j + (uint32_t)lane;
+                if (s < N) vel[s] = t[j];
+            }
+        }
     }
     for (uint32_t r = lane; r < N; r += 64) owner[r] = 0xFFFFFFFFu;
     __syncthreads();
@@ -323,6 +338,51 @@ template <typename R, bool VR, int D>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_collide(CollideArgs<R> a) {
     extern __shared__ __align__(16) unsigned char smem[];
     collide_lds_body<R, VR, D, false>(a, smem, a.sched ? a.sched[blockIdx.x] : blockIdx.x);
+}
+
+// Large homogeneous instances: one workgroup of kWideThreads threads per
+// instance (the particle loops spread over its waves, NTC windows of
+// kWideThreads consecutive candidates), so that an instance of a few
+// thousand particles does not run on a single wave held by its LDS size.
+template <typename R, bool VR>
+__global__ __launch_bounds__(kWideThreads) void k_collide_wide(CollideArgs<R> a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int T = kWideThreads;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t cell = a.sched[blockIdx.x];
+    const uint32_t base = a.start[cell];
+    const uint32_t N = a.start[cell + 1] - base;
+    if (N > (uint32_t)a.cap) {
+        if (tid == 0) {
+            const uint32_t q = atomicAdd(&a.st->big_count, 1u);
+            a.big_list[q] = cell;
+        }
+        return;
+    }
+    const uint32_t step = (uint32_t)a.st->step_cur;
+    const CellPrefetch pf = prefetch_cell<R, VR, false>(a, cell);
+    const int cap = a.cap;
+    Vel4<R> *vel = (Vel4<R> *)smem;
+    uint32_t *owner = (uint32_t *)(vel + cap);
+    GroupScratch *gs = (GroupScratch *)(owner + cap + 4);  // 16-byte aligned: cap is a multiple of 32
+    for (uint32_t s0 = 0; s0 < N; s0 += 2 * T) {
+        Vel4<R> t[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const uint32_t s = s0 + (uint32_t)T * (uint32_t)j + tid;
+            if (s < N)
+                t[j] = Vel4<R>{a.s.cx[base + s], a.s.cy[base + s], a.s.cz[base + s], VR ? a.s.w[base + s] : (R)1};
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const uint32_t s = s0 + (uint32_t)T * (uint32_t)j + tid;
+            if (s < N) vel[s] = t[j];
+        }
+    }
+    for (uint32_t r = tid; r < N; r += T) owner[r] = 0xFFFFFFFFu;
+    __syncthreads();
+    const LdsView<R> view{vel, owner};
+    process_cell<R, VR, LdsView<R>, T>(a, view, cell, N, step, pf, nullptr, base, gs);
 }
 
 template <typename R, bool VR, int D>
