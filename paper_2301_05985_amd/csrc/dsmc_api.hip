@@ -30,8 +30,8 @@ using namespace dsmc;
 namespace {
 
 constexpr int kGraphSteps = 8;  // steps recorded per graph (even: the sort ping-pongs)
-constexpr unsigned kWallGrid = 256;
-constexpr uint32_t kWideMin = 512;  // homogeneous instances above this size run on a workgroup of waves  // workgroups of the wall-flight kernel (grid-stride)
+constexpr unsigned kWallGrid = 256;  // workgroups of the wall-flight kernel (grid-stride)
+constexpr uint32_t kWideMin = 1024;  // homogeneous instances above this size run on a workgroup of waves
 constexpr size_t kAlign = 256;
 constexpr size_t kMaxLds = 64 * 1024;
 
