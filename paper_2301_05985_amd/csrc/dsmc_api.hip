@@ -278,14 +278,22 @@ void launch_collide(dsmc_ctx *c, Launcher &L, int src) {
         else
             hipLaunchKernelGGL((k_collide_persistent<R, VR, false>), dim3((unsigned)c->persistent_grid), dim3(64),
                                c->lds, L.s, a, (const uint2 *)c->units, c->n_units);
-    } else if (D == 0 && !learned && c->nwide > 0) {
-        hipLaunchKernelGGL((k_collide_wide<R, VR>), dim3(c->nwide), dim3(kWideThreads), c->lds_wide, L.s, a);
+    } else if (D == 0 && c->nwide > 0) {
+        if (learned)
+            hipLaunchKernelGGL((k_collide_wide_learned<R, VR>), dim3(c->nwide), dim3(kWideThreads), c->lds_wide, L.s,
+                               a);
+        else
+            hipLaunchKernelGGL((k_collide_wide<R, VR>), dim3(c->nwide), dim3(kWideThreads), c->lds_wide, L.s, a);
         if ((int64_t)c->nwide < c->ncell) {
             CollideArgs<R> as = a;
             as.sched = c->sched + c->nwide;
             as.cap = c->cap_small;
-            hipLaunchKernelGGL((k_collide<R, VR, D>), dim3((unsigned)(c->ncell - c->nwide)), dim3(64), c->lds_small,
-                               L.s, as);
+            if (learned)
+                hipLaunchKernelGGL((k_collide_learned<R, VR, D>), dim3((unsigned)(c->ncell - c->nwide)), dim3(64),
+                                   c->lds_small, L.s, as);
+            else
+                hipLaunchKernelGGL((k_collide<R, VR, D>), dim3((unsigned)(c->ncell - c->nwide)), dim3(64),
+                                   c->lds_small, L.s, as);
         }
     } else if (learned)
         hipLaunchKernelGGL((k_collide_learned<R, VR, D>), dim3((unsigned)c->ncell), dim3(64), c->lds,

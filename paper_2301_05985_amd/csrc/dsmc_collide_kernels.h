@@ -344,9 +344,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
 // instance (the particle loops spread over its waves, NTC windows of
 // kWideThreads consecutive candidates), so that an instance of a few
 // thousand particles does not run on a single wave held by its LDS size.
-template <typename R, bool VR>
-__global__ __launch_bounds__(kWideThreads) void k_collide_wide(CollideArgs<R> a) {
-    extern __shared__ __align__(16) unsigned char smem[];
+template <typename R, bool VR, bool LEARNED>
+__device__ __forceinline__ void collide_wide_body(const CollideArgs<R> &a, unsigned char *smem) {
     constexpr int T = kWideThreads;
     const uint32_t tid = threadIdx.x;
     const uint32_t cell = a.sched[blockIdx.x];
@@ -382,7 +381,20 @@ __global__ __launch_bounds__(kWideThreads) void k_collide_wide(CollideArgs<R> a)
     for (uint32_t r = tid; r < N; r += T) owner[r] = 0xFFFFFFFFu;
     __syncthreads();
     const LdsView<R> view{vel, owner};
-    process_cell<R, VR, LdsView<R>, T>(a, view, cell, N, step, pf, nullptr, base, gs);
+    if (LEARNED) process_cell_learned<R, VR, LdsView<R>, T>(a, view, cell, N, step, pf, nullptr, base, gs);
+    else process_cell<R, VR, LdsView<R>, T>(a, view, cell, N, step, pf, nullptr, base, gs);
+}
+
+template <typename R, bool VR>
+__global__ __launch_bounds__(kWideThreads) void k_collide_wide(CollideArgs<R> a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    collide_wide_body<R, VR, false>(a, smem);
+}
+
+template <typename R, bool VR>
+__global__ __launch_bounds__(kWideThreads) void k_collide_wide_learned(CollideArgs<R> a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    collide_wide_body<R, VR, true>(a, smem);
 }
 
 template <typename R, bool VR, int D>

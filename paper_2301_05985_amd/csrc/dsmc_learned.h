@@ -156,20 +156,29 @@ __device__ double learned_majorant(const CollideArgs<R> &a, const View &v, uint3
     return gp;
 }
 
-// Same as process_cell, with the learned majorant.
-template <typename R, bool VR, typename View>
+// Same as process_cell, with the learned majorant.  A workgroup cell
+// (T > 64) computes the majorant on its first wave and shares it through LDS.
+template <typename R, bool VR, typename View, int T = 64>
 __device__ void process_cell_learned(const CollideArgs<R> &a, const View &v, uint32_t cell, uint32_t N,
                                      uint32_t step, const CellPrefetch &pf, double *red = nullptr,
-                                     uint32_t wb_base = 0) {
-    const int lane = lane_id();
+                                     uint32_t wb_base = 0, GroupScratch *gs = nullptr) {
     uint32_t M = 0, acc = 0, over = 0;
     if (N >= 2) {
         const double V = a.volume ? a.volume[cell] : a.Vuni;
-        int used = 0;
-        const double gmax = learned_majorant<R>(a, v, cell, N, V, used);
-        if (lane == 0) {
-            const int slot = used == 1 ? kDiagLearned : (used == -1 ? kDiagFallback : kDiagSkip);
-            diag_add(a.st, slot, 1ull);
+        double gmax = 0.0;
+        if (threadIdx.x < 64) {
+            int used = 0;
+            gmax = learned_majorant<R>(a, v, cell, N, V, used);
+            if (threadIdx.x == 0) {
+                const int slot = used == 1 ? kDiagLearned : (used == -1 ? kDiagFallback : kDiagSkip);
+                diag_add(a.st, slot, 1ull);
+            }
+        }
+        if constexpr (T > 64) {
+            if (threadIdx.x == 0) gs->d[0][8] = gmax;
+            __syncthreads();
+            gmax = gs->d[0][8];
+            __syncthreads();  // the scratch is reused
         }
         const double Nd = (double)N;
         const double Mreal = candidates_real<R>(a, Nd, gmax, V);
@@ -177,13 +186,13 @@ __device__ void process_cell_learned(const CollideArgs<R> &a, const View &v, uin
         double Mf = floor(Mreal + unif53(r.v[0], r.v[1]));
         if (!(Mf >= 0.0)) Mf = 0.0;
         if (Mf > 2147483647.0) {
-            if (lane == 0) set_error(a.st, DSMC_ECAPACITY);
+            if (threadIdx.x == 0) set_error(a.st, DSMC_ECAPACITY);
             Mf = 0.0;
         }
         M = (uint32_t)Mf;
-        ntc_loop<R, VR>(v, N, gmax, M, cell, step, a.k0, a.k1, a.molecule, a.omega1, acc, over);
+        ntc_loop<R, VR, View, T>(v, N, gmax, M, cell, step, a.k0, a.k1, a.molecule, a.omega1, acc, over, gs);
     }
-    sample_cell<R, VR>(a, v, cell, N, M, acc, over, pf, red, wb_base);
+    sample_cell<R, VR, View, T>(a, v, cell, N, M, acc, over, pf, red, wb_base, gs);
 }
 
 }  // namespace dsmc

@@ -96,9 +96,21 @@ def _homog(counts, seed=0, dt=0.2, molecule=0, shift=1.0):
 
 
 @pytest.mark.parametrize("real", ["f64", "f32"])
+def test_homogeneous_weights_bit_exact(gpu, real):
+    # importance weights in homogeneous instances, one- and four-wave cells
+    _announce("homogeneous weights %s" % real)
+    p, parts = _homog([70, 1300, 600, 2, 1100], dt=0.3)
+    p = dict(p, vr=1, vr_T0=1.0)
+    rng = np.random.default_rng(21)
+    parts = dict(parts, w=1.0 + 0.05 * rng.standard_normal(len(parts["cx"])))
+    g, orc = _run(gpu, p, parts, 8, real, chunks=2)
+    _compare(g, orc, exact=True)
+
+
+@pytest.mark.parametrize("real", ["f64", "f32"])
 def test_homogeneous_bit_exact(gpu, real):
     _announce("homogeneous %s" % real)
-    p, parts = _homog([0, 1, 2, 3, 50, 64, 65, 127, 257, 300, 611, 1024], dt=0.3)
+    p, parts = _homog([0, 1, 2, 3, 50, 64, 65, 127, 257, 300, 611, 1024, 1025, 1500], dt=0.3)
     g, orc = _run(gpu, p, parts, 12, real, chunks=2)
     assert orc.counters[:, 1].sum() > 500
     _compare(g, orc, exact=True)
