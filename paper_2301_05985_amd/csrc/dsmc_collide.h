@@ -1,5 +1,6 @@
 // dsmc_collide.h -- per-cell NTC collisions, importance weights and moment
-// sampling, one 64-lane wave per cell.
+// sampling, one 64-lane wave per cell (or a workgroup of waves for large
+// homogeneous instances).
 //
 // Method (Bird 1994, no-time-counter scheme): a cell of N particles takes
 //   M = floor( 1/2 N (N-1) F_N sigma g_max dt / V  +  U0 )
@@ -10,15 +11,17 @@
 // mass.  Candidates are sequential by definition -- candidate k sees the
 // velocities left by candidates 0..k-1.
 //
-// Wave mapping: 64 consecutive candidates are drawn at once, one per lane.
-// Lanes that will write (accepted pairs; every candidate when importance
-// weights are carried) mark their two particles in an LDS owner array with
-// an atomic min of their lane number.  The first lane whose particles were
-// marked by an earlier lane ends the batch: every lane before it read exactly
+// Wave mapping: 64 consecutive candidates are drawn at once, one per lane
+// (256 on a workgroup cell).  Lanes that will write velocities (accepted
+// pairs) mark their two particles in an LDS owner array with an atomic min
+// of their candidate index.  The first candidate whose particles were marked
+// by an earlier one ends the batch: every candidate before it read exactly
 // the state the sequential definition gives it, and the writers among them
 // touch disjoint particles, so they commit in parallel.  The next batch
-// starts at the first uncommitted candidate.  Results are bit-identical to
-// the sequential loop.
+// starts at the first uncommitted candidate.  Importance weights, which
+// every candidate updates, are applied afterwards in rounds of candidates
+// that share no particle with an earlier pending one.  Results are
+// bit-identical to the sequential loop.
 #pragma once
 #include "dsmc_kernels.h"
 
