@@ -1,6 +1,7 @@
 // dsmc_collide_kernels.h -- the collision kernels: cells staged in LDS (one
-// wave per cell) and, for cells above the LDS capacity, a global-memory
-// variant; each with the exact or the learned majorant.
+// wave per cell, or a workgroup of waves per large homogeneous instance)
+// and, for cells above the LDS capacity, a global-memory variant; each with
+// the exact or the learned majorant.
 #pragma once
 #include "dsmc_collide.h"
 #include "dsmc_learned.h"
