@@ -567,22 +567,25 @@ __global__ __launch_bounds__(256) void k_scan_lookback(uint32_t *count, uint32_t
     if (wv == 0) {
         // wave-wide look-back: lane l inspects tile j - l, 64 predecessors per
         // round; the window is summed up to the nearest inclusive prefix once
-        // every tile before it has published its total
+        // every tile before it has published its total.  A flag carries its
+        // value in the same 64-bit word, so relaxed device-scope atomics
+        // suffice (release/acquire would write back and invalidate L2 on
+        // every store and poll)
         uint32_t prefix = 0;
         if (tile == 0) {
             if (lane == 0)
-                __hip_atomic_store(&flags[0], kFlagInc | (uint64_t)tile_total, __ATOMIC_RELEASE,
+                __hip_atomic_store(&flags[0], kFlagInc | (uint64_t)tile_total, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
         } else {
             if (lane == 0)
-                __hip_atomic_store(&flags[tile], kFlagAgg | (uint64_t)tile_total, __ATOMIC_RELEASE,
+                __hip_atomic_store(&flags[tile], kFlagAgg | (uint64_t)tile_total, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
             int j = tile - 1;
             uint32_t polls = 0;
             while (j >= 0) {
                 const int idx = j - lane;
                 // before tile 0: an inclusive prefix of zero ends the window
-                const uint64_t f = idx >= 0 ? __hip_atomic_load(&flags[idx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)
+                const uint64_t f = idx >= 0 ? __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                                             : kFlagInc;
                 const unsigned long long incm = __ballot((f & kFlagInc) != 0);
                 const int first = incm ? __ffsll((long long)incm) - 1 : 64;
@@ -601,7 +604,7 @@ __global__ __launch_bounds__(256) void k_scan_lookback(uint32_t *count, uint32_t
                 j -= 64;
             }
             if (lane == 0)
-                __hip_atomic_store(&flags[tile], kFlagInc | (uint64_t)(prefix + tile_total), __ATOMIC_RELEASE,
+                __hip_atomic_store(&flags[tile], kFlagInc | (uint64_t)(prefix + tile_total), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
         }
         if (lane == 0) tile_prefix = prefix;
@@ -626,7 +629,7 @@ __global__ __launch_bounds__(256) void k_scan_lookback(uint32_t *count, uint32_t
     // last workgroup out: clear the flags, advance the step
     __syncthreads();
     if (t == 0) {
-        __threadfence();
+        // the flags this workgroup read were consumed before the barrier
         const uint32_t d = atomicAdd(done, 1u);
         last = d == gridDim.x - 1;
     }
