@@ -111,7 +111,7 @@ Layout make_layout(const dsmc_config &c) {
         L.count = take(nc * 4);
         L.cursor = take(nc * 4);
         L.flags = take(((nc + kScanTile - 1) / kScanTile) * 8);
-        L.done = take(4);
+        L.done = take(8);
         L.offset2 = take((nc + 1) * 4);
         L.code = take(n);
         L.far_head = take(nc * 4);
@@ -645,7 +645,7 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
     if (hipMemsetAsync(c->st, 0, sizeof(DevState), c->stream) != hipSuccess) return fail(DSMC_EHIP);
     if (cfg->dims >= 1 && hipMemsetAsync(c->count, 0, (size_t)c->ncell * 4, c->stream) != hipSuccess)
         return fail(DSMC_EHIP);
-    if (cfg->dims >= 1 && hipMemsetAsync(c->ws + L.flags, 0, L.done + 4 - L.flags, c->stream) != hipSuccess)
+    if (cfg->dims >= 1 && hipMemsetAsync(c->ws + L.flags, 0, L.done + 8 - L.flags, c->stream) != hipSuccess)
         return fail(DSMC_EHIP);
     if (cfg->cell_volume) {
         c->volume_host.assign(cfg->cell_volume, cfg->cell_volume + c->ncell);

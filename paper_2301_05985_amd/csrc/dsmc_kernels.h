@@ -528,12 +528,16 @@ __global__ __launch_bounds__(64) void k_canonical(Soa<R> src, Soa<R> dst, const 
 // found by walking back over earlier tiles' flags, 64 at a time (one per
 // lane of the first wave).  Workgroups are dispatched in index order, so
 // every tile it waits on is resident or finished; the walk still gives up
-// (and reports an error) after a bounded number of polls.  The
-// last workgroup to finish clears the flags for the next launch and, when
-// `advance` is set (every step; not at set-up), advances the step
-// bookkeeping.
+// (and reports an error) after a bounded number of polls.  A flag is one
+// 64-bit word: status (2 bits), the launch's epoch (30 bits) and the value
+// (32 bits); a flag of an earlier launch has another epoch and reads as not
+// yet published, so flags are never cleared.  done[0] counts finished
+// workgroups, done[1] holds the last launch's epoch; the last workgroup to
+// finish resets the one, advances the other and, when `advance` is set
+// (every step; not at set-up), advances the step bookkeeping.
 constexpr int kScanTile = 1024;
-constexpr uint64_t kFlagAgg = 1ull << 32, kFlagInc = 2ull << 32;
+constexpr uint64_t kFlagAgg = 1ull << 62, kFlagInc = 2ull << 62, kFlagStatus = 3ull << 62;
+constexpr uint32_t kEpochMask = (1u << 30) - 1u;
 
 __global__ __launch_bounds__(256) void k_scan_lookback(uint32_t *count, uint32_t *offset, uint32_t *cursor,
                                                        int ncell, uint64_t *flags, uint32_t *done,
@@ -572,25 +576,28 @@ __global__ __launch_bounds__(256) void k_scan_lookback(uint32_t *count, uint32_t
         // suffice (release/acquire would write back and invalidate L2 on
         // every store and poll)
         uint32_t prefix = 0;
+        const uint64_t epoch = (uint64_t)((done[1] + 1u) & kEpochMask) << 32;
         if (tile == 0) {
             if (lane == 0)
-                __hip_atomic_store(&flags[0], kFlagInc | (uint64_t)tile_total, __ATOMIC_RELAXED,
+                __hip_atomic_store(&flags[0], kFlagInc | epoch | (uint64_t)tile_total, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
         } else {
             if (lane == 0)
-                __hip_atomic_store(&flags[tile], kFlagAgg | (uint64_t)tile_total, __ATOMIC_RELAXED,
+                __hip_atomic_store(&flags[tile], kFlagAgg | epoch | (uint64_t)tile_total, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
             int j = tile - 1;
             uint32_t polls = 0;
             while (j >= 0) {
                 const int idx = j - lane;
-                // before tile 0: an inclusive prefix of zero ends the window
-                const uint64_t f = idx >= 0 ? __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                            : kFlagInc;
-                const unsigned long long incm = __ballot((f & kFlagInc) != 0);
+                // before tile 0: an inclusive prefix of zero ends the window;
+                // a flag of another launch counts as unpublished
+                uint64_t f = idx >= 0 ? __hip_atomic_load(&flags[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                      : kFlagInc | epoch;
+                if ((f & ((uint64_t)kEpochMask << 32)) != epoch) f = 0;
+                const unsigned long long incm = __ballot((f & kFlagStatus) == kFlagInc);
                 const int first = incm ? __ffsll((long long)incm) - 1 : 64;
                 const unsigned long long need = first >= 63 ? ~0ull : ((1ull << (first + 1)) - 1ull);
-                const unsigned long long waiting = __ballot((f & (kFlagInc | kFlagAgg)) == 0) & need;
+                const unsigned long long waiting = __ballot((f & kFlagStatus) == 0) & need;
                 if (waiting) {
                     if (++polls > (1u << 24)) {
                         if (lane == 0) set_error(st, DSMC_EHIP);
@@ -604,7 +611,7 @@ __global__ __launch_bounds__(256) void k_scan_lookback(uint32_t *count, uint32_t
                 j -= 64;
             }
             if (lane == 0)
-                __hip_atomic_store(&flags[tile], kFlagInc | (uint64_t)(prefix + tile_total), __ATOMIC_RELAXED,
+                __hip_atomic_store(&flags[tile], kFlagInc | epoch | (uint64_t)(prefix + tile_total), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
         }
         if (lane == 0) tile_prefix = prefix;
@@ -626,19 +633,18 @@ __global__ __launch_bounds__(256) void k_scan_lookback(uint32_t *count, uint32_t
             if (c0 + k < ncell) { offset[c0 + k] = rv[k]; cursor[c0 + k] = rv[k]; count[c0 + k] = 0u; }
     }
     if (c0 <= ncell - 1 && ncell - 1 <= c0 + 3) offset[ncell] = run;
-    // last workgroup out: clear the flags, advance the step
+    // last workgroup out: next epoch, advance the step
     __syncthreads();
     if (t == 0) {
-        // the flags this workgroup read were consumed before the barrier
-        const uint32_t d = atomicAdd(done, 1u);
+        const uint32_t d = atomicAdd(&done[0], 1u);
         last = d == gridDim.x - 1;
     }
     __syncthreads();
     if (last) {
-        for (int k = t; k < (int)gridDim.x; k += 256)
-            __hip_atomic_store(&flags[k], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (t == 0) {
-            *done = 0u;
+            // every workgroup read done[1] before its arrival was counted
+            done[0] = 0u;
+            done[1] = (done[1] + 1u) & kEpochMask;
             if (advance) {
                 st->step_cur = st->step_next;
                 st->step_next = st->step_next + 1;
