@@ -23,7 +23,7 @@ NSUM = 26
 MLP_NPARAM = 64 * 6 + 64 + 64 * 64 + 64 + 64 + 1  # 4673
 
 WALL_DIFFUSE, WALL_SPECULAR, WALL_PERIODIC = 0, 1, 2
-HARD_SPHERE, MAXWELL, VHS = 0, 1, 2
+HARD_SPHERE, MAXWELL, VHS, VSS = 0, 1, 2, 3
 
 
 def build(force=False):
@@ -65,6 +65,7 @@ class OrcCfg(ctypes.Structure):
         ("only_cells", ctypes.c_void_p),
         ("n_only", ctypes.c_int64),
         ("omega", ctypes.c_double),
+        ("alpha", ctypes.c_double),
     ]
 
 
@@ -110,6 +111,9 @@ def lib():
             g = getattr(_lib, "orc_scatter" + sfx)
             g.restype = None
             g.argtypes = [P, P, ctypes.c_double if sfx == "_f64" else ctypes.c_float, P]
+            g = getattr(_lib, "orc_scatter_vss" + sfx)
+            g.restype = None
+            g.argtypes = [P, P, P, ctypes.c_double]
             g = getattr(_lib, "orc_pair" + sfx)
             g.restype = None
             g.argtypes = [P, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
@@ -176,6 +180,7 @@ def make_cfg(p):
     c.key[0], c.key[1] = seed_key(p.get("seed", 0))
     c.mlp_delta = p.get("mlp_delta", 0.0)
     c.omega = float(p.get("omega", 0.5))
+    c.alpha = float(p.get("alpha", 1.0))
     return c
 
 
@@ -322,6 +327,16 @@ def scatter(ci, cj, n, dtype=np.float64):
     d = a - b
     g2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]
     getattr(lib(), "orc_scatter" + _sfx(dtype))(_ptr(a), _ptr(b), g2, _ptr(nn))
+    return a, b
+
+
+def scatter_vss(ci, cj, n, alpha, dtype=np.float64):
+    """Variable-soft-sphere collision of one pair: deflection from the
+    isotropic unit vector n, exponent alpha (1 = isotropic)."""
+    a = np.array(ci, dtype=dtype)
+    b = np.array(cj, dtype=dtype)
+    nn = np.array(n, dtype=dtype)
+    getattr(lib(), "orc_scatter_vss" + _sfx(dtype))(_ptr(a), _ptr(b), _ptr(nn), 1.0 / alpha)
     return a, b
 
 

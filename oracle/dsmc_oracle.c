@@ -109,7 +109,7 @@ static uint32_t mulhi32(uint32_t r, uint32_t n)
 
 /* ---------------------------------------------------------------- types */
 typedef struct {
-    int32_t dims, nx, ny, molecule;     /* molecule: 0 hard sphere, 1 Maxwell */
+    int32_t dims, nx, ny, molecule;     /* molecule: 0 hard sphere, 1 Maxwell, 2 VHS, 3 VSS */
     int32_t vr, majorant, n_inst, max_wall_hits;
     double Lx, Ly, dt, sigma, FN, vr_T0;
     int32_t wall_kind[4];               /* 0 diffuse, 1 specular, 2 periodic; x-,x+,y-,y+ */
@@ -123,7 +123,8 @@ typedef struct {
     const int64_t *cell_ids;            /* dims == 0: random-stream id of each instance, or NULL (= index) */
     const int64_t *only_cells;          /* if not NULL: collide and sample only these cells ... */
     int64_t n_only;                     /* ... (sorted ascending, n_only of them) */
-    double omega;                       /* molecule 2 (VHS): viscosity index in [0.5, 1] */
+    double omega;                       /* molecules 2 (VHS), 3 (VSS): viscosity index in [0.5, 1] */
+    double alpha;                       /* molecule 3 (VSS): scattering exponent in [1, 2] */
 } orc_cfg;
 
 typedef struct {
@@ -600,13 +601,67 @@ static double vhs_pow(double x, double a)
 double orc_vhs_pow(double x, double a) { return vhs_pow(x, a); }
 #endif
 
+/* ------------------------------------------------- VSS scattering */
+/* Variable soft spheres (Koura & Matsumoto 1991; Bird 1994): the relative velocity g keeps its length and is deflected by chi with
+ * cos chi = 2 B^(1/alpha) - 1, B uniform on (0, 1), about g at a uniform
+ * azimuth eps; the centre-of-mass velocity is kept.  alpha = 1 is isotropic
+ * scattering.  Both random numbers come from the collision's isotropic unit
+ * vector n (the same one hard spheres use): B = (1 + n_z) / 2 is uniform
+ * because n_z is, and (cos eps, sin eps) = (n_x, n_y) / |(n_x, n_y)|.  The
+ * deflected vector is written in the frame of g with the two unit normals
+ *   A = (h, -g_x g_y / h, -g_x g_z / h) / g  and  C = (0, g_z, -g_y) / h,
+ *   h = sqrt(g_y^2 + g_z^2):  g' = g (cos chi g/g + sin chi (sin eps A + cos eps C))
+ * (Bird's component formulas); when h = 0 the normals are the y and z axes.
+ * Everything in double, in this order; the results are rounded to REAL. */
+void FN(orc_scatter_vss)(REAL ci[3], REAL cj[3], const REAL n[3], double inv_alpha)
+{
+    double gx = (double)ci[0] - (double)cj[0];
+    double gy = (double)ci[1] - (double)cj[1];
+    double gz = (double)ci[2] - (double)cj[2];
+    double g = sqrt((gx * gx + gy * gy) + gz * gz);
+    /* deflection */
+    double B = 0.5 * (1.0 + (double)n[2]);
+    double cchi = 2.0 * vhs_pow(B, inv_alpha) - 1.0;
+    double schi2 = 1.0 - cchi * cchi;
+    double schi = schi2 > 0.0 ? sqrt(schi2) : 0.0;
+    /* azimuth */
+    double nx = (double)n[0], ny = (double)n[1];
+    double rho2 = nx * nx + ny * ny;
+    double ce = 1.0, se = 0.0;
+    if (rho2 > 0.0) {
+        double rho = sqrt(rho2);
+        ce = nx / rho;
+        se = ny / rho;
+    }
+    double h2 = gy * gy + gz * gz;
+    double px, py, pz;
+    if (h2 > 0.0) {
+        double h = sqrt(h2);
+        px = cchi * gx + (schi * se) * h;
+        py = cchi * gy + schi * (((ce * g) * gz - (se * gx) * gy) / h);
+        pz = cchi * gz - schi * (((ce * g) * gy + (se * gx) * gz) / h);
+    } else {
+        px = cchi * gx;
+        py = (schi * ce) * g;
+        pz = (schi * se) * g;
+    }
+    double pv[3] = {px, py, pz};
+    for (int d = 0; d < 3; ++d) {
+        double cm = 0.5 * ((double)ci[d] + (double)cj[d]);
+        double t = 0.5 * pv[d];
+        ci[d] = (REAL)(cm + t);
+        cj[d] = (REAL)(cm - t);
+    }
+}
+
 /* NTC collisions in one cell (Bird 1994), with the cell's particles listed in
  * canonical order (list[0..n-1]).  Candidate count
  * M = floor(1/2 N (N-1) F_N sigma g_max dt / V + U0); candidate k draws the
  * ordered pair (i, j) from block 0 of its PAIR stream and is accepted iff
  * (U g_max)^2 < g^2 (hard spheres; Maxwell molecules accept every candidate,
- * with sigma * g_max replaced by the constant sigma g = K).  Candidates are
- * processed strictly in order k = 0, 1, ... */
+ * with sigma * g_max replaced by the constant sigma g = K; variable hard and
+ * soft spheres accept with probability (g / g_max)^(2 - 2 omega)).  Candidates
+ * are processed strictly in order k = 0, 1, ... */
 static int collide_cell(const orc_cfg *cfg, soa_t *s, const int64_t *list, int64_t n,
                         uint32_t cell, uint32_t step, double V, uint64_t *cnt, orc_diag *diag,
                         int32_t *learned_flag)
@@ -634,8 +689,8 @@ static int collide_cell(const orc_cfg *cfg, soa_t *s, const int64_t *list, int64
     double Mreal;
     if (cfg->molecule == 1)
         Mreal = (((((0.5 * (double)n) * (double)(n - 1)) * cfg->FN) * cfg->sigma) * cfg->dt) / V;
-    else if (cfg->molecule == 2)
-        /* VHS: (sigma_T g)_max = sigma g_max^(2 - 2 omega) */
+    else if (cfg->molecule >= 2)
+        /* VHS and VSS: (sigma_T g)_max = sigma g_max^(2 - 2 omega) */
         Mreal = ((((((0.5 * (double)n) * (double)(n - 1)) * cfg->FN) * cfg->sigma) *
                   vhs_pow(gmax * gmax, 1.0 - cfg->omega)) * cfg->dt) / V;
     else
@@ -664,8 +719,8 @@ static int collide_cell(const orc_cfg *cfg, soa_t *s, const int64_t *list, int64
         if (cfg->molecule == 1) {
             accept = 1;
             p = 1.0;
-        } else if (cfg->molecule == 2) {
-            /* VHS: accept with probability (g / g_max)^(2 - 2 omega),
+        } else if (cfg->molecule >= 2) {
+            /* VHS, VSS: accept with probability (g / g_max)^(2 - 2 omega),
              * i.e. iff U < (g^2 / g_max^2)^(1 - omega), in double */
             double U = IS_F32 ? (double)u24(r[2]) : u53(r[2], r[3]);
             p = vhs_pow((double)g2 / (gmax * gmax), 1.0 - cfg->omega);
@@ -682,7 +737,10 @@ static int collide_cell(const orc_cfg *cfg, soa_t *s, const int64_t *list, int64
         if (accept) {
             REAL nn[3];
             FN(orc_direction)(cfg->key, (uint32_t)k, cell, step, nn);
-            FN(orc_scatter)(ci, cj, g2, nn);
+            if (cfg->molecule == 3)
+                FN(orc_scatter_vss)(ci, cj, nn, 1.0 / cfg->alpha);
+            else
+                FN(orc_scatter)(ci, cj, g2, nn);
             s->cx[pi] = ci[0]; s->cy[pi] = ci[1]; s->cz[pi] = ci[2];
             s->cx[pj] = cj[0]; s->cy[pj] = cj[1]; s->cz[pj] = cj[2];
             acc_count++;

@@ -19,7 +19,7 @@ import math
 import numpy as np
 
 WALL_DIFFUSE, WALL_SPECULAR, WALL_PERIODIC = 0, 1, 2
-HARD_SPHERE, MAXWELL, VHS = 0, 1, 2
+HARD_SPHERE, MAXWELL, VHS, VSS = 0, 1, 2, 3
 
 
 def _maxwellian(rng, n, T):

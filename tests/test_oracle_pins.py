@@ -570,3 +570,113 @@ def test_vhs_relaxes_to_the_maxwellian_and_conserves():
     assert abs(kx - 3.0) < 0.25  # started at 2.04 (bimodal)
     for d in range(3):
         assert stats.kstest(cc[d] / math.sqrt(T), "norm").pvalue > 1e-3
+
+
+# ------------------------------------------------------ VSS molecules
+def _sphere(rng, n):
+    v = rng.standard_normal((n, 3))
+    return v / np.linalg.norm(v, axis=1)[:, None]
+
+
+def _vss_batch(alpha, n, seed, degenerate=False):
+    rng = np.random.default_rng(seed)
+    ci = rng.standard_normal((n, 3)) * 1.3 + 0.2
+    cj = rng.standard_normal((n, 3)) * 0.8 - 0.1
+    if degenerate:  # relative velocity along the x axis: the second frame
+        cj[:, 1:] = ci[:, 1:]
+    nn = _sphere(rng, n)
+    out_i, out_j = np.empty_like(ci), np.empty_like(cj)
+    for k in range(n):
+        out_i[k], out_j[k] = oracle.scatter_vss(ci[k], cj[k], nn[k], alpha)
+    return ci, cj, out_i, out_j
+
+
+@pytest.mark.parametrize("degenerate", [False, True])
+def test_vss_collision_conserves_momentum_and_energy(degenerate):
+    for alpha in (1.0, 1.4, 2.0):
+        ci, cj, ai, aj = _vss_batch(alpha, 400, 31, degenerate)
+        assert np.abs((ai + aj) - (ci + cj)).max() < 1e-14
+        g, gp = ci - cj, ai - aj
+        e0 = (ci ** 2).sum(1) + (cj ** 2).sum(1)
+        e1 = (ai ** 2).sum(1) + (aj ** 2).sum(1)
+        assert np.abs(e1 / e0 - 1).max() < 1e-14
+        # |g'| = |g| up to the rounding of the velocities themselves
+        scale = np.linalg.norm(ci, axis=1) + np.linalg.norm(cj, axis=1)
+        assert (np.abs(np.linalg.norm(gp, axis=1) - np.linalg.norm(g, axis=1)) / scale).max() < 1e-14
+
+
+@pytest.mark.parametrize("alpha", [1.0, 1.4, 2.0])
+def test_vss_deflection_law(alpha):
+    # cos chi = 2 B^(1/alpha) - 1 with B uniform: ((1 + cos chi)/2)^alpha is
+    # uniform; E[cos chi] = (alpha - 1)/(alpha + 1) and the viscosity factor
+    # E[sin^2 chi] = 4 alpha / ((alpha + 1)(alpha + 2)); the azimuth about g,
+    # measured in a frame that is not the one used to build g', is uniform
+    n = 20000
+    ci, cj, ai, aj = _vss_batch(alpha, n, 41)
+    g, gp = ci - cj, ai - aj
+    gn = g / np.linalg.norm(g, axis=1)[:, None]
+    cchi = (gp * gn).sum(1) / np.linalg.norm(gp, axis=1)
+    assert stats.kstest(((1 + cchi) / 2) ** alpha, "uniform").pvalue > 1e-3
+    m1 = (alpha - 1) / (alpha + 1)
+    assert abs(cchi.mean() - m1) < 5 * cchi.std() / math.sqrt(n)
+    s2 = 1 - cchi ** 2
+    assert abs(s2.mean() - 4 * alpha / ((alpha + 1) * (alpha + 2))) < 5 * s2.std() / math.sqrt(n)
+    perp = gp - (gp * gn).sum(1)[:, None] * gn
+    e1 = np.cross(gn, np.array([0.3, -0.5, 0.81]))
+    e1 /= np.linalg.norm(e1, axis=1)[:, None]
+    e2 = np.cross(gn, e1)
+    phi = np.arctan2((perp * e2).sum(1), (perp * e1).sum(1))
+    assert stats.kstest(phi, "uniform", args=(-math.pi, 2 * math.pi)).pvalue > 1e-3
+
+
+def test_vss_maxwell_group_momentum_decay_closed_form():
+    # Maxwell molecules (omega = 1: every candidate accepted) with VSS
+    # scattering.  One collision moves each partner's velocity by (g' - g)/2,
+    # whose mean over the scattering law is -(1 - E[cos chi]) g / 2 =
+    # -g / (alpha + 1).  For a uniform ordered pair of an N-particle cell, the
+    # momentum of a marked half, taken relative to its share of the total,
+    # D = S_+ - (N_+ / N) S, therefore shrinks in expectation by the factor
+    # r = 1 - 2 / ((alpha + 1)(N - 1)) per candidate: E[D_end] = D_0 r^M for
+    # M candidates, whatever the velocity distribution.
+    N, n_inst, alpha, steps = 100, 400, 2.0, 10
+    dt = 15.0 / (0.5 * N * (N - 1))  # about 15 candidates per step
+    rng = np.random.default_rng(17)
+    c = rng.standard_normal((3, N * n_inst))
+    c[0] += np.where((np.arange(N * n_inst) % N) < N // 2, 1.5, -1.5)
+    off = np.arange(n_inst + 1, dtype=np.int64) * N
+    p = dict(dims=0, n_cells=(n_inst, 1), dt=dt, sigma=1.0, FN=1.0, molecule=W.VSS, omega=1.0,
+             alpha=alpha, seed=8, inst_offset=off, cell_volume=np.ones(n_inst))
+    o = oracle.Oracle(p, dict(cx=c[0].copy(), cy=c[1].copy(), cz=c[2].copy()))
+    o.run(steps)
+    assert (o.counters[:, 0] == o.counters[:, 1]).all()
+    M = o.counters[:, 0].astype(float)
+
+    def D(cx):
+        v = cx.reshape(n_inst, N)
+        return v[:, : N // 2].sum(1) - 0.5 * v.sum(1)
+
+    d0, d1 = D(c[0]), D(o.cx)
+    def ratio(a):
+        return d1 / (d0 * (1 - 2 / ((a + 1) * (N - 1))) ** M)
+    q = ratio(alpha)
+    se = q.std() / math.sqrt(n_inst)
+    assert abs(q.mean() - 1) < 5 * se
+    # isotropic scattering (alpha = 1) would predict a faster decay
+    assert abs(ratio(1.0).mean() - 1) > 10 * se
+
+
+def test_vss_run_conserves_and_keeps_vhs_collision_counts_on_first_step():
+    # the scattering law does not enter the majorant or the acceptance: the
+    # first step's candidate counts equal the VHS run's, and the collisions
+    # conserve momentum and energy
+    p, parts = W.relaxation(N=3000, steps=1)
+    a = oracle.Oracle(dict(p, molecule=W.VHS, omega=0.81), parts)
+    b = oracle.Oracle(dict(p, molecule=W.VSS, omega=0.81, alpha=1.6), parts)
+    c0 = np.stack([b.cx, b.cy, b.cz])
+    a.run(1)
+    b.run(1)
+    assert np.array_equal(a.counters[:, 0], b.counters[:, 0])
+    c = np.stack([b.cx, b.cy, b.cz])
+    assert np.abs(c.sum(1) - c0.sum(1)).max() < 1e-10
+    assert abs((c ** 2).sum() / (c0 ** 2).sum() - 1) < 1e-13
+    assert not np.array_equal(c, np.stack([a.cx, a.cy, a.cz]))
