@@ -270,10 +270,16 @@ def main():
         p6 = dict(p3, molecule=W.VHS, omega=0.81)
         sec.append(run_workload("batched 4096 cells, variable hard spheres (omega 0.81), exact majorant, FP32",
                                 dict(p6, **best3), parts3, 200, 20, torch))
+        p6s = dict(p3, molecule=W.VSS, omega=0.81, alpha=1.4)
+        sec.append(run_workload("batched 4096 cells, variable soft spheres (omega 0.81, alpha 1.4), exact majorant, "
+                                "FP32", dict(p6s, **best3), parts3, 200, 20, torch))
         p7, parts7 = W.cavity(Kn=args.kn, real="f32")
         p7 = dict(p7, molecule=W.VHS, omega=0.74)
         sec.append(run_workload("cavity 256x256 x 100, variable hard spheres (omega 0.74), VR, FP32", p7, parts7,
                                 100, 10, torch))
+        p7s = dict(p7, molecule=W.VSS, alpha=1.4)
+        sec.append(run_workload("cavity 256x256 x 100, variable soft spheres (omega 0.74, alpha 1.4), VR, FP32",
+                                p7s, parts7, 100, 10, torch))
         # the rest of the cavity's Knudsen sweep
         for kn in (0.1, 1.0):
             if kn == args.kn:

@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define DSMC_ABI_VERSION 3
+#define DSMC_ABI_VERSION 4
 #define DSMC_NSUM 26          /* FP64 running sums per cell (see dsmc_sample) */
 #define DSMC_MLP_NPARAM 4673  /* learned-majorant network 6-64-64-1 */
 
@@ -60,8 +60,13 @@ enum { DSMC_WALL_DIFFUSE = 0, DSMC_WALL_SPECULAR = 1, DSMC_WALL_PERIODIC = 2 };
 /* Molecular models: hard spheres (sigma_T constant), Maxwell molecules
  * (sigma_T g constant), variable hard spheres (sigma_T = sigma g^(1 - 2 omega),
  * omega in [0.5, 1]; acceptance (g / g_max)^(2 - 2 omega) evaluated by a fixed
- * sequence of double operations, isotropic scattering). */
-enum { DSMC_HARD_SPHERE = 0, DSMC_MAXWELL = 1, DSMC_VHS = 2 };
+ * sequence of double operations, isotropic scattering) and variable soft
+ * spheres (Koura & Matsumoto 1991: the VHS cross-section and acceptance, and
+ * a deflection chi about the relative velocity with cos chi = 2 B^(1/alpha) - 1,
+ * B uniform, alpha in [1, 2]; B and the azimuth are taken from the pair's
+ * isotropic unit vector n as B = (1 + n_z)/2 and the direction of (n_x, n_y),
+ * the turn computed in double in a fixed order). */
+enum { DSMC_HARD_SPHERE = 0, DSMC_MAXWELL = 1, DSMC_VHS = 2, DSMC_VSS = 3 };
 /* Majorant of the relative speed used by the NTC scheme in each cell:
  *   EXACT    (r_(1) + r_(2)) (1 + eps): radii about the velocity bounding-box
  *            midpoint; a bound on every pair, O(N) per cell;
@@ -79,7 +84,8 @@ typedef struct {
     int32_t abi_version;      /* must equal DSMC_ABI_VERSION */
     int32_t dims;             /* 0, 1 or 2 */
     int32_t real_bytes;       /* 4: FP32 positions/velocities/weights, 8: FP64 */
-    int32_t molecule;         /* DSMC_HARD_SPHERE, DSMC_MAXWELL (sigma * g = const) or DSMC_VHS */
+    int32_t molecule;         /* DSMC_HARD_SPHERE, DSMC_MAXWELL (sigma * g = const), DSMC_VHS or
+                                 DSMC_VSS */
     int32_t n_cells[2];       /* (nx, ny); dims 1: ny ignored; dims 0: (n_instances, 1) */
     int32_t majorant;         /* DSMC_MAJORANT_EXACT, _LEARNED or _DIAMETER */
     int32_t vr;               /* 1: importance-weight variance reduction */
@@ -104,8 +110,9 @@ typedef struct {
     int64_t chunk_work;       /* persistent kernel: up to 64 consecutive instances of the
                                  schedule form one work unit while they hold fewer than this
                                  many particles (0 -> one instance per unit) */
-    double omega;             /* DSMC_VHS: viscosity index in [0.5, 1]; sigma is the total
-                                 cross-section at unit relative speed */
+    double omega;             /* DSMC_VHS, DSMC_VSS: viscosity index in [0.5, 1]; sigma is the
+                                 total cross-section at unit relative speed */
+    double alpha;             /* DSMC_VSS: scattering exponent in [1, 2] (1: isotropic) */
 } dsmc_config;
 
 /* How homogeneous instances are distributed over the GPU.  Both process the

@@ -55,9 +55,12 @@ dsmc_status validate(const dsmc_config *c) {
     if (c->abi_version != DSMC_ABI_VERSION) return DSMC_EABI;
     if (c->dims < 0 || c->dims > 2) return DSMC_EINVAL;
     if (c->real_bytes != 4 && c->real_bytes != 8) return DSMC_EINVAL;
-    if (c->molecule != DSMC_HARD_SPHERE && c->molecule != DSMC_MAXWELL && c->molecule != DSMC_VHS)
+    if (c->molecule != DSMC_HARD_SPHERE && c->molecule != DSMC_MAXWELL && c->molecule != DSMC_VHS &&
+        c->molecule != DSMC_VSS)
         return DSMC_EINVAL;
-    if (c->molecule == DSMC_VHS && !(c->omega >= 0.5 && c->omega <= 1.0)) return DSMC_EINVAL;
+    if ((c->molecule == DSMC_VHS || c->molecule == DSMC_VSS) && !(c->omega >= 0.5 && c->omega <= 1.0))
+        return DSMC_EINVAL;
+    if (c->molecule == DSMC_VSS && !(c->alpha >= 1.0 && c->alpha <= 2.0)) return DSMC_EINVAL;
     if (c->majorant < DSMC_MAJORANT_EXACT || c->majorant > DSMC_MAJORANT_DIAMETER) return DSMC_EINVAL;
     if (c->n_cells[0] < 1 || (c->dims == 2 && c->n_cells[1] < 1)) return DSMC_EINVAL;
     if (n_cells_of(*c) > (int64_t)1 << 30) return DSMC_EINVAL;
@@ -234,6 +237,7 @@ CollideArgs<R> collide_args(dsmc_ctx *c, int src, int dst) {
     a.FN = c->cfg.FN;
     a.molecule = c->cfg.molecule;
     a.omega1 = 1.0 - c->cfg.omega;
+    a.inv_alpha = c->cfg.molecule == DSMC_VSS ? 1.0 / c->cfg.alpha : 1.0;
     a.cap = c->cap;
     a.majorant = c->cfg.majorant;
     a.k0 = (uint32_t)(c->cfg.seed & 0xFFFFFFFFull);

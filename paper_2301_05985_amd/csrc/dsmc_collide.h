@@ -7,8 +7,10 @@
 // candidates; candidate k draws an ordered pair of distinct canonical ranks
 // (i, j) and is accepted with probability g_ij / g_max (hard spheres; Maxwell
 // molecules accept every candidate and use sigma*g = const in place of
-// sigma*g_max).  An accepted pair scatters isotropically about its centre of
-// mass.  Candidates are sequential by definition -- candidate k sees the
+// sigma*g_max; variable hard and soft spheres accept with probability
+// (g / g_max)^(2 - 2 omega)).  An accepted pair scatters isotropically about
+// its centre of mass (variable soft spheres: by the deflection law of the
+// exponent alpha).  Candidates are sequential by definition -- candidate k sees the
 // velocities left by candidates 0..k-1.
 //
 // Wave mapping: 64 consecutive candidates are drawn at once, one per lane
@@ -40,7 +42,8 @@ struct CollideArgs {
     Regroup rg;
     const double *volume;          // per-cell volume, or null for Vuni
     double Vuni, dt, sigma, FN;
-    double omega1;                 // VHS: 1 - omega
+    double omega1;                 // VHS, VSS: 1 - omega
+    double inv_alpha;              // VSS: 1 / alpha
     int molecule, cap, majorant;
     uint32_t k0, k1;
     double *sums;                  // [ncell][26] running FP64 sums
@@ -355,6 +358,54 @@ __device__ __forceinline__ void direction(bool pending, uint32_t first, uint32_t
     }
 }
 
+// Variable-soft-sphere collision of the pair (a, b) (Koura & Matsumoto 1991):
+// the relative velocity g = a - b keeps its length and turns by the angle chi
+// with cos chi = 2 B^(1/alpha) - 1 about g, at azimuth eps; the mean velocity
+// is kept.  B and eps come from the pair's isotropic unit vector n:
+// B = (1 + n_z) / 2, (cos eps, sin eps) = (n_x, n_y) / |(n_x, n_y)|.  The turn
+// is taken in the frame of g spanned by the unit normals
+// (h, -g_x g_y / h, -g_x g_z / h) / |g| and (0, g_z, -g_y) / h,
+// h = |(g_y, g_z)| (Bird's component form), or the y and z axes when h = 0.
+// Double throughout, in a fixed order; the new velocities are rounded to R.
+template <typename R>
+__device__ __forceinline__ void vss_pair(R ax, R ay, R az, R bx, R by, R bz, R nx, R ny, R nz, double inv_alpha,
+                                         R &oax, R &oay, R &oaz, R &obx, R &oby, R &obz) {
+    const double gx = (double)ax - (double)bx, gy = (double)ay - (double)by, gz = (double)az - (double)bz;
+    const double g = sqrt((gx * gx + gy * gy) + gz * gz);
+    const double cchi = 2.0 * vhs_pow(0.5 * (1.0 + (double)nz), inv_alpha) - 1.0;
+    const double s2 = 1.0 - cchi * cchi;
+    const double schi = s2 > 0.0 ? sqrt(s2) : 0.0;
+    const double ex = (double)nx, ey = (double)ny;
+    const double rho2 = ex * ex + ey * ey;
+    double ce = 1.0, se = 0.0;
+    if (rho2 > 0.0) {
+        const double rho = sqrt(rho2);
+        ce = ex / rho;
+        se = ey / rho;
+    }
+    const double h2 = gy * gy + gz * gz;
+    double px, py, pz;
+    if (h2 > 0.0) {
+        const double h = sqrt(h2);
+        px = cchi * gx + (schi * se) * h;
+        py = cchi * gy + schi * (((ce * g) * gz - (se * gx) * gy) / h);
+        pz = cchi * gz - schi * (((ce * g) * gy + (se * gx) * gz) / h);
+    } else {
+        px = cchi * gx;
+        py = (schi * ce) * g;
+        pz = (schi * se) * g;
+    }
+    const double mx = 0.5 * ((double)ax + (double)bx), my = 0.5 * ((double)ay + (double)by),
+                 mz = 0.5 * ((double)az + (double)bz);
+    const double tx = 0.5 * px, ty = 0.5 * py, tz = 0.5 * pz;
+    oax = (R)(mx + tx);
+    oay = (R)(my + ty);
+    oaz = (R)(mz + tz);
+    obx = (R)(mx - tx);
+    oby = (R)(my - ty);
+    obz = (R)(mz - tz);
+}
+
 // Random draws of the fresh candidates (lanes with `fresh` set): the pair
 // (i, j) and acceptance number U from block 0 of the candidate's PAIR
 // stream, the scattering direction from blocks 1, 2, ...
@@ -452,7 +503,8 @@ __device__ __forceinline__ void draw_candidates(bool fresh, uint32_t k, uint32_t
 template <typename R, typename View, int T>
 __device__ __forceinline__ uint32_t velocity_window(const View &v, bool live, uint32_t k, uint32_t kb, uint32_t wend,
                                                     uint32_t i, uint32_t j, R U, R nx, R ny, R nz, R gm, R gm2,
-                                                    double gmax2, double om1, int molecule, bool &commit,
+                                                    double gmax2, double om1, double inv_alpha, int molecule,
+                                                    bool &commit,
                                                     bool &accept, R &g2_out, double &pacc, uint32_t &acc,
                                                     uint32_t &over, GroupScratch *gs) {
     R ax = 0, ay = 0, az = 0, bx = 0, by = 0, bz = 0, g2 = 0;
@@ -465,7 +517,7 @@ __device__ __forceinline__ uint32_t velocity_window(const View &v, bool live, ui
         g2 = (dx * dx + dy * dy) + dz * dz;
         if (molecule == DSMC_MAXWELL) {
             accept = true;
-        } else if (molecule == DSMC_VHS) {
+        } else if (molecule == DSMC_VHS || molecule == DSMC_VSS) {
             // accept with probability (g / g_max)^(2 - 2 omega), in double
             pacc = vhs_pow((double)g2 / gmax2, om1);
             accept = (double)U < pacc;
@@ -494,12 +546,19 @@ __device__ __forceinline__ uint32_t velocity_window(const View &v, bool live, ui
     }
     const bool coll = commit && accept;
     if (coll) {
-        const R g = sqrt(g2);
-        const R hg = (R)0.5 * g;
-        const R mx = (R)0.5 * (ax + bx), my = (R)0.5 * (ay + by), mz = (R)0.5 * (az + bz);
-        const R tx = hg * nx, ty = hg * ny, tz = hg * nz;
-        v.put(i, mx + tx, my + ty, mz + tz);
-        v.put(j, mx - tx, my - ty, mz - tz);
+        if (molecule == DSMC_VSS) {
+            R oax, oay, oaz, obx, oby, obz;
+            vss_pair<R>(ax, ay, az, bx, by, bz, nx, ny, nz, inv_alpha, oax, oay, oaz, obx, oby, obz);
+            v.put(i, oax, oay, oaz);
+            v.put(j, obx, oby, obz);
+        } else {
+            const R g = sqrt(g2);
+            const R hg = (R)0.5 * g;
+            const R mx = (R)0.5 * (ax + bx), my = (R)0.5 * (ay + by), mz = (R)0.5 * (az + bz);
+            const R tx = hg * nx, ty = hg * ny, tz = hg * nz;
+            v.put(i, mx + tx, my + ty, mz + tz);
+            v.put(j, mx - tx, my - ty, mz - tz);
+        }
     }
     if (molecule != DSMC_MAXWELL && commit && g2 > gm2) over++;
     acc += (uint32_t)__popcll(__ballot(coll));
@@ -510,7 +569,8 @@ __device__ __forceinline__ uint32_t velocity_window(const View &v, bool live, ui
 
 template <typename R, bool VR, typename View, int T = 64>
 __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uint32_t cell,
-                         uint32_t step, uint32_t k0, uint32_t k1, int molecule, double om1, uint32_t &n_acc,
+                         uint32_t step, uint32_t k0, uint32_t k1, int molecule, double om1, double inv_alpha,
+                         uint32_t &n_acc,
                          uint32_t &n_over, GroupScratch *gs = nullptr) {
     constexpr uint32_t W = (uint32_t)T;  // candidates per window (one per thread)
     const R gm = (R)gmax;
@@ -547,8 +607,8 @@ __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uin
         R g2;
         double pacc;
         const uint32_t kend = velocity_window<R, View, T>(v, act && !done, k, kb, wend, i, j, U, nx, ny, nz, gm, gm2,
-                                                          gmax2, om1, molecule, commit, accept, g2, pacc, acc, over,
-                                                          gs);
+                                                          gmax2, om1, inv_alpha, molecule, commit, accept, g2, pacc,
+                                                          acc, over, gs);
         kb = kend;
         if (!VR) {
             // committed threads move on to the candidate W later
@@ -562,7 +622,7 @@ __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uin
             done = true;
             acc_k = accept;
             p = (!accept && molecule != DSMC_MAXWELL)
-                    ? (molecule == DSMC_VHS ? pacc : sqrt((double)g2) / gmax)
+                    ? ((molecule == DSMC_VHS || molecule == DSMC_VSS) ? pacc : sqrt((double)g2) / gmax)
                     : 1.0;
         }
         if (kb < gend) continue;
@@ -787,11 +847,11 @@ __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cel
 // Real-valued NTC candidate count 1/2 N (N-1) F_N (sigma g)_max dt / V, in
 // this left-to-right order: (sigma g)_max = sigma g_max (hard spheres),
 // sigma (Maxwell molecules, sigma g constant) or sigma g_max^(2 - 2 omega)
-// (variable hard spheres).
+// (variable hard and soft spheres).
 template <typename R>
 __device__ __forceinline__ double candidates_real(const CollideArgs<R> &a, double Nd, double gmax, double V) {
     if (a.molecule == DSMC_MAXWELL) return (((((0.5 * Nd) * (Nd - 1.0)) * a.FN) * a.sigma) * a.dt) / V;
-    if (a.molecule == DSMC_VHS)
+    if (a.molecule == DSMC_VHS || a.molecule == DSMC_VSS)
         return ((((((0.5 * Nd) * (Nd - 1.0)) * a.FN) * a.sigma) * vhs_pow(gmax * gmax, a.omega1)) * a.dt) / V;
     return ((((((0.5 * Nd) * (Nd - 1.0)) * a.FN) * a.sigma) * gmax) * a.dt) / V;
 }
@@ -820,7 +880,8 @@ __device__ void process_cell(const CollideArgs<R> &a, const View &v, uint32_t ce
             Mf = 0.0;
         }
         M = (uint32_t)Mf;
-        ntc_loop<R, VR, View, T>(v, N, gmax, M, cell, step, a.k0, a.k1, a.molecule, a.omega1, acc, over, gs);
+        ntc_loop<R, VR, View, T>(v, N, gmax, M, cell, step, a.k0, a.k1, a.molecule, a.omega1, a.inv_alpha, acc,
+                                 over, gs);
     }
     sample_cell<R, VR, View, T>(a, v, cell, N, M, acc, over, pf, red, wb_base, gs);
 }

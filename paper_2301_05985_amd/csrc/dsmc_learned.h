@@ -190,7 +190,8 @@ __device__ void process_cell_learned(const CollideArgs<R> &a, const View &v, uin
             Mf = 0.0;
         }
         M = (uint32_t)Mf;
-        ntc_loop<R, VR, View, T>(v, N, gmax, M, cell, step, a.k0, a.k1, a.molecule, a.omega1, acc, over, gs);
+        ntc_loop<R, VR, View, T>(v, N, gmax, M, cell, step, a.k0, a.k1, a.molecule, a.omega1, a.inv_alpha, acc,
+                                 over, gs);
     }
     sample_cell<R, VR, View, T>(a, v, cell, N, M, acc, over, pf, red, wb_base, gs);
 }

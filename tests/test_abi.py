@@ -91,6 +91,14 @@ def test_vhs_needs_a_viscosity_index_in_range(lib):
         assert _ws(lib, cfg)[0] == code, omega
 
 
+def test_vss_needs_omega_and_alpha_in_range(lib):
+    p, parts = W.cavity(nx=4, ny=4, per_cell=5)
+    for omega, alpha, code in ((0.81, 1.6, 0), (0.5, 1.0, 0), (1.0, 2.0, 0), (0.3, 1.5, -1),
+                               (0.81, 0.9, -1), (0.81, 2.5, -1), (0.81, float("nan"), -1)):
+        cfg = binding.make_config(dict(p, molecule=W.VSS, omega=omega, alpha=alpha), len(parts["cx"]))
+        assert _ws(lib, cfg)[0] == code, (omega, alpha)
+
+
 def test_autotune_signature_separates_workloads():
     # the cache key changes with everything that changes the collision cost
     from paper_2301_05985_amd import autotune

@@ -109,13 +109,17 @@ def _synthetic_net(seed, center):
     return M.from_bf16(M.to_bf16(p.astype(np.float32)))
 
 
-@pytest.mark.parametrize("real,sizes", [("f32", (48, 30, 600)), ("f64", (48, 30, 600)), ("f32", (12, 900, 1600))])
-def test_learned_collisions_bit_exact_against_oracle(gpu, real, sizes):
-    # the last case has instances above 1024 particles (workgroup cells)
-    _announce("learned collide %s %s" % (real, sizes))
+@pytest.mark.parametrize("real,sizes,mol", [("f32", (48, 30, 600), "hs"), ("f64", (48, 30, 600), "hs"),
+                                            ("f32", (12, 900, 1600), "hs"), ("f32", (48, 30, 600), "vss")])
+def test_learned_collisions_bit_exact_against_oracle(gpu, real, sizes, mol):
+    # the third case has instances above 1024 particles (workgroup cells);
+    # the last one runs variable soft spheres
+    _announce("learned collide %s %s %s" % (real, sizes, mol))
     from paper_2301_05985_amd.binding import Simulation
     n_inst, nmin, nmax = sizes
     p, parts = W.batched(n_inst=n_inst, nmin=nmin, nmax=nmax, real=real, steps=6, dt=0.2)
+    if mol == "vss":
+        p = dict(p, molecule=W.VSS, omega=0.81, alpha=1.5)
     dtype = np.float32 if real == "f32" else np.float64
     off = p["inst_offset"]
     c = [np.asarray(parts[k], dtype=dtype) for k in ("cx", "cy", "cz")]

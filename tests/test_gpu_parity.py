@@ -287,6 +287,33 @@ def test_vhs_walled(gpu, case):
     _compare(g, orc, exact=exact, rtol=1e-12)
 
 
+@pytest.mark.parametrize("real", ["f64", "f32"])
+def test_vss_homogeneous_bit_exact(gpu, real):
+    # variable soft spheres (omega 0.81, alpha 1.6): VHS acceptance, and the
+    # deflection computed in double from the pair's unit vector; one-wave and
+    # four-wave cells, with importance weights
+    _announce("vss homogeneous %s" % real)
+    p, parts = _homog([2, 40, 300, 900, 64, 65, 1100, 1500], dt=0.2)
+    p = dict(p, molecule=W.VSS, omega=0.81, alpha=1.6, vr=1, vr_T0=1.0)
+    rng = np.random.default_rng(23)
+    parts = dict(parts, w=1.0 + 0.05 * rng.standard_normal(len(parts["cx"])))
+    g, orc = _run(gpu, p, parts, 10, real, chunks=2)
+    assert orc.counters[:, 1].sum() > 200
+    _compare(g, orc, exact=True)
+
+
+@pytest.mark.parametrize("real", ["f64", "f32"])
+def test_vss_walled_bit_exact(gpu, real):
+    # periodic-specular cavity with weights, particles moving between cells
+    _announce("vss walled %s" % real)
+    p, parts = W.cavity(nx=12, ny=10, per_cell=25, Kn=0.01, real=real, dt=0.01)
+    p["wall_kind"] = (W.WALL_PERIODIC, W.WALL_PERIODIC, W.WALL_SPECULAR, W.WALL_SPECULAR)
+    p = dict(p, molecule=W.VSS, omega=0.74, alpha=1.4)
+    g, orc = _run(gpu, p, parts, 10, real, chunks=2)
+    assert orc.counters[:, 1].sum() > 100
+    _compare(g, orc, exact=True)
+
+
 def test_relaxation_full_size_f64(gpu):
     # relaxation workload at its full size: 10,000 particles in one cell,
     # FP64, 200 steps, bit-exact against the oracle
