@@ -190,7 +190,8 @@ __device__ __forceinline__ double wave_max_nonneg(double v) {
 }
 
 template <typename R, typename View, int T = 64>
-__device__ double exact_bound(const View &v, uint32_t N, double &r_top, GroupScratch *gs = nullptr) {
+__device__ double exact_bound(const View &v, uint32_t N, double &r_top, GroupScratch *gs = nullptr,
+                              double *mid = nullptr) {
     const uint32_t tid = threadIdx.x;
     double m0, m1, m2;
     if constexpr (sizeof(R) == 4) {
@@ -242,6 +243,11 @@ __device__ double exact_bound(const View &v, uint32_t N, double &r_top, GroupScr
         m0 = 0.5 * ((double)hi0 + (double)lo0);
         m1 = 0.5 * ((double)hi1 + (double)lo1);
         m2 = 0.5 * ((double)hi2 + (double)lo2);
+    }
+    if (mid) {
+        mid[0] = m0;
+        mid[1] = m1;
+        mid[2] = m2;
     }
     double a1 = 0.0, a2 = 0.0;  // largest, second largest r^2 of this lane
     for (uint32_t r = tid; r < N; r += T) {

@@ -29,33 +29,51 @@ struct Features { float f[kMlpIn]; };
 // Features of the cell held by the view: FP64 moments, rounded once to float.
 //   log2(number density), u_x / sqrt(T), u_y / sqrt(T), log2(T),
 //   P_xx / p - 1, P_xy / p
-template <typename R, typename View>
-__device__ Features cell_features(const View &v, uint32_t N, double FNum, double V) {
-    const int lane = lane_id();
-    double s0 = 0, s1 = 0, s2 = 0, sxx = 0, syy = 0, szz = 0, sxy = 0;
-    for (uint32_t r = lane; r < N; r += 64) {
+// The T threads of the cell each sum their particles; the seven sums are
+// reduced over the wave by recursive halving and over the waves of a
+// workgroup in a fixed order.
+template <typename R, typename View, int T = 64>
+__device__ Features cell_features(const View &v, uint32_t N, double FNum, double V, GroupScratch *gs = nullptr) {
+    double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // sx, sy, sz, sxx, syy, szz, sxy, (pad)
+    for (uint32_t r = threadIdx.x; r < N; r += T) {
         R a, b, c;
         v.get(r, a, b, c);
         const double vx = (double)a, vy = (double)b, vz = (double)c;
-        s0 += vx; s1 += vy; s2 += vz;
-        sxx += vx * vx; syy += vy * vy; szz += vz * vz; sxy += vx * vy;
+        q[0] += vx; q[1] += vy; q[2] += vz;
+        q[3] += vx * vx; q[4] += vy * vy; q[5] += vz * vz; q[6] += vx * vy;
     }
-    s0 = wave_sum(s0); s1 = wave_sum(s1); s2 = wave_sum(s2);
-    sxx = wave_sum(sxx); syy = wave_sum(syy); szz = wave_sum(szz); sxy = wave_sum(sxy);
+    const double t = wave_sum_many<8>(q);  // lane L: total of sum L >> 3
+    double S[7];
+#pragma unroll
+    for (int k = 0; k < 7; ++k) S[k] = __shfl(t, 8 * k, 64);
+    if constexpr (T > 64) {
+        if (lane_id() == 0) {
+#pragma unroll
+            for (int k = 0; k < 7; ++k) gs->d[threadIdx.x >> 6][8 + k] = S[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            S[k] = gs->d[0][8 + k];
+#pragma unroll
+            for (int w = 1; w < T / 64; ++w) S[k] += gs->d[w][8 + k];
+        }
+        __syncthreads();  // the scratch is reused
+    }
     const double Nd = (double)N;
-    const double ux = s0 / Nd, uy = s1 / Nd, uz = s2 / Nd;
-    double T = (((sxx + syy) + szz) / Nd - ((ux * ux + uy * uy) + uz * uz)) / 3.0;
-    if (!(T > 1e-300)) T = 1e-300;
+    const double ux = S[0] / Nd, uy = S[1] / Nd, uz = S[2] / Nd;
+    double Tk = (((S[3] + S[4]) + S[5]) / Nd - ((ux * ux + uy * uy) + uz * uz)) / 3.0;
+    if (!(Tk > 1e-300)) Tk = 1e-300;
     const double dens = (Nd * FNum) / V;
-    const double Pxx = dens * (sxx / Nd - ux * ux);
-    const double Pxy = dens * (sxy / Nd - ux * uy);
-    const double pr = dens * T;
-    const double sT = sqrt(T);
+    const double Pxx = dens * (S[3] / Nd - ux * ux);
+    const double Pxy = dens * (S[6] / Nd - ux * uy);
+    const double pr = dens * Tk;
+    const double sT = sqrt(Tk);
     Features F;
     F.f[0] = (float)log2(dens);
     F.f[1] = (float)(ux / sT);
     F.f[2] = (float)(uy / sT);
-    F.f[3] = (float)log2(T);
+    F.f[3] = (float)log2(Tk);
     F.f[4] = (float)(Pxx / pr - 1.0);
     F.f[5] = (float)(Pxy / pr);
     return F;
@@ -81,67 +99,81 @@ __device__ __forceinline__ float mlp_forward_wave(const float *P, const Features
 }
 
 // Verified learned majorant; returns the majorant and sets used to
-// 1 (learned), 0 (proposal not below the exact bound), -1 (fallback).
-template <typename R, typename View>
-__device__ double learned_majorant(const CollideArgs<R> &a, const View &v, uint32_t cell, uint32_t N,
-                                   double V, int &used) {
+// 1 (learned), 0 (proposal not below the exact bound), -1 (fallback).  Run by
+// all T threads of the cell (every wave evaluates the network; the results
+// are identical); the particle passes are spread over the threads.  Only the
+// size of S and whether some pair of S exceeds the proposal decide, so the
+// order in which members are found does not matter.
+template <typename R, typename View, int T = 64>
+__device__ double learned_majorant(const CollideArgs<R> &a, const View &v, uint32_t N, double V, int &used,
+                                   GroupScratch *gs = nullptr) {
     const int lane = lane_id();
-    double r1;
-    const double gb = exact_bound<R>(v, N, r1);
-    const Features F = cell_features<R>(v, N, a.FN, V);
+    double r1, mid[3];
+    const double gb = exact_bound<R, View, T>(v, N, r1, gs, mid);
+    const Features F = cell_features<R, View, T>(v, N, a.FN, V, gs);
     const float y = mlp_forward_wave(a.mlp, F);
     double kk = ceil(64.0 * ((double)y + a.delta));
     if (!(kk > -(double)kLatticeHalf)) kk = -(double)kLatticeHalf;
     if (kk > (double)kLatticeHalf) kk = (double)kLatticeHalf;
     const double gp = a.lattice[(int)kk + kLatticeHalf];
     if (!(gp < gb)) { used = 0; return gb; }
-    // bounding-box midpoint (same reductions as the exact bound)
-    double lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY, hi0 = -INFINITY, hi1 = -INFINITY, hi2 = -INFINITY;
-    for (uint32_t r = lane; r < N; r += 64) {
+    const double m0 = mid[0], m1 = mid[1], m2 = mid[2];
+    const auto in_s = [&](uint32_t r) {
         R x, yv, z;
         v.get(r, x, yv, z);
-        lo0 = fmin(lo0, (double)x); hi0 = fmax(hi0, (double)x);
-        lo1 = fmin(lo1, (double)yv); hi1 = fmax(hi1, (double)yv);
-        lo2 = fmin(lo2, (double)z); hi2 = fmax(hi2, (double)z);
-    }
-    lo0 = wave_min(lo0); lo1 = wave_min(lo1); lo2 = wave_min(lo2);
-    hi0 = wave_max(hi0); hi1 = wave_max(hi1); hi2 = wave_max(hi2);
-    const double m0 = 0.5 * (hi0 + lo0), m1 = 0.5 * (hi1 + lo1), m2 = 0.5 * (hi2 + lo2);
-    // collect S (at most 64 members, one per lane)
-    uint32_t mine = 0xFFFFFFFFu;
+        const double dx = (double)x - m0, dy = (double)yv - m1, dz = (double)z - m2;
+        return sqrt((dx * dx + dy * dy) + dz * dz) + r1 > gp;
+    };
+    uint32_t mine = 0xFFFFFFFFu;  // rank of the member held by this lane
     uint32_t ns = 0;
     bool overflow = false;
-    for (uint32_t r0 = 0; r0 < N && !overflow; r0 += 64) {
-        const uint32_t r = r0 + (uint32_t)lane;
-        bool in = false;
-        if (r < N) {
-            R x, yv, z;
-            v.get(r, x, yv, z);
-            const double dx = (double)x - m0, dy = (double)yv - m1, dz = (double)z - m2;
-            in = sqrt((dx * dx + dy * dy) + dz * dz) + r1 > gp;
+    if constexpr (T > 64) {
+        // members listed in LDS in the order they are found (slot from an
+        // LDS counter); the list overlays the double scratch, free here
+        uint32_t *list = (uint32_t *)&gs->d[0][0];
+        uint32_t *count = &gs->u[0][7];
+        if (threadIdx.x == 0) *count = 0u;
+        __syncthreads();
+        for (uint32_t r = threadIdx.x; r < N; r += T) {
+            if (in_s(r)) {
+                const uint32_t slot = atomicAdd(count, 1u);
+                if (slot < 64u) list[slot] = r;
+            }
         }
-        const unsigned long long m = __ballot(in);
-        const uint32_t cnt = (uint32_t)__popcll(m);
-        if (ns + cnt > 64) { overflow = true; break; }
-        // the q-th member (in lane order) moves to lane ns + q
-        const int qq = lane - (int)ns;
-        int src = 0;
-        if (qq >= 0 && qq < (int)cnt) {
-            unsigned long long mm = m;
-            for (int t = 0; t < qq; ++t) mm &= mm - 1ull;
-            src = __ffsll((long long)mm) - 1;
+        __syncthreads();
+        ns = *count;
+        overflow = ns > 64u;
+        if (!overflow && (uint32_t)lane < ns) mine = list[lane];
+        __syncthreads();  // the scratch is reused
+    } else {
+        for (uint32_t r0 = 0; r0 < N && !overflow; r0 += 64) {
+            const uint32_t r = r0 + (uint32_t)lane;
+            const bool in = r < N && in_s(r);
+            const unsigned long long m = __ballot(in);
+            const uint32_t cnt = (uint32_t)__popcll(m);
+            if (ns + cnt > 64) { overflow = true; break; }
+            // the q-th member (in lane order) moves to lane ns + q
+            const int qq = lane - (int)ns;
+            int src = 0;
+            if (qq >= 0 && qq < (int)cnt) {
+                unsigned long long mm = m;
+                for (int t = 0; t < qq; ++t) mm &= mm - 1ull;
+                src = __ffsll((long long)mm) - 1;
+            }
+            const uint32_t val = __shfl(r, src, 64);
+            if (qq >= 0 && qq < (int)cnt) mine = val;
+            ns += cnt;
         }
-        const uint32_t val = __shfl(r, src, 64);
-        if (qq >= 0 && qq < (int)cnt) mine = val;
-        ns += cnt;
     }
     bool ok = !overflow;
     if (ok && ns >= 2) {
+        // every wave holds all members (lane s: member s); wave w compares
+        // the pairs (l, b) with l < b, b = w, w + T/64, ...
         R x = 0, yv = 0, z = 0;
         if ((uint32_t)lane < ns) v.get(mine, x, yv, z);
         const double gp2 = gp * gp;
         bool bad = false;
-        for (uint32_t b = 0; b < ns; ++b) {
+        for (uint32_t b = threadIdx.x >> 6; b < ns; b += T / 64) {
             const R bx = __shfl(x, b, 64), by = __shfl(yv, b, 64), bz = __shfl(z, b, 64);
             if ((uint32_t)lane < ns && b > (uint32_t)lane) {
                 const double dx = (double)x - (double)bx, dy = (double)yv - (double)by, dz = (double)z - (double)bz;
@@ -149,15 +181,19 @@ __device__ double learned_majorant(const CollideArgs<R> &a, const View &v, uint3
                 if (g2 > gp2) bad = true;
             }
         }
-        ok = __ballot(bad) == 0ull;
+        uint32_t nbad = __ballot(bad) != 0ull ? 1u : 0u;
+        grp_put<T>(gs, 6, nbad);
+        grp_sync<T>();
+        nbad = grp_sum<T>(gs, 6, nbad);
+        grp_sync<T>();  // the scratch is reused
+        ok = nbad == 0u;
     }
     if (!ok) { used = -1; return gb; }
     used = 1;
     return gp;
 }
 
-// Same as process_cell, with the learned majorant.  A workgroup cell
-// (T > 64) computes the majorant on its first wave and shares it through LDS.
+// Same as process_cell, with the learned majorant.
 template <typename R, bool VR, typename View, int T = 64>
 __device__ void process_cell_learned(const CollideArgs<R> &a, const View &v, uint32_t cell, uint32_t N,
                                      uint32_t step, const CellPrefetch &pf, double *red = nullptr,
@@ -165,20 +201,11 @@ __device__ void process_cell_learned(const CollideArgs<R> &a, const View &v, uin
     uint32_t M = 0, acc = 0, over = 0;
     if (N >= 2) {
         const double V = a.volume ? a.volume[cell] : a.Vuni;
-        double gmax = 0.0;
-        if (threadIdx.x < 64) {
-            int used = 0;
-            gmax = learned_majorant<R>(a, v, cell, N, V, used);
-            if (threadIdx.x == 0) {
-                const int slot = used == 1 ? kDiagLearned : (used == -1 ? kDiagFallback : kDiagSkip);
-                diag_add(a.st, slot, 1ull);
-            }
-        }
-        if constexpr (T > 64) {
-            if (threadIdx.x == 0) gs->d[0][8] = gmax;
-            __syncthreads();
-            gmax = gs->d[0][8];
-            __syncthreads();  // the scratch is reused
+        int used = 0;
+        const double gmax = learned_majorant<R, View, T>(a, v, N, V, used, gs);
+        if (threadIdx.x == 0) {
+            const int slot = used == 1 ? kDiagLearned : (used == -1 ? kDiagFallback : kDiagSkip);
+            diag_add(a.st, slot, 1ull);
         }
         const double Nd = (double)N;
         const double Mreal = candidates_real<R>(a, Nd, gmax, V);
