@@ -562,7 +562,8 @@ static int cmp_by_id(const void *a, const void *b)
  *         s = (m - 1)/(m + 1), |s| < 0.1716, by its odd series through s^27
  *         (Horner in s^2); log2 x = e + ln m / ln 2.
  *   exp2: y = n + f, n = floor(y), f in [0, 1); 2^f = e^(f ln 2) by its
- *         Taylor series through degree 18 (Horner); scaled by 2^n exactly. */
+ *         Taylor series through degree 18 (Horner on the coefficients 1/k!,
+ *         a multiply and an add per degree); scaled by 2^n exactly. */
 static const double VHS_LN2 = 0.69314718055994530942;
 static const double VHS_INV_LN2 = 1.44269504088896340736;
 static double vhs_log2(double x)
@@ -582,10 +583,17 @@ static double vhs_log2(double x)
 }
 static double vhs_exp2(double y)
 {
+    /* Taylor coefficients 1/k!, k = 0..18: each the rounded quotient of two
+     * exactly representable integers */
+    static const double c[19] = {
+        1.0, 1.0, 1.0 / 2.0, 1.0 / 6.0, 1.0 / 24.0, 1.0 / 120.0, 1.0 / 720.0, 1.0 / 5040.0,
+        1.0 / 40320.0, 1.0 / 362880.0, 1.0 / 3628800.0, 1.0 / 39916800.0, 1.0 / 479001600.0,
+        1.0 / 6227020800.0, 1.0 / 87178291200.0, 1.0 / 1307674368000.0, 1.0 / 20922789888000.0,
+        1.0 / 355687428096000.0, 1.0 / 6402373705728000.0};
     double n = floor(y);
     double f = (y - n) * VHS_LN2;
-    double t = 1.0;
-    for (int k = 18; k >= 1; --k) t = 1.0 + (f * t) / (double)k;
+    double t = c[18];
+    for (int k = 17; k >= 0; --k) t = t * f + c[k];
     return ldexp(t, (int)n);
 }
 static double vhs_pow(double x, double a)

@@ -63,7 +63,8 @@ __device__ __forceinline__ float unif24(uint32_t a) { return (float)(a >> 8) * 0
 //   log2: x = m 2^e, m in [sqrt(1/2), sqrt(2)); ln m = 2 atanh(s) with
 //         s = (m - 1)/(m + 1) by its odd series through s^27 (Horner in s^2).
 //   exp2: y = n + f, n = floor(y); 2^f = e^(f ln 2) by its Taylor series
-//         through degree 18 (Horner); scaled by 2^n exactly.
+//         through degree 18, Horner on the coefficients 1/k! (one multiply
+//         and one add per degree, no division); scaled by 2^n exactly.
 __device__ __forceinline__ double vhs_log2(double x) {
     int e;
     double m = frexp(x, &e);
@@ -79,12 +80,27 @@ __device__ __forceinline__ double vhs_log2(double x) {
     const double lnm = (2.0 * sv) * t;
     return (double)e + lnm * 1.44269504088896340736;
 }
+// 1/k! for k = 0..18, each the correctly rounded quotient of 1 and the
+// exact integer k! (below 2^53), evaluated at compile time.
+struct InvFactorials {
+    double c[19];
+};
+constexpr InvFactorials inv_factorials() {
+    InvFactorials r{};
+    double f = 1.0;
+    for (int k = 0; k <= 18; ++k) {
+        if (k > 0) f *= (double)k;
+        r.c[k] = 1.0 / f;
+    }
+    return r;
+}
 __device__ __forceinline__ double vhs_exp2(double y) {
+    constexpr InvFactorials kC = inv_factorials();
     const double n = floor(y);
     const double f = (y - n) * 0.69314718055994530942;
-    double t = 1.0;
+    double t = kC.c[18];
 #pragma unroll
-    for (int k = 18; k >= 1; --k) t = 1.0 + (f * t) / (double)k;
+    for (int k = 17; k >= 0; --k) t = t * f + kC.c[k];
     return ldexp(t, (int)n);
 }
 __device__ __forceinline__ double vhs_pow(double x, double a) {
