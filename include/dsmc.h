@@ -156,6 +156,16 @@ typedef struct {
     uint64_t big_cells;       /* cell-steps processed by the global-memory collision kernel */
 } dsmc_diag;
 
+/* Where a cell is collided.  A cell (or instance) is staged in the 64 KiB of
+ * LDS a workgroup may hold if it has at most `cap` particles, and is collided
+ * in global memory otherwise (counted in big_cells); both give the same
+ * results.  With fit = floor(65472 / (4 real_bytes + 4)) rounded down to a
+ * multiple of 32 (3264 in FP32, 1792 in FP64):
+ *   dims == 0:  cap = the largest instance rounded up to a multiple of 32
+ *               (at least 32), at most fit;
+ *   dims >= 1:  cap = 3 x (mean particles per cell) + 64 rounded up to a
+ *               multiple of 32, at least 64, at most fit. */
+
 /* Bytes of device workspace the configuration needs (second particle
  * buffer of the regrouping, per-cell ranges, code bytes and mover lists,
  * FP64 running sums, counters, scratch).  EINVAL on an invalid

@@ -124,3 +124,49 @@ def test_one_and_two_particles(gpu, n):
                  cz=np.array([-0.4, 0.9])[:n], w=np.ones(n), id=np.arange(n, dtype=np.uint32))
     g, sums, cnt, ns, seq, d, orc = _both(p, parts, 20)
     _check(g, sums, cnt, seq, d, orc)
+
+
+def _lds_fit(real):
+    # the largest multiple of 32 particles whose LDS staging fits 64 KiB
+    return (65472 // (4 * (8 if real == "f64" else 4) + 4)) // 32 * 32
+
+
+@pytest.mark.parametrize("real", ["f64", "f32"])
+def test_instances_at_lds_capacity_and_one_above(gpu, real):
+    # the largest instance that is staged in LDS and the smallest one that
+    # is not (global-memory kernel), side by side
+    cap = _lds_fit(real)
+    _announce("instances at capacity %s (%d)" % (real, cap))
+    counts = [cap, cap + 1, 50]
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    rng = np.random.default_rng(14)
+    c = rng.standard_normal((3, int(off[-1])))
+    c[0, :cap // 2] += 1.0
+    p = dict(dims=0, n_cells=(len(counts), 1), dt=0.05, sigma=3e-4, FN=1.0, molecule=0, seed=9,
+             inst_offset=off, cell_volume=np.ones(len(counts)))
+    steps = 3
+    g, sums, cnt, ns, seq, d, orc = _both(p, dict(cx=c[0], cy=c[1], cz=c[2], id=np.arange(len(c[0]), dtype=np.uint32)),
+                                          steps, real)
+    assert d["big_cells"] == steps  # only the instance above capacity
+    assert cnt[0, 1] > 100 and cnt[1, 1] > 100
+    _check(g, sums, cnt, seq, d, orc, fields=("cx", "cy", "cz"))
+
+
+@pytest.mark.parametrize("extra", [0, 1])
+def test_walled_cell_at_lds_capacity_and_one_above(gpu, extra):
+    # 160 particles in 8 cells: the per-cell capacity is 3 x 20 + 64 rounded
+    # up to 128; cell 0 holds 128 (staged in LDS) or 129 (global memory).
+    # A tiny time step keeps every particle in its cell.
+    _announce("walled cell at capacity + %d" % extra)
+    p, _ = W.fourier(n_cells=8, per_cell=1, Kn=0.05, dt=1e-7)
+    p["wall_kind"] = (W.WALL_SPECULAR, W.WALL_SPECULAR, 0, 0)
+    p["sigma"] = 1300.0
+    n, n0 = 160, 128 + extra
+    rng = np.random.default_rng(12)
+    x = np.concatenate([rng.uniform(0.01, 0.115, n0), rng.uniform(0.135, 0.99, n - n0)])
+    c = rng.standard_normal((3, n))
+    parts = dict(x=x, cx=c[0], cy=c[1], cz=c[2], w=np.ones(n), id=rng.permutation(n).astype(np.uint32))
+    g, sums, cnt, ns, seq, d, orc = _both(p, parts, 4, "f32")
+    assert (d["big_cells"] > 0) == bool(extra)
+    assert cnt[0, 1] > 20
+    _check(g, sums, cnt, seq, d, orc)
