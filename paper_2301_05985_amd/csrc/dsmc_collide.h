@@ -189,9 +189,12 @@ __device__ __forceinline__ double wave_max_nonneg(double v) {
     return __longlong_as_double((long long)(((uint64_t)hmax << 32) | lmax));
 }
 
-template <typename R, typename View, int T = 64>
+// With SUMS the pass over r^2 also adds this thread's particles into the
+// seven first and second moments sums[0..6] (sx, sy, sz, sxx, syy, szz, sxy),
+// in the thread's particle order.
+template <typename R, typename View, int T = 64, bool SUMS = false>
 __device__ double exact_bound(const View &v, uint32_t N, double &r_top, GroupScratch *gs = nullptr,
-                              double *mid = nullptr) {
+                              double *mid = nullptr, double *sums = nullptr) {
     const uint32_t tid = threadIdx.x;
     double m0, m1, m2;
     if constexpr (sizeof(R) == 4) {
@@ -257,6 +260,11 @@ __device__ double exact_bound(const View &v, uint32_t N, double &r_top, GroupScr
         const double r2 = (dx * dx + dy * dy) + dz * dz;
         if (r2 > a1) { a2 = a1; a1 = r2; }
         else if (r2 > a2) { a2 = r2; }
+        if constexpr (SUMS) {
+            const double vx = (double)a, vy = (double)b, vz = (double)c;
+            sums[0] += vx; sums[1] += vy; sums[2] += vz;
+            sums[3] += vx * vx; sums[4] += vy * vy; sums[5] += vz * vz; sums[6] += vx * vy;
+        }
     }
     double t1 = wave_max_nonneg(a1);
     const unsigned long long at = __ballot(a1 == t1);

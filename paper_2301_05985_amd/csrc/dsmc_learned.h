@@ -26,57 +26,74 @@ constexpr int kMlpIn = 6, kMlpH = 64;
 
 struct Features { float f[kMlpIn]; };
 
-// Features of the cell held by the view: FP64 moments, rounded once to float.
+// Features from the seven moment sums of a cell, sum k on lane k (k < 7),
+// identical on every lane:
 //   log2(number density), u_x / sqrt(T), u_y / sqrt(T), log2(T),
-//   P_xx / p - 1, P_xy / p
-// The T threads of the cell each sum their particles; the seven sums are
-// reduced over the wave by recursive halving and over the waves of a
-// workgroup in a fixed order.
-template <typename R, typename View, int T = 64>
-__device__ Features cell_features(const View &v, uint32_t N, double FNum, double V, GroupScratch *gs = nullptr) {
+//   P_xx / p - 1, P_xy / p      (FP64, each rounded once to float)
+// The independent divisions (and the two logarithms) of each stage run side
+// by side on different lanes; every value is the same IEEE operation on the
+// same operands as in the written-out formulas.
+__device__ __forceinline__ Features features_from_lane_sums(double S, uint32_t N, double FNum, double V) {
+    const int lane = lane_id();
+    const auto rl = [](double x, int l) {
+        const uint64_t b = (uint64_t)__double_as_longlong(x);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+        return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+    };
+    const double Nd = (double)N;
+    const double s3 = rl(S, 3), s4 = rl(S, 4), s5 = rl(S, 5);
+    // stage 1: u_x, u_y, u_z, <c^2>, <c_x^2>, <c_x c_y>, density
+    double num = S, den = Nd;
+    if (lane == 3) num = (s3 + s4) + s5;
+    if (lane == 4) num = s3;
+    if (lane == 5) num = rl(S, 6);
+    if (lane == 6) { num = Nd * FNum; den = V; }
+    const double q = num / den;
+    const double ux = rl(q, 0), uy = rl(q, 1), uz = rl(q, 2), ec2 = rl(q, 3), exx = rl(q, 4), exy = rl(q, 5),
+                 dens = rl(q, 6);
+    // stage 2: temperature, pressures
+    double Tk = (ec2 - ((ux * ux + uy * uy) + uz * uz)) / 3.0;
+    if (!(Tk > 1e-300)) Tk = 1e-300;
+    const double Pxx = dens * (exx - ux * ux);
+    const double Pxy = dens * (exy - ux * uy);
+    const double pr = dens * Tk;
+    const double sT = sqrt(Tk);
+    // stage 3: feature k on lane k
+    double n3 = 1.0, d3 = 1.0, lg = 1.0;
+    if (lane == 1) { n3 = ux; d3 = sT; }
+    if (lane == 2) { n3 = uy; d3 = sT; }
+    if (lane == 4) { n3 = Pxx; d3 = pr; }
+    if (lane == 5) { n3 = Pxy; d3 = pr; }
+    if (lane == 0) lg = dens;
+    if (lane == 3) lg = Tk;
+    const double dq = n3 / d3;
+    const double lq = log2(lg);
+    const float f = (float)(lane == 0 || lane == 3 ? lq : (lane == 4 ? dq - 1.0 : dq));
+    Features F;
+#pragma unroll
+    for (int k = 0; k < kMlpIn; ++k) F.f[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(f), k));
+    return F;
+}
+
+// Moment sums of this lane (7 values) reduced over the wave, sum k to lane k.
+__device__ __forceinline__ double wave_sums_to_lanes(double (&q)[8]) {
+    const double t = wave_sum_many<8>(q);  // lane L: total of sum L >> 3
+    return __shfl(t, (lane_id() & 7) << 3, 64);
+}
+
+// Features of the cell held by the view (one wave), for the training data.
+template <typename R, typename View>
+__device__ Features cell_features(const View &v, uint32_t N, double FNum, double V) {
     double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // sx, sy, sz, sxx, syy, szz, sxy, (pad)
-    for (uint32_t r = threadIdx.x; r < N; r += T) {
+    for (uint32_t r = lane_id(); r < N; r += 64) {
         R a, b, c;
         v.get(r, a, b, c);
         const double vx = (double)a, vy = (double)b, vz = (double)c;
         q[0] += vx; q[1] += vy; q[2] += vz;
         q[3] += vx * vx; q[4] += vy * vy; q[5] += vz * vz; q[6] += vx * vy;
     }
-    const double t = wave_sum_many<8>(q);  // lane L: total of sum L >> 3
-    double S[7];
-#pragma unroll
-    for (int k = 0; k < 7; ++k) S[k] = __shfl(t, 8 * k, 64);
-    if constexpr (T > 64) {
-        if (lane_id() == 0) {
-#pragma unroll
-            for (int k = 0; k < 7; ++k) gs->d[threadIdx.x >> 6][8 + k] = S[k];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < 7; ++k) {
-            S[k] = gs->d[0][8 + k];
-#pragma unroll
-            for (int w = 1; w < T / 64; ++w) S[k] += gs->d[w][8 + k];
-        }
-        __syncthreads();  // the scratch is reused
-    }
-    const double Nd = (double)N;
-    const double ux = S[0] / Nd, uy = S[1] / Nd, uz = S[2] / Nd;
-    double Tk = (((S[3] + S[4]) + S[5]) / Nd - ((ux * ux + uy * uy) + uz * uz)) / 3.0;
-    if (!(Tk > 1e-300)) Tk = 1e-300;
-    const double dens = (Nd * FNum) / V;
-    const double Pxx = dens * (S[3] / Nd - ux * ux);
-    const double Pxy = dens * (S[6] / Nd - ux * uy);
-    const double pr = dens * Tk;
-    const double sT = sqrt(Tk);
-    Features F;
-    F.f[0] = (float)log2(dens);
-    F.f[1] = (float)(ux / sT);
-    F.f[2] = (float)(uy / sT);
-    F.f[3] = (float)log2(Tk);
-    F.f[4] = (float)(Pxx / pr - 1.0);
-    F.f[5] = (float)(Pxy / pr);
-    return F;
+    return features_from_lane_sums(wave_sums_to_lanes(q), N, FNum, V);
 }
 
 // Network output (log2 units), identical on every lane.
@@ -89,8 +106,10 @@ __device__ __forceinline__ float mlp_forward_wave(const float *P, const Features
     for (int i = 0; i < kMlpIn; ++i) acc = fmaf(W1[h * kMlpIn + i], F.f[i], acc);
     const float a1 = acc > 0.0f ? acc : 0.0f;
     acc = b2[h];
-#pragma unroll 16
-    for (int i = 0; i < kMlpH; ++i) acc = fmaf(W2T[i * kMlpH + h], __shfl(a1, i, 64), acc);
+    // hidden value i read from lane i as a scalar (no LDS permute)
+#pragma unroll
+    for (int i = 0; i < kMlpH; ++i)
+        acc = fmaf(W2T[i * kMlpH + h], __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a1), i)), acc);
     const float a2 = acc > 0.0f ? acc : 0.0f;
     float s = w3[h] * a2;
 #pragma unroll
@@ -109,13 +128,37 @@ __device__ double learned_majorant(const CollideArgs<R> &a, const View &v, uint3
                                    GroupScratch *gs = nullptr) {
     const int lane = lane_id();
     double r1, mid[3];
-    const double gb = exact_bound<R, View, T>(v, N, r1, gs, mid);
-    const Features F = cell_features<R, View, T>(v, N, a.FN, V, gs);
-    const float y = mlp_forward_wave(a.mlp, F);
-    double kk = ceil(64.0 * ((double)y + a.delta));
-    if (!(kk > -(double)kLatticeHalf)) kk = -(double)kLatticeHalf;
-    if (kk > (double)kLatticeHalf) kk = (double)kLatticeHalf;
-    const double gp = a.lattice[(int)kk + kLatticeHalf];
+    double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // moment sums of this thread's particles
+    const double gb = exact_bound<R, View, T, true>(v, N, r1, gs, mid, q);
+    // the proposal: on the first wave only (shared through LDS in a workgroup)
+    double S = wave_sums_to_lanes(q);
+    if constexpr (T > 64) {
+        if (lane < 7) gs->d[threadIdx.x >> 6][8 + lane] = S;
+        __syncthreads();
+    }
+    double gp = 0.0;
+    if (threadIdx.x < 64) {
+        if constexpr (T > 64) {
+            // the waves' sums in a fixed order
+            if (lane < 7) {
+                S = gs->d[0][8 + lane];
+#pragma unroll
+                for (int w = 1; w < T / 64; ++w) S += gs->d[w][8 + lane];
+            }
+        }
+        const Features F = features_from_lane_sums(S, N, a.FN, V);
+        const float y = mlp_forward_wave(a.mlp, F);
+        double kk = ceil(64.0 * ((double)y + a.delta));
+        if (!(kk > -(double)kLatticeHalf)) kk = -(double)kLatticeHalf;
+        if (kk > (double)kLatticeHalf) kk = (double)kLatticeHalf;
+        gp = a.lattice[(int)kk + kLatticeHalf];
+    }
+    if constexpr (T > 64) {
+        if (threadIdx.x == 0) gs->d[0][16] = gp;
+        __syncthreads();
+        gp = gs->d[0][16];
+        __syncthreads();  // the scratch is reused
+    }
     if (!(gp < gb)) { used = 0; return gb; }
     const double m0 = mid[0], m1 = mid[1], m2 = mid[2];
     const auto in_s = [&](uint32_t r) {
