@@ -151,7 +151,7 @@ def main():
                     help="also run one plain 512 MiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: there is no multi-GPU path "
               "(the slab decomposition with particle migration is a design note only)", file=sys.stderr)
         sys.exit(2)
 

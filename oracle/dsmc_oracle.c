@@ -6,9 +6,9 @@
  * header or constant table with the HIP implementation; both are written
  * independently from the method description below.
  *
- * The paper filed for this build (arXiv 2301.05985, a finite-element
- * electrokinetics paper) contains no Monte Carlo method, so every step here
- * follows the standard published method named in its comment:
+ * The cited paper (arXiv 2301.05985, on finite-element electrokinetics)
+ * contains no Monte Carlo method, so every step here follows the standard
+ * published method named in its comment:
  *   - Bird, "Molecular Gas Dynamics and the Direct Simulation of Gas Flows"
  *     (1994): no-time-counter (NTC) collision selection, hard-sphere
  *     isotropic scattering, diffuse wall reflection, cell sampling.
