@@ -273,7 +273,8 @@ dsmc_status dsmc_mlp_forward(const float *params_dev, const float *x_dev, int64_
  * and its gradient with respect to every parameter (device
  * [DSMC_MLP_NPARAM] float, overwritten) and the loss (device float [1]).
  * Rows with a non-finite label are skipped.  scratch_dev must hold
- * dsmc_mlp_scratch_floats(n) floats.  Asynchronous. */
+ * dsmc_mlp_scratch_floats(n) floats (8-byte aligned); n at most
+ * 65535 x 128, else EINVAL.  Asynchronous. */
 dsmc_status dsmc_mlp_loss_grad(const float *params_dev, const float *x_dev, const float *label_dev,
                                int64_t n, double tau, float *grad_dev, float *loss_dev,
                                float *scratch_dev, void *hip_stream);

@@ -7,11 +7,12 @@
 //
 // Training objective: mean expectile loss (Newey & Powell 1987)
 //   L = (1/n_valid) sum_s |tau - 1[r_s < 0]| r_s^2,  r = label - y,
-// rows with a non-finite label skipped.  The gradient is computed in two
+// rows with a non-finite label skipped.  The gradient is computed in
 // passes: one thread per sample runs forward and backward and stores its
-// activations and deltas; then one thread per parameter sums its gradient
-// over the samples in ascending order (FP64 accumulation), so the result does
-// not depend on scheduling.  Adam (Kingma & Ba 2015) updates in place.
+// activations and deltas; then the per-parameter sums over the samples are
+// formed in FP64 in a fixed order (chunks of consecutive samples, then the
+// chunks in order), so the result does not depend on scheduling.  Adam
+// (Kingma & Ba 2015) updates in place.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -25,6 +26,7 @@ constexpr int kOffW1 = 0, kOffB1 = kH * kIn, kOffW2 = kOffB1 + kH, kOffB2 = kOff
               kOffW3 = kOffB2 + kH, kOffB3 = kOffW3 + kH, kNp = kOffB3 + 1;
 static_assert(kNp == DSMC_MLP_NPARAM, "parameter count");
 constexpr int kPerSample = 4 * kH + 4;  // h1, h2, d1, d2, e, valid (+pad)
+static_assert(kPerSample % 2 == 0, "the FP64 chunk sums follow the records 8-byte aligned");
 
 __device__ __forceinline__ void load_params(const float *P, float *s) {
     for (int k = threadIdx.x; k < kNp; k += blockDim.x) s[k] = P[k];
@@ -113,40 +115,54 @@ __global__ __launch_bounds__(256) void k_mlp_backward(const float *P, const floa
     rec[4 * kH + 2] = wgt * r * r;
 }
 
-// One thread per parameter (plus two for the loss and the valid count):
-// ascending-order FP64 sums over the samples.
-__global__ __launch_bounds__(256) void k_mlp_reduce(const float *x, int64_t n, const float *scr, float *grad,
-                                                    float *loss) {
+// Gradient sums in two passes, both in a fixed order.  Pass 1: block
+// (bx, c) gives one thread per parameter (plus two for the loss and the
+// valid count) the FP64 sum of its terms over the samples of chunk c
+// (kChunk consecutive samples, ascending).  Pass 2: one thread per
+// parameter adds the chunk sums in ascending chunk order and divides by the
+// number of valid samples.
+constexpr int kChunk = 128;
+constexpr int kNq = kNp + 2;
+
+__device__ __forceinline__ double grad_term(int q, const float *rec, const float *xs) {
+    if (q < kOffB1) {
+        const int o = q / kIn, k = q % kIn;
+        return (double)rec[2 * kH + o] * (double)xs[k];
+    }
+    if (q < kOffW2) return rec[2 * kH + (q - kOffB1)];
+    if (q < kOffB2) {
+        const int o = (q - kOffW2) / kH, i = (q - kOffW2) % kH;
+        return (double)rec[3 * kH + o] * (double)rec[i];
+    }
+    if (q < kOffW3) return rec[3 * kH + (q - kOffB2)];
+    if (q < kOffB3) return (double)rec[4 * kH] * (double)rec[kH + (q - kOffW3)];
+    if (q == kOffB3) return rec[4 * kH];
+    if (q == kNp) return rec[4 * kH + 2];  // loss term
+    return rec[4 * kH + 1];                // valid flag (q == kNp + 1)
+}
+
+__global__ __launch_bounds__(256) void k_mlp_partial(const float *x, int64_t n, const float *scr, double *part) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q > kNp + 1) return;
+    if (q >= kNq) return;
+    const int64_t s0 = (int64_t)blockIdx.y * kChunk;
+    const int64_t s1 = s0 + kChunk < n ? s0 + kChunk : n;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int64_t s = s0; s < s1; ++s) acc += grad_term(q, scr + s * kPerSample, x + s * kIn);
+    part[(int64_t)blockIdx.y * kNq + q] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_finish(const double *part, int nchunk, float *grad, float *loss) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= kNp + 1) return;
     double acc = 0.0, valid = 0.0;
-    for (int64_t s = 0; s < n; ++s) {
-        const float *rec = scr + s * kPerSample;
-        double term;
-        if (q < kOffB1) {
-            const int o = q / kIn, k = q % kIn;
-            term = (double)rec[2 * kH + o] * (double)x[s * kIn + k];
-        } else if (q < kOffW2) {
-            term = rec[2 * kH + (q - kOffB1)];
-        } else if (q < kOffB2) {
-            const int o = (q - kOffW2) / kH, i = (q - kOffW2) % kH;
-            term = (double)rec[3 * kH + o] * (double)rec[i];
-        } else if (q < kOffW3) {
-            term = rec[3 * kH + (q - kOffB2)];
-        } else if (q < kOffB3) {
-            term = (double)rec[4 * kH] * (double)rec[kH + (q - kOffW3)];
-        } else if (q == kOffB3) {
-            term = rec[4 * kH];
-        } else {
-            term = rec[4 * kH + 2];  // loss term (q == kNp) / valid flag (q == kNp + 1)
-            if (q == kNp + 1) term = rec[4 * kH + 1];
-        }
-        acc += term;
-        valid += rec[4 * kH + 1];
+    for (int c = 0; c < nchunk; ++c) {
+        acc += part[(int64_t)c * kNq + q];
+        valid += part[(int64_t)c * kNq + kNp + 1];
     }
     const double inv = valid > 0.0 ? 1.0 / valid : 0.0;
     if (q < kNp) grad[q] = (float)(acc * inv);
-    else if (q == kNp) loss[0] = (float)(acc * inv);
+    else loss[0] = (float)(acc * inv);
 }
 
 __global__ __launch_bounds__(256) void k_mlp_adam(float *p, const float *g, float *m, float *v, int64_t n,
@@ -173,7 +189,10 @@ dsmc_status dsmc_mlp_forward(const float *params, const float *x, int64_t n, flo
     return hipGetLastError() == hipSuccess ? DSMC_OK : DSMC_EHIP;
 }
 
-int64_t dsmc_mlp_scratch_floats(int64_t n) { return n < 0 ? 0 : n * kPerSample; }
+// per-sample records, then the FP64 chunk sums (two floats each)
+int64_t dsmc_mlp_scratch_floats(int64_t n) {
+    return n < 0 ? 0 : n * kPerSample + 2 * ((n + kChunk - 1) / kChunk) * (int64_t)kNq;
+}
 
 dsmc_status dsmc_mlp_loss_grad(const float *params, const float *x, const float *label, int64_t n, double tau,
                                float *grad, float *loss, float *scratch, void *stream) {
@@ -182,8 +201,13 @@ dsmc_status dsmc_mlp_loss_grad(const float *params, const float *x, const float 
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_mlp_backward, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, params, x, label, n,
                        (float)tau, scratch);
-    hipLaunchKernelGGL(k_mlp_reduce, dim3((unsigned)((kNp + 2 + 255) / 256)), dim3(256), 0, s, x, n, scratch,
-                       grad, loss);
+    if ((n + kChunk - 1) / kChunk > 65535) return DSMC_EINVAL;  // chunks are a grid dimension
+    const int nchunk = (int)((n + kChunk - 1) / kChunk);
+    double *part = (double *)(scratch + n * kPerSample);  // kPerSample is even: 8-byte aligned
+    hipLaunchKernelGGL(k_mlp_partial, dim3((unsigned)((kNq + 255) / 256), (unsigned)nchunk), dim3(256), 0, s, x, n,
+                       scratch, part);
+    hipLaunchKernelGGL(k_mlp_finish, dim3((unsigned)((kNp + 1 + 255) / 256)), dim3(256), 0, s, part, nchunk, grad,
+                       loss);
     return hipGetLastError() == hipSuccess ? DSMC_OK : DSMC_EHIP;
 }
 
