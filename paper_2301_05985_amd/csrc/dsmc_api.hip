@@ -901,10 +901,10 @@ dsmc_status dsmc_collect_features(dsmc_ctx *c, float *features, float *labels, f
     // runs are grouped at set-up)
     HIP_TRY(hipStreamSynchronize(c->stream));
     if (c->cfg.real_bytes == 4)
-        hipLaunchKernelGGL(k_collect_features<float>, dim3((unsigned)c->ncell), dim3(64), 0, c->stream,
+        hipLaunchKernelGGL(k_collect_features<float>, dim3((unsigned)c->ncell), dim3(kCollectThreads), 0, c->stream,
                            collide_args<float>(c, c->cur, c->cur), (int)c->ncell, features, labels, bounds);
     else
-        hipLaunchKernelGGL(k_collect_features<double>, dim3((unsigned)c->ncell), dim3(64), 0, c->stream,
+        hipLaunchKernelGGL(k_collect_features<double>, dim3((unsigned)c->ncell), dim3(kCollectThreads), 0, c->stream,
                            collide_args<double>(c, c->cur, c->cur), (int)c->ncell, features, labels, bounds);
     HIP_TRY(hipGetLastError());
     return DSMC_OK;

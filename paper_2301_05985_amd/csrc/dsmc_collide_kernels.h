@@ -468,26 +468,31 @@ __global__ __launch_bounds__(64) void k_collide_persistent(CollideArgs<R> a, con
 
 // Training data for the learned majorant: per cell, the six input features
 // and log2 of the exact largest pairwise relative speed (brute force over all
-// pairs, in double); -inf for cells with fewer than two particles.
+// pairs, in double); -inf for cells with fewer than two particles.  A
+// workgroup of kCollectThreads per cell: the pairs are spread over all its
+// threads (the maximum does not depend on the order), the O(N) features and
+// bound are taken on the first wave.
+constexpr int kCollectThreads = 256;
+
 template <typename R>
-__global__ __launch_bounds__(64) void k_collect_features(CollideArgs<R> a, int ncell, float *feat, float *label,
-                                                         float *bound) {
+__global__ __launch_bounds__(kCollectThreads) void k_collect_features(CollideArgs<R> a, int ncell, float *feat,
+                                                                      float *label, float *bound) {
+    __shared__ double wave_best[kCollectThreads / 64];
     const int lane = lane_id();
+    const uint32_t tid = threadIdx.x;
     const uint32_t cell = blockIdx.x;
     if ((int)cell >= ncell) return;
     const uint32_t base = a.start[cell];
     const uint32_t N = a.start[cell + 1] - base;
     const GlobalView<R> v{a.s.cx + base, a.s.cy + base, a.s.cz + base, nullptr, nullptr, nullptr};
     if (N < 2) {
-        if (lane < 6) feat[(size_t)cell * 6 + lane] = 0.0f;
-        if (lane == 0) label[cell] = -INFINITY;
-        if (lane == 0 && bound) bound[cell] = -INFINITY;
+        if (tid < 6) feat[(size_t)cell * 6 + tid] = 0.0f;
+        if (tid == 0) label[cell] = -INFINITY;
+        if (tid == 0 && bound) bound[cell] = -INFINITY;
         return;
     }
-    const double V = a.volume ? a.volume[cell] : a.Vuni;
-    const Features F = cell_features<R>(v, N, a.FN, V);
     double best = 0.0;
-    for (uint32_t r = lane; r < N; r += 64) {
+    for (uint32_t r = tid; r < N; r += kCollectThreads) {
         R x, y, z;
         v.get(r, x, y, z);
         for (uint32_t t = r + 1; t < N; ++t) {
@@ -499,6 +504,13 @@ __global__ __launch_bounds__(64) void k_collect_features(CollideArgs<R> a, int n
         }
     }
     best = wave_max_t(best);
+    if (lane == 0) wave_best[tid >> 6] = best;
+    __syncthreads();
+    if (tid >= 64) return;
+#pragma unroll
+    for (int w = 1; w < kCollectThreads / 64; ++w) best = fmax(best, wave_best[w]);
+    const double V = a.volume ? a.volume[cell] : a.Vuni;
+    const Features F = cell_features<R>(v, N, a.FN, V);
     if (lane < 6) feat[(size_t)cell * 6 + lane] = F.f[lane == 0 ? 0 : lane == 1 ? 1 : lane == 2 ? 2 : lane == 3 ? 3 : lane == 4 ? 4 : 5];
     if (lane == 0) label[cell] = (float)log2(sqrt(best));
     if (bound) {
