@@ -128,3 +128,22 @@ def test_init_rejects_misaligned_particle_arrays(lib):
                            ctypes.c_size_t(1 << 40), None, ctypes.byref(ctx))
         assert rc == -1, field
         assert not ctx.value
+
+
+def test_mlp_scratch_size_and_batch_limit(lib):
+    # per-sample records (260 floats) plus the FP64 sums of every chunk of
+    # 128 samples (4,675 parameters + loss + valid count, two floats each)
+    for n in (1, 127, 128, 129, 4096, 100000):
+        chunks = -(-n // 128)
+        assert lib.dsmc_mlp_scratch_floats(n) == n * 260 + 2 * chunks * (4673 + 2), n
+    assert lib.dsmc_mlp_scratch_floats(-1) == 0
+    # a batch needing more than 65,535 chunks is refused before any launch
+    # (the addresses are never dereferenced)
+    fake = ctypes.c_void_p(1 << 40)
+    big = 65535 * 128 + 1
+    rc = lib.dsmc_mlp_loss_grad(fake, fake, fake, big, 0.95, fake, fake, fake, None)
+    assert rc == -1
+    rc = lib.dsmc_mlp_loss_grad(fake, fake, fake, 0, 0.95, fake, fake, fake, None)
+    assert rc == -1
+    rc = lib.dsmc_mlp_loss_grad(fake, fake, fake, 16, 1.5, fake, fake, fake, None)
+    assert rc == -1
