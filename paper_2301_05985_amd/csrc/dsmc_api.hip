@@ -306,7 +306,14 @@ void launch_collide(dsmc_ctx *c, Launcher &L, int src) {
         hipLaunchKernelGGL((k_collide<R, VR, D>), dim3((unsigned)c->ncell), dim3(64), c->lds, L.s, a);
     if (c->any_big_possible) {
         L.mark("collide_big");
-        if (learned)
+        if (D == 0) {
+            // homogeneous instances: a four-wave workgroup per instance
+            if (learned)
+                hipLaunchKernelGGL((k_collide_big_wide_learned<R, VR>), dim3(c->big_grid), dim3(kWideThreads), 0,
+                                   L.s, a);
+            else
+                hipLaunchKernelGGL((k_collide_big_wide<R, VR>), dim3(c->big_grid), dim3(kWideThreads), 0, L.s, a);
+        } else if (learned)
             hipLaunchKernelGGL((k_collide_big_learned<R, VR, D>), dim3(c->big_grid), dim3(64), 0, L.s, a);
         else
             hipLaunchKernelGGL((k_collide_big<R, VR, D>), dim3(c->big_grid), dim3(64), 0, L.s, a);

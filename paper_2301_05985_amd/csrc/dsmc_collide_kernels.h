@@ -386,6 +386,41 @@ __device__ __forceinline__ void collide_wide_body(const CollideArgs<R> &a, unsig
     else process_cell<R, VR, LdsView<R>, T>(a, view, cell, N, step, pf, nullptr, base, gs);
 }
 
+// Homogeneous instances above the LDS capacity: one kWideThreads workgroup
+// each, operating on the instance in global memory (owner marks in the
+// global scratch array, read and set by device-scope atomics).
+template <typename R, bool VR, bool LEARNED>
+__device__ __forceinline__ void collide_big_wide_body(const CollideArgs<R> &a) {
+    constexpr int T = kWideThreads;
+    __shared__ GroupScratch gs;
+    const uint32_t step = (uint32_t)a.st->step_cur;
+    const uint32_t nbig = a.st->big_count;
+    for (uint32_t q = blockIdx.x; q < nbig; q += gridDim.x) {
+        const uint32_t cell = a.big_list[q];
+        const uint32_t base = a.start[cell];
+        const uint32_t N = a.start[cell + 1] - base;
+        const GlobalView<R> view{a.s.cx + base, a.s.cy + base, a.s.cz + base,
+                                 VR ? a.s.w + base : nullptr, nullptr, a.owner_g + base};
+        for (uint32_t r = threadIdx.x; r < N; r += T) view.clear_own(r);
+        __syncthreads();
+        const CellPrefetch pf = prefetch_cell<R, VR, false>(a, cell);
+        if (LEARNED) process_cell_learned<R, VR, GlobalView<R>, T>(a, view, cell, N, step, pf, nullptr, 0, &gs);
+        else process_cell<R, VR, GlobalView<R>, T>(a, view, cell, N, step, pf, nullptr, 0, &gs);
+        if (threadIdx.x == 0) diag_add(a.st, kDiagBig, 1ull);
+        __syncthreads();
+    }
+}
+
+template <typename R, bool VR>
+__global__ __launch_bounds__(kWideThreads) void k_collide_big_wide(CollideArgs<R> a) {
+    collide_big_wide_body<R, VR, false>(a);
+}
+
+template <typename R, bool VR>
+__global__ __launch_bounds__(kWideThreads) void k_collide_big_wide_learned(CollideArgs<R> a) {
+    collide_big_wide_body<R, VR, true>(a);
+}
+
 template <typename R, bool VR>
 __global__ __launch_bounds__(kWideThreads) void k_collide_wide(CollideArgs<R> a) {
     extern __shared__ __align__(16) unsigned char smem[];

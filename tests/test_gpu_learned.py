@@ -110,10 +110,12 @@ def _synthetic_net(seed, center):
 
 
 @pytest.mark.parametrize("real,sizes,mol", [("f32", (48, 30, 600), "hs"), ("f64", (48, 30, 600), "hs"),
-                                            ("f32", (12, 900, 1600), "hs"), ("f32", (48, 30, 600), "vss")])
+                                            ("f32", (12, 900, 1600), "hs"), ("f32", (48, 30, 600), "vss"),
+                                            ("f64", (8, 1500, 2400), "hs")])
 def test_learned_collisions_bit_exact_against_oracle(gpu, real, sizes, mol):
     # the third case has instances above 1024 particles (workgroup cells);
-    # the last one runs variable soft spheres
+    # the fourth runs variable soft spheres; the last has FP64 instances
+    # above the LDS capacity (global-memory workgroups)
     _announce("learned collide %s %s %s" % (real, sizes, mol))
     from paper_2301_05985_amd.binding import Simulation
     n_inst, nmin, nmax = sizes
@@ -134,6 +136,8 @@ def test_learned_collisions_bit_exact_against_oracle(gpu, real, sizes, mol):
         assert (log == 1).any() and (log == 0).any() and (log == -1).any(), np.unique(log, return_counts=True)
     else:
         assert (np.diff(off) > 1024).any()
+    if real == "f64" and nmax > 1792:
+        assert (np.diff(off) > 1792).any()
     sim = Simulation(dict(p, majorant=1), parts)
     sim.set_majorant_model(M.to_bf16(net), delta)
     sim.step(6)
