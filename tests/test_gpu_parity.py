@@ -367,6 +367,30 @@ def test_repeatable_and_direct_launch_matches_graph(gpu):
         assert np.array_equal(runs[0][k], runs[2][k], equal_nan=True), k
 
 
+def test_graph_replays_match_separate_launches_after_every_replay(gpu):
+    # the 8-step graph replayed four times, with host reads in between,
+    # against the same steps launched one kernel at a time: identical state
+    # and sums after every replay
+    _announce("graph replays")
+    from paper_2301_05985_amd.binding import Simulation
+    p, parts = W.cavity(nx=16, ny=16, per_cell=30, Kn=0.02, real="f32", dt=2e-3)
+    g, e = Simulation(p, parts), Simulation(p, parts)
+    for rep in range(4):
+        g.step(8)
+        for _ in range(4):
+            e.profile_step()  # two steps each
+        sg, cg, ng = g.sample()
+        se, ce, ne = e.sample()
+        assert ng == ne == 8 * (rep + 1)
+        assert np.array_equal(cg, ce), rep
+        assert np.array_equal(sg, se, equal_nan=True), rep
+        a, b = g.particles(), e.particles()
+        for k in ("x", "y", "cx", "cy", "cz", "w"):
+            assert np.array_equal(a[k], b[k], equal_nan=True), (rep, k)
+    g.close()
+    e.close()
+
+
 def test_too_many_wall_hits_is_reported(gpu):
     _announce("wall hit limit")
     from paper_2301_05985_amd.binding import Simulation, DsmcError
