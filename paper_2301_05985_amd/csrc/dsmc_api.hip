@@ -246,6 +246,9 @@ CollideArgs<R> collide_args(dsmc_ctx *c, int src, int dst) {
     a.counters = c->counters;
     a.st = c->st;
     a.big_list = c->big_list;
+    a.bigc = c->cfg.dims == 0 ? &c->st->big_slot[0] : &c->st->big_count;
+    a.queue = &c->st->queue[0];
+    a.step_off = 0;
     a.perm_g = c->perm;
     a.owner_g = c->owner;
     a.mlp = (c->cfg.majorant == DSMC_MAJORANT_LEARNED && c->mlp_loaded) ? c->mlp : nullptr;
@@ -271,8 +274,14 @@ struct Launcher {
 };
 
 template <typename R, bool VR, int D>
-void launch_collide(dsmc_ctx *c, Launcher &L, int src) {
+void launch_collide(dsmc_ctx *c, Launcher &L, int src, int slot) {
     CollideArgs<R> a = collide_args<R>(c, src, D == 0 ? src : src ^ 1);
+    if (D == 0) {
+        // step `slot` of a batch recorded behind one bookkeeping launch
+        a.step_off = (uint32_t)slot;
+        a.bigc = &c->st->big_slot[slot];
+        a.queue = &c->st->queue[slot * kQueues * kQueueStride];
+    }
     const bool learned = a.mlp != nullptr && c->cfg.molecule != DSMC_MAXWELL;
     L.mark(learned ? "collide_learned" : "collide");
     if (D == 0 && c->cfg.schedule == DSMC_SCHEDULE_PERSISTENT) {
@@ -384,30 +393,38 @@ void walled_setup(dsmc_ctx *c, bool initial) {
     }
 }
 
+// Step k of a batch of nsteps consecutive steps.  Homogeneous runs put one
+// bookkeeping launch in front of every kStepSlots steps; walled runs keep
+// their bookkeeping in the scan.
 template <typename R, bool VR>
-void enqueue_step_t(dsmc_ctx *c, Launcher &L, int src) {
+void enqueue_step_t(dsmc_ctx *c, Launcher &L, int src, int k, int nsteps) {
     if (c->cfg.dims == 0) {
-        L.mark("begin_step");
-        hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(64), 0, L.s, c->st);
-        launch_collide<R, VR, 0>(c, L, src);
+        if (k % kStepSlots == 0) {
+            L.mark("begin_step");
+            hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(64), 0, L.s, c->st, std::min(kStepSlots, nsteps - k));
+        }
+        launch_collide<R, VR, 0>(c, L, src, k % kStepSlots);
         return;
     }
     if (c->cfg.dims == 1) {
         launch_stream<R, 1, VR>(c, L, src);
-        launch_collide<R, VR, 1>(c, L, src);
+        launch_collide<R, VR, 1>(c, L, src, 0);
     } else {
         launch_stream<R, 2, VR>(c, L, src);
-        launch_collide<R, VR, 2>(c, L, src);
+        launch_collide<R, VR, 2>(c, L, src, 0);
     }
 }
 
-// Enqueue one step reading buffer `src`; returns the buffer holding the result.
-int enqueue_step(dsmc_ctx *c, Launcher &L, int src) {
+// Enqueue step k of a batch of nsteps reading buffer `src`; returns the
+// buffer holding the result.
+int enqueue_step(dsmc_ctx *c, Launcher &L, int src, int k = 0, int nsteps = 1) {
     const bool vr = c->cfg.vr != 0;
     if (c->cfg.real_bytes == 4) {
-        if (vr) enqueue_step_t<float, true>(c, L, src); else enqueue_step_t<float, false>(c, L, src);
+        if (vr) enqueue_step_t<float, true>(c, L, src, k, nsteps);
+        else enqueue_step_t<float, false>(c, L, src, k, nsteps);
     } else {
-        if (vr) enqueue_step_t<double, true>(c, L, src); else enqueue_step_t<double, false>(c, L, src);
+        if (vr) enqueue_step_t<double, true>(c, L, src, k, nsteps);
+        else enqueue_step_t<double, false>(c, L, src, k, nsteps);
     }
     return c->cfg.dims == 0 ? src : src ^ 1;
 }
@@ -417,7 +434,7 @@ dsmc_status record_graph(dsmc_ctx *c, int src, int steps, hipGraphExec_t *out) {
     HIP_TRY(hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
     Launcher L{c->capture, nullptr, nullptr};
     int b = src;
-    for (int k = 0; k < steps; ++k) b = enqueue_step(c, L, b);
+    for (int k = 0; k < steps; ++k) b = enqueue_step(c, L, b, k, steps);
     hipError_t e = hipStreamEndCapture(c->capture, &g);
     if (e != hipSuccess) return DSMC_EHIP;
     e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);

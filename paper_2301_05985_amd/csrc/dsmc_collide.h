@@ -50,6 +50,9 @@ struct CollideArgs {
     unsigned long long *counters;  // [ncell][2] candidates, accepted
     DevState *st;
     uint32_t *big_list;            // cells too large for the LDS kernel
+    unsigned int *bigc;            // their count (the step's slot for homogeneous runs)
+    unsigned int *queue;           // persistent kernel: the step's work-unit queues
+    uint32_t step_off;             // homogeneous runs: step within the recorded batch
     uint32_t *perm_g, *owner_g;    // [n] scratch of the global-memory kernel
     // learned majorant
     const float *mlp;              // [4673] FP32 weights or null

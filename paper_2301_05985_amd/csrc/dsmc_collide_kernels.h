@@ -263,12 +263,12 @@ __device__ __forceinline__ void collide_lds_body(const CollideArgs<R> &a, unsign
     const uint32_t N = a.start[cell + 1] - base;
     if (N > (uint32_t)a.cap) {
         if (lane == 0) {
-            const uint32_t q = atomicAdd(&a.st->big_count, 1u);
+            const uint32_t q = atomicAdd(a.bigc, 1u);
             a.big_list[q] = cell;
         }
         return;
     }
-    const uint32_t step = (uint32_t)a.st->step_cur;
+    const uint32_t step = (uint32_t)(a.st->step_cur + a.step_off);
     const CellPrefetch pf = prefetch_cell<R, VR, true>(a, cell);
     const int cap = a.cap;
     Vel4<R> *vel = (Vel4<R> *)smem;
@@ -311,8 +311,8 @@ __device__ __forceinline__ void collide_lds_body(const CollideArgs<R> &a, unsign
 template <typename R, bool VR, int D, bool LEARNED>
 __device__ __forceinline__ void collide_big_body(const CollideArgs<R> &a) {
     const int lane = lane_id();
-    const uint32_t step = (uint32_t)a.st->step_cur;
-    const uint32_t nbig = a.st->big_count;
+    const uint32_t step = (uint32_t)(a.st->step_cur + a.step_off);
+    const uint32_t nbig = *a.bigc;
     for (uint32_t q = blockIdx.x; q < nbig; q += gridDim.x) {
         const uint32_t cell = a.big_list[q];
         const uint32_t base = a.start[cell];
@@ -354,12 +354,12 @@ __device__ __forceinline__ void collide_wide_body(const CollideArgs<R> &a, unsig
     const uint32_t N = a.start[cell + 1] - base;
     if (N > (uint32_t)a.cap) {
         if (tid == 0) {
-            const uint32_t q = atomicAdd(&a.st->big_count, 1u);
+            const uint32_t q = atomicAdd(a.bigc, 1u);
             a.big_list[q] = cell;
         }
         return;
     }
-    const uint32_t step = (uint32_t)a.st->step_cur;
+    const uint32_t step = (uint32_t)(a.st->step_cur + a.step_off);
     const CellPrefetch pf = prefetch_cell<R, VR, false>(a, cell);
     const int cap = a.cap;
     Vel4<R> *vel = (Vel4<R> *)smem;
@@ -393,8 +393,8 @@ template <typename R, bool VR, bool LEARNED>
 __device__ __forceinline__ void collide_big_wide_body(const CollideArgs<R> &a) {
     constexpr int T = kWideThreads;
     __shared__ GroupScratch gs;
-    const uint32_t step = (uint32_t)a.st->step_cur;
-    const uint32_t nbig = a.st->big_count;
+    const uint32_t step = (uint32_t)(a.st->step_cur + a.step_off);
+    const uint32_t nbig = *a.bigc;
     for (uint32_t q = blockIdx.x; q < nbig; q += gridDim.x) {
         const uint32_t cell = a.big_list[q];
         const uint32_t base = a.start[cell];
@@ -467,7 +467,7 @@ __global__ __launch_bounds__(64) void k_collide_persistent(CollideArgs<R> a, con
     // blocking claim: the next unit of queue q, moving on when q is exhausted
     while (left > 0) {
         uint32_t k = 0;
-        if (lane_id() == 0) k = atomicAdd(&a.st->queue[q * kQueueStride], 1u);
+        if (lane_id() == 0) k = atomicAdd(&a.queue[q * kQueueStride], 1u);
         k = (uint32_t)__builtin_amdgcn_readfirstlane((int)k);
         u = q + k * kQueues;
         if (u < n_units) break;
@@ -478,7 +478,7 @@ __global__ __launch_bounds__(64) void k_collide_persistent(CollideArgs<R> a, con
     while (u < n_units) {
         const uint2 w = units[u];
         uint32_t pending = 0;
-        if (lane_id() == 0) pending = atomicAdd(&a.st->queue[q * kQueueStride], 1u);
+        if (lane_id() == 0) pending = atomicAdd(&a.queue[q * kQueueStride], 1u);
         for (uint32_t k = 0; k < w.y; ++k) {
             collide_lds_body<R, VR, 0, LEARNED>(a, smem, a.sched[w.x + k]);
             __syncthreads();
@@ -490,7 +490,7 @@ __global__ __launch_bounds__(64) void k_collide_persistent(CollideArgs<R> a, con
         u = n_units;
         while (left > 0) {
             uint32_t k = 0;
-            if (lane_id() == 0) k = atomicAdd(&a.st->queue[q * kQueueStride], 1u);
+            if (lane_id() == 0) k = atomicAdd(&a.queue[q * kQueueStride], 1u);
             k = (uint32_t)__builtin_amdgcn_readfirstlane((int)k);
             u = q + k * kQueues;
             if (u < n_units) break;

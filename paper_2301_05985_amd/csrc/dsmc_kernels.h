@@ -27,21 +27,26 @@ constexpr int kDiagPerStripe = 8;
 // that the queue atomics of one step spread over eight addresses.
 constexpr int kQueues = 8;
 constexpr int kQueueStride = 32;
+constexpr int kStepSlots = 8;
 
 struct DevState {
     unsigned long long step_next;   // index of the next step to stream
     unsigned long long step_cur;    // index of the step being collided
     unsigned long long n_samples;   // sampled steps since the last reset
     unsigned int error;             // first device error (positive code), 0 = none
-    unsigned int big_count;         // cells queued for the global-memory collision kernel
+    unsigned int big_count;         // walled runs: cells queued for the global-memory collision kernel
     unsigned int far_count;         // entries of this step's overflow mover list
     unsigned int wall_count;        // entries of this step's wall list
     unsigned int pad0;
     unsigned long long pad[3];
     unsigned long long diag[kDiagStripes * kDiagPerStripe];
-    // work-unit queues of the persistent collision kernel, one 128-byte line
-    // each: queue q hands out the units q, q + kQueues, q + 2 kQueues, ...
-    unsigned int queue[kQueues * kQueueStride];
+    // Homogeneous runs record up to kStepSlots steps per graph with a single
+    // bookkeeping launch in front; step k of the batch uses slot k: its
+    // big-instance count and the work-unit queues of the persistent
+    // collision kernel (one 128-byte line each: queue q hands out the units
+    // q, q + kQueues, q + 2 kQueues, ...).
+    unsigned int big_slot[kStepSlots];
+    unsigned int queue[kStepSlots * kQueues * kQueueStride];
 };
 enum { kDiagOvershoot = 0, kDiagWallHits, kDiagLearned, kDiagFallback, kDiagSkip, kDiagVrNonfinite,
        kDiagBig };
@@ -657,15 +662,17 @@ __global__ __launch_bounds__(256) void k_scan_lookback(uint32_t *count, uint32_t
     }
 }
 
-// Step bookkeeping for homogeneous instances (no sort pass).
-__global__ void k_begin_step(DevState *st) {
+// Step bookkeeping for homogeneous instances (no sort pass), once for a
+// batch of nsteps <= kStepSlots steps: step k of the batch has index
+// step_cur + k and uses slot k.
+__global__ void k_begin_step(DevState *st, int nsteps) {
     if (threadIdx.x == 0) {
         st->step_cur = st->step_next;
-        st->step_next = st->step_next + 1;
-        st->n_samples = st->n_samples + 1;
-        st->big_count = 0;
+        st->step_next = st->step_next + (unsigned long long)nsteps;
+        st->n_samples = st->n_samples + (unsigned long long)nsteps;
     }
-    if (threadIdx.x < kQueues) st->queue[threadIdx.x * kQueueStride] = 0;
+    if (threadIdx.x < kStepSlots) st->big_slot[threadIdx.x] = 0;
+    if (threadIdx.x < kStepSlots * kQueues) st->queue[threadIdx.x * kQueueStride] = 0;
 }
 
 }  // namespace dsmc
