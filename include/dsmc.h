@@ -1,8 +1,8 @@
 /*
  * dsmc.h -- C ABI of the MI355X (gfx950) direct simulation Monte Carlo hot path.
  *
- * The paper filed for this project (arXiv 2301.05985) contains no Monte Carlo
- * method; the operations below follow the standard published DSMC method:
+ * The cited paper (arXiv 2301.05985) contains no Monte Carlo method; the
+ * operations below follow the standard published DSMC method:
  * Bird, "Molecular Gas Dynamics and the Direct Simulation of Gas Flows" (1994)
  * for free flight, diffuse/specular/periodic walls, cell indexing, the
  * no-time-counter (NTC) collision scheme and cell sampling; Salmon et al.
