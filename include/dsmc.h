@@ -160,7 +160,9 @@ typedef struct {
  * LDS a workgroup may hold if it has at most `cap` particles, and is collided
  * in global memory otherwise (counted in big_cells); both give the same
  * results.  With fit = floor(65472 / (4 real_bytes + 4)) rounded down to a
- * multiple of 32 (3264 in FP32, 1792 in FP64):
+ * multiple of 32 (3264 in FP32, 1792 in FP64; homogeneous runs without
+ * weights, whose owner marks share the weight slots: floor(65472 /
+ * (4 real_bytes)) rounded down, 4064 in FP32, 2016 in FP64):
  *   dims == 0:  cap = the largest instance rounded up to a multiple of 32
  *               (at least 32), at most fit;
  *   dims >= 1:  cap = 3 x (mean particles per cell) + 64 rounded up to a

@@ -576,8 +576,10 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
     // LDS capacity per cell (one wave per cell)
     // LDS per cell: velocity and weight of each particle side by side (16 B,
     // 32 B in double), owner marks (+4 padding entries; in walled runs they
-    // first hold the gather's selection)
-    const size_t per = 4 * rb + 4;
+    // first hold the gather's selection).  Homogeneous runs without weights
+    // keep the owner marks in the weight slots.
+    const bool packed = cfg->dims == 0 && !cfg->vr;
+    const size_t per = packed ? 4 * rb : 4 * rb + 4;
     const int cap_fit = (int)std::min<size_t>((kMaxLds - 64) / per, 65535) / 32 * 32;
     std::vector<uint32_t> start_host;
     std::vector<uint32_t> sched_host;

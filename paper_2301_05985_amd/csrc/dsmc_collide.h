@@ -116,8 +116,11 @@ struct alignas(16) Vel4 {
     R x, y, z, w;
 };
 
-// Cell staged in LDS (index = rank in the cell's collision order).
-template <typename R>
+// Cell staged in LDS (index = rank in the cell's collision order).  Without
+// weights (PACKED) a particle's owner mark lives in the unused weight slot
+// of its row (its first 32 bits), 16 instead of 20 bytes per particle in
+// FP32, so more cells fit in LDS at once.
+template <typename R, bool PACKED = false>
 struct LdsView {
     static constexpr bool kInLds = true;
     Vel4<R> *p;
@@ -129,9 +132,12 @@ struct LdsView {
     __device__ __forceinline__ void put(uint32_t r, R a, R b, R c) const { p[r].x = a; p[r].y = b; p[r].z = c; }
     __device__ __forceinline__ R getw(uint32_t r) const { return p[r].w; }
     __device__ __forceinline__ void putw(uint32_t r, R v) const { p[r].w = v; }
-    __device__ __forceinline__ uint32_t *own(uint32_t r) const { return &owner[r]; }
-    __device__ __forceinline__ uint32_t read_own(uint32_t r) const { return owner[r]; }
-    __device__ __forceinline__ void clear_own(uint32_t r) const { owner[r] = 0xFFFFFFFFu; }
+    __device__ __forceinline__ uint32_t *own(uint32_t r) const {
+        if constexpr (PACKED) return reinterpret_cast<uint32_t *>(&p[r].w);
+        else return &owner[r];
+    }
+    __device__ __forceinline__ uint32_t read_own(uint32_t r) const { return *own(r); }
+    __device__ __forceinline__ void clear_own(uint32_t r) const { *own(r) = 0xFFFFFFFFu; }
 };
 
 // Cell operated on in place in global memory, through a rank -> slot map.

@@ -271,8 +271,9 @@ __device__ __forceinline__ void collide_lds_body(const CollideArgs<R> &a, unsign
     const uint32_t step = (uint32_t)(a.st->step_cur + a.step_off);
     const CellPrefetch pf = prefetch_cell<R, VR, true>(a, cell);
     const int cap = a.cap;
+    constexpr bool kPacked = D == 0 && !VR;  // owner marks in the weight slots
     Vel4<R> *vel = (Vel4<R> *)smem;
-    uint32_t *owner = (uint32_t *)(vel + cap);  // cap + 4 entries
+    uint32_t *owner = kPacked ? nullptr : (uint32_t *)(vel + cap);  // cap + 4 entries
     if (D > 0) {
         gather_cell<R, VR, D>(a, cell, base, N, owner, vel);  // the owner array holds the selection
         __syncthreads();
@@ -295,9 +296,9 @@ __device__ __forceinline__ void collide_lds_body(const CollideArgs<R> &a, unsign
             }
         }
     }
-    for (uint32_t r = lane; r < N; r += 64) owner[r] = 0xFFFFFFFFu;
+    const LdsView<R, kPacked> view{vel, owner};
+    for (uint32_t r = lane; r < N; r += 64) view.clear_own(r);
     __syncthreads();
-    const LdsView<R> view{vel, owner};
     // the sampling writes the cell back and reduces its sums through the
     // cell's LDS area
     if (LEARNED) process_cell_learned<R, VR>(a, view, cell, N, step, pf, (double *)smem, base);
@@ -362,9 +363,11 @@ __device__ __forceinline__ void collide_wide_body(const CollideArgs<R> &a, unsig
     const uint32_t step = (uint32_t)(a.st->step_cur + a.step_off);
     const CellPrefetch pf = prefetch_cell<R, VR, false>(a, cell);
     const int cap = a.cap;
+    constexpr bool kPacked = !VR;  // owner marks in the weight slots
     Vel4<R> *vel = (Vel4<R> *)smem;
-    uint32_t *owner = (uint32_t *)(vel + cap);
-    GroupScratch *gs = (GroupScratch *)(owner + cap + 4);  // 16-byte aligned: cap is a multiple of 32
+    uint32_t *owner = kPacked ? nullptr : (uint32_t *)(vel + cap);
+    // 16-byte aligned: cap is a multiple of 32
+    GroupScratch *gs = kPacked ? (GroupScratch *)(vel + cap) : (GroupScratch *)(owner + cap + 4);
     for (uint32_t s0 = 0; s0 < N; s0 += 2 * T) {
         Vel4<R> t[2];
 #pragma unroll
@@ -379,11 +382,11 @@ __device__ __forceinline__ void collide_wide_body(const CollideArgs<R> &a, unsig
             if (s < N) vel[s] = t[j];
         }
     }
-    for (uint32_t r = tid; r < N; r += T) owner[r] = 0xFFFFFFFFu;
+    const LdsView<R, kPacked> view{vel, owner};
+    for (uint32_t r = tid; r < N; r += T) view.clear_own(r);
     __syncthreads();
-    const LdsView<R> view{vel, owner};
-    if (LEARNED) process_cell_learned<R, VR, LdsView<R>, T>(a, view, cell, N, step, pf, nullptr, base, gs);
-    else process_cell<R, VR, LdsView<R>, T>(a, view, cell, N, step, pf, nullptr, base, gs);
+    if (LEARNED) process_cell_learned<R, VR, LdsView<R, kPacked>, T>(a, view, cell, N, step, pf, nullptr, base, gs);
+    else process_cell<R, VR, LdsView<R, kPacked>, T>(a, view, cell, N, step, pf, nullptr, base, gs);
 }
 
 // Homogeneous instances above the LDS capacity: one kWideThreads workgroup

@@ -126,16 +126,18 @@ def test_one_and_two_particles(gpu, n):
     _check(g, sums, cnt, seq, d, orc)
 
 
-def _lds_fit(real):
+def _lds_fit(real, packed=False):
     # the largest multiple of 32 particles whose LDS staging fits 64 KiB
-    return (65472 // (4 * (8 if real == "f64" else 4) + 4)) // 32 * 32
+    # (homogeneous runs without weights keep no separate owner array)
+    rb = 8 if real == "f64" else 4
+    return (65472 // (4 * rb + (0 if packed else 4))) // 32 * 32
 
 
 @pytest.mark.parametrize("real", ["f64", "f32"])
 def test_instances_at_lds_capacity_and_one_above(gpu, real):
     # the largest instance that is staged in LDS and the smallest one that
     # is not (global-memory kernel), side by side
-    cap = _lds_fit(real)
+    cap = _lds_fit(real, packed=True)
     _announce("instances at capacity %s (%d)" % (real, cap))
     counts = [cap, cap + 1, 50]
     off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
