@@ -116,6 +116,22 @@ def test_homogeneous_bit_exact(gpu, real):
     _compare(g, orc, exact=True)
 
 
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_homogeneous_random_sizes_bit_exact(gpu, seed):
+    # random instance sizes (empty, single, one-wave, four-wave and, in
+    # FP64, above the LDS capacity), several graph replays, both precisions
+    _announce("homogeneous random sizes seed=%d" % seed)
+    rng = np.random.default_rng(100 + seed)
+    counts = list(rng.integers(0, 1400, size=14)) + [0, 1, 2, 2100]
+    rng.shuffle(counts)
+    p, parts = _homog([int(k) for k in counts], seed=seed, dt=0.1)
+    p["sigma"] = 0.004
+    for real in ("f32", "f64"):
+        g, orc = _run(gpu, p, parts, 9, real, chunks=2)
+        assert orc.counters[:, 1].sum() > 100
+        _compare(g, orc, exact=True)
+
+
 def test_homogeneous_maxwell_bit_exact(gpu):
     _announce("homogeneous maxwell f64")
     p, parts = _homog([2, 40, 300, 900], molecule=W.MAXWELL, dt=0.1)
