@@ -145,7 +145,7 @@ def main():
     ap.add_argument("--kn", type=float, default=0.01)
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 512 MiB device-to-device copy (reference for HBM byte counters)")
