@@ -50,8 +50,7 @@ def test_fourier_conductivity_matches_chapman_enskog(gpu):
     ratio = k0_meas / (k0_ce * corr)
     print("[gpu case] conductivity ratio %.4f (cell correction %.4f, q %.1f)" % (ratio, corr, qm), flush=True)
     assert qm < 0.0  # heat flows from the hot wall (x = 1) to the cold one
-    # measured 0.972 +- 0.011 over seeds, precisions and time steps (slow
-    # thermal modes make single runs scatter); fewer particles per cell give
-    # less (0.93 at 30), more give more (0.98 at 400): the bound is a 5%
-    # check of the law, not a convergence study
+    # about 0.98 over seeds, 25-400 particles per cell, precisions and time
+    # steps (slow thermal modes make single runs scatter by 0.4-2%): the
+    # bound is a 5% check of the law, not a convergence study
     assert abs(ratio - 1.0) < 0.05
