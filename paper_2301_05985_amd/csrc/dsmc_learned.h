@@ -210,35 +210,22 @@ __device__ double learned_majorant(const CollideArgs<R> &a, const View &v, uint3
     }
     bool ok = !overflow;
     if (ok && ns >= 2) {
-        // every wave holds all members (lane s: member s); wave w compares
-        // the pairs (l, b) with l < b, b = w, w + T/64, ...
+        // every wave holds all members (lane s: member s)
         R x = 0, yv = 0, z = 0;
         if ((uint32_t)lane < ns) v.get(mine, x, yv, z);
         const double gp2 = gp * gp;
         bool bad = false;
-        if constexpr (T == 64) {
-            // one wave: lane l compares its member with member (l + d) mod ns,
-            // d = 1 .. ns/2, which covers every pair in half the rounds
-            for (uint32_t d = 1; d <= ns / 2; ++d) {
-                uint32_t q = (uint32_t)lane + d;
-                q = q >= ns ? q - ns : q;
-                const R bx = __shfl(x, (int)q, 64), by = __shfl(yv, (int)q, 64), bz = __shfl(z, (int)q, 64);
-                if ((uint32_t)lane < ns) {
-                    const double dx = (double)x - (double)bx, dy = (double)yv - (double)by,
-                                 dz = (double)z - (double)bz;
-                    const double g2 = (dx * dx + dy * dy) + dz * dz;
-                    if (g2 > gp2) bad = true;
-                }
-            }
-        } else {
-            for (uint32_t b = threadIdx.x >> 6; b < ns; b += T / 64) {
-                const R bx = __shfl(x, b, 64), by = __shfl(yv, b, 64), bz = __shfl(z, b, 64);
-                if ((uint32_t)lane < ns && b > (uint32_t)lane) {
-                    const double dx = (double)x - (double)bx, dy = (double)yv - (double)by,
-                                 dz = (double)z - (double)bz;
-                    const double g2 = (dx * dx + dy * dy) + dz * dz;
-                    if (g2 > gp2) bad = true;
-                }
+        // lane l compares its member with member (l + d) mod ns for
+        // d = 1 .. ns/2, which covers every pair in half the rounds of the
+        // triangle; wave w takes d = 1 + w, 1 + w + T/64, ...
+        for (uint32_t d = 1 + (threadIdx.x >> 6); d <= ns / 2; d += T / 64) {
+            uint32_t q = (uint32_t)lane + d;
+            q = q >= ns ? q - ns : q;
+            const R bx = __shfl(x, (int)q, 64), by = __shfl(yv, (int)q, 64), bz = __shfl(z, (int)q, 64);
+            if ((uint32_t)lane < ns) {
+                const double dx = (double)x - (double)bx, dy = (double)yv - (double)by, dz = (double)z - (double)bz;
+                const double g2 = (dx * dx + dy * dy) + dz * dz;
+                if (g2 > gp2) bad = true;
             }
         }
         uint32_t nbad = __ballot(bad) != 0ull ? 1u : 0u;
