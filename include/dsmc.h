@@ -222,8 +222,13 @@ dsmc_status dsmc_set_step(dsmc_ctx *ctx, uint64_t next_step);
  * output is log2 of the predicted largest relative speed of the cell, and the
  * proposal is the lattice value 2^(k/64), k = ceil(64 (y + delta)).  The
  * proposal is used only where the kernel proves it bounds every pair of the
- * cell; elsewhere the exact bound is used, so results keep the law of the
- * exact method.  EINVAL if n is wrong or cfg->majorant is not LEARNED. */
+ * cell (every pair speed at most 2^(k/64) (1 - eps), eps = 2^-20 in FP32,
+ * 2^-50 in FP64); elsewhere the exact bound is used, so results keep the law
+ * of the exact method.  Under either majorant a pair that an earlier collision
+ * of the same step made faster than the cell's majorant is accepted with
+ * probability 1 instead of g / g_max (counted in dsmc_diag.overshoot; the
+ * tighter learned majorant has a somewhat higher count).  EINVAL if n is
+ * wrong or cfg->majorant is not LEARNED. */
 dsmc_status dsmc_set_majorant_model(dsmc_ctx *ctx, const uint16_t *bf16_weights_host, int64_t n,
                                     double delta);
 

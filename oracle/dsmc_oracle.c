@@ -485,9 +485,9 @@ static double lattice_value(int64_t k) { return exp2((double)k / 64.0); }
 
 /* Learned majorant with exact verification (project design).  The proposal
  * is used only when it is below the exact bound and provably bounds every
- * pair: pairs whose speed can exceed g_pred both lie in
- * S = {p : r_p + r_(1) > g_pred}; if |S| > 64 the proposal is rejected,
- * otherwise all pairs of S are checked by brute force.  Otherwise the exact
+ * pair: with g_v = g_pred (1 - eps), pairs whose speed can exceed g_v both lie
+ * in S = {p : r_p + r_(1) > g_v}; if |S| > 64 the proposal is rejected,
+ * otherwise all pairs of S are checked by brute force against g_v.  Otherwise the exact
  * bound is used.  Returns the majorant; *used = 1 learned, 0 skip, -1 fallback. */
 double FN(orc_learned_majorant)(const orc_cfg *cfg, const REAL *cx, const REAL *cy, const REAL *cz,
                                 const int64_t *list, int64_t n, double V, int *used)
@@ -518,27 +518,31 @@ double FN(orc_learned_majorant)(const orc_cfg *cfg, const REAL *cx, const REAL *
         r[a] = sqrt((dx * dx + dy * dy) + dz * dz);
         if (r[a] > r1) r1 = r[a];
     }
+    /* verification threshold: the proposal less the exact bound's rounding
+     * margin, so that a verified pair stays below the proposal also after
+     * both are rounded to the working precision of the acceptance test */
+    double eps = IS_F32 ? 9.5367431640625e-07 /* 2^-20 */ : 8.8817841970012523e-16 /* 2^-50 */;
+    double gv = gp * (1.0 - eps);
     int64_t S[64];
     int64_t ns = 0;
     int ok = 1;
     for (int64_t a = 0; a < n; ++a) {
-        if (r[a] + r1 > gp) {
+        if (r[a] + r1 > gv) {
             if (ns == 64) { ok = 0; break; }
             S[ns++] = list ? list[a] : a;
         }
     }
     free(r);
     if (ok) {
-        /* every pair with speed above g_pred lies inside S; compare in the
-         * working precision of the acceptance test, against g_pred^2 */
-        double gp2 = gp * gp;
+        /* every pair with speed above g_v lies inside S; compare against g_v^2 */
+        double gv2 = gv * gv;
         for (int64_t a = 0; a < ns && ok; ++a)
             for (int64_t b = a + 1; b < ns; ++b) {
                 double dx = (double)cx[S[a]] - (double)cx[S[b]];
                 double dy = (double)cy[S[a]] - (double)cy[S[b]];
                 double dz = (double)cz[S[a]] - (double)cz[S[b]];
                 double g2 = (dx * dx + dy * dy) + dz * dz;
-                if (g2 > gp2) { ok = 0; break; }
+                if (g2 > gv2) { ok = 0; break; }
             }
     }
     if (!ok) { *used = -1; return gb; }

@@ -4,12 +4,15 @@
 // FP32 arithmetic) predicts log2 of the largest relative speed in a cell from
 // six moments of its pre-collision state.  The proposal is rounded up to the
 // lattice 2^(k/64) and used only if (a) it is below the exact bound and
-// (b) the kernel proves that it bounds every pair: a pair faster than g_pred
-// has both members in S = {p : r_p + r_(1) > g_pred} (r_p = distance to the
-// bounding-box midpoint), so if |S| <= 64 all pairs of S are compared with
-// g_pred in double; otherwise, or if a pair exceeds it, the exact bound is
-// used.  The decision depends only on the pre-collision state, so the
-// collision law is that of the exact method.
+// (b) the kernel proves that it bounds every pair: with g_v = g_pred (1 - eps)
+// (eps the exact bound's rounding margin), a pair faster than g_v has both
+// members in S = {p : r_p + r_(1) > g_v} (r_p = distance to the bounding-box
+// midpoint), so if |S| <= 64 all pairs of S are compared with g_v in double;
+// otherwise, or if a pair exceeds it, the exact bound is used.  The decision
+// depends only on the pre-collision state, so the collision law is that of
+// the exact method (both majorants bound the pre-collision pairs; a pair made
+// faster than the majorant by an earlier collision of the same step has its
+// acceptance truncated at 1 under either, and is counted as an overshoot).
 //
 // One wave per cell; hidden unit h of both layers lives on lane h, the
 // output is reduced by the butterfly with strides 32..1 (a fixed order, so
@@ -160,12 +163,17 @@ __device__ double learned_majorant(const CollideArgs<R> &a, const View &v, uint3
         __syncthreads();  // the scratch is reused
     }
     if (!(gp < gb)) { used = 0; return gb; }
+    // verified against gp (1 - eps), eps the exact bound's rounding margin:
+    // a pair that passes then stays below the proposal also after the
+    // proposal and the pair's squared speed are rounded to the working
+    // precision of the acceptance test
+    const double gv = gp * (1.0 - (sizeof(R) == 4 ? 0x1.0p-20 : 0x1.0p-50));
     const double m0 = mid[0], m1 = mid[1], m2 = mid[2];
     const auto in_s = [&](uint32_t r) {
         R x, yv, z;
         v.get(r, x, yv, z);
         const double dx = (double)x - m0, dy = (double)yv - m1, dz = (double)z - m2;
-        return sqrt((dx * dx + dy * dy) + dz * dz) + r1 > gp;
+        return sqrt((dx * dx + dy * dy) + dz * dz) + r1 > gv;
     };
     uint32_t mine = 0xFFFFFFFFu;  // rank of the member held by this lane
     uint32_t ns = 0;
@@ -213,7 +221,7 @@ __device__ double learned_majorant(const CollideArgs<R> &a, const View &v, uint3
         // every wave holds all members (lane s: member s)
         R x = 0, yv = 0, z = 0;
         if ((uint32_t)lane < ns) v.get(mine, x, yv, z);
-        const double gp2 = gp * gp;
+        const double gv2 = gv * gv;
         bool bad = false;
         // lane l compares its member with member (l + d) mod ns for
         // d = 1 .. ns/2, which covers every pair in half the rounds of the
@@ -225,7 +233,7 @@ __device__ double learned_majorant(const CollideArgs<R> &a, const View &v, uint3
             if ((uint32_t)lane < ns) {
                 const double dx = (double)x - (double)bx, dy = (double)yv - (double)by, dz = (double)z - (double)bz;
                 const double g2 = (dx * dx + dy * dy) + dz * dz;
-                if (g2 > gp2) bad = true;
+                if (g2 > gv2) bad = true;
             }
         }
         uint32_t nbad = __ballot(bad) != 0ull ? 1u : 0u;

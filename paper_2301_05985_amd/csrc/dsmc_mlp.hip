@@ -198,10 +198,10 @@ dsmc_status dsmc_mlp_loss_grad(const float *params, const float *x, const float 
                                float *grad, float *loss, float *scratch, void *stream) {
     if (!params || !x || !label || !grad || !loss || !scratch || n <= 0 || !(tau > 0.0 && tau < 1.0))
         return DSMC_EINVAL;
+    if ((n + kChunk - 1) / kChunk > 65535) return DSMC_EINVAL;  // chunks are a grid dimension
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(k_mlp_backward, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, params, x, label, n,
                        (float)tau, scratch);
-    if ((n + kChunk - 1) / kChunk > 65535) return DSMC_EINVAL;  // chunks are a grid dimension
     const int nchunk = (int)((n + kChunk - 1) / kChunk);
     double *part = (double *)(scratch + n * kPerSample);  // kPerSample is even: 8-byte aligned
     hipLaunchKernelGGL(k_mlp_partial, dim3((unsigned)((kNq + 255) / 256), (unsigned)nchunk), dim3(256), 0, s, x, n,

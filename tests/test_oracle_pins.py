@@ -142,6 +142,81 @@ def test_exact_bound_is_order_independent():
     assert oracle.exact_bound(*c) == oracle.exact_bound(*c[:, o])
 
 
+def _random_cells(rng, trials):
+    """Random velocity sets, some with repeated velocities and some tiny."""
+    for t in range(trials):
+        n = int(rng.choice([0, 1, 2, 3, int(rng.integers(4, 90))]))
+        c = rng.standard_normal((3, n)) * rng.uniform(0.2, 2.5) + rng.standard_normal((3, 1))
+        if n >= 4 and t % 3 == 0:
+            # duplicated particles (same velocity twice or more)
+            k = int(rng.integers(1, n // 2 + 1))
+            c[:, n - k:] = c[:, :k]
+        yield c
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_diameter_is_the_largest_pairwise_distance(dtype):
+    # brute force by scipy's pairwise distances (a library routine, in a
+    # different summation and root order) over random cells with duplicates
+    from scipy.spatial.distance import pdist
+    rng = np.random.default_rng(21)
+    for c in _random_cells(rng, 300):
+        cw = c.astype(dtype)
+        d = oracle.diameter(*cw, dtype=dtype)
+        n = c.shape[1]
+        if n < 2:
+            assert d == 0.0
+            continue
+        ref = pdist(cw.T.astype(np.float64)).max()
+        assert abs(d - ref) <= 1e-15 * max(ref, 1e-300), (n, d, ref)
+        # the value is attained by some pair (not a bound)
+        assert d <= ref * (1 + 1e-15)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_features_are_the_cell_moments(dtype):
+    # the six network inputs recomputed from their definitions with numpy's
+    # mean, variance and covariance routines: log2 of the number density,
+    # mean velocity over sqrt(T), log2 T (T = the mean of the three velocity
+    # variances), P_xx / p - 1 and P_xy / p with p = n T
+    rng = np.random.default_rng(22)
+    for c in _random_cells(rng, 300):
+        n = c.shape[1]
+        if n < 2:
+            continue
+        cw = c.astype(dtype)
+        FNum, V = float(rng.uniform(0.5, 40.0)), float(rng.uniform(0.01, 3.0))
+        f = oracle.features(*cw, FNum, V, dtype=dtype).astype(np.float64)
+        v = cw.astype(np.float64)
+        u = v.mean(axis=1)
+        var = v.var(axis=1)                 # population variances
+        T = var.mean()
+        if not T > 1e-12:
+            continue                        # all velocities equal
+        dens = n * FNum / V
+        cov_xy = np.cov(v[0], v[1], bias=True)[0, 1]
+        ref = np.array([math.log2(dens), u[0] / math.sqrt(T), u[1] / math.sqrt(T), math.log2(T),
+                        var[0] / T - 1.0, cov_xy / T])
+        # features are FP64 values rounded once to float: agreement to float
+        # rounding plus the FP64 cancellation of the moment differences
+        scale = 1.0 + np.abs(v).max() ** 2 / T
+        tol = 2.0 ** -23 * np.abs(ref) + 1e-13 * scale
+        assert (np.abs(f - ref) <= tol).all(), (n, f, ref)
+
+
+def test_features_pin_detects_planted_slips():
+    # the pin's reference distinguishes the plausible slips (P_xy over the
+    # pressure instead of p = n T, a natural logarithm, a missing -1)
+    rng = np.random.default_rng(23)
+    c = rng.standard_normal((3, 50)) * 1.3 + np.array([[0.4], [-0.2], [0.1]])
+    f = oracle.features(*c, 2.0, 0.5).astype(np.float64)
+    T = c.var(axis=1).mean()
+    pxy = np.cov(c[0], c[1], bias=True)[0, 1]
+    assert abs(f[5] - pxy / T) < 1e-6 and abs(f[5] - pxy / (T * 100 * 2.0 / 0.5)) > 1e-3
+    assert abs(f[3] - math.log2(T)) < 1e-6 and abs(f[3] - math.log(T)) > 1e-3
+    assert abs(f[4] - (c[0].var() / T - 1.0)) < 1e-6 and abs(f[4] - c[0].var() / T) > 0.5
+
+
 # ------------------------------------------------------- variance reduction
 def test_vr_update_martingale_and_equilibrium_invariance():
     rng = np.random.default_rng(11)
