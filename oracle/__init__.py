@@ -66,6 +66,9 @@ class OrcCfg(ctypes.Structure):
         ("n_only", ctypes.c_int64),
         ("omega", ctypes.c_double),
         ("alpha", ctypes.c_double),
+        ("vr_reconstruct", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+        ("vr_kappa", ctypes.c_double),
     ]
 
 
@@ -124,6 +127,9 @@ def lib():
             g = getattr(_lib, "orc_features" + sfx)
             g.restype = None
             g.argtypes = [P, P, P, P, ctypes.c_int64, ctypes.c_double, ctypes.c_double, P]
+            g = getattr(_lib, "orc_vr_reconstruct" + sfx)
+            g.restype = ctypes.c_int
+            g.argtypes = [P, P, P, P, P, ctypes.c_int64, ctypes.c_double]
             g = getattr(_lib, "orc_cell_of" + sfx)
             g.restype = ctypes.c_int64
             if sfx == "_f64":
@@ -181,6 +187,8 @@ def make_cfg(p):
     c.mlp_delta = p.get("mlp_delta", 0.0)
     c.omega = float(p.get("omega", 0.5))
     c.alpha = float(p.get("alpha", 1.0))
+    c.vr_reconstruct = int(p.get("vr_reconstruct", 0))
+    c.vr_kappa = float(p.get("vr_kappa", 1.0))
     return c
 
 
@@ -362,6 +370,15 @@ def features(cx, cy, cz, FNum, V, dtype=np.float64):
     getattr(lib(), "orc_features" + _sfx(dtype))(_ptr(cx), _ptr(cy), _ptr(cz), None, len(cx),
                                                  FNum, V, _ptr(out))
     return out
+
+
+def vr_reconstruct(cx, cy, cz, w, T0, dtype=np.float64):
+    """Re-estimated weights of one cell (returns (new weights, replaced?))."""
+    cx, cy, cz = (np.ascontiguousarray(a, dtype=dtype) for a in (cx, cy, cz))
+    ww = np.ascontiguousarray(w, dtype=dtype).copy()
+    ok = getattr(lib(), "orc_vr_reconstruct" + _sfx(dtype))(_ptr(cx), _ptr(cy), _ptr(cz), _ptr(ww), None,
+                                                            len(cx), float(T0))
+    return ww, bool(ok)
 
 
 def cell_of(params, x, y, dtype=np.float64):

@@ -125,6 +125,9 @@ typedef struct {
     int64_t n_only;                     /* ... (sorted ascending, n_only of them) */
     double omega;                       /* molecules 2 (VHS), 3 (VSS): viscosity index in [0.5, 1] */
     double alpha;                       /* molecule 3 (VSS): scattering exponent in [1, 2] */
+    int32_t vr_reconstruct;             /* K > 0: re-estimate the weights in steps s with s mod K == 0 */
+    int32_t pad_;
+    double vr_kappa;                    /* weighted runs: majorant factor (>= 1; 0 is read as 1) */
 } orc_cfg;
 
 typedef struct {
@@ -698,6 +701,7 @@ static int collide_cell(const orc_cfg *cfg, soa_t *s, const int64_t *list, int64
     } else {
         gmax = FN(orc_exact_bound)(s->cx, s->cy, s->cz, list, n);
     }
+    if (cfg->vr && cfg->vr_kappa > 1.0 && cfg->molecule != 1) gmax = gmax * cfg->vr_kappa;
     double Mreal;
     if (cfg->molecule == 1)
         Mreal = (((((0.5 * (double)n) * (double)(n - 1)) * cfg->FN) * cfg->sigma) * cfg->dt) / V;
@@ -761,6 +765,84 @@ static int collide_cell(const orc_cfg *cfg, soa_t *s, const int64_t *list, int64
     cnt[0] += (uint64_t)M;
     cnt[1] += acc_count;
     return 0;
+}
+
+/* ------------------------------------------------ weight re-estimation */
+/* Re-estimation of the importance weights of one cell (project reading of the
+ * reconstruction step of Al-Mohssen & Hadjiconstantinou 2010; the weights
+ * W ~ f_eq / f carry, besides that smooth ratio, a per-particle noise that
+ * the collision update amplifies).  The deviations d_i = W_i - 1 are replaced
+ * by their least-squares projection onto the 13 functions of the velocity
+ * whose sums the cell samples, taken of v = c / sqrt(T0):
+ *   phi(v) = (1, v_x, v_y, v_z, v_x^2, v_y^2, v_z^2, v_x v_y, v_x v_z, v_y v_z,
+ *             v_x |v|^2, v_y |v|^2, v_z |v|^2),
+ * i.e. d'_i = phi(v_i) . a with G a = b, G = sum_i phi(v_i) phi(v_i)^T and
+ * b = sum_i d_i phi(v_i).  Then sum_i d'_i phi_k(v_i) = b_k: every sampled
+ * weighted moment of the cell is unchanged, and d = 0 gives d' = 0 exactly
+ * (unit weights stay exactly 1).  G is factorised by Cholesky (G = L L^T) and
+ * the two triangular systems are solved in order; a cell with fewer than 26
+ * particles, or with a pivot not above 1e-12 times its diagonal entry of G,
+ * keeps its weights.  All in double; W'_i = 1 + d'_i rounded to REAL.
+ * Returns 1 if the weights were replaced. */
+#define NRB 13
+static void recon_basis(double vx, double vy, double vz, double phi[NRB])
+{
+    double v2 = (vx * vx + vy * vy) + vz * vz;
+    phi[0] = 1.0; phi[1] = vx; phi[2] = vy; phi[3] = vz;
+    phi[4] = vx * vx; phi[5] = vy * vy; phi[6] = vz * vz;
+    phi[7] = vx * vy; phi[8] = vx * vz; phi[9] = vy * vz;
+    phi[10] = vx * v2; phi[11] = vy * v2; phi[12] = vz * v2;
+}
+
+int FN(orc_vr_reconstruct)(const REAL *cx, const REAL *cy, const REAL *cz, REAL *w, const int64_t *list,
+                           int64_t n, double T0)
+{
+    if (n < 2 * NRB) return 0;
+    double G[NRB][NRB], b[NRB], L[NRB][NRB], a[NRB], y[NRB], phi[NRB];
+    memset(G, 0, sizeof(G));
+    memset(b, 0, sizeof(b));
+    memset(L, 0, sizeof(L));
+    double sc = 1.0 / sqrt(T0);
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t p = list ? list[q] : q;
+        recon_basis((double)cx[p] * sc, (double)cy[p] * sc, (double)cz[p] * sc, phi);
+        double d = (double)w[p] - 1.0;
+        for (int k = 0; k < NRB; ++k) {
+            b[k] += d * phi[k];
+            for (int l = 0; l <= k; ++l) G[k][l] += phi[k] * phi[l];
+        }
+    }
+    /* Cholesky, column by column */
+    for (int k = 0; k < NRB; ++k) {
+        double piv = G[k][k];
+        for (int j = 0; j < k; ++j) piv -= L[k][j] * L[k][j];
+        if (!(piv > 1e-12 * G[k][k])) return 0;
+        L[k][k] = sqrt(piv);
+        for (int i = k + 1; i < NRB; ++i) {
+            double t = G[i][k];
+            for (int j = 0; j < k; ++j) t -= L[i][j] * L[k][j];
+            L[i][k] = t / L[k][k];
+        }
+    }
+    /* L y = b, then L^T a = y */
+    for (int k = 0; k < NRB; ++k) {
+        double t = b[k];
+        for (int j = 0; j < k; ++j) t -= L[k][j] * y[j];
+        y[k] = t / L[k][k];
+    }
+    for (int k = NRB - 1; k >= 0; --k) {
+        double t = y[k];
+        for (int j = k + 1; j < NRB; ++j) t -= L[j][k] * a[j];
+        a[k] = t / L[k][k];
+    }
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t p = list ? list[q] : q;
+        recon_basis((double)cx[p] * sc, (double)cy[p] * sc, (double)cz[p] * sc, phi);
+        double d = 0.0;
+        for (int k = 0; k < NRB; ++k) d += a[k] * phi[k];
+        w[p] = (REAL)(1.0 + d);
+    }
+    return 1;
 }
 
 /* Cell sampling (Bird 1994): raw FP64 sums S0 = N, S1 = sum c (3),
@@ -836,7 +918,7 @@ void FN(orc_initial_layout)(const orc_cfg *cfg, int64_t np, const REAL *x, const
 /* Run nsteps time steps starting at step index step0.  Particle arrays are
  * modified in place (storage order is never changed).  sums[n_cells][26] and
  * counters[n_cells][2] (candidates, accepted) are accumulated.  Per step:
- * stream -> group -> collide -> sample.
+ * stream -> group -> collide -> (re-estimate the weights) -> sample.
  *
  * Walled runs (dims 1, 2) carry the particle sequence layout[0..np-1]
  * (indices into the arrays) from step to step: after streaming, the new
@@ -883,6 +965,8 @@ int FN(orc_run)(const orc_cfg *cfg, int64_t np, REAL *x, REAL *y, REAL *cx, REAL
             uint32_t key_id = (cfg->dims == 0 && cfg->cell_ids) ? (uint32_t)cfg->cell_ids[c] : (uint32_t)c;
             rc = collide_cell(cfg, &s, list + start[c], n, key_id, step, V, &counters[2 * c], diag, &lf);
             if (learned_log) learned_log[(int64_t)si * ncell + c] = lf;
+            if (rc == 0 && cfg->vr && cfg->vr_reconstruct > 0 && step % (uint32_t)cfg->vr_reconstruct == 0)
+                FN(orc_vr_reconstruct)(cx, cy, cz, w, list + start[c], n, cfg->vr_T0);
             if (rc == 0) {
                 rc = sample_cell(cfg, &s, list + start[c], n, &sums[NSUM * c]);
                 if (rc == 1) { diag->vr_nonfinite++; rc = 0; }
