@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define DSMC_ABI_VERSION 4
+#define DSMC_ABI_VERSION 5
 #define DSMC_NSUM 26          /* FP64 running sums per cell (see dsmc_sample) */
 #define DSMC_MLP_NPARAM 4673  /* learned-majorant network 6-64-64-1 */
 
@@ -106,13 +106,18 @@ typedef struct {
                                  particle in a corner may bounce between two walls many times) */
     int32_t schedule;         /* homogeneous instances: DSMC_SCHEDULE_GRID or _PERSISTENT */
     int32_t persistent_waves; /* waves of the persistent kernel (0 -> 8 per compute unit) */
-    int32_t reserved;
+    int32_t vr_reconstruct;   /* vr == 1: re-estimate the weights in every step whose index is a
+                                 multiple of this (0: never); see dsmc_step */
     int64_t chunk_work;       /* persistent kernel: up to 64 consecutive instances of the
                                  schedule form one work unit while they hold fewer than this
                                  many particles (0 -> one instance per unit) */
     double omega;             /* DSMC_VHS, DSMC_VSS: viscosity index in [0.5, 1]; sigma is the
                                  total cross-section at unit relative speed */
     double alpha;             /* DSMC_VSS: scattering exponent in [1, 2] (1: isotropic) */
+    double vr_kappa;          /* vr == 1: factor (1 <= kappa <= 16; 0 reads as 1) applied to the
+                                 relative-speed majorant, so that the acceptance probability p of
+                                 every candidate is at most 1 / kappa and the weight update's
+                                 1 / (1 - p) at most kappa / (kappa - 1) */
 } dsmc_config;
 
 /* How homogeneous instances are distributed over the GPU.  Both process the
@@ -190,7 +195,23 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *particles, void *w
  * particle (dims >= 1), the scan of the new cells' counts, then per cell the
  * gather of its particles into the new sequence (dims >= 1), NTC collisions
  * with the majorant chosen by cfg->majorant, the importance-weight update
- * (vr == 1), and accumulation of the cell moments into the running sums. */
+ * (vr == 1), the re-estimation of the weights (vr == 1, vr_reconstruct > 0,
+ * steps whose index is a multiple of vr_reconstruct), and accumulation of the
+ * cell moments into the running sums.
+ *
+ * Weight re-estimation (the reconstruction step of Al-Mohssen &
+ * Hadjiconstantinou 2010 in this library's form): in a cell of at least 26
+ * particles the deviations W - 1 are replaced by their least-squares
+ * projection onto the 13 functions 1, v, v_d v_e, v_d |v|^2 of
+ * v = c / sqrt(vr_T0), the functions whose weighted sums the cell samples.
+ * Every sampled weighted sum of the cell keeps its value (to rounding), unit
+ * weights stay exactly 1, and the per-particle noise that the collision
+ * update multiplies is removed.  A cell whose normal equations have a pivot
+ * not above 1e-12 times its diagonal entry keeps its weights.  The weights
+ * stay finite where the raw update diverges when collisions per particle and
+ * step are few (about 0.1); with many collisions per step, or with a
+ * reference temperature far from the flow's, the weights can still diverge
+ * (vr_nonfinite counts the cells). */
 dsmc_status dsmc_step(dsmc_ctx *ctx, int32_t n_steps);
 
 /* Synchronise the stream and copy out the running sums (host

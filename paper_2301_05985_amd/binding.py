@@ -14,7 +14,7 @@ from . import build as _build
 
 NSUM = 26
 MLP_NPARAM = 4673
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 STATUS = {0: "DSMC_OK", -1: "DSMC_EINVAL", -2: "DSMC_ENOMEM", -3: "DSMC_EHIP",
           -4: "DSMC_ENONFINITE", -5: "DSMC_EWALLHITS", -6: "DSMC_ECAPACITY", -7: "DSMC_EABI"}
@@ -36,8 +36,9 @@ class Config(ctypes.Structure):
         ("wall_u", (ctypes.c_double * 3) * 4), ("seed", ctypes.c_uint64),
         ("n_particles", ctypes.c_int64), ("cell_volume", ctypes.c_void_p),
         ("inst_offset", ctypes.c_void_p), ("max_wall_hits", ctypes.c_int32),
-        ("schedule", ctypes.c_int32), ("persistent_waves", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("schedule", ctypes.c_int32), ("persistent_waves", ctypes.c_int32), ("vr_reconstruct", ctypes.c_int32),
         ("chunk_work", ctypes.c_int64), ("omega", ctypes.c_double), ("alpha", ctypes.c_double),
+        ("vr_kappa", ctypes.c_double),
     ]
 
 
@@ -133,6 +134,8 @@ def make_config(p, n_particles):
     c.chunk_work = int(p.get("chunk_work", 0))
     c.omega = float(p.get("omega", 0.5))
     c.alpha = float(p.get("alpha", 1.0))
+    c.vr_reconstruct = int(p.get("vr_reconstruct", 0))
+    c.vr_kappa = float(p.get("vr_kappa", 1.0))
     return c
 
 

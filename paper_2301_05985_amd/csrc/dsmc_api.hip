@@ -67,6 +67,8 @@ dsmc_status validate(const dsmc_config *c) {
     if (c->n_particles < 0 || c->n_particles > (int64_t)0x7FFFFFFF) return DSMC_EINVAL;
     if (!(c->dt > 0) || !(c->sigma >= 0) || !(c->FN > 0)) return DSMC_EINVAL;
     if (c->vr && !(c->vr_T0 > 0)) return DSMC_EINVAL;
+    if (c->vr_reconstruct < 0 || !(c->vr_kappa == 0.0 || c->vr_kappa >= 1.0) || !(c->vr_kappa <= 16.0))
+        return DSMC_EINVAL;
     if (c->dims >= 1) {
         if (!(c->length[0] > 0) || (c->dims == 2 && !(c->length[1] > 0))) return DSMC_EINVAL;
         for (int k = 0; k < (c->dims == 2 ? 4 : 2); ++k) {
@@ -254,6 +256,9 @@ CollideArgs<R> collide_args(dsmc_ctx *c, int src, int dst) {
     a.mlp = (c->cfg.majorant == DSMC_MAJORANT_LEARNED && c->mlp_loaded) ? c->mlp : nullptr;
     a.lattice = c->lattice;
     a.delta = c->mlp_delta;
+    a.vr_reest = c->cfg.vr ? c->cfg.vr_reconstruct : 0;
+    a.vr_scale = c->cfg.vr ? 1.0 / std::sqrt(c->cfg.vr_T0) : 1.0;
+    a.vr_kappa = c->cfg.vr ? c->cfg.vr_kappa : 1.0;
     return a;
 }
 

@@ -58,6 +58,10 @@ struct CollideArgs {
     const float *mlp;              // [4673] FP32 weights or null
     const double *lattice;         // lattice values 2^(k/64), k in [-4096, 4096]
     double delta;
+    // importance weights: re-estimation every vr_reest steps (0: never) with
+    // velocities scaled by vr_scale = 1 / sqrt(T0); majorant factor vr_kappa
+    int vr_reest;
+    double vr_scale, vr_kappa;
 };
 
 constexpr int kNsum = 26;
@@ -711,6 +715,248 @@ __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uin
     grp_sync<T>();
 }
 
+// ------------------------------------------------- weight re-estimation
+// Importance-weight re-estimation of one cell (reconstruction step after
+// Al-Mohssen & Hadjiconstantinou 2010, in this project's reading): the
+// deviations d_i = W_i - 1 are replaced by their least-squares projection
+// onto the 13 functions of v = c / sqrt(T0)
+//   phi = (1, v_x, v_y, v_z, v_x^2, v_y^2, v_z^2, v_x v_y, v_x v_z, v_y v_z,
+//          v_x |v|^2, v_y |v|^2, v_z |v|^2),
+// whose raw-velocity counterparts are the functions the cell samples: every
+// sampled weighted moment keeps its value, unit weights stay exactly 1.  The
+// normal equations G a = b, G = sum phi phi^T, b = sum d phi, are solved by
+// Gauss-Jordan elimination in double (in the elimination order the pivots
+// are those of the Cholesky factorisation); a cell of fewer than 26
+// particles, or one whose k-th pivot is not above 1e-12 G_kk, keeps its
+// weights.
+//
+// G is assembled from 51 monomial sums: the monomials of degree 0-4 (index
+// 0 for 1; 1-3 for v_x, v_y, v_z; 4-9 for xx yy zz xy xz yz; 10-19 and 20-34
+// for degrees 3 and 4 in lexicographic order of the exponents), the degree-3
+// monomials times |v|^2 (35-44) and xx yy zz xy xz yz times |v|^4 (45-50);
+// b takes 13 more sums (51-63).  The sums are taken in four passes of 16
+// over the cell's particles (0-15, 16-31, 32-47, 48-63), each reduced by
+// recursive halving, so that few registers are live at a time.
+constexpr int kReMin = 26;      // smallest cell that is re-estimated
+constexpr int kReBasis = 13;
+
+struct GramTable {
+    uint8_t n[kReBasis][kReBasis];     // number of monomial sums of entry G_rc (1 or 3)
+    uint8_t t[kReBasis][kReBasis][3];  // their indices
+};
+
+// exponents (x, y, z) and power of |v|^2 of the basis functions
+constexpr int kReExp[kReBasis][4] = {{0, 0, 0, 0}, {1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {2, 0, 0, 0},
+                                     {0, 2, 0, 0}, {0, 0, 2, 0}, {1, 1, 0, 0}, {1, 0, 1, 0}, {0, 1, 1, 0},
+                                     {1, 0, 0, 1}, {0, 1, 0, 1}, {0, 0, 1, 1}};
+
+// rank of the exponents (i, j, n - i - j) among the monomials of degree n in
+// lexicographic (descending) order
+constexpr int lex_rank(int n, int i, int j) {
+    int r = 0;
+    for (int ii = i + 1; ii <= n; ++ii) r += n - ii + 1;
+    return r + (n - i - j);
+}
+constexpr int deg2_slot(int i, int j, int k) {
+    return i == 2 ? 0 : j == 2 ? 1 : k == 2 ? 2 : (i == 1 && j == 1) ? 3 : (i == 1 && k == 1) ? 4 : 5;
+}
+constexpr int mono_index(int i, int j, int k) {
+    const int n = i + j + k;
+    return n == 0 ? 0 : n == 1 ? (i ? 1 : j ? 2 : 3) : n == 2 ? 4 + deg2_slot(i, j, k)
+         : n == 3 ? 10 + lex_rank(3, i, j) : 20 + lex_rank(4, i, j);
+}
+constexpr GramTable make_gram_table() {
+    GramTable g{};
+    for (int r = 0; r < kReBasis; ++r)
+        for (int c = 0; c < kReBasis; ++c) {
+            const int i = kReExp[r][0] + kReExp[c][0], j = kReExp[r][1] + kReExp[c][1],
+                      k = kReExp[r][2] + kReExp[c][2], t = kReExp[r][3] + kReExp[c][3];
+            if (t == 0) {
+                g.n[r][c] = 1;
+                g.t[r][c][0] = (uint8_t)mono_index(i, j, k);
+            } else if (t == 2) {
+                g.n[r][c] = 1;
+                g.t[r][c][0] = (uint8_t)(45 + deg2_slot(i, j, k));
+            } else if (i + j + k == 3) {
+                g.n[r][c] = 1;
+                g.t[r][c][0] = (uint8_t)(35 + lex_rank(3, i, j));
+            } else {  // |v|^2 = v_x^2 + v_y^2 + v_z^2
+                g.n[r][c] = 3;
+                g.t[r][c][0] = (uint8_t)mono_index(i + 2, j, k);
+                g.t[r][c][1] = (uint8_t)mono_index(i, j + 2, k);
+                g.t[r][c][2] = (uint8_t)mono_index(i, j, k + 2);
+            }
+        }
+    return g;
+}
+__constant__ const GramTable kGram = make_gram_table();
+
+struct Reest {
+    bool on;
+    double sc;            // 1 / sqrt(T0)
+    double a[kReBasis];   // coefficients of the new deviation
+};
+
+// Sum q[0..15] over the cell's threads: on return lane L of every wave holds
+// the total of q[L >> 2] (the waves of a workgroup added in a fixed order).
+template <int T>
+__device__ __forceinline__ double cell_sum16(double (&q)[16], GroupScratch *gs) {
+    double t = wave_sum_many<16>(q);
+    if constexpr (T > 64) {
+        const int lane = lane_id();
+        if ((lane & 3) == 0) gs->d[threadIdx.x >> 6][lane >> 2] = t;
+        __syncthreads();
+        t = gs->d[0][lane >> 2];
+#pragma unroll
+        for (int w = 1; w < T / 64; ++w) t += gs->d[w][lane >> 2];
+        __syncthreads();  // the scratch is reused
+    }
+    return t;
+}
+
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// One pass of the Gram sums: PASS 0-3 accumulates sums 16 PASS .. 16 PASS + 15.
+template <int PASS, typename R, typename View, int T>
+__device__ __forceinline__ double gram_pass(const View &v, uint32_t N, double sc, GroupScratch *gs) {
+    double q[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) q[u] = 0.0;
+    for (uint32_t r = threadIdx.x; r < N; r += T) {
+        R a, b, c;
+        v.get(r, a, b, c);
+        const double x = (double)a * sc, y = (double)b * sc, z = (double)c * sc;
+        const double xx = x * x, yy = y * y, zz = z * z;
+        if constexpr (PASS == 0) {  // 1, x y z, xx yy zz xy xz yz, xxx xxy xxz xyy xyz xzz
+            const double xy = x * y;
+            q[0] += 1.0; q[1] += x; q[2] += y; q[3] += z;
+            q[4] += xx; q[5] += yy; q[6] += zz; q[7] += xy; q[8] = fma(x, z, q[8]); q[9] = fma(y, z, q[9]);
+            q[10] = fma(xx, x, q[10]); q[11] = fma(xx, y, q[11]); q[12] = fma(xx, z, q[12]);
+            q[13] = fma(xy, y, q[13]); q[14] = fma(xy, z, q[14]); q[15] = fma(x, zz, q[15]);
+        } else if constexpr (PASS == 1) {  // yyy yyz yzz zzz, degree 4 (first 12)
+            const double xxx = xx * x, xxy = xx * y, xxz = xx * z, xyy = x * yy, yyy = yy * y;
+            q[0] += yyy; q[1] = fma(yy, z, q[1]); q[2] = fma(y, zz, q[2]); q[3] = fma(zz, z, q[3]);
+            q[4] = fma(xxx, x, q[4]); q[5] = fma(xxx, y, q[5]); q[6] = fma(xxx, z, q[6]);
+            q[7] = fma(xxy, y, q[7]); q[8] = fma(xxy, z, q[8]); q[9] = fma(xxz, z, q[9]);
+            q[10] = fma(xyy, y, q[10]); q[11] = fma(xyy, z, q[11]); q[12] = fma(x * y, zz, q[12]);
+            q[13] = fma(x * zz, z, q[13]); q[14] = fma(yyy, y, q[14]); q[15] = fma(yyy, z, q[15]);
+        } else if constexpr (PASS == 2) {  // yyzz yzzz zzzz, degree 3 times s, xx yy zz times s^2
+            const double s = (xx + yy) + zz;
+            q[0] = fma(yy, zz, q[0]); q[1] = fma(y * z, zz, q[1]); q[2] = fma(zz, zz, q[2]);
+            q[3] = fma(xx * x, s, q[3]); q[4] = fma(xx * y, s, q[4]); q[5] = fma(xx * z, s, q[5]);
+            q[6] = fma(x * yy, s, q[6]); q[7] = fma((x * y) * z, s, q[7]); q[8] = fma(x * zz, s, q[8]);
+            q[9] = fma(yy * y, s, q[9]); q[10] = fma(yy * z, s, q[10]); q[11] = fma(y * zz, s, q[11]);
+            q[12] = fma(zz * z, s, q[12]);
+            const double s2 = s * s;
+            q[13] = fma(xx, s2, q[13]); q[14] = fma(yy, s2, q[14]); q[15] = fma(zz, s2, q[15]);
+        } else {  // xy xz yz times s^2, then b: d phi_k
+            const double s = (xx + yy) + zz, s2 = s * s;
+            const double d = (double)v.getw(r) - 1.0;
+            const double dx = d * x, dy = d * y, dz = d * z;
+            q[0] = fma(x * y, s2, q[0]); q[1] = fma(x * z, s2, q[1]); q[2] = fma(y * z, s2, q[2]);
+            q[3] += d; q[4] += dx; q[5] += dy; q[6] += dz;
+            q[7] = fma(dx, x, q[7]); q[8] = fma(dy, y, q[8]); q[9] = fma(dz, z, q[9]);
+            q[10] = fma(dx, y, q[10]); q[11] = fma(dx, z, q[11]); q[12] = fma(dy, z, q[12]);
+            q[13] = fma(dx, s, q[13]); q[14] = fma(dy, s, q[14]); q[15] = fma(dz, s, q[15]);
+        }
+    }
+    return cell_sum16<T>(q, gs);
+}
+
+// Coefficients of the re-estimated deviations of the cell (identical on
+// every thread), or re.on = false if the cell keeps its weights.
+template <typename R, typename View, int T>
+__device__ void reestimate_cell(const View &v, uint32_t N, double sc, Reest &re, GroupScratch *gs) {
+    re.on = false;
+    re.sc = sc;
+    const double t0 = gram_pass<0, R, View, T>(v, N, sc, gs);
+    const double t1 = gram_pass<1, R, View, T>(v, N, sc, gs);
+    const double t2 = gram_pass<2, R, View, T>(v, N, sc, gs);
+    const double t3 = gram_pass<3, R, View, T>(v, N, sc, gs);
+    // sum g on lane 4 (g mod 16) + g / 16
+    const int lane = lane_id();
+    const int qb = lane & 3;
+    const double sum = qb == 0 ? t0 : (qb == 1 ? t1 : (qb == 2 ? t2 : t3));
+    const auto fetch = [&](int g) { return __shfl(sum, 4 * (g & 15) + (g >> 4), 64); };
+    // augmented matrix [G | b], four lanes per row: lane 4 r + q holds the
+    // entries (r, q + 4 j), j = 0..3 (column 13 is b)
+    const int row = lane >> 2, qc = lane & 3;
+    const bool has_row = row < kReBasis;
+    const int rr = has_row ? row : 0;
+    double M[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int col = qc + 4 * j;
+        const int cc = col < kReBasis ? col : 0;
+        // every lane takes part in the shuffles; values of lanes without the
+        // entry are discarded
+        const int nt = kGram.n[rr][cc];
+        const double e0 = fetch(col == kReBasis ? 51 + rr : kGram.t[rr][cc][0]);
+        const double e1 = fetch(nt == 3 ? kGram.t[rr][cc][1] : 0);
+        const double e2 = fetch(nt == 3 ? kGram.t[rr][cc][2] : 0);
+        M[j] = (!has_row || col > kReBasis) ? 0.0 : ((col < kReBasis && nt == 3) ? (e0 + e1) + e2 : e0);
+    }
+    // this lane's original diagonal entry (for the pivot test)
+    const int sl = row >> 2;
+    const double mdiag = sl == 0 ? M[0] : (sl == 1 ? M[1] : (sl == 2 ? M[2] : M[3]));
+    const double dg = (has_row && qc == (row & 3)) ? mdiag : 0.0;
+    // Gauss-Jordan: row k is divided by the pivot, every other row r loses
+    // M[r][k] / pivot times row k; for row k itself that is the same update
+    // with the factor 1 - 1 / pivot.  The reciprocal is the hardware
+    // estimate refined by two Newton steps.
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < kReBasis; ++k) {
+        const int kl = 4 * k + (k & 3);
+        const double piv = readlane_f64(M[k >> 2], kl);
+        ok = ok && piv > 1e-12 * readlane_f64(dg, kl);
+        double inv = __builtin_amdgcn_rcp(piv);
+        inv = fma(inv, fma(-piv, inv, 1.0), inv);
+        inv = fma(inv, fma(-piv, inv, 1.0), inv);
+        const double mrk = __shfl(M[k >> 2], 4 * rr + (k & 3), 64);
+        const double f = row == k ? 1.0 - inv : mrk * inv;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) M[j] = fma(-f, __shfl(M[j], 4 * k + qc, 64), M[j]);
+    }
+    if (!ok) return;  // a pivot not above 1e-12 G_kk: the cell keeps its weights
+    // solution: column 13 (lane 4 r + 1, slot 3)
+#pragma unroll
+    for (int r = 0; r < kReBasis; ++r) re.a[r] = readlane_f64(M[3], 4 * r + 1);
+    re.on = true;
+}
+
+// New weight of a particle from the re-estimated deviation.
+template <typename R>
+__device__ __forceinline__ R reestimated_weight(const Reest &re, R a, R b, R c) {
+    const double x = (double)a * re.sc, y = (double)b * re.sc, z = (double)c * re.sc;
+    const double s = (x * x + y * y) + z * z;
+    double d = re.a[0];
+    d = fma(re.a[1], x, d); d = fma(re.a[2], y, d); d = fma(re.a[3], z, d);
+    d = fma(re.a[4], x * x, d); d = fma(re.a[5], y * y, d); d = fma(re.a[6], z * z, d);
+    d = fma(re.a[7], x * y, d); d = fma(re.a[8], x * z, d); d = fma(re.a[9], y * z, d);
+    d = fma((re.a[10] * x + re.a[11] * y) + re.a[12] * z, s, d);
+    return (R)(1.0 + d);
+}
+
+// Re-estimate the weights of the cell held by the view (in place), if due.
+template <typename R, typename View, int T>
+__device__ __forceinline__ void reestimate_weights(const View &v, uint32_t N, double sc, GroupScratch *gs) {
+    Reest re;
+    reestimate_cell<R, View, T>(v, N, sc, re, gs);
+    if (!re.on) return;
+    for (uint32_t r = threadIdx.x; r < N; r += T) {
+        R a, b, c;
+        v.get(r, a, b, c);
+        v.putw(r, reestimated_weight<R>(re, a, b, c));
+    }
+    grp_sync<T>();
+}
+
 // The running sum a lane owns in the moment reduction, or -1.  Cells in
 // global memory: lane L owns sum L.  Cells staged in LDS: the four lanes of
 // quad r add up row r (moment r) together, and lane 4 r + h keeps the total
@@ -879,6 +1125,12 @@ __device__ __forceinline__ double candidates_real(const CollideArgs<R> &a, doubl
     return ((((((0.5 * Nd) * (Nd - 1.0)) * a.FN) * a.sigma) * gmax) * a.dt) / V;
 }
 
+// Whether the weights of a cell of N particles are re-estimated in this step.
+template <typename R>
+__device__ __forceinline__ bool reestimate_now(const CollideArgs<R> &a, uint32_t N, uint32_t step) {
+    return a.vr_reest > 0 && N >= (uint32_t)kReMin && step % (uint32_t)a.vr_reest == 0u;
+}
+
 // Majorant, candidate count, NTC loop and sampling of one cell; the view
 // already holds the cell in canonical order.
 template <typename R, bool VR, typename View, int T = 64>
@@ -889,9 +1141,11 @@ __device__ void process_cell(const CollideArgs<R> &a, const View &v, uint32_t ce
     if (N >= 2) {
         double rt;
         double gmax = 1.0;
-        if (a.molecule != DSMC_MAXWELL)
+        if (a.molecule != DSMC_MAXWELL) {
             gmax = a.majorant == DSMC_MAJORANT_DIAMETER ? pair_diameter<R, View, T>(v, N, gs)
                                                         : exact_bound<R, View, T>(v, N, rt, gs);
+            if (VR && a.vr_kappa > 1.0) gmax = gmax * a.vr_kappa;
+        }
         const double V = a.volume ? a.volume[cell] : a.Vuni;
         const double Nd = (double)N;
         const double Mreal = candidates_real<R>(a, Nd, gmax, V);
@@ -906,6 +1160,7 @@ __device__ void process_cell(const CollideArgs<R> &a, const View &v, uint32_t ce
         ntc_loop<R, VR, View, T>(v, N, gmax, M, cell, step, a.k0, a.k1, a.molecule, a.omega1, a.inv_alpha, acc,
                                  over, gs);
     }
+    if (VR && reestimate_now(a, N, step)) reestimate_weights<R, View, T>(v, N, a.vr_scale, gs);
     sample_cell<R, VR, View, T>(a, v, cell, N, M, acc, over, pf, red, wb_base, gs);
 }
 

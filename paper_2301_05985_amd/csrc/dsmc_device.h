@@ -194,12 +194,42 @@ template <int K, int HALF, int OFF>
 struct HalvingStep {
     // one level: keep HALF values, receive the partner's copy of them
     static __device__ __forceinline__ void run(double (&v)[K], int lane) {
-        const bool upper = (lane & OFF) != 0;
+        if constexpr (OFF == 32 || OFF == 16) {
+            // gfx950 lane swaps: v_permlane32_swap exchanges the upper half
+            // of the first register with the lower half of the second
+            // (v_permlane16_swap the odd rows of 16 with the even ones), so
+            // the lower half of each 2 OFF lanes ends with (own v[k],
+            // partner's v[k]) and the upper half with (partner's v[HALF + k],
+            // own v[HALF + k]): the same two terms as the select-and-shuffle
+            // form, without the selects
 #pragma unroll
-        for (int k = 0; k < HALF; ++k) {
-            const double keep = upper ? v[HALF + k] : v[k];
-            const double send = upper ? v[k] : v[HALF + k];
-            v[k] = keep + __shfl_xor(send, OFF, 64);
+            for (int k = 0; k < HALF; ++k) {
+                const uint64_t a = (uint64_t)__double_as_longlong(v[k]);
+                const uint64_t b = (uint64_t)__double_as_longlong(v[HALF + k]);
+                uint32_t xl, yl, xh, yh;
+                if constexpr (OFF == 32) {
+                    const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)a, (uint32_t)b, false, false);
+                    const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(a >> 32), (uint32_t)(b >> 32), false,
+                                                                     false);
+                    xl = lo[0]; yl = lo[1]; xh = hi[0]; yh = hi[1];
+                } else {
+                    const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)a, (uint32_t)b, false, false);
+                    const auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(a >> 32), (uint32_t)(b >> 32), false,
+                                                                     false);
+                    xl = lo[0]; yl = lo[1]; xh = hi[0]; yh = hi[1];
+                }
+                const double x = __longlong_as_double((long long)(((uint64_t)xh << 32) | xl));
+                const double y = __longlong_as_double((long long)(((uint64_t)yh << 32) | yl));
+                v[k] = x + y;
+            }
+        } else {
+            const bool upper = (lane & OFF) != 0;
+#pragma unroll
+            for (int k = 0; k < HALF; ++k) {
+                const double keep = upper ? v[HALF + k] : v[k];
+                const double send = upper ? v[k] : v[HALF + k];
+                v[k] = keep + __shfl_xor(send, OFF, 64);
+            }
         }
         HalvingStep<K, HALF / 2, OFF / 2>::run(v, lane);
     }

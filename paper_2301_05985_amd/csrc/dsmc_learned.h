@@ -257,7 +257,8 @@ __device__ void process_cell_learned(const CollideArgs<R> &a, const View &v, uin
     if (N >= 2) {
         const double V = a.volume ? a.volume[cell] : a.Vuni;
         int used = 0;
-        const double gmax = learned_majorant<R, View, T>(a, v, N, V, used, gs);
+        double gmax = learned_majorant<R, View, T>(a, v, N, V, used, gs);
+        if (VR && a.vr_kappa > 1.0 && a.molecule != DSMC_MAXWELL) gmax = gmax * a.vr_kappa;
         if (threadIdx.x == 0) {
             const int slot = used == 1 ? kDiagLearned : (used == -1 ? kDiagFallback : kDiagSkip);
             diag_add(a.st, slot, 1ull);
@@ -275,6 +276,7 @@ __device__ void process_cell_learned(const CollideArgs<R> &a, const View &v, uin
         ntc_loop<R, VR, View, T>(v, N, gmax, M, cell, step, a.k0, a.k1, a.molecule, a.omega1, a.inv_alpha, acc,
                                  over, gs);
     }
+    if (VR && reestimate_now(a, N, step)) reestimate_weights<R, View, T>(v, N, a.vr_scale, gs);
     sample_cell<R, VR, View, T>(a, v, cell, N, M, acc, over, pf, red, wb_base, gs);
 }
 
