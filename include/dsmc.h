@@ -308,6 +308,21 @@ dsmc_status dsmc_mlp_loss_grad(const float *params_dev, const float *x_dev, cons
                                float *scratch_dev, void *hip_stream);
 int64_t dsmc_mlp_scratch_floats(int64_t n);
 
+/* dsmc_mlp_loss_grad without the scratch argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid allocation): it allocates nothing and uses a scratch
+ * array of the library's own, about 5.5 MB per device, held from library
+ * load to process end.  Same arguments, results and asynchrony as
+ * dsmc_mlp_loss_grad; n at most DSMC_MLP_NOALLOC_MAX, else EINVAL.  The
+ * stream must belong to the current device (EINVAL otherwise; NULL is the
+ * current device's default stream).  All calls on one device share the
+ * array: calls whose work overlaps on one device (different streams, or
+ * host threads racing) corrupt each other's results; calls queued on one
+ * stream are safe. */
+#define DSMC_MLP_NOALLOC_MAX 4096
+dsmc_status dsmc_mlp_loss_grad_noalloc(const float *params_dev, const float *x_dev, const float *label_dev,
+                                       int64_t n, double tau, float *grad_dev, float *loss_dev, void *hip_stream);
+
 /* One Adam update (Kingma & Ba 2015) of params in place from grad, with the
  * first and second moment buffers m, v (device [n_param] float) and the
  * 1-based step index t.  Asynchronous. */

@@ -14,6 +14,7 @@ from . import build as _build
 
 NSUM = 26
 MLP_NPARAM = 4673
+MLP_NOALLOC_MAX = 4096
 ABI_VERSION = 5
 
 STATUS = {0: "DSMC_OK", -1: "DSMC_EINVAL", -2: "DSMC_ENOMEM", -3: "DSMC_EHIP",
@@ -89,6 +90,7 @@ def load():
         "dsmc_collect_features": [P, P, P, P],
         "dsmc_mlp_forward": [P, P, I64, P, P],
         "dsmc_mlp_loss_grad": [P, P, P, I64, D, P, P, P, P],
+        "dsmc_mlp_loss_grad_noalloc": [P, P, P, I64, D, P, P, P],
         "dsmc_mlp_adam": [P, P, P, P, I64, I64, D, D, D, D, P],
     }
     for name, args in sig.items():

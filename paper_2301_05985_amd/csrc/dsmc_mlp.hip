@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "../../include/dsmc.h"
 
@@ -177,6 +178,56 @@ __global__ __launch_bounds__(256) void k_mlp_adam(float *p, const float *g, floa
     p[k] = p[k] - lr * (mk / c1) / (sqrtf(vk / c2) + eps);
 }
 
+// Scratch of the allocation-free loss-gradient call: the per-sample records
+// and the FP64 chunk sums of at most DSMC_MLP_NOALLOC_MAX samples, in device
+// memory that the library holds from load to process end (one copy per
+// device).  Every element a call reads is written earlier in the same call,
+// so nothing has to start at zero.
+constexpr int64_t kNoallocFloats =
+    (int64_t)DSMC_MLP_NOALLOC_MAX * kPerSample + 2 * (((int64_t)DSMC_MLP_NOALLOC_MAX + kChunk - 1) / kChunk) * kNq;
+static __device__ __align__(256) float scratch[kNoallocFloats];
+
+// Device address of `scratch` on each device, taken once per device (with
+// that device current) and reused; the array's host-side name is never
+// passed to a kernel.
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+float *g_noalloc_ptr[kMaxDevices] = {};
+
+dsmc_status noalloc_scratch(hipStream_t stream, float **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return DSMC_EHIP;
+    if (dev < 0 || dev >= kMaxDevices) return DSMC_EINVAL;
+    if (stream) {
+        // the scratch address belongs to the current device: the stream must too
+        hipDevice_t sdev = -1;
+        if (hipStreamGetDevice(stream, &sdev) != hipSuccess) return DSMC_EHIP;
+        if ((int)sdev != dev) return DSMC_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return DSMC_EHIP;
+        g_noalloc_ptr[dev] = (float *)ptr;
+    }
+    *out = g_noalloc_ptr[dev];
+    return DSMC_OK;
+}
+
+// Loss and gradient with the given scratch (validated arguments).
+dsmc_status loss_grad(const float *params, const float *x, const float *label, int64_t n, double tau, float *grad,
+                      float *loss, float *scr, hipStream_t s) {
+    const int nchunk = (int)((n + kChunk - 1) / kChunk);
+    hipLaunchKernelGGL(k_mlp_backward, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, params, x, label, n,
+                       (float)tau, scr);
+    double *part = (double *)(scr + n * kPerSample);  // kPerSample is even: 8-byte aligned
+    hipLaunchKernelGGL(k_mlp_partial, dim3((unsigned)((kNq + 255) / 256), (unsigned)nchunk), dim3(256), 0, s, x, n,
+                       scr, part);
+    hipLaunchKernelGGL(k_mlp_finish, dim3((unsigned)((kNp + 1 + 255) / 256)), dim3(256), 0, s, part, nchunk, grad,
+                       loss);
+    return hipGetLastError() == hipSuccess ? DSMC_OK : DSMC_EHIP;
+}
+
 }  // namespace
 
 extern "C" {
@@ -199,16 +250,17 @@ dsmc_status dsmc_mlp_loss_grad(const float *params, const float *x, const float 
     if (!params || !x || !label || !grad || !loss || !scratch || n <= 0 || !(tau > 0.0 && tau < 1.0))
         return DSMC_EINVAL;
     if ((n + kChunk - 1) / kChunk > 65535) return DSMC_EINVAL;  // chunks are a grid dimension
-    hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_mlp_backward, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, params, x, label, n,
-                       (float)tau, scratch);
-    const int nchunk = (int)((n + kChunk - 1) / kChunk);
-    double *part = (double *)(scratch + n * kPerSample);  // kPerSample is even: 8-byte aligned
-    hipLaunchKernelGGL(k_mlp_partial, dim3((unsigned)((kNq + 255) / 256), (unsigned)nchunk), dim3(256), 0, s, x, n,
-                       scratch, part);
-    hipLaunchKernelGGL(k_mlp_finish, dim3((unsigned)((kNp + 1 + 255) / 256)), dim3(256), 0, s, part, nchunk, grad,
-                       loss);
-    return hipGetLastError() == hipSuccess ? DSMC_OK : DSMC_EHIP;
+    return loss_grad(params, x, label, n, tau, grad, loss, scratch, (hipStream_t)stream);
+}
+
+dsmc_status dsmc_mlp_loss_grad_noalloc(const float *params, const float *x, const float *label, int64_t n,
+                                       double tau, float *grad, float *loss, void *stream) {
+    if (!params || !x || !label || !grad || !loss || n <= 0 || !(tau > 0.0 && tau < 1.0)) return DSMC_EINVAL;
+    if (n > DSMC_MLP_NOALLOC_MAX) return DSMC_EINVAL;
+    float *scr = nullptr;
+    const dsmc_status st = noalloc_scratch((hipStream_t)stream, &scr);
+    if (st != DSMC_OK) return st;
+    return loss_grad(params, x, label, n, tau, grad, loss, scr, (hipStream_t)stream);
 }
 
 dsmc_status dsmc_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t n_param, int64_t t,
