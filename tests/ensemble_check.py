@@ -29,3 +29,21 @@ def ensemble_verdict(x, mean, std, R, level=1e-3):
     zmax_bound = float(stats.t.isf(level / (2.0 * M), R - 1))
     ok = frac <= frac_bound and zmax <= zmax_bound
     return ok, dict(frac=frac, frac_bound=frac_bound, zmax=zmax, zmax_bound=zmax_bound, M=M)
+
+
+def ensemble_mean_shift(x, mean, std, R, k_sigma=4.0):
+    """Aggregate check for independent cells: the mean of z over the cells,
+    per estimator (columns of x), has expectation 0 and standard error
+    sqrt(((R - 1) / (R - 3)) / M) (the variance of Student's t with R - 1
+    degrees of freedom over M cells).  Passes when every column's mean is
+    within k_sigma standard errors; sensitive to a small shift common to all
+    cells, which the per-cell 3-sigma fraction does not see."""
+    z = ensemble_z(x, mean, std, R)
+    z = z.reshape(z.shape[0], -1)
+    out = []
+    for k in range(z.shape[1]):
+        zk = z[:, k][np.isfinite(z[:, k])]
+        se = np.sqrt((R - 1.0) / (R - 3.0) / zk.size)
+        out.append(float(zk.mean() / se))
+    return all(abs(v) <= k_sigma for v in out), out
+

@@ -1,0 +1,109 @@
+"""Ensemble tests of the FP32 GPU path against FP64-oracle statistics.
+
+One GPU realisation (Philox seed 0) of each reduced workload against 32
+independent realisations of the oracle's double-precision build (seeds
+1..32, same initial state; tests/golden/make_ensemble.py): per cell and
+estimator z = (x - mean) / (std sqrt(1 + 1/R)); the 3-sigma fraction and the
+largest |z| must be those of Student's t (tests/ensemble_check.py).  For
+independent cells the mean of z per estimator is also checked.
+
+The learned majorant is checked here for equal accuracy with the exact one:
+both runs of the batched cells pass against the same ensemble (computed
+with the exact majorant), with the rate of candidates whose pair outran the
+pre-collision majorant (overshoot) bounded for both."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from tests.ensemble_check import ensemble_mean_shift, ensemble_verdict
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "golden"))
+import make_ensemble as E  # noqa: E402
+
+
+def _announce(name):
+    print("[gpu case] %s" % name, flush=True)
+
+
+def golden(name):
+    d = np.load(os.path.join(HERE, "golden", "ensemble_%s_f64.npz" % name))
+    return d["mean"], d["std"], int(d["R"])
+
+
+def _burn_and_sample(p, parts, burn, sample):
+    from paper_2301_05985_amd.binding import Simulation
+    sim = Simulation(p, parts)
+    sim.step(burn)
+    sim.sample(reset=True)
+    sim.step(sample)
+    sums, cnt, ns = sim.sample()
+    d = sim.diagnostics()
+    sim.close()
+    assert ns == sample and d["status"] == 0, d
+    return sums, cnt, d
+
+
+def test_cavity_fp32_against_fp64_ensemble(gpu):
+    _announce("cavity 32x32 fp32 vs fp64 ensemble")
+    p, parts = E.params(0)
+    sums, _, _ = _burn_and_sample(p, parts, E.BURN, E.SAMPLE)
+    ok, info = ensemble_verdict(E.estimates(sums, E.SAMPLE), *golden("cavity32"))
+    print(info, flush=True)
+    assert ok, info
+
+
+def test_weighted_cavity_fp32_against_fp64_ensemble(gpu):
+    # importance weights re-estimated every step; the variance-reduced
+    # estimators of density, velocity, temperature, shear stress, heat flux
+    _announce("weighted cavity 32x32 fp32 vs fp64 ensemble")
+    p, parts = E.params_vr(0)
+    sums, _, d = _burn_and_sample(p, parts, E.BURN, E.SAMPLE)
+    assert d["vr_nonfinite"] == 0
+    ok, info = ensemble_verdict(E.estimates_vr(sums, E.SAMPLE, p), *golden("cavity32vr"))
+    print(info, flush=True)
+    assert ok, info
+
+
+@pytest.fixture(scope="module")
+def batched_model(gpu):
+    # a network trained on the GPU on this workload's own kind of cells
+    # (seeds 1-4, held-out seed 5 for the margin), as the pipeline does at
+    # full size
+    from paper_2301_05985_amd import learned
+    return learned.train_model(n_epochs=4, steps=64, every=4, n_inst=1024, nmin=E.NMIN, nmax=E.NMAX)
+
+
+@pytest.mark.parametrize("majorant", ["exact", "learned"])
+def test_batched_fp32_majorants_against_fp64_ensemble(gpu, batched_model, majorant):
+    _announce("batched 256 fp32 %s majorant vs fp64 ensemble" % majorant)
+    from paper_2301_05985_amd import learned
+    from paper_2301_05985_amd.binding import Simulation
+    p, parts = E.params_batched(0)
+    if majorant == "learned":
+        sim = learned.simulation_with_model(dict(p, majorant=1), parts, batched_model)
+    else:
+        sim = Simulation(p, parts)
+    sim.step(E.SAMPLE_B)
+    sums, cnt, ns = sim.sample()
+    d = sim.diagnostics()
+    sim.close()
+    assert ns == E.SAMPLE_B and d["status"] == 0
+    mean, std, R = golden("batched256")
+    x = E.estimates_batched(sums, E.SAMPLE_B)
+    ok, info = ensemble_verdict(x, mean, std, R)
+    print(majorant, info, flush=True)
+    assert ok, info
+    ok, shift = ensemble_mean_shift(x, mean, std, R)
+    print(majorant, "mean z / standard error per estimator", shift, flush=True)
+    assert ok, shift
+    cand = int(cnt[:, 0].sum())
+    rate = d["overshoot"] / max(cand, 1)
+    print(majorant, "overshoot", d["overshoot"], "of", cand, "candidates", flush=True)
+    assert rate < 1e-3
+    if majorant == "learned":
+        # the verified proposal is in use in a good share of the cell-steps
+        assert d["learned_used"] > 0.1 * 256 * E.SAMPLE_B, d

@@ -1,8 +1,7 @@
 """GPU checks at the workloads' full sizes, in the launch configuration the
 benchmark times: outputs the oracle can compute one by one (sampled cells or
 instances, every particle's free flight), properties that hold at any size
-(conservation, permutation of the particles), and an FP32 ensemble test of
-the cell estimators against independent oracle runs."""
+(conservation, permutation of the particles)."""
 import math
 import os
 import sys
@@ -13,7 +12,6 @@ import pytest
 import oracle
 from oracle import mlp_oracle as M
 from paper_2301_05985_amd import workloads as W
-from tests.ensemble_check import ensemble_verdict
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -21,26 +19,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 def _announce(name):
     print("[gpu case] %s" % name, flush=True)
-
-
-def test_cavity_fp32_ensemble(gpu):
-    # reduced cavity (32 x 32 cells, 50 per cell, Kn 0.05, lid 0.2), FP32,
-    # one GPU realisation against 32 independent oracle realisations
-    _announce("cavity ensemble fp32")
-    sys.path.insert(0, os.path.join(HERE, "golden"))
-    import make_ensemble as E
-    from paper_2301_05985_amd.binding import Simulation
-    d = np.load(os.path.join(HERE, "golden", "ensemble_cavity32.npz"))
-    p, parts = E.params(0)
-    sim = Simulation(p, parts)
-    sim.step(E.BURN)
-    sim.sample(reset=True)
-    sim.step(E.SAMPLE)
-    sums, _, ns = sim.sample()
-    assert ns == E.SAMPLE
-    ok, info = ensemble_verdict(E.estimates(sums, ns), d["mean"], d["std"], int(d["R"]))
-    print(info, flush=True)
-    assert ok, info
 
 
 def test_cavity_full_size_one_step_against_the_oracle(gpu):
