@@ -3,10 +3,11 @@
 
 Default (no flags): the 2-D lid-driven cavity at its full size -- 256 x 256
 cells, 100 particles per cell (6,553,600 particles), Kn = 0.01, diffuse walls,
-importance weights, FP32 state with FP64 moment sums -- W untimed warm-up
-steps, then exactly K timed steps (one step = free flight with walls, the
-stable regrouping by cell, per-cell majorant + NTC collisions + weight
-update, moment sampling).  Rank 0 prints one JSON line.
+importance weights re-estimated every step, FP32 state with FP64 moment sums
+-- W untimed warm-up steps, then exactly K timed steps (one step = free
+flight with walls, the stable regrouping by cell, per-cell majorant + NTC
+collisions + weight update + weight re-estimation, moment sampling).  Rank 0
+prints one JSON line.
 
 Also reported in the same line: per-kernel durations measured live with HIP
 events on the run's stream (roofline of the dominant kernel), the CPU oracle
@@ -101,6 +102,7 @@ def run_workload(name, p, parts, steps, warmup, torch):
     n = len(parts["cx"])
     out = {
         "workload": name, "particles": n, "steps": steps, "ms_per_step": ms / steps,
+        "overshoot_per_candidate": diag["overshoot"] / max(cand, 1),
         "particle_steps_per_s": n * steps / (ms * 1e-3),
         "collisions_per_s": acc / (ms * 1e-3), "candidates_per_s": cand / (ms * 1e-3),
         "acceptance": acc / max(cand, 1), "dtype": p.get("real", "f64"),
@@ -121,9 +123,21 @@ def kernel_profile(sim, torch, steps):
     return {k: float(np.mean(v)) for k, v in acc.items()}
 
 
-def cpu_baseline(p, parts, n_steps):
+def host_cpu():
+    """Model name and logical CPU count of the host (from /proc/cpuinfo)."""
+    model, n = None, 0
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                n += 1
+                model = model or line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": n or os.cpu_count()}
+
+
+def _oracle_rate(p, parts, n_steps, dtype):
     import oracle
-    dtype = np.float32 if p.get("real") == "f32" else np.float64
     orc = oracle.Oracle(p, parts, dtype)
     orc.run(1)  # the first step streams from the unsorted initial state, like the GPU warm-up
     acc0 = int(orc.counters[:, 1].sum())
@@ -132,10 +146,20 @@ def cpu_baseline(p, parts, n_steps):
     dt = time.perf_counter() - t0
     n = len(parts["cx"])
     acc = int(orc.counters[:, 1].sum()) - acc0  # accepted in the timed steps only
-    return {"value": n * n_steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": "%d steps of the same workload after 1 untimed step (%.1f s single-threaded, "
-                      "FP%d oracle build)" % (n_steps, dt, 32 if dtype == np.float32 else 64),
-            "collisions_per_s": acc / dt}
+    return n * n_steps / dt, acc / dt, dt
+
+
+def cpu_baseline(p, parts, n_steps, n_steps64):
+    """The oracle on one host core: its double-precision build (the plain
+    FP64 reference) and its single-precision build (the decisions of the
+    FP32 path), each on a bounded number of steps of the same workload."""
+    v64, c64, t64 = _oracle_rate(p, parts, n_steps64, np.float64)
+    v32, c32, t32 = _oracle_rate(p, parts, n_steps, np.float32)
+    return {"value": v64, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "%d steps of the same workload after 1 untimed step, FP64 oracle build, single-threaded "
+                      "(%.1f s)" % (n_steps64, t64),
+            "collisions_per_s": c64, "host": host_cpu(),
+            "fp32_build": {"value": v32, "collisions_per_s": c32, "steps": n_steps, "seconds": t32}}
 
 
 def main():
@@ -146,7 +170,8 @@ def main():
     ap.add_argument("--kn", type=float, default=0.01)
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--cpu-steps64", type=int, default=6)
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 512 MiB device-to-device copy (reference for HBM byte counters)")
@@ -177,8 +202,9 @@ def main():
 
     # ---------------- headline: full-size cavity
     p, parts = W.cavity(Kn=args.kn, real="f32")
+    p["vr_reconstruct"] = 1
     name = "cavity 256x256 cells x 100 particles (6,553,600), Kn=%g, diffuse walls, lid 0.01*sqrt(2), " \
-           "VR weights, FP32 state / FP64 sums" % args.kn
+           "VR weights re-estimated every step, FP32 state / FP64 sums" % args.kn
     print("[bench] headline: %s" % name, file=sys.stderr, flush=True)
     sim = Simulation(p, parts)
     ms, wall, cand, acc = _timed_steps(sim, torch, args.steps, args.warmup)
@@ -224,7 +250,7 @@ def main():
                    "parallelism": "single GPU"},
         "collisions_per_s": acc / (ms * 1e-3), "candidates_per_s": cand / (ms * 1e-3),
         "acceptance": acc / max(cand, 1),
-        "diagnostics": {k: diag[k] for k in ("overshoot", "wall_hits", "vr_nonfinite", "big_cells")},
+        "diagnostics": {k: diag[k] for k in ("steps", "overshoot", "wall_hits", "vr_nonfinite", "big_cells")},
         "roofline": roof,
     }
 
@@ -232,7 +258,9 @@ def main():
         sec = []
         print("[bench] secondary workloads", file=sys.stderr, flush=True)
         p2, parts2 = W.fourier(real="f32")
-        sec.append(run_workload("fourier 200 cells x 200 (40,000), Kn=0.1, VR, FP32", p2, parts2, 2000, 100, torch))
+        p2["vr_reconstruct"] = 1
+        sec.append(run_workload("fourier 200 cells x 200 (40,000), Kn=0.1, VR re-estimated every step, FP32", p2,
+                                parts2, 2000, 100, torch))
         p3, parts3 = W.batched(real="f32")
         # launch parameters of the collision step picked by the autotuner
         # (grid vs persistent work queue; identical results either way)
@@ -252,22 +280,36 @@ def main():
         model = learned.train_model(log=lambda s: print("[bench] " + s, file=sys.stderr, flush=True))
         t_train = time.perf_counter() - t0
         p5 = dict(p3, majorant=1)
-        best5, times5 = autotune.tune(p5, parts3, steps=20, warmup=8, model=(model["bits"], model["delta"]), log=tlog)
-        sim5 = learned.simulation_with_model(dict(p5, **best5), parts3, model)
-        ms5, wall5, cand5, acc5 = _timed_steps(sim5, torch, 200, 20)
-        d5 = sim5.diagnostics()
-        sim5.close()
         n3 = len(parts3["cx"])
         cells = 4096 * 220
-        sec.append({"workload": "batched 4096 cells, learned majorant (verified, exact-bound fallback), FP32",
-                    "particles": n3, "steps": 200,
-                    "ms_per_step": ms5 / 200, "particle_steps_per_s": n3 * 200 / (ms5 * 1e-3),
-                    "collisions_per_s": acc5 / (ms5 * 1e-3), "candidates_per_s": cand5 / (ms5 * 1e-3),
-                    "acceptance": acc5 / max(cand5, 1), "learned_used_frac": d5["learned_used"] / cells,
-                    "fallback_frac": d5["fallback"] / cells, "skip_frac": d5["learned_skip"] / cells,
-                    "delta": model["delta"], "train_samples": model["n_train"],
-                    "launch": best5, "launch_candidates_ms_per_step": times5,
-                    "train_loss": model["loss_history"], "train_seconds": t_train})
+        # the calibration's table: per cell-size bin, at the chosen margin,
+        # the candidates a verified proposal saves and what the network and
+        # the verification cost (candidate-equivalents per step of 4096 cells)
+        tab = model["calibration"]
+        j = int(round((model["delta"] + 0.64) / 0.01))
+        edges = [2] + [64 << b for b in range(7)]
+        breakeven = [{"cells_from_N": edges[b], "saved": float(tab[j, b, 0]), "cost": float(tab[j, b, 1]),
+                      "used": int(tab[j, b, 2]), "fallback": int(tab[j, b, 3])} for b in range(tab.shape[1])]
+        for label, gate in (("calibrated size gate", model["min_n"]), ("every cell", 0)):
+            m5 = dict(model, min_n=gate)
+            best5, times5 = autotune.tune(p5, parts3, steps=20, warmup=8, model=(m5["bits"], m5["delta"], gate),
+                                          log=tlog)
+            sim5 = learned.simulation_with_model(dict(p5, **best5), parts3, m5)
+            ms5, wall5, cand5, acc5 = _timed_steps(sim5, torch, 200, 20)
+            d5 = sim5.diagnostics()
+            sim5.close()
+            sec.append({"workload": "batched 4096 cells, learned majorant (verified, exact-bound fallback), %s, "
+                                    "FP32" % label,
+                        "particles": n3, "steps": 200, "min_n": gate,
+                        "ms_per_step": ms5 / 200, "particle_steps_per_s": n3 * 200 / (ms5 * 1e-3),
+                        "collisions_per_s": acc5 / (ms5 * 1e-3), "candidates_per_s": cand5 / (ms5 * 1e-3),
+                        "acceptance": acc5 / max(cand5, 1), "learned_used_frac": d5["learned_used"] / cells,
+                        "fallback_frac": d5["fallback"] / cells, "skip_frac": d5["learned_skip"] / cells,
+                        "overshoot": d5["overshoot"], "overshoot_per_candidate": d5["overshoot"] / max(cand5, 1),
+                        "delta": model["delta"], "train_samples": model["n_train"],
+                        "launch": best5, "launch_candidates_ms_per_step": times5,
+                        "train_loss": model["loss_history"], "train_seconds": t_train,
+                        "calibration_at_delta": breakeven})
         p6 = dict(p3, molecule=W.VHS, omega=0.81)
         sec.append(run_workload("batched 4096 cells, variable hard spheres (omega 0.81), exact majorant, FP32",
                                 dict(p6, **best3), parts3, 200, 20, torch))
@@ -275,7 +317,7 @@ def main():
         sec.append(run_workload("batched 4096 cells, variable soft spheres (omega 0.81, alpha 1.4), exact majorant, "
                                 "FP32", dict(p6s, **best3), parts3, 200, 20, torch))
         p7, parts7 = W.cavity(Kn=args.kn, real="f32")
-        p7 = dict(p7, molecule=W.VHS, omega=0.74)
+        p7 = dict(p7, molecule=W.VHS, omega=0.74, vr_reconstruct=1)
         sec.append(run_workload("cavity 256x256 x 100, variable hard spheres (omega 0.74), VR, FP32", p7, parts7,
                                 100, 10, torch))
         p7s = dict(p7, molecule=W.VSS, alpha=1.4)
@@ -286,6 +328,7 @@ def main():
             if kn == args.kn:
                 continue
             pk, partsk = W.cavity(Kn=kn, real="f32")
+            pk["vr_reconstruct"] = 1
             sec.append(run_workload("cavity 256x256 x 100, Kn=%g, VR, FP32" % kn, pk, partsk, 100, 10, torch))
         p1, parts1 = W.relaxation()
         sec.append(run_workload("relaxation 10,000 particles one cell FP64", p1, parts1, 200, 0, torch))
@@ -293,7 +336,7 @@ def main():
 
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(p, parts, args.cpu_steps)
+        line["cpu_baseline"] = cpu_baseline(p, parts, args.cpu_steps, args.cpu_steps64)
     print(json.dumps(line), flush=True)
 
 

@@ -225,6 +225,24 @@ dsmc_status dsmc_step(dsmc_ctx *ctx, int32_t n_steps);
 dsmc_status dsmc_sample(dsmc_ctx *ctx, double *sums_host, uint64_t *counters_host,
                         uint64_t *n_samples, int32_t reset);
 
+/* Cell estimates from the running sums of dsmc_sample (host arithmetic in
+ * FP64, no GPU work; Bird 1994 ratio estimators of time-summed moments).
+ * sums_host [n_cells][DSMC_NSUM], n_samples sampled steps, F_N, cell
+ * volumes (host [n_cells], or NULL for volume_uniform).  Plain (vr == 0):
+ * with <Q> = S_Q F_N / (V n_samples),
+ *   n = <1>, u = <c> / n, T = (tr <c c> / n - |u|^2) / 3,
+ *   P_de = <c_d c_e> - n u_d u_e,
+ *   q_d = 1/2 (<c_d |c|^2> - 2 u_e <c_d c_e> - u_d tr <c c> + 2 n u_d |u|^2);
+ * weighted (vr == 1): every <Q> is the reference equilibrium's (vr_n0, at
+ * rest, vr_T0) plus the (1 - W)-weighted sums scaled the same way.  Writes
+ * out_host [n_cells][DSMC_NEST] = n, u_x, u_y, u_z, T, P_xx, P_yy, P_zz,
+ * P_xy, P_xz, P_yz, q_x, q_y, q_z (NaN in a cell without particles).
+ * EINVAL on NULL pointers, n_cells < 0 or n_samples == 0. */
+#define DSMC_NEST 14
+dsmc_status dsmc_estimators(const double *sums_host, int64_t n_cells, uint64_t n_samples, double FN,
+                            const double *volume_host, double volume_uniform, int32_t vr, double vr_n0,
+                            double vr_T0, double *out_host);
+
 /* Device pointers of the buffers that hold the current particle state, in
  * sequence order (walled runs alternate between the caller's buffers and
  * the workspace).  Valid until the next dsmc_step. */
@@ -248,10 +266,13 @@ dsmc_status dsmc_set_step(dsmc_ctx *ctx, uint64_t next_step);
  * of the exact method.  Under either majorant a pair that an earlier collision
  * of the same step made faster than the cell's majorant is accepted with
  * probability 1 instead of g / g_max (counted in dsmc_diag.overshoot; the
- * tighter learned majorant has a somewhat higher count).  EINVAL if n is
- * wrong or cfg->majorant is not LEARNED. */
+ * tighter learned majorant has a somewhat higher count).  Cells of fewer
+ * than min_n particles skip the network and use the exact bound (counted as
+ * learned_skip): a size gate for cells whose possible saving of candidates
+ * cannot repay the network and the verification (see dsmc_mlp_calibrate).
+ * EINVAL if n is wrong, min_n < 0 or cfg->majorant is not LEARNED. */
 dsmc_status dsmc_set_majorant_model(dsmc_ctx *ctx, const uint16_t *bf16_weights_host, int64_t n,
-                                    double delta);
+                                    double delta, int32_t min_n);
 
 /* Checkpoint: with host_blob == NULL, *bytes receives the size needed;
  * otherwise the particle state (in sequence order), step index, running
@@ -284,12 +305,16 @@ const char *dsmc_status_string(dsmc_status status);
 /* For every cell (dims 0: instance) of the current state, write the six
  * FP32 input features of the learned majorant (device [n_cells][6]), the
  * label log2 of the exact largest pairwise relative speed (device [n_cells]
- * float; -inf marks cells with fewer than two particles) and, if bounds_dev
- * is not NULL, log2 of the EXACT-mode bound (device [n_cells] float).
+ * float; -inf marks cells with fewer than two particles), if bounds_dev is
+ * not NULL log2 of the EXACT-mode bound, and if slimits_dev is not NULL
+ * log2 of the 65th largest r_p + r_(1) (the verification's set S holds at
+ * most 64 members exactly when the proposal's threshold is at least this;
+ * -inf when the cell has at most 64 particles) (device [n_cells] float).
  * Features: log2(number density), u_x/sqrt(T), u_y/sqrt(T), log2(T),
  * P_xx/p - 1, P_xy/p, from FP64 moments of the cell (walled runs: the
  * particles currently grouped in the cell).  Asynchronous. */
-dsmc_status dsmc_collect_features(dsmc_ctx *ctx, float *features_dev, float *labels_dev, float *bounds_dev);
+dsmc_status dsmc_collect_features(dsmc_ctx *ctx, float *features_dev, float *labels_dev, float *bounds_dev,
+                                  float *slimits_dev);
 
 /* Forward pass of the 6-64-64-1 ReLU network in FP32 (params device
  * [DSMC_MLP_NPARAM] float, layout as in dsmc_set_majorant_model; x device
@@ -322,6 +347,63 @@ int64_t dsmc_mlp_scratch_floats(int64_t n);
 #define DSMC_MLP_NOALLOC_MAX 4096
 dsmc_status dsmc_mlp_loss_grad_noalloc(const float *params_dev, const float *x_dev, const float *label_dev,
                                        int64_t n, double tau, float *grad_dev, float *loss_dev, void *hip_stream);
+
+/* Feature statistics and standardisation for training: over the rows with
+ * a finite label, the means m_k and sample standard deviations s_k (at least
+ * 1e-6) of the six features, the mean label and the row count, in FP64 and a
+ * fixed order, into stats_dev (device, DSMC_MLP_NSTATS doubles: m[6], s[6],
+ * mean label, count) and, if stats_host is not NULL, the same on the host
+ * (then synchronising); xs_dev [n][6] receives (x - m) / s for every row.
+ * Asynchronous otherwise. */
+#define DSMC_MLP_NSTATS 14
+dsmc_status dsmc_mlp_standardize(const float *x_dev, const float *label_dev, int64_t n, float *xs_dev,
+                                 double *stats_dev, double *stats_host, void *hip_stream);
+
+/* Fold the standardisation into the first layer of a network trained on
+ * standardised inputs (params device, in place): W1[h][k] /= s_k,
+ * b1[h] -= sum_k W1[h][k] m_k / s_k (stats_dev from dsmc_mlp_standardize),
+ * so that the network takes the raw features.  Asynchronous. */
+dsmc_status dsmc_mlp_fold_inputs(float *params_dev, const double *stats_dev, void *hip_stream);
+
+/* bfloat16 bits of n floats (device to device), rounded to nearest with ties
+ * to even (NaN stays NaN).  Asynchronous. */
+dsmc_status dsmc_mlp_to_bf16(const float *params_dev, int64_t n, uint16_t *bits_dev, void *hip_stream);
+
+/* Cost model of the learned majorant for dsmc_mlp_calibrate, hard spheres.
+ * Costs are in candidate-equivalents (the time of one NTC candidate of the
+ * exact method). */
+typedef struct {
+    double n_scale;       /* particles per unit number density in a cell: V / F_N */
+    double cand_scale;    /* candidates per unit majorant and ordered pair: 0.5 F_N sigma dt / V */
+    double eps;           /* the exact bound's rounding margin: 2^-20 (FP32 runs) or 2^-50 (FP64) */
+    double cost_network;  /* per cell whose network is evaluated (features, network, lattice) */
+    double cost_member;   /* per particle of a cell whose proposal is verified (membership of S) */
+    double cost_verify;   /* per cell whose proposal is verified (collecting S, the pair check, and
+                             the extra candidates of a fallback) */
+} dsmc_calib_model;
+#define DSMC_CALIB_NDELTA 128 /* margins delta_j = -0.64 + 0.01 j */
+#define DSMC_CALIB_NBINS 8    /* cell sizes [2, 64), [64, 128), ..., [4096, inf) */
+#define DSMC_CALIB_FIELDS 4   /* saved candidates, cost, cells using the proposal, fallbacks */
+
+/* Choose the lattice margin delta and the size gate min_n of the learned
+ * majorant on held-out cells (features, labels, bounds and slimits from
+ * dsmc_collect_features; bits the network in bfloat16, device).  For each
+ * margin and cell-size bin: a cell's proposal is verified when it is below
+ * the exact bound, and used when its threshold 2^(k/64) (1 - eps) is at
+ * least the largest pair speed and the cell's slimit; a used proposal saves
+ * cand_scale N (N - 1) (bound - proposal) candidates; every cell pays
+ * cost_network, every verified cell N cost_member + cost_verify.  Returns
+ * the margin and gate (the smallest bin edge, or 0) of the largest net
+ * saving; if no gate saves more than it costs, min_n = INT32_MAX (the
+ * network is never used) and delta is the margin of the largest gross
+ * saving.  table_host (may be NULL) receives [DSMC_CALIB_NDELTA]
+ * [DSMC_CALIB_NBINS][DSMC_CALIB_FIELDS] doubles.  work_dev: device, 256-byte
+ * aligned, at least dsmc_mlp_calib_work_bytes(n).  Synchronising. */
+size_t dsmc_mlp_calib_work_bytes(int64_t n);
+dsmc_status dsmc_mlp_calibrate(const uint16_t *bits_dev, const float *features_dev, const float *labels_dev,
+                               const float *bounds_dev, const float *slimits_dev, int64_t n,
+                               const dsmc_calib_model *model, void *work_dev, size_t work_bytes,
+                               double *delta_out, int32_t *min_n_out, double *table_host, void *hip_stream);
 
 /* One Adam update (Kingma & Ba 2015) of params in place from grad, with the
  * first and second moment buffers m, v (device [n_param] float) and the

@@ -69,6 +69,7 @@ class OrcCfg(ctypes.Structure):
         ("vr_reconstruct", ctypes.c_int32),
         ("pad_", ctypes.c_int32),
         ("vr_kappa", ctypes.c_double),
+        ("mlp_min_n", ctypes.c_int64),
     ]
 
 
@@ -189,6 +190,7 @@ def make_cfg(p):
     c.alpha = float(p.get("alpha", 1.0))
     c.vr_reconstruct = int(p.get("vr_reconstruct", 0))
     c.vr_kappa = float(p.get("vr_kappa", 1.0))
+    c.mlp_min_n = int(p.get("mlp_min_n", 0))
     return c
 
 

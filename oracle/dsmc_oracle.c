@@ -128,6 +128,7 @@ typedef struct {
     int32_t vr_reconstruct;             /* K > 0: re-estimate the weights in steps s with s mod K == 0 */
     int32_t pad_;
     double vr_kappa;                    /* weighted runs: majorant factor (>= 1; 0 is read as 1) */
+    int64_t mlp_min_n;                  /* learned majorant: cells of fewer particles use the exact bound */
 } orc_cfg;
 
 typedef struct {
@@ -490,12 +491,15 @@ static double lattice_value(int64_t k) { return exp2((double)k / 64.0); }
  * is used only when it is below the exact bound and provably bounds every
  * pair: with g_v = g_pred (1 - eps), pairs whose speed can exceed g_v both lie
  * in S = {p : r_p + r_(1) > g_v}; if |S| > 64 the proposal is rejected,
- * otherwise all pairs of S are checked by brute force against g_v.  Otherwise the exact
+ * otherwise all pairs of S are checked by brute force against g_v.  Cells of
+ * fewer than mlp_min_n particles skip the proposal.  Otherwise the exact
  * bound is used.  Returns the majorant; *used = 1 learned, 0 skip, -1 fallback. */
 double FN(orc_learned_majorant)(const orc_cfg *cfg, const REAL *cx, const REAL *cy, const REAL *cz,
                                 const int64_t *list, int64_t n, double V, int *used)
 {
     double gb = FN(orc_exact_bound)(cx, cy, cz, list, n);
+    /* size gate: small cells cannot repay the network and the verification */
+    if (n < cfg->mlp_min_n) { *used = 0; return gb; }
     float f[MLP_IN];
     FN(orc_features)(cx, cy, cz, list, n, cfg->FN, V, f);
     float y = FN(orc_mlp_forward_f32)(cfg->mlp, f);

@@ -92,7 +92,7 @@ def tune(params, particles, candidates=None, steps=8, warmup=8, model=None, use_
     """Return (best launch parameters, {candidate label: ms per step}).
 
     Walled workloads have a single schedule and return it untimed.
-    ``model`` is ``(bf16_weights, delta)`` for learned-majorant runs."""
+    ``model`` is ``(bf16_weights, delta, min_n)`` for learned-majorant runs."""
     if params.get("dims", 0) != 0:
         return dict(GRID), {}
     key = "%s/%s" % (_arch(), signature(params))

@@ -13,8 +13,11 @@ import numpy as np
 from . import build as _build
 
 NSUM = 26
+NEST = 14
 MLP_NPARAM = 4673
+MLP_NSTATS = 14
 MLP_NOALLOC_MAX = 4096
+CALIB_NDELTA, CALIB_NBINS, CALIB_FIELDS = 128, 8, 4
 ABI_VERSION = 5
 
 STATUS = {0: "DSMC_OK", -1: "DSMC_EINVAL", -2: "DSMC_ENOMEM", -3: "DSMC_EHIP",
@@ -41,6 +44,25 @@ class Config(ctypes.Structure):
         ("chunk_work", ctypes.c_int64), ("omega", ctypes.c_double), ("alpha", ctypes.c_double),
         ("vr_kappa", ctypes.c_double),
     ]
+
+
+class CalibModel(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("n_scale", "cand_scale", "eps", "cost_network", "cost_member",
+                                                "cost_verify")]
+
+
+def estimators(sums, n_samples, FN, volume=None, volume_uniform=1.0, vr=False, vr_n0=0.0, vr_T0=1.0):
+    """Cell estimates from running sums (the library's dsmc_estimators):
+    columns n, u_x, u_y, u_z, T, P_xx, P_yy, P_zz, P_xy, P_xz, P_yz, q_x, q_y, q_z."""
+    L = load()
+    s = np.ascontiguousarray(sums, dtype=np.float64)
+    nc = s.shape[0]
+    vol = None if volume is None else np.ascontiguousarray(np.broadcast_to(volume, (nc,)), dtype=np.float64)
+    out = np.zeros((nc, NEST), dtype=np.float64)
+    check(L.dsmc_estimators(s.ctypes.data, nc, int(n_samples), float(FN), vol.ctypes.data if vol is not None else None,
+                            float(volume_uniform), int(bool(vr)), float(vr_n0), float(vr_T0), out.ctypes.data),
+          "dsmc_estimators")
+    return out
 
 
 class Soa(ctypes.Structure):
@@ -82,12 +104,17 @@ def load():
         "dsmc_particles": [P, P],
         "dsmc_diagnostics": [P, P],
         "dsmc_set_step": [P, ctypes.c_uint64],
-        "dsmc_set_majorant_model": [P, P, I64, D],
+        "dsmc_set_majorant_model": [P, P, I64, D, I32],
         "dsmc_checkpoint": [P, P, P],
         "dsmc_restore": [P, P, ctypes.c_size_t],
         "dsmc_profile_step": [P, P, I32, P, P, I32],
         "dsmc_destroy": [P],
-        "dsmc_collect_features": [P, P, P, P],
+        "dsmc_collect_features": [P, P, P, P, P],
+        "dsmc_estimators": [P, I64, ctypes.c_uint64, D, P, D, I32, D, D, P],
+        "dsmc_mlp_standardize": [P, P, I64, P, P, P, P],
+        "dsmc_mlp_fold_inputs": [P, P, P],
+        "dsmc_mlp_to_bf16": [P, I64, P, P],
+        "dsmc_mlp_calibrate": [P, P, P, P, P, I64, P, P, ctypes.c_size_t, P, P, P, P],
         "dsmc_mlp_forward": [P, P, I64, P, P],
         "dsmc_mlp_loss_grad": [P, P, P, I64, D, P, P, P, P],
         "dsmc_mlp_loss_grad_noalloc": [P, P, P, I64, D, P, P, P],
@@ -101,6 +128,8 @@ def load():
     L.dsmc_status_string.restype = ctypes.c_char_p
     L.dsmc_mlp_scratch_floats.argtypes = [I64]
     L.dsmc_mlp_scratch_floats.restype = I64
+    L.dsmc_mlp_calib_work_bytes.argtypes = [I64]
+    L.dsmc_mlp_calib_work_bytes.restype = ctypes.c_size_t
     _lib = L
     return L
 
@@ -290,7 +319,7 @@ class Simulation:
         nm = names.value.decode().split("\n")[: nk.value]
         return list(zip(nm, ms[: nk.value].tolist()))
 
-    def set_majorant_model(self, bf16_weights, delta):
+    def set_majorant_model(self, bf16_weights, delta, min_n=0):
         w = np.ascontiguousarray(bf16_weights, dtype=np.uint16)
-        check(self.L.dsmc_set_majorant_model(self.ctx, w.ctypes.data, w.size, float(delta)),
+        check(self.L.dsmc_set_majorant_model(self.ctx, w.ctypes.data, w.size, float(delta), int(min_n)),
               "dsmc_set_majorant_model")

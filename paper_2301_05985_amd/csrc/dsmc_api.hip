@@ -187,6 +187,7 @@ struct dsmc_ctx {
     float *mlp = nullptr;
     bool mlp_loaded = false;
     double mlp_delta = 0.0;
+    uint32_t mlp_min_n = 0;
     DevState *st = nullptr;
     Geo geo;
     double Vuni = 1.0;
@@ -256,6 +257,7 @@ CollideArgs<R> collide_args(dsmc_ctx *c, int src, int dst) {
     a.mlp = (c->cfg.majorant == DSMC_MAJORANT_LEARNED && c->mlp_loaded) ? c->mlp : nullptr;
     a.lattice = c->lattice;
     a.delta = c->mlp_delta;
+    a.mlp_min_n = c->mlp_min_n;
     a.vr_reest = c->cfg.vr ? c->cfg.vr_reconstruct : 0;
     a.vr_scale = c->cfg.vr ? 1.0 / std::sqrt(c->cfg.vr_T0) : 1.0;
     a.vr_kappa = c->cfg.vr ? c->cfg.vr_kappa : 1.0;
@@ -796,8 +798,9 @@ dsmc_status dsmc_set_step(dsmc_ctx *c, uint64_t next_step) {
     return DSMC_OK;
 }
 
-dsmc_status dsmc_set_majorant_model(dsmc_ctx *c, const uint16_t *bf16, int64_t n, double delta) {
-    if (!c || !bf16 || n != DSMC_MLP_NPARAM || c->cfg.majorant != DSMC_MAJORANT_LEARNED || !std::isfinite(delta))
+dsmc_status dsmc_set_majorant_model(dsmc_ctx *c, const uint16_t *bf16, int64_t n, double delta, int32_t min_n) {
+    if (!c || !bf16 || n != DSMC_MLP_NPARAM || c->cfg.majorant != DSMC_MAJORANT_LEARNED || !std::isfinite(delta) ||
+        min_n < 0)
         return DSMC_EINVAL;
     std::vector<float> in(DSMC_MLP_NPARAM), w(DSMC_MLP_NPARAM);
     for (int64_t i = 0; i < n; ++i) {
@@ -816,6 +819,7 @@ dsmc_status dsmc_set_majorant_model(dsmc_ctx *c, const uint16_t *bf16, int64_t n
     const bool was = c->mlp_loaded;
     c->mlp_loaded = true;
     c->mlp_delta = delta;
+    c->mlp_min_n = (uint32_t)min_n;
     // the collision kernel's arguments change: re-record the graphs
     for (int b = 0; b < 2; ++b) {
         if (c->g1[b]) { (void)hipGraphExecDestroy(c->g1[b]); c->g1[b] = nullptr; }
@@ -925,7 +929,43 @@ dsmc_status dsmc_profile_step(dsmc_ctx *c, float *ms_host, int32_t max_kernels, 
     return device_status(c);
 }
 
-dsmc_status dsmc_collect_features(dsmc_ctx *c, float *features, float *labels, float *bounds) {
+dsmc_status dsmc_estimators(const double *sums, int64_t n_cells, uint64_t n_samples, double FN,
+                            const double *volume, double volume_uniform, int32_t vr, double vr_n0, double vr_T0,
+                            double *out) {
+    if (!sums || !out || n_cells < 0 || n_samples == 0 || !(FN > 0)) return DSMC_EINVAL;
+    if (!volume && !(volume_uniform > 0)) return DSMC_EINVAL;
+    for (int64_t c = 0; c < n_cells; ++c) {
+        const double *S = sums + (size_t)c * DSMC_NSUM;
+        const double V = volume ? volume[c] : volume_uniform;
+        const double f = FN / (V * (double)n_samples);
+        // density-weighted moments <1>, <c_d>, <c_d c_e> (xx yy zz xy xz yz), <c_d |c|^2>
+        double d[13];
+        for (int k = 0; k < 13; ++k) d[k] = (vr ? S[13 + k] : S[k]) * f;
+        if (vr) {
+            d[0] += vr_n0;
+            for (int k = 4; k < 7; ++k) d[k] += vr_n0 * vr_T0;
+        }
+        double *o = out + (size_t)c * DSMC_NEST;
+        const double n = d[0];
+        const double u[3] = {d[1] / n, d[2] / n, d[3] / n};
+        const double uu = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
+        const double tr = (d[4] + d[5]) + d[6];
+        // full second-moment matrix from xx yy zz xy xz yz
+        const double M[3][3] = {{d[4], d[7], d[8]}, {d[7], d[5], d[9]}, {d[8], d[9], d[6]}};
+        o[0] = n;
+        o[1] = u[0]; o[2] = u[1]; o[3] = u[2];
+        o[4] = (tr / n - uu) / 3.0;
+        const int pd[6] = {0, 1, 2, 0, 0, 1}, pe[6] = {0, 1, 2, 1, 2, 2};
+        for (int k = 0; k < 6; ++k) o[5 + k] = M[pd[k]][pe[k]] - n * u[pd[k]] * u[pe[k]];
+        for (int a = 0; a < 3; ++a) {
+            const double ue = (u[0] * M[a][0] + u[1] * M[a][1]) + u[2] * M[a][2];
+            o[11 + a] = 0.5 * (((d[10 + a] - 2.0 * ue) - u[a] * tr) + 2.0 * n * u[a] * uu);
+        }
+    }
+    return DSMC_OK;
+}
+
+dsmc_status dsmc_collect_features(dsmc_ctx *c, float *features, float *labels, float *bounds, float *slimits) {
     if (!c || !features || !labels) return DSMC_EINVAL;
     if (c->sticky != DSMC_OK) return c->sticky;
     // the current buffer holds the particle sequence grouped by cell (walled
@@ -933,10 +973,10 @@ dsmc_status dsmc_collect_features(dsmc_ctx *c, float *features, float *labels, f
     HIP_TRY(hipStreamSynchronize(c->stream));
     if (c->cfg.real_bytes == 4)
         hipLaunchKernelGGL(k_collect_features<float>, dim3((unsigned)c->ncell), dim3(kCollectThreads), 0, c->stream,
-                           collide_args<float>(c, c->cur, c->cur), (int)c->ncell, features, labels, bounds);
+                           collide_args<float>(c, c->cur, c->cur), (int)c->ncell, features, labels, bounds, slimits);
     else
         hipLaunchKernelGGL(k_collect_features<double>, dim3((unsigned)c->ncell), dim3(kCollectThreads), 0, c->stream,
-                           collide_args<double>(c, c->cur, c->cur), (int)c->ncell, features, labels, bounds);
+                           collide_args<double>(c, c->cur, c->cur), (int)c->ncell, features, labels, bounds, slimits);
     HIP_TRY(hipGetLastError());
     return DSMC_OK;
 }

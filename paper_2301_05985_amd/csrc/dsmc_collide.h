@@ -58,6 +58,7 @@ struct CollideArgs {
     const float *mlp;              // [4673] FP32 weights or null
     const double *lattice;         // lattice values 2^(k/64), k in [-4096, 4096]
     double delta;
+    uint32_t mlp_min_n;            // cells of fewer particles skip the network
     // importance weights: re-estimation every vr_reest steps (0: never) with
     // velocities scaled by vr_scale = 1 / sqrt(T0); majorant factor vr_kappa
     int vr_reest;

@@ -509,12 +509,17 @@ __global__ __launch_bounds__(64) void k_collide_persistent(CollideArgs<R> a, con
 // pairs, in double); -inf for cells with fewer than two particles.  A
 // workgroup of kCollectThreads per cell: the pairs are spread over all its
 // threads (the maximum does not depend on the order), the O(N) features and
-// bound are taken on the first wave.
+// bound are taken on the first wave.  Optionally log2 of the exact bound and
+// log2 of the 65th largest r_p + r_(1) (radii about the velocity box
+// midpoint, as in the verification; -inf when N <= 64): a proposal passes
+// the verification's limit |S| <= 64 exactly when its verification
+// threshold is at least that value.  It is found by bisection on the
+// threshold (60 halvings of [0, 2 r_(1)], counting the members above it).
 constexpr int kCollectThreads = 256;
 
 template <typename R>
 __global__ __launch_bounds__(kCollectThreads) void k_collect_features(CollideArgs<R> a, int ncell, float *feat,
-                                                                      float *label, float *bound) {
+                                                                      float *label, float *bound, float *slim) {
     __shared__ double wave_best[kCollectThreads / 64];
     const int lane = lane_id();
     const uint32_t tid = threadIdx.x;
@@ -527,6 +532,7 @@ __global__ __launch_bounds__(kCollectThreads) void k_collect_features(CollideArg
         if (tid < 6) feat[(size_t)cell * 6 + tid] = 0.0f;
         if (tid == 0) label[cell] = -INFINITY;
         if (tid == 0 && bound) bound[cell] = -INFINITY;
+        if (tid == 0 && slim) slim[cell] = -INFINITY;
         return;
     }
     double best = 0.0;
@@ -551,10 +557,32 @@ __global__ __launch_bounds__(kCollectThreads) void k_collect_features(CollideArg
     const Features F = cell_features<R>(v, N, a.FN, V);
     if (lane < 6) feat[(size_t)cell * 6 + lane] = F.f[lane == 0 ? 0 : lane == 1 ? 1 : lane == 2 ? 2 : lane == 3 ? 3 : lane == 4 ? 4 : 5];
     if (lane == 0) label[cell] = (float)log2(sqrt(best));
-    if (bound) {
-        double rt;
-        const double gb = exact_bound<R>(v, N, rt);
-        if (lane == 0) bound[cell] = (float)log2(gb);
+    if (bound || slim) {
+        double rt, mid[3];
+        const double gb = exact_bound<R>(v, N, rt, nullptr, mid);
+        if (lane == 0 && bound) bound[cell] = (float)log2(gb);
+        if (slim) {
+            float out = -INFINITY;
+            if (N > 64u) {
+                const auto above = [&](double thr) {
+                    uint32_t cnt = 0;
+                    for (uint32_t r = lane; r < N; r += 64) {
+                        R x, y, z;
+                        v.get(r, x, y, z);
+                        const double dx = (double)x - mid[0], dy = (double)y - mid[1], dz = (double)z - mid[2];
+                        cnt += (sqrt((dx * dx + dy * dy) + dz * dz) + rt > thr) ? 1u : 0u;
+                    }
+                    return wave_sum_u32(cnt);
+                };
+                double lo = 0.0, hi = 2.0 * rt * (1.0 + 0x1.0p-40) + 1e-300;
+                for (int it = 0; it < 60; ++it) {
+                    const double m = 0.5 * (lo + hi);
+                    if (above(m) <= 64u) hi = m; else lo = m;
+                }
+                out = (float)log2(hi);
+            }
+            if (lane == 0) slim[cell] = out;
+        }
     }
 }
 

@@ -133,6 +133,9 @@ __device__ double learned_majorant(const CollideArgs<R> &a, const View &v, uint3
     double r1, mid[3];
     double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // moment sums of this thread's particles
     const double gb = exact_bound<R, View, T, true>(v, N, r1, gs, mid, q);
+    // size gate: cells too small to repay the network and the verification
+    // take the exact bound directly
+    if (N < a.mlp_min_n) { used = 0; return gb; }
     // the proposal: on the first wave only (shared through LDS in a workgroup)
     double S = wave_sums_to_lanes(q);
     if constexpr (T > 64) {

@@ -147,3 +147,27 @@ def test_mlp_scratch_size_and_batch_limit(lib):
     assert rc == -1
     rc = lib.dsmc_mlp_loss_grad(fake, fake, fake, 16, 1.5, fake, fake, fake, None)
     assert rc == -1
+
+
+@pytest.mark.parametrize("vr", [False, True])
+def test_estimators_match_the_oracle(lib, vr):
+    # host arithmetic of the library against the oracle's numpy estimators
+    import oracle
+    rng = np.random.default_rng(12)
+    nc, ns = 40, 37
+    c = rng.standard_normal((nc, 200, 3)) * 1.3 + rng.standard_normal((nc, 1, 3)) * 0.4
+    w = 1.0 + 0.05 * rng.standard_normal((nc, 200))
+    x, y, z = c[..., 0], c[..., 1], c[..., 2]
+    s2 = x * x + y * y + z * z
+    q = np.stack([np.ones_like(x), x, y, z, x * x, y * y, z * z, x * y, x * z, y * z, x * s2, y * s2, z * s2], -1)
+    sums = np.concatenate([q.sum(1), ((1 - w)[..., None] * q).sum(1)], 1) * ns
+    V = rng.uniform(0.5, 2.0, nc)
+    ref = oracle.estimators(sums, ns, 2.0, V, vr=vr, vr_n0=300.0, vr_T0=1.2)
+    out = binding.estimators(sums, ns, 2.0, volume=V, vr=vr, vr_n0=300.0, vr_T0=1.2)
+    P = ref["P"]
+    want = np.concatenate([ref["n"][:, None], ref["u"], ref["T"][:, None],
+                           np.stack([P[:, 0, 0], P[:, 1, 1], P[:, 2, 2], P[:, 0, 1], P[:, 0, 2], P[:, 1, 2]], 1),
+                           ref["q"]], 1)
+    assert np.allclose(out, want, rtol=1e-12, atol=1e-9 * np.abs(want).max())
+    assert lib.dsmc_estimators(None, nc, ns, 2.0, None, 1.0, 0, 0.0, 1.0, None) == -1
+

@@ -154,3 +154,23 @@ def test_batched_full_size_conservation_fp32(gpu):
     _, cnt, _ = sim.sample()
     assert cnt[:, 1].sum() > 100000
     sim.close()
+
+
+def test_cavity_full_size_weights_stay_finite_over_10k_steps(gpu):
+    # the benchmark's cavity (6,553,600 particles, Kn 0.01, weights
+    # re-estimated every step) over the configuration's 10,000 steps: no
+    # cell's weighted sums turn non-finite and no device error is raised
+    _announce("cavity full size, weights re-estimated, 10000 steps")
+    from paper_2301_05985_amd.binding import Simulation
+    p, parts = W.cavity(Kn=0.01, real="f32")
+    p["vr_reconstruct"] = 1
+    sim = Simulation(p, parts)
+    for _ in range(10):
+        sim.step(1000)
+        d = sim.diagnostics()
+        print("steps %d vr_nonfinite %d" % (d["steps"], d["vr_nonfinite"]), flush=True)
+        assert d["status"] == 0 and d["vr_nonfinite"] == 0, d
+    w = sim.particles()["w"].astype(np.float64)
+    sim.close()
+    print("max |W - 1| %.3g, rms %.3g" % (np.abs(w - 1).max(), np.sqrt(np.mean((w - 1) ** 2))), flush=True)
+    assert np.isfinite(w).all()

@@ -85,20 +85,102 @@ def test_collected_features_and_labels_match_oracle(gpu):
     from paper_2301_05985_amd.binding import Simulation
     p, parts = W.batched(n_inst=64, nmin=1, nmax=400, real="f32", steps=1)
     sim = Simulation(p, parts)
-    f, y = learned.collect(sim)
-    f, y = f.cpu().numpy(), y.cpu().numpy()
+    f, y, bd, sl = (t.cpu().numpy() for t in learned.collect(sim, with_bound=True))
     off = p["inst_offset"]
     c = [np.asarray(parts[k], dtype=np.float32) for k in ("cx", "cy", "cz")]
+    big = 0
     for b in range(64):
         s, e = off[b], off[b + 1]
         if e - s < 2:
-            assert y[b] == -np.inf
+            assert y[b] == -np.inf and bd[b] == -np.inf and sl[b] == -np.inf
             continue
         fo = oracle.features(c[0][s:e], c[1][s:e], c[2][s:e], 1.0, 1.0, dtype=np.float32)
         assert np.abs(f[b] - fo).max() <= 1e-6 * max(1.0, np.abs(fo).max()), (b, f[b], fo)
         d = oracle.diameter(c[0][s:e], c[1][s:e], c[2][s:e], dtype=np.float32)
         assert abs(y[b] - math.log2(d)) <= 1e-6
+        assert abs(bd[b] - math.log2(oracle.exact_bound(c[0][s:e], c[1][s:e], c[2][s:e], np.float32))) <= 1e-6
+        # the |S| <= 64 threshold: the 65th largest r_p + r_(1) (numpy)
+        v = np.stack([c[k][s:e].astype(np.float64) for k in range(3)])
+        mid = 0.5 * (v.max(1) + v.min(1))
+        r = np.sqrt(((v - mid[:, None]) ** 2).sum(0))
+        t = np.sort(r + r.max())[::-1]
+        if e - s <= 64:
+            assert sl[b] == -np.inf
+        else:
+            big += 1
+            assert abs(sl[b] - math.log2(t[64])) <= 1e-6, (b, sl[b], math.log2(t[64]))
+    assert big > 10
     sim.close()
+
+
+def test_standardize_fold_and_bf16_export(gpu):
+    # statistics against numpy, the fold against the network on standardised
+    # inputs, the bfloat16 rounding against torch's conversion
+    _announce("standardize, fold, bf16")
+    import torch
+    from paper_2301_05985_amd import learned
+    rng = np.random.default_rng(8)
+    n = 5000
+    x = (rng.standard_normal((n, 6)) * [1, 2, 0.5, 3, 0.1, 0.2] + [8, -1, 0.3, 1, 0.05, 0]).astype(np.float32)
+    y = rng.standard_normal(n).astype(np.float32)
+    y[::13] = -np.inf
+    xg, yg = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    xs, stats_dev, stats = learned.standardize(xg, yg)
+    ok = np.isfinite(y)
+    xd = x[ok].astype(np.float64)
+    assert np.allclose(stats[:6], xd.mean(0), rtol=1e-12, atol=1e-12)
+    assert np.allclose(stats[6:12], xd.std(0, ddof=1), rtol=1e-10)
+    assert abs(stats[12] - y[ok].astype(np.float64).mean()) < 1e-12 and stats[13] == ok.sum()
+    ref = ((x.astype(np.float64) - stats[:6]) / stats[6:12]).astype(np.float32)
+    assert np.array_equal(xs.cpu().numpy(), ref)
+    p = torch.from_numpy((M.init_params(3) * 0.3).astype(np.float32)).cuda()
+    before = learned.forward(p, xs).cpu().numpy()
+    bits_dev, bits = learned.export_bf16(p, stats_dev)
+    after = learned.forward(p, xg).cpu().numpy()
+    assert np.abs(after - before).max() <= 1e-4 * (1 + np.abs(before).max())
+    assert np.array_equal(bits, p.to(torch.bfloat16).view(torch.int16).cpu().numpy().view(np.uint16))
+
+
+def test_calibration_table_matches_its_definition(gpu):
+    # the library's table against the definition evaluated with numpy on the
+    # same network outputs, for several margins
+    _announce("calibration table")
+    import torch
+    from paper_2301_05985_amd import binding, learned
+    xv, yv, bv, sv = learned.generate(seeds=(7,), steps=8, every=4, n_inst=512, nmin=20, nmax=1200, with_bound=True)
+    net = _synthetic_net(5, float(np.nanmedian(yv.cpu().numpy()[np.isfinite(yv.cpu().numpy())])))
+    bits_dev = torch.from_numpy(M.to_bf16(net).view(np.int16)).cuda()
+    sigma, dt = 0.01, 0.05
+    costs = dict(cost_network=3.0, cost_member=0.01, cost_verify=5.0)
+    delta, min_n, table = learned.calibrate(bits_dev, xv, yv, bv, sv, sigma, dt, costs=costs)
+    ypred = learned.forward(bits_dev.view(torch.bfloat16).float(), xv).cpu().numpy().astype(np.float64)
+    x, lab, bnd, slm = (t.cpu().numpy().astype(np.float64) for t in (xv, yv, bv, sv))
+    N = np.rint(np.exp2(x[:, 0]))
+    keep = np.isfinite(lab) & (N >= 2)
+    edges = 64.0 * 2.0 ** np.arange(binding.CALIB_NBINS - 1)
+    bins = np.searchsorted(edges, N, side="right")
+    for j in (0, 40, 64, 90, 127):
+        d = -0.64 + 0.01 * j
+        k = np.clip(np.ceil(64.0 * (ypred + d)), -4096, 4096)
+        gp = k / 64.0
+        ver = keep & (gp < bnd)
+        gv = gp + math.log2(1.0 - 2.0 ** -20)
+        used = ver & (gv >= lab) & (gv >= slm)
+        gain = np.where(used, 0.5 * sigma * dt * N * (N - 1) * (np.exp2(bnd) - np.exp2(gp)), 0.0)
+        cost = np.where(keep, costs["cost_network"] + np.where(ver, N * costs["cost_member"] + costs["cost_verify"], 0),
+                        0)
+        for b in range(binding.CALIB_NBINS):
+            m = bins == b
+            assert table[j, b, 2] == (used & m).sum() and table[j, b, 3] == (ver & ~used & m).sum(), (j, b)
+            assert abs(table[j, b, 0] - gain[m].sum()) <= 1e-3 * (1 + m.sum())
+            assert abs(table[j, b, 1] - cost[m].sum()) <= 1e-3 * (1 + m.sum())
+    # the returned margin and gate maximise the net saving over the table
+    net_gain = np.cumsum((table[:, :, 0] - table[:, :, 1])[:, ::-1], axis=1)[:, ::-1]
+    if net_gain.max() > 0:
+        jb, gb = np.unravel_index(np.argmax(net_gain), net_gain.shape)
+        assert abs(delta - (-0.64 + 0.01 * jb)) < 1e-12 and min_n == (0 if gb == 0 else 32 << gb)
+    else:
+        assert min_n == 2 ** 31 - 1
 
 
 def _synthetic_net(seed, center):
@@ -129,7 +211,9 @@ def test_learned_collisions_bit_exact_against_oracle(gpu, real, sizes, mol):
          for b in range(n_inst)]
     net = _synthetic_net(7, math.log2(np.median(d)))
     delta = 0.01
-    q = dict(p, majorant=1, mlp=net, mlp_delta=delta)
+    # a size gate in the middle of the sizes: small cells skip the network
+    gate = int(np.median(np.diff(off))) if real == "f32" and mol == "hs" else 0
+    q = dict(p, majorant=1, mlp=net, mlp_delta=delta, mlp_min_n=gate)
     orc = oracle.Oracle(q, parts, dtype)
     log = orc.run(6, learned_log=True)
     if nmax <= 600:
@@ -139,7 +223,7 @@ def test_learned_collisions_bit_exact_against_oracle(gpu, real, sizes, mol):
     if real == "f64" and nmax > 2016:
         assert (np.diff(off) > 2016).any()  # FP64 LDS capacity without weights
     sim = Simulation(dict(p, majorant=1), parts)
-    sim.set_majorant_model(M.to_bf16(net), delta)
+    sim.set_majorant_model(M.to_bf16(net), delta, gate)
     sim.step(6)
     st, so = sim.particles(), orc.state()
     _, cnt, _ = sim.sample()
@@ -183,6 +267,10 @@ def test_training_reduces_candidates_at_equal_collision_rate(gpu):
     model = learned.train_model(n_epochs=6, seeds=(1, 2), val_seed=3, steps=64, every=4, n_inst=1024,
                                 log=lambda s: print(s, flush=True))
     assert model["loss_history"][-1] < model["loss_history"][0]
+    print("calibrated margin %.2f, size gate %d" % (model["delta"], model["min_n"]), flush=True)
+    # the network's effect on the candidates, with every cell using it (the
+    # size gate weighs that effect against the network's cost)
+    model = dict(model, min_n=0)
     p, parts = W.batched(n_inst=1024, real="f32", seed=0)
     a = Simulation(p, parts)
     b = learned.simulation_with_model(p, parts, model)

@@ -94,3 +94,26 @@ def test_learned_run_has_same_collision_rate_law():
     assert cb[0] < ca[0]                       # fewer candidates with the tighter majorant
     se = math.sqrt(ca[1] + cb[1])
     assert abs(ca[1] - cb[1]) < 5 * se          # same expected number of collisions
+
+
+def test_size_gate_reproduces_exact_run_for_small_cells():
+    # cells below the gate take the exact bound without the network: with
+    # the gate above every cell the run is the exact run bit for bit; with a
+    # gate inside the sizes only the cells at or above it use the proposal
+    p, parts = W.batched(n_inst=16, nmin=40, nmax=400, real="f32", steps=4)
+    sizes = np.diff(p["inst_offset"])
+    net = const_net(float(np.log2(6.0)))
+    a, b, log = _pair(dict(p, mlp_min_n=0), parts, net, steps=4)
+    q = dict(p, majorant=1, mlp=net, mlp_delta=0.0, mlp_min_n=10 ** 6)
+    c = oracle.Oracle(q, parts, np.float32)
+    logc = c.run(4, learned_log=True)
+    assert (logc == 0).all()
+    for k in ("cx", "cy", "cz"):
+        assert np.array_equal(getattr(a, k), getattr(c, k))
+    gate = int(np.median(sizes))
+    d = oracle.Oracle(dict(q, mlp_min_n=gate), parts, np.float32)
+    logd = d.run(4, learned_log=True)
+    small = sizes < gate
+    assert (logd[:, small] == 0).all()
+    assert np.array_equal(logd[:, ~small], log[:, ~small])
+
