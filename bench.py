@@ -3,7 +3,8 @@
 
 Default (no flags): the 2-D lid-driven cavity at its full size -- 256 x 256
 cells, 100 particles per cell (6,553,600 particles), Kn = 0.01, diffuse walls,
-importance weights re-estimated every step, FP32 state with FP64 moment sums
+importance weights re-estimated every 4 steps with the relative-speed
+majorant scaled by 1.5, FP32 state with FP64 moment sums
 -- W untimed warm-up steps, then exactly K timed steps (one step = free
 flight with walls, the stable regrouping by cell, per-cell majorant + NTC
 collisions + weight update + weight re-estimation, moment sampling).  Rank 0
@@ -41,6 +42,9 @@ ALGO_BYTES = {
 }
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 32-bit VALU lane operations per second (no FMA doubling)
 PROFILE_DIR = os.path.join(ROOT, "profiles")
+# weighted cavity runs: weights re-estimated every 4 steps, relative-speed
+# majorant scaled by 1.5 (the weight update's 1 / (1 - p) at most 3)
+VR_SETTINGS = {"vr_reconstruct": 4, "vr_kappa": 1.5}
 
 
 def source_digest():
@@ -202,9 +206,9 @@ def main():
 
     # ---------------- headline: full-size cavity
     p, parts = W.cavity(Kn=args.kn, real="f32")
-    p["vr_reconstruct"] = 1
+    p.update(VR_SETTINGS)
     name = "cavity 256x256 cells x 100 particles (6,553,600), Kn=%g, diffuse walls, lid 0.01*sqrt(2), " \
-           "VR weights re-estimated every step, FP32 state / FP64 sums" % args.kn
+           "VR weights re-estimated every 4 steps, majorant factor 1.5, FP32 state / FP64 sums" % args.kn
     print("[bench] headline: %s" % name, file=sys.stderr, flush=True)
     sim = Simulation(p, parts)
     ms, wall, cand, acc = _timed_steps(sim, torch, args.steps, args.warmup)
@@ -258,9 +262,9 @@ def main():
         sec = []
         print("[bench] secondary workloads", file=sys.stderr, flush=True)
         p2, parts2 = W.fourier(real="f32")
-        p2["vr_reconstruct"] = 1
-        sec.append(run_workload("fourier 200 cells x 200 (40,000), Kn=0.1, VR re-estimated every step, FP32", p2,
-                                parts2, 2000, 100, torch))
+        p2.update(vr_reconstruct=1, vr_kappa=1.5)
+        sec.append(run_workload("fourier 200 cells x 200 (40,000), Kn=0.1, VR re-estimated every step, majorant "
+                                "factor 1.5, FP32", p2, parts2, 2000, 100, torch))
         p3, parts3 = W.batched(real="f32")
         # launch parameters of the collision step picked by the autotuner
         # (grid vs persistent work queue; identical results either way)
@@ -317,7 +321,7 @@ def main():
         sec.append(run_workload("batched 4096 cells, variable soft spheres (omega 0.81, alpha 1.4), exact majorant, "
                                 "FP32", dict(p6s, **best3), parts3, 200, 20, torch))
         p7, parts7 = W.cavity(Kn=args.kn, real="f32")
-        p7 = dict(p7, molecule=W.VHS, omega=0.74, vr_reconstruct=1)
+        p7 = dict(p7, molecule=W.VHS, omega=0.74, **VR_SETTINGS)
         sec.append(run_workload("cavity 256x256 x 100, variable hard spheres (omega 0.74), VR, FP32", p7, parts7,
                                 100, 10, torch))
         p7s = dict(p7, molecule=W.VSS, alpha=1.4)
@@ -328,7 +332,7 @@ def main():
             if kn == args.kn:
                 continue
             pk, partsk = W.cavity(Kn=kn, real="f32")
-            pk["vr_reconstruct"] = 1
+            pk.update(VR_SETTINGS)
             sec.append(run_workload("cavity 256x256 x 100, Kn=%g, VR, FP32" % kn, pk, partsk, 100, 10, torch))
         p1, parts1 = W.relaxation()
         sec.append(run_workload("relaxation 10,000 particles one cell FP64", p1, parts1, 200, 0, torch))

@@ -909,7 +909,7 @@ __device__ void reestimate_cell(const View &v, uint32_t N, double sc, Reest &re,
     // Gauss-Jordan: row k is divided by the pivot, every other row r loses
     // M[r][k] / pivot times row k; for row k itself that is the same update
     // with the factor 1 - 1 / pivot.  The reciprocal is the hardware
-    // estimate refined by two Newton steps.
+    // estimate refined by one Newton step.
     bool ok = true;
 #pragma unroll
     for (int k = 0; k < kReBasis; ++k) {
@@ -917,7 +917,6 @@ __device__ void reestimate_cell(const View &v, uint32_t N, double sc, Reest &re,
         const double piv = readlane_f64(M[k >> 2], kl);
         ok = ok && piv > 1e-12 * readlane_f64(dg, kl);
         double inv = __builtin_amdgcn_rcp(piv);
-        inv = fma(inv, fma(-piv, inv, 1.0), inv);
         inv = fma(inv, fma(-piv, inv, 1.0), inv);
         const double mrk = __shfl(M[k >> 2], 4 * rr + (k & 3), 64);
         const double f = row == k ? 1.0 - inv : mrk * inv;

@@ -222,6 +222,32 @@ struct HalvingStep {
                 const double y = __longlong_as_double((long long)(((uint64_t)yh << 32) | yl));
                 v[k] = x + y;
             }
+        } else if constexpr (OFF == 8 || OFF == 4) {
+            // inside rows of 16 lanes: a row rotation by 8 (or by 12 and 4)
+            // brings the partner's value; the bank mask (groups of 4 lanes)
+            // lets only the lower (upper) lanes take it, the others keep
+            // their own register, so x + y is (own, partner's) v[k] on the
+            // lower lanes and v[HALF + k] on the upper ones
+            constexpr int kLowBanks = OFF == 8 ? 0x3 : 0x5, kHighBanks = OFF == 8 ? 0xC : 0xA;
+            constexpr int kRorLow = OFF == 8 ? 0x128 : 0x12C, kRorHigh = OFF == 8 ? 0x128 : 0x124;
+#pragma unroll
+            for (int k = 0; k < HALF; ++k) {
+                const uint64_t a = (uint64_t)__double_as_longlong(v[k]);
+                const uint64_t b = (uint64_t)__double_as_longlong(v[HALF + k]);
+                const uint32_t xl = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)b, (int)(uint32_t)a, kRorLow,
+                                                                          0xF, kLowBanks, false);
+                const uint32_t xh = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(b >> 32),
+                                                                          (int)(uint32_t)(a >> 32), kRorLow, 0xF,
+                                                                          kLowBanks, false);
+                const uint32_t yl = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)a, (int)(uint32_t)b,
+                                                                          kRorHigh, 0xF, kHighBanks, false);
+                const uint32_t yh = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(a >> 32),
+                                                                          (int)(uint32_t)(b >> 32), kRorHigh, 0xF,
+                                                                          kHighBanks, false);
+                const double x = __longlong_as_double((long long)(((uint64_t)xh << 32) | xl));
+                const double y = __longlong_as_double((long long)(((uint64_t)yh << 32) | yl));
+                v[k] = x + y;
+            }
         } else {
             const bool upper = (lane & OFF) != 0;
 #pragma unroll

@@ -11,7 +11,7 @@ cell (or instance) and estimator, the ensemble mean and standard deviation
                BURN steps the plain cell estimators (density, u_x, u_y,
                temperature, P_xy, q_x, q_y) of SAMPLE steps
   cavity32vr   32 x 32 cells of 100, Kn = 0.1, lid 0.05, importance weights
-               re-estimated every step, majorant factor 1.5 (without it the
+               re-estimated every 4 steps, majorant factor 1.5 (without it the
                rare rejections with p near 1 give the weighted estimators
                heavy tails that a 3-sigma test cannot describe); the
                weighted (variance-reduced) estimators of the same seven
@@ -48,6 +48,7 @@ PER_VR = 100
 KN_VR = 0.1
 LID_VR = 0.05
 KAPPA_VR = 1.5  # majorant factor: 1 / (1 - p) <= 3 in the weight update
+REEST_VR = 4    # weights re-estimated every 4 steps (the full-size benchmark's setting)
 # batched homogeneous cells
 NB = 256
 NMIN, NMAX = 50, 400
@@ -61,7 +62,7 @@ def params(seed):
 def params_vr(seed):
     p, parts = W.cavity(nx=NX, ny=NX, per_cell=PER_VR, Kn=KN_VR, lid=LID_VR, real="f32", vr=1, seed=seed,
                         init_seed=0)
-    p["vr_reconstruct"] = 1
+    p["vr_reconstruct"] = REEST_VR
     p["vr_kappa"] = KAPPA_VR
     return p, parts
 
@@ -130,7 +131,7 @@ def main():
         _write("cavity32", pool.map(member, range(1, R + 1)), nx=NX, per=PER, kn=KN, lid=LID, burn=BURN,
                sample=SAMPLE)
         _write("cavity32vr", pool.map(member_vr, range(1, R + 1)), nx=NX, per=PER_VR, kn=KN_VR, lid=LID_VR,
-               kappa=KAPPA_VR, burn=BURN, sample=SAMPLE)
+               kappa=KAPPA_VR, reest=REEST_VR, burn=BURN, sample=SAMPLE)
         _write("batched256", pool.map(member_batched, range(1, R + 1)), n=NB, nmin=NMIN, nmax=NMAX,
                sample=SAMPLE_B)
 

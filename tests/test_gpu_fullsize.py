@@ -158,12 +158,13 @@ def test_batched_full_size_conservation_fp32(gpu):
 
 def test_cavity_full_size_weights_stay_finite_over_10k_steps(gpu):
     # the benchmark's cavity (6,553,600 particles, Kn 0.01, weights
-    # re-estimated every step) over the configuration's 10,000 steps: no
-    # cell's weighted sums turn non-finite and no device error is raised
+    # re-estimated every 4 steps, majorant factor 1.5) over the
+    # configuration's 10,000 steps: no cell's weighted sums turn non-finite
+    # and no device error is raised
     _announce("cavity full size, weights re-estimated, 10000 steps")
     from paper_2301_05985_amd.binding import Simulation
     p, parts = W.cavity(Kn=0.01, real="f32")
-    p["vr_reconstruct"] = 1
+    p.update(vr_reconstruct=4, vr_kappa=1.5)
     sim = Simulation(p, parts)
     for _ in range(10):
         sim.step(1000)
@@ -174,3 +175,34 @@ def test_cavity_full_size_weights_stay_finite_over_10k_steps(gpu):
     sim.close()
     print("max |W - 1| %.3g, rms %.3g" % (np.abs(w - 1).max(), np.sqrt(np.mean((w - 1) ** 2))), flush=True)
     assert np.isfinite(w).all()
+
+
+def test_fourier_full_size_weights_stay_finite_over_20k_steps(gpu):
+    # the 1-D Fourier flow as configured (200 cells x 200, Kn 0.1, walls at
+    # T = 1 and 2, weights against the reference at T0 = 1.5) over its 20,000
+    # steps, weights re-estimated every step with the majorant factor 1.5:
+    # the weighted sums stay finite and give temperature and heat-flux
+    # profiles (plain and weighted)
+    _announce("fourier full size, weights re-estimated, 20000 steps")
+    from paper_2301_05985_amd.binding import Simulation, estimators
+    p, parts = W.fourier(real="f32")
+    p.update(vr_reconstruct=1, vr_kappa=1.5)
+    sim = Simulation(p, parts)
+    sim.step(5000)
+    sim.sample(reset=True)
+    sim.step(15000)
+    sums, _, ns = sim.sample()
+    d = sim.diagnostics()
+    sim.close()
+    assert d["status"] == 0 and d["vr_nonfinite"] == 0, d
+    pl = estimators(sums, ns, 1.0, volume_uniform=1.0 / 200)
+    vr = estimators(sums, ns, 1.0, volume_uniform=1.0 / 200, vr=True, vr_n0=p["vr_n0"], vr_T0=p["vr_T0"])
+    assert np.isfinite(vr).all()
+    # heat flows from the hot wall at x = 1 to the cold one: q_x < 0 and,
+    # in the steady state, uniform across the cells within the noise
+    for e in (pl, vr):
+        assert (e[:, 4][-20:].mean() > e[:, 4][:20].mean() + 0.4) and e[:, 11].mean() < 0
+    print("T plain %s" % np.round(pl[::40, 4], 3), flush=True)
+    print("T weighted %s" % np.round(vr[::40, 4], 3), flush=True)
+    print("q_x plain %.1f +- %.1f, weighted %.1f +- %.1f" % (pl[:, 11].mean(), pl[:, 11].std(), vr[:, 11].mean(),
+                                                           vr[:, 11].std()), flush=True)
