@@ -18,6 +18,7 @@ network is available, the learned majorant, and the single-cell relaxation).
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -118,10 +119,22 @@ def run_workload(name, p, parts, steps, warmup, torch):
     return out
 
 
-def kernel_profile(sim, torch, steps):
-    """Per-kernel durations (ms) from HIP events around every launch."""
+def kernel_profile(sim, torch, steps, period=1):
+    """Per-kernel durations (ms) from HIP events around every launch.  Each
+    profile_step advances two steps and times the second; `extra` more steps
+    between calls make the timed step index advance by a stride prime to
+    `period` (the weight re-estimation interval), so over a multiple of
+    `period` calls every residue of the step index modulo the period is
+    timed equally often and the averages are those of consecutive steps."""
     acc = {}
-    for _ in range(steps):
+    extra = 0
+    if period > 1:
+        steps = -(-steps // period) * period
+        while math.gcd(2 + extra, period) != 1:
+            extra += 1
+    for i in range(steps):
+        if extra and i > 0:
+            sim.step(extra)
         for name, ms in sim.profile_step():
             acc.setdefault(name, []).append(ms)
     return {k: float(np.mean(v)) for k, v in acc.items()}
@@ -176,7 +189,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--cpu-steps64", type=int, default=6)
-    ap.add_argument("--profile-steps", type=int, default=10)
+    ap.add_argument("--profile-steps", type=int, default=12)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 512 MiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -215,7 +228,7 @@ def main():
     n = len(parts["cx"])
     value = n * args.steps / (ms * 1e-3)
     print("[bench] timed %d steps: %.3f ms/step" % (args.steps, ms / args.steps), file=sys.stderr, flush=True)
-    prof = kernel_profile(sim, torch, args.profile_steps)
+    prof = kernel_profile(sim, torch, args.profile_steps, period=max(int(p.get("vr_reconstruct", 0)), 1))
     diag = sim.diagnostics()
     sim.close()
     del sim

@@ -118,6 +118,12 @@ typedef struct {
                                  relative-speed majorant, so that the acceptance probability p of
                                  every candidate is at most 1 / kappa and the weight update's
                                  1 / (1 - p) at most kappa / (kappa - 1) */
+    int32_t wide_min;         /* homogeneous instances, grid schedule: instances of more than this
+                                 many particles run on a workgroup of four waves (0 -> 1024, else
+                                 at least 64; DSMC_EINVAL otherwise).  Changes no result. */
+    int32_t occupancy;        /* homogeneous instances, grid schedule: waves per SIMD the one-wave
+                                 collision kernel is compiled for, 5 or 6 (0 -> 5; DSMC_EINVAL
+                                 otherwise).  Changes no result. */
 } dsmc_config;
 
 /* How homogeneous instances are distributed over the GPU.  Both process the

@@ -10,6 +10,13 @@ instances are processed, never their arithmetic (every draw is keyed by
 instance, step and candidate), so all candidates give identical results and
 the tuner may pick purely on time.
 
+When the grid schedule wins, two of its kernel parameters are refined one at
+a time (coordinate descent from the defaults): ``wide_min``, the size above
+which an instance runs on a four-wave workgroup instead of one wave, and, for
+weighted runs, ``occupancy``, the waves per SIMD the one-wave kernel is
+compiled for (5, or 6 with a few register spills).  Neither changes a bit of
+the result either.
+
 The tuner times each candidate on a scratch simulation built from a copy of
 the caller's initial state and caches the winner in a JSON file keyed by the
 GPU architecture and a signature of the workload (kind, precision, weights,
@@ -26,7 +33,10 @@ CANDIDATES = [GRID] + [
     {"schedule": 1, "persistent_waves": w, "chunk_work": c}
     for w in (1024, 2048, 4096) for c in (0, 256, 1024)
 ]
-LAUNCH_KEYS = ("schedule", "persistent_waves", "chunk_work")
+LAUNCH_KEYS = ("schedule", "persistent_waves", "chunk_work", "wide_min", "occupancy")
+# refinements of the grid schedule, each tried against the best so far
+WIDE_MIN = (512, 2048)
+OCCUPANCY = (6,)
 
 
 def cache_path():
@@ -88,11 +98,24 @@ def time_candidate(params, particles, cand, steps=8, warmup=8, model=None):
         sim.close()
 
 
-def tune(params, particles, candidates=None, steps=8, warmup=8, model=None, use_cache=True, log=None):
+def refinements(params, best):
+    """Axes (key, values) of the second stage for a first-stage winner."""
+    if best.get("schedule", 0) != 0:
+        return []
+    axes = [("wide_min", WIDE_MIN)]
+    if params.get("vr", 0):
+        axes.append(("occupancy", OCCUPANCY))
+    return axes
+
+
+def tune(params, particles, candidates=None, steps=8, warmup=8, model=None, use_cache=True, log=None,
+         refine=None):
     """Return (best launch parameters, {candidate label: ms per step}).
 
     Walled workloads have a single schedule and return it untimed.
-    ``model`` is ``(bf16_weights, delta, min_n)`` for learned-majorant runs."""
+    ``model`` is ``(bf16_weights, delta, min_n)`` for learned-majorant runs.
+    ``refine`` (default: only when ``candidates`` is not given) adds the
+    coordinate-descent stage over the grid schedule's kernel parameters."""
     if params.get("dims", 0) != 0:
         return dict(GRID), {}
     key = "%s/%s" % (_arch(), signature(params))
@@ -101,16 +124,26 @@ def tune(params, particles, candidates=None, steps=8, warmup=8, model=None, use_
         hit = _load_cache(path).get(key)
         if hit is not None:
             return {k: hit["best"][k] for k in hit["best"] if k in LAUNCH_KEYS}, hit.get("times", {})
+    if refine is None:
+        refine = candidates is None
     times = {}
     best, best_t = None, float("inf")
-    for cand in candidates or CANDIDATES:
-        label = json.dumps(cand, sort_keys=True)
-        t = time_candidate(params, particles, cand, steps, warmup, model)
-        times[label] = t
-        if log:
-            log("autotune %s: %.4f ms/step" % (label, t))
-        if t < best_t:
-            best, best_t = dict(cand), t
+
+    def run(cands):
+        nonlocal best, best_t
+        for cand in cands:
+            label = json.dumps(cand, sort_keys=True)
+            t = time_candidate(params, particles, cand, steps, warmup, model)
+            times[label] = t
+            if log:
+                log("autotune %s: %.4f ms/step" % (label, t))
+            if t < best_t:
+                best, best_t = dict(cand), t
+
+    run(candidates or CANDIDATES)
+    if refine:
+        for axis, values in refinements(params, best):
+            run([dict(best, **{axis: v}) for v in values])
     if use_cache:
         table = _load_cache(path)
         table[key] = {"best": best, "times": times}

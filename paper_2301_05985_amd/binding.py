@@ -42,7 +42,7 @@ class Config(ctypes.Structure):
         ("inst_offset", ctypes.c_void_p), ("max_wall_hits", ctypes.c_int32),
         ("schedule", ctypes.c_int32), ("persistent_waves", ctypes.c_int32), ("vr_reconstruct", ctypes.c_int32),
         ("chunk_work", ctypes.c_int64), ("omega", ctypes.c_double), ("alpha", ctypes.c_double),
-        ("vr_kappa", ctypes.c_double),
+        ("vr_kappa", ctypes.c_double), ("wide_min", ctypes.c_int32), ("occupancy", ctypes.c_int32),
     ]
 
 
@@ -167,6 +167,8 @@ def make_config(p, n_particles):
     c.alpha = float(p.get("alpha", 1.0))
     c.vr_reconstruct = int(p.get("vr_reconstruct", 0))
     c.vr_kappa = float(p.get("vr_kappa", 1.0))
+    c.wide_min = int(p.get("wide_min", 0))
+    c.occupancy = int(p.get("occupancy", 0))
     return c
 
 

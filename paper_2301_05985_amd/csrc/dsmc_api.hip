@@ -31,7 +31,7 @@ namespace {
 
 constexpr int kGraphSteps = 8;  // steps recorded per graph (even: the sort ping-pongs)
 constexpr unsigned kWallGrid = 256;  // workgroups of the wall-flight kernel (grid-stride)
-constexpr uint32_t kWideMin = 1024;  // homogeneous instances above this size run on a workgroup of waves
+constexpr uint32_t kWideMin = 1024;  // default: homogeneous instances above this size run on a workgroup of waves
 constexpr size_t kAlign = 256;
 constexpr size_t kMaxLds = 64 * 1024;
 
@@ -69,6 +69,8 @@ dsmc_status validate(const dsmc_config *c) {
     if (c->vr && !(c->vr_T0 > 0)) return DSMC_EINVAL;
     if (c->vr_reconstruct < 0 || !(c->vr_kappa == 0.0 || c->vr_kappa >= 1.0) || !(c->vr_kappa <= 16.0))
         return DSMC_EINVAL;
+    if (c->wide_min < 0 || (c->wide_min > 0 && c->wide_min < 64)) return DSMC_EINVAL;
+    if (c->occupancy != 0 && c->occupancy != 5 && c->occupancy != 6) return DSMC_EINVAL;
     if (c->dims >= 1) {
         if (!(c->length[0] > 0) || (c->dims == 2 && !(c->length[1] > 0))) return DSMC_EINVAL;
         for (int k = 0; k < (c->dims == 2 ? 4 : 2); ++k) {
@@ -280,6 +282,19 @@ struct Launcher {
     }
 };
 
+// One-wave collision kernel with the configured occupancy variant
+// (homogeneous instances on the grid schedule; walled runs always take the
+// default).  Six waves per SIMD fits the weighted kernel into 80 registers at
+// the price of a few spills; without weights both variants are the same code.
+template <typename R, bool VR, int D>
+void launch_collide_wave(dsmc_ctx *c, dim3 grid, size_t lds, hipStream_t s, const CollideArgs<R> &a) {
+    const int occ = D == 0 ? c->cfg.occupancy : 0;
+    if (D == 0 && occ == 6)
+        hipLaunchKernelGGL((k_collide<R, VR, D, 6>), grid, dim3(64), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_collide<R, VR, D, 5>), grid, dim3(64), lds, s, a);
+}
+
 template <typename R, bool VR, int D>
 void launch_collide(dsmc_ctx *c, Launcher &L, int src, int slot) {
     CollideArgs<R> a = collide_args<R>(c, src, D == 0 ? src : src ^ 1);
@@ -312,14 +327,13 @@ void launch_collide(dsmc_ctx *c, Launcher &L, int src, int slot) {
                 hipLaunchKernelGGL((k_collide_learned<R, VR, D>), dim3((unsigned)(c->ncell - c->nwide)), dim3(64),
                                    c->lds_small, L.s, as);
             else
-                hipLaunchKernelGGL((k_collide<R, VR, D>), dim3((unsigned)(c->ncell - c->nwide)), dim3(64),
-                                   c->lds_small, L.s, as);
+                launch_collide_wave<R, VR, D>(c, dim3((unsigned)(c->ncell - c->nwide)), c->lds_small, L.s, as);
         }
     } else if (learned)
         hipLaunchKernelGGL((k_collide_learned<R, VR, D>), dim3((unsigned)c->ncell), dim3(64), c->lds,
                            L.s, a);
     else
-        hipLaunchKernelGGL((k_collide<R, VR, D>), dim3((unsigned)c->ncell), dim3(64), c->lds, L.s, a);
+        launch_collide_wave<R, VR, D>(c, dim3((unsigned)c->ncell), c->lds, L.s, a);
     if (c->any_big_possible) {
         L.mark("collide_big");
         if (D == 0) {
@@ -622,11 +636,13 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
             k += cnt;
         }
         c->n_units = (uint32_t)units_host.size();
-        // wide instances: the prefix of the longest-first order above kWideMin
+        // wide instances: the prefix of the longest-first order above the
+        // configured threshold
+        const int64_t wide_min = cfg->wide_min > 0 ? cfg->wide_min : (int64_t)kWideMin;
         if (cfg->schedule == DSMC_SCHEDULE_GRID) {
             uint32_t nw = 0;
             while (nw < (uint32_t)c->ncell &&
-                   cfg->inst_offset[sched_host[nw] + 1] - cfg->inst_offset[sched_host[nw]] > (int64_t)kWideMin)
+                   cfg->inst_offset[sched_host[nw] + 1] - cfg->inst_offset[sched_host[nw]] > (int64_t)wide_min)
                 ++nw;
             const size_t lw = std::max<size_t>((size_t)c->cap * per + 16 + 16 + sizeof(GroupScratch),
                                                (size_t)13 * 66 * 8);

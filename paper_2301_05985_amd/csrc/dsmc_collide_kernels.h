@@ -334,10 +334,11 @@ __device__ __forceinline__ void collide_big_body(const CollideArgs<R> &a) {
     }
 }
 
-// At least five waves per SIMD: the register budget that the LDS footprint
-// of a typical walled cell with weights also allows.
-template <typename R, bool VR, int D>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_collide(CollideArgs<R> a) {
+// At least OCC waves per SIMD (5 by default: the register budget that the
+// LDS footprint of a typical walled cell with weights also allows; 6 is
+// compiled too for homogeneous instances, where the autotuner picks one).
+template <typename R, bool VR, int D, int OCC = 5>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void k_collide(CollideArgs<R> a) {
     extern __shared__ __align__(16) unsigned char smem[];
     collide_lds_body<R, VR, D, false>(a, smem, a.sched ? a.sched[blockIdx.x] : blockIdx.x);
 }

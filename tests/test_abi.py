@@ -60,6 +60,8 @@ def test_workspace_size_valid_configs(lib):
     ("abi_version", 99, -7), ("dims", 3, -1), ("real_bytes", 2, -1), ("dt", 0.0, -1),
     ("FN", -1.0, -1), ("molecule", 5, -1), ("majorant", 7, -1), ("n_particles", -5, -1),
     ("schedule", 2, -1), ("persistent_waves", -1, -1), ("chunk_work", -3, -1),
+    ("vr_reconstruct", -1, -1), ("vr_kappa", 0.5, -1), ("vr_kappa", 17.0, -1), ("wide_min", 32, -1),
+    ("wide_min", -1, -1), ("occupancy", 4, -1), ("occupancy", 7, -1),
 ])
 def test_workspace_size_rejects_invalid(lib, field, value, code):
     p, parts = W.cavity(nx=4, ny=4, per_cell=5)
@@ -171,3 +173,23 @@ def test_estimators_match_the_oracle(lib, vr):
     assert np.allclose(out, want, rtol=1e-12, atol=1e-9 * np.abs(want).max())
     assert lib.dsmc_estimators(None, nc, ns, 2.0, None, 1.0, 0, 0.0, 1.0, None) == -1
 
+
+
+def test_grid_kernel_parameters_accepted(lib):
+    p, parts = W.batched(n_inst=8, nmin=10, nmax=20)
+    off = np.ascontiguousarray(p["inst_offset"], dtype=np.int64)
+    for over in (dict(wide_min=64), dict(wide_min=5000), dict(occupancy=5), dict(occupancy=6),
+                 dict(vr_kappa=16.0), dict(vr_reconstruct=4)):
+        cfg = binding.make_config(dict(p, **over), len(parts["cx"]))
+        cfg.inst_offset = off.ctypes.data
+        assert _ws(lib, cfg)[0] == 0, over
+
+
+def test_autotune_refines_only_the_grid_schedule():
+    from paper_2301_05985_amd import autotune
+    p, _ = W.batched(n_inst=64, nmin=10, nmax=200)
+    assert autotune.refinements(p, {"schedule": 1, "persistent_waves": 1024, "chunk_work": 0}) == []
+    assert [a for a, _ in autotune.refinements(p, dict(autotune.GRID))] == ["wide_min"]
+    assert [a for a, _ in autotune.refinements(dict(p, vr=1), dict(autotune.GRID))] == ["wide_min", "occupancy"]
+    for a, values in autotune.refinements(dict(p, vr=1), dict(autotune.GRID)):
+        assert a in autotune.LAUNCH_KEYS and len(values) > 0

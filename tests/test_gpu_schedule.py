@@ -2,8 +2,10 @@
 the grid launch and the persistent work-queue launch (any number of waves,
 any grouping of small instances into work units) give identical bits, with
 large instances routed through the global-memory kernel in both; the
-persistent launch matches the oracle bit for bit; the autotuner picks one of
-its candidates and caches it."""
+persistent launch matches the oracle bit for bit; so do the grid launch's
+kernel parameters (the four-wave size threshold, the occupancy variant); the
+autotuner picks one of its candidates, refines the grid schedule's
+parameters, and caches the result."""
 import json
 
 import numpy as np
@@ -21,6 +23,12 @@ SCHEDULES = [
     {"schedule": 1, "persistent_waves": 1024, "chunk_work": 256},
     {"schedule": 1, "persistent_waves": 2048, "chunk_work": 4000},
     {"schedule": 1, "persistent_waves": 8192, "chunk_work": 10 ** 6},
+    # grid schedule with its kernel parameters moved: every instance on one
+    # wave, most on four-wave workgroups, and the six-wave register budget
+    {"schedule": 0, "wide_min": 10 ** 6},
+    {"schedule": 0, "wide_min": 64},
+    {"schedule": 0, "wide_min": 512, "occupancy": 6},
+    {"schedule": 0, "occupancy": 5},
 ]
 
 
@@ -101,3 +109,33 @@ def test_autotune_picks_and_caches(gpu, tmp_path, monkeypatch):
     assert len(table) == 1
     again, t2 = autotune.tune(p, parts, candidates=cands)
     assert again == best and t2 == times
+
+
+def test_grid_parameters_match_oracle(gpu):
+    # weighted FP32 instances on the six-wave kernel, most of them on
+    # four-wave workgroups: bit-identical to the oracle
+    _announce("grid parameters vs oracle")
+    p, parts = W.batched(n_inst=64, nmin=10, nmax=300, real="f32", seed=11)
+    rng = np.random.default_rng(3)
+    p = dict(p, vr=1, schedule=0, wide_min=64, occupancy=6)
+    parts = dict(parts, w=1.0 + 0.05 * rng.standard_normal(len(parts["cx"])))
+    st, _, cnt, _ = _run(p, parts, 7)
+    orc = oracle.Oracle(p, parts, np.float32)
+    orc.run(7)
+    for k in ("cx", "cy", "cz", "w"):
+        assert np.array_equal(st[k], getattr(orc, k)), k
+    assert np.array_equal(cnt, orc.counters)
+
+
+def test_autotune_refines_grid(gpu, tmp_path, monkeypatch):
+    _announce("autotune refinement")
+    from paper_2301_05985_amd import autotune
+    monkeypatch.setenv("DSMC_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    p, parts = W.batched(n_inst=256, nmin=50, nmax=2000, real="f32", seed=4)
+    p = dict(p, vr=1)
+    parts = dict(parts, w=np.ones(len(parts["cx"])))
+    best, times = autotune.tune(p, parts, candidates=[autotune.GRID], refine=True, steps=4, warmup=4)
+    # the grid candidate, two thresholds, then the occupancy on the winner
+    assert len(times) == 1 + len(autotune.WIDE_MIN) + len(autotune.OCCUPANCY)
+    assert best["schedule"] == 0
+    assert set(best) <= set(autotune.LAUNCH_KEYS)
