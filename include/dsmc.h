@@ -52,7 +52,8 @@ typedef enum {
     DSMC_EHIP = -3,        /* a HIP runtime call failed */
     DSMC_ENONFINITE = -4,  /* a velocity became NaN or infinite */
     DSMC_EWALLHITS = -5,   /* a particle hit walls more than max_wall_hits times in one step */
-    DSMC_ECAPACITY = -6,   /* a per-cell candidate count or cell size exceeded the kernels' limits */
+    DSMC_ECAPACITY = -6,   /* a per-cell candidate count (at most 2^24 per step) or cell size
+                              exceeded the kernels' limits */
     DSMC_EABI = -7         /* abi_version mismatch */
 } dsmc_status;
 

@@ -720,7 +720,7 @@ static int collide_cell(const orc_cfg *cfg, soa_t *s, const int64_t *list, int64
     double U0 = u53(r[0], r[1]);
     double Mf = floor(Mreal + U0);
     if (!(Mf >= 0.0)) Mf = 0.0;
-    if (Mf > 2147483647.0) return ERR_CAPACITY;
+    if (Mf > 16777216.0) return ERR_CAPACITY; /* at most 2^24 candidates per cell and step */
     int64_t M = (int64_t)Mf;
     REAL gm = (REAL)gmax;
     uint64_t acc_count = 0;

@@ -288,11 +288,13 @@ struct Launcher {
 // the price of a few spills; without weights both variants are the same code.
 template <typename R, bool VR, int D>
 void launch_collide_wave(dsmc_ctx *c, dim3 grid, size_t lds, hipStream_t s, const CollideArgs<R> &a) {
-    const int occ = D == 0 ? c->cfg.occupancy : 0;
-    if (D == 0 && occ == 6)
-        hipLaunchKernelGGL((k_collide<R, VR, D, 6>), grid, dim3(64), lds, s, a);
-    else
-        hipLaunchKernelGGL((k_collide<R, VR, D, 5>), grid, dim3(64), lds, s, a);
+    if constexpr (D == 0) {
+        if (c->cfg.occupancy == 6) {
+            hipLaunchKernelGGL((k_collide<R, VR, D, 6>), grid, dim3(64), lds, s, a);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_collide<R, VR, D, 5>), grid, dim3(64), lds, s, a);
 }
 
 template <typename R, bool VR, int D>

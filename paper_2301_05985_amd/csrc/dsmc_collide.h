@@ -66,6 +66,10 @@ struct CollideArgs {
 };
 
 constexpr int kNsum = 26;
+// Most NTC candidates one cell may take in one step (2^24); a larger count
+// stops the step with DSMC_ECAPACITY, so that a run whose velocities have
+// blown up ends with an error instead of keeping a wave busy for minutes.
+constexpr double kMaxCandidates = 16777216.0;
 
 // A cell is processed by T threads: one wave (T = 64), or a workgroup of
 // T / 64 waves for large homogeneous instances.  Wave-level results of a
@@ -1152,7 +1156,7 @@ __device__ void process_cell(const CollideArgs<R> &a, const View &v, uint32_t ce
         const u32x4 r = draw(0, kTagNcand, 0, cell, step, a.k0, a.k1);
         double Mf = floor(Mreal + unif53(r.v[0], r.v[1]));
         if (!(Mf >= 0.0)) Mf = 0.0;
-        if (Mf > 2147483647.0) {
+        if (Mf > kMaxCandidates) {
             if (threadIdx.x == 0) set_error(a.st, DSMC_ECAPACITY);
             Mf = 0.0;
         }

@@ -271,7 +271,7 @@ __device__ void process_cell_learned(const CollideArgs<R> &a, const View &v, uin
         const u32x4 r = draw(0, kTagNcand, 0, cell, step, a.k0, a.k1);
         double Mf = floor(Mreal + unif53(r.v[0], r.v[1]));
         if (!(Mf >= 0.0)) Mf = 0.0;
-        if (Mf > 2147483647.0) {
+        if (Mf > kMaxCandidates) {
             if (threadIdx.x == 0) set_error(a.st, DSMC_ECAPACITY);
             Mf = 0.0;
         }

@@ -419,6 +419,23 @@ def test_too_many_wall_hits_is_reported(gpu):
     assert e.value.code == -5
 
 
+def test_runaway_candidate_count_is_reported(gpu):
+    # a cross-section 10^6 times too large asks for more than 2^24 candidates
+    # in a cell: the step stops with DSMC_ECAPACITY before its candidate loop,
+    # like the oracle
+    _announce("candidate count limit")
+    from paper_2301_05985_amd.binding import Simulation, DsmcError
+    p, parts = W.batched(n_inst=4, nmin=2000, nmax=3000, real="f32", seed=1)
+    p = dict(p, sigma=p["sigma"] * 1e6)
+    s = Simulation(p, parts)
+    s.step(1)
+    with pytest.raises(DsmcError) as e:
+        s.sample()
+    assert e.value.code == -6
+    with pytest.raises(RuntimeError, match="status -6"):
+        oracle.Oracle(p, parts, np.float32).run(1)
+
+
 @pytest.mark.parametrize("real", ["f64", "f32"])
 def test_diameter_majorant_bit_exact(gpu, real):
     # majorant = the largest pair speed of each cell (brute force)

@@ -307,6 +307,21 @@ def test_candidate_count_is_floor_of_mreal_plus_uniform():
     assert (o.counters[:, 1] == o.counters[:, 0]).all()  # Maxwell molecules accept all
 
 
+def test_candidate_count_limit():
+    # at most 2^24 candidates per cell and step; one more is a capacity error
+    # (Maxwell molecules: M_real = 1/2 (N - 1) dt exactly here)
+    N = 200
+    for M_real, ok in ((2.0 ** 24 - 2.0, True), (2.0 ** 24 + 1.5, False)):
+        p, parts = W.bkw(N=N, n_inst=1, K0=1.0, dt=M_real / (0.5 * (N - 1)), steps=1)
+        o = oracle.Oracle(p, parts)
+        if ok:
+            o.run(1)
+            assert o.counters[0, 0] in (2 ** 24 - 2, 2 ** 24 - 1)
+        else:
+            with pytest.raises(RuntimeError, match="status -6"):
+                o.run(1)
+
+
 def test_hard_sphere_acceptance_rate_matches_exact_mean_relative_speed():
     # Given the state, each candidate is accepted with probability g / g_max for
     # a uniformly drawn ordered pair: E[accepted] = E[M] * mean_pairs(g) / g_max.
