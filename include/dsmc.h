@@ -166,6 +166,9 @@ typedef struct {
     uint64_t learned_skip;    /* cell-steps whose proposal was not below the exact bound */
     uint64_t vr_nonfinite;    /* cell samples with non-finite weighted sums (weight divergence) */
     uint64_t big_cells;       /* cell-steps processed by the global-memory collision kernel */
+    uint64_t bounds_violations; /* kernel index checks that failed (bounds-checking build only) */
+    uint64_t bounds_checked;  /* 1 if the library was built with kernel index checks
+                                 (-DDSMC_BOUNDS_CHECK), else 0 */
 } dsmc_diag;
 
 /* Where a cell is collided.  A cell (or instance) is staged in the 64 KiB of

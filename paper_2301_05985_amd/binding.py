@@ -72,14 +72,16 @@ class Soa(ctypes.Structure):
 class Diag(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in (
         "steps", "candidates", "accepted", "overshoot", "wall_hits", "learned_used", "fallback",
-        "learned_skip", "vr_nonfinite", "big_cells")]
+        "learned_skip", "vr_nonfinite", "big_cells", "bounds_violations", "bounds_checked")]
 
 
 _lib = None
 
 
 def lib_path():
-    return _build.LIB
+    """The in-tree library, or the build named by DSMC_HIP_LIB (for instance
+    the bounds-checking variant, _lib/libdsmc_hip_bounds.so)."""
+    return os.environ.get("DSMC_HIP_LIB") or _build.LIB
 
 
 def load():

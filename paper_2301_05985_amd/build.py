@@ -15,6 +15,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libdsmc_hip.so")
+# the same sources with kernel index checks (-DDSMC_BOUNDS_CHECK): failed
+# checks are counted in dsmc_diag.bounds_violations; for tests
+LIB_BOUNDS = os.path.join(OUT_DIR, "libdsmc_hip_bounds.so")
 SOURCES = ["dsmc_api.hip", "dsmc_mlp.hip"]
 HEADERS = ["dsmc_device.h", "dsmc_kernels.h", "dsmc_collide.h", "dsmc_learned.h",
            "dsmc_collide_kernels.h"]
@@ -38,16 +41,29 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose=False):
-    """Compile every HIP source into the in-tree shared library (always rebuilds)."""
+def build(verbose=False, bounds=True):
+    """Compile every HIP source into the in-tree shared library and, unless
+    bounds is False, the bounds-checking variant beside it (both at once;
+    always rebuilds).  Returns the release library's path."""
     os.makedirs(OUT_DIR, exist_ok=True)
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), *FLAGS, "-I", os.path.join(ROOT, "include"),
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    jobs = []
+    for out, extra in ((LIB, []), (LIB_BOUNDS, ["-DDSMC_BOUNDS_CHECK"])):
+        if out == LIB_BOUNDS and not bounds:
+            continue
+        tmp = out + ".tmp%d" % os.getpid()
+        cmd = [hipcc(), *FLAGS, *extra, "-I", os.path.join(ROOT, "include"),
+               *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        jobs.append((subprocess.Popen(cmd), tmp, out, cmd))
+    failed = None
+    for proc, tmp, out, cmd in jobs:
+        if proc.wait() != 0:
+            failed = failed or subprocess.CalledProcessError(proc.returncode, cmd)
+        else:
+            os.replace(tmp, out)
+    if failed:
+        raise failed
     return LIB
 
 

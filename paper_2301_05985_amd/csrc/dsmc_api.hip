@@ -216,6 +216,8 @@ Regroup regroup_of(const dsmc_ctx *c) {
     r.far_src = c->far_src;
     r.far_next = c->far_next;
     r.slots = mover_slots(c->cfg);
+    r.n = (uint32_t)c->n;
+    r.ncell = (uint32_t)c->ncell;
     return r;
 }
 
@@ -263,6 +265,8 @@ CollideArgs<R> collide_args(dsmc_ctx *c, int src, int dst) {
     a.vr_reest = c->cfg.vr ? c->cfg.vr_reconstruct : 0;
     a.vr_scale = c->cfg.vr ? 1.0 / std::sqrt(c->cfg.vr_T0) : 1.0;
     a.vr_kappa = c->cfg.vr ? c->cfg.vr_kappa : 1.0;
+    a.n_total = (uint32_t)c->n;
+    a.n_cells = (uint32_t)c->ncell;
     return a;
 }
 
@@ -806,6 +810,10 @@ dsmc_status dsmc_diagnostics(dsmc_ctx *c, dsmc_diag *out) {
     out->learned_skip = tot[kDiagSkip];
     out->vr_nonfinite = tot[kDiagVrNonfinite];
     out->big_cells = tot[kDiagBig];
+    out->bounds_violations = tot[kDiagBounds];
+#ifdef DSMC_BOUNDS_CHECK
+    out->bounds_checked = 1;
+#endif
     return device_status(c);
 }
 

@@ -63,6 +63,7 @@ struct CollideArgs {
     // velocities scaled by vr_scale = 1 / sqrt(T0); majorant factor vr_kappa
     int vr_reest;
     double vr_scale, vr_kappa;
+    uint32_t n_total, n_cells;     // particles and cells (index checks of the bounds-checking build)
 };
 
 constexpr int kNsum = 26;
@@ -118,6 +119,35 @@ __device__ __forceinline__ void grp_sync() {
     if constexpr (T > 64) __syncthreads();
 }
 
+// Rank check of a cell view in the bounds-checking build: a rank at or
+// above the limit (the staged cell's capacity, or the size of a cell in
+// global memory) is counted in the diagnostics and replaced by rank 0.  The
+// release build keeps no state and returns the rank.
+struct ViewCheck {
+#ifdef DSMC_BOUNDS_CHECK
+    uint32_t lim = 0xFFFFFFFFu;
+    DevState *st = nullptr;
+#endif
+    __device__ __forceinline__ uint32_t operator()(uint32_t r) const {
+#ifdef DSMC_BOUNDS_CHECK
+        return st ? bounds_ck(r, lim, st) : r;
+#else
+        return r;
+#endif
+    }
+};
+__device__ __forceinline__ ViewCheck view_check(uint32_t lim, DevState *st) {
+    ViewCheck v{};
+#ifdef DSMC_BOUNDS_CHECK
+    v.lim = lim;
+    v.st = st;
+#else
+    (void)lim;
+    (void)st;
+#endif
+    return v;
+}
+
 // One particle of a cell staged in LDS: velocity and weight side by side,
 // so that a particle is read with one 16-byte access (two in double).
 template <typename R>
@@ -134,14 +164,19 @@ struct LdsView {
     static constexpr bool kInLds = true;
     Vel4<R> *p;
     uint32_t *owner;
+    ViewCheck ck;
     __device__ __forceinline__ void get(uint32_t r, R &a, R &b, R &c) const {
-        const Vel4<R> t = p[r];
+        const Vel4<R> t = p[ck(r)];
         a = t.x; b = t.y; c = t.z;
     }
-    __device__ __forceinline__ void put(uint32_t r, R a, R b, R c) const { p[r].x = a; p[r].y = b; p[r].z = c; }
-    __device__ __forceinline__ R getw(uint32_t r) const { return p[r].w; }
-    __device__ __forceinline__ void putw(uint32_t r, R v) const { p[r].w = v; }
+    __device__ __forceinline__ void put(uint32_t r, R a, R b, R c) const {
+        r = ck(r);
+        p[r].x = a; p[r].y = b; p[r].z = c;
+    }
+    __device__ __forceinline__ R getw(uint32_t r) const { return p[ck(r)].w; }
+    __device__ __forceinline__ void putw(uint32_t r, R v) const { p[ck(r)].w = v; }
     __device__ __forceinline__ uint32_t *own(uint32_t r) const {
+        r = ck(r);
         if constexpr (PACKED) return reinterpret_cast<uint32_t *>(&p[r].w);
         else return &owner[r];
     }
@@ -156,7 +191,11 @@ struct GlobalView {
     R *cx, *cy, *cz, *w;
     const uint32_t *perm;  // rank -> slot inside the cell, or null for the identity
     uint32_t *owner;
-    __device__ __forceinline__ uint32_t at(uint32_t r) const { return perm ? perm[r] : r; }
+    ViewCheck ck;
+    __device__ __forceinline__ uint32_t at(uint32_t r) const {
+        r = ck(r);
+        return perm ? ck(perm[r]) : r;
+    }
     __device__ __forceinline__ void get(uint32_t r, R &a, R &b, R &c) const {
         const uint32_t q = at(r); a = cx[q]; b = cy[q]; c = cz[q];
     }
@@ -165,14 +204,14 @@ struct GlobalView {
     }
     __device__ __forceinline__ R getw(uint32_t r) const { return w[at(r)]; }
     __device__ __forceinline__ void putw(uint32_t r, R v) const { w[at(r)] = v; }
-    __device__ __forceinline__ uint32_t *own(uint32_t r) const { return &owner[r]; }
+    __device__ __forceinline__ uint32_t *own(uint32_t r) const { return &owner[ck(r)]; }
     // the marks are set by device-scope atomics; read and clear them at the
     // same scope so no stale L1 line is seen
     __device__ __forceinline__ uint32_t read_own(uint32_t r) const {
-        return __hip_atomic_load(&owner[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return __hip_atomic_load(&owner[ck(r)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __device__ __forceinline__ void clear_own(uint32_t r) const {
-        __hip_atomic_store(&owner[r], 0xFFFFFFFFu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&owner[ck(r)], 0xFFFFFFFFu, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 };
 
@@ -1107,10 +1146,11 @@ __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cel
     const bool nonfinite = writer && !isfinite(tot);
     const bool bad_plain = __ballot(nonfinite && idx < 13) != 0ull;
     const bool bad_vr = __ballot(nonfinite && idx >= 13) != 0ull;
-    if (writer) a.sums[(size_t)cell * kNsum + idx] = pf.sum + tot;
+    const uint32_t ce = bounds_ck(cell, a.n_cells, a.st);
+    if (writer) a.sums[(size_t)ce * kNsum + idx] = pf.sum + tot;
     if (tid == 0) {
-        a.counters[2 * (size_t)cell] = pf.cand + M;
-        a.counters[2 * (size_t)cell + 1] = pf.acc + acc;
+        a.counters[2 * (size_t)ce] = pf.cand + M;
+        a.counters[2 * (size_t)ce + 1] = pf.acc + acc;
         if (over) diag_add(a.st, kDiagOvershoot, (unsigned long long)over);
         if (bad_plain) set_error(a.st, DSMC_ENONFINITE);
         if (bad_vr) diag_add(a.st, kDiagVrNonfinite, 1ull);

@@ -210,6 +210,7 @@ __device__ __forceinline__ void gather_j(const CollideArgs<R> &a, uint32_t base,
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         if (e0 + 64u * (uint32_t)j + lane < N) {
+            q[j] = bounds_ck(q[j], a.n_total, a.st);
             x[j] = a.src.x[q[j]];
             if (D == 2) y[j] = a.src.y[q[j]];
             c0[j] = a.src.cx[q[j]]; c1[j] = a.src.cy[q[j]]; c2[j] = a.src.cz[q[j]];
@@ -220,7 +221,7 @@ __device__ __forceinline__ void gather_j(const CollideArgs<R> &a, uint32_t base,
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         if (e0 + 64u * (uint32_t)j + lane < N) {
-            const uint32_t o = base + (r[j] < N ? r[j] : N - 1);
+            const uint32_t o = bounds_ck(base + (r[j] < N ? r[j] : N - 1), a.n_total, a.st);
             a.s.x[o] = x[j];
             if (D == 2) a.s.y[o] = y[j];
             a.s.id[o] = id[j];
@@ -296,7 +297,7 @@ __device__ __forceinline__ void collide_lds_body(const CollideArgs<R> &a, unsign
             }
         }
     }
-    const LdsView<R, kPacked> view{vel, owner};
+    const LdsView<R, kPacked> view{vel, owner, view_check((uint32_t)cap, a.st)};
     for (uint32_t r = lane; r < N; r += 64) view.clear_own(r);
     __syncthreads();
     // the sampling writes the cell back and reduces its sums through the
@@ -323,7 +324,7 @@ __device__ __forceinline__ void collide_big_body(const CollideArgs<R> &a) {
             __syncthreads();
         }
         const GlobalView<R> view{a.s.cx + base, a.s.cy + base, a.s.cz + base,
-                                 VR ? a.s.w + base : nullptr, nullptr, a.owner_g + base};
+                                 VR ? a.s.w + base : nullptr, nullptr, a.owner_g + base, view_check(N, a.st)};
         for (uint32_t r = lane; r < N; r += 64) view.clear_own(r);
         __syncthreads();
         const CellPrefetch pf = prefetch_cell<R, VR, false>(a, cell);
@@ -383,7 +384,7 @@ __device__ __forceinline__ void collide_wide_body(const CollideArgs<R> &a, unsig
             if (s < N) vel[s] = t[j];
         }
     }
-    const LdsView<R, kPacked> view{vel, owner};
+    const LdsView<R, kPacked> view{vel, owner, view_check((uint32_t)cap, a.st)};
     for (uint32_t r = tid; r < N; r += T) view.clear_own(r);
     __syncthreads();
     if (LEARNED) process_cell_learned<R, VR, LdsView<R, kPacked>, T>(a, view, cell, N, step, pf, nullptr, base, gs);
@@ -404,7 +405,7 @@ __device__ __forceinline__ void collide_big_wide_body(const CollideArgs<R> &a) {
         const uint32_t base = a.start[cell];
         const uint32_t N = a.start[cell + 1] - base;
         const GlobalView<R> view{a.s.cx + base, a.s.cy + base, a.s.cz + base,
-                                 VR ? a.s.w + base : nullptr, nullptr, a.owner_g + base};
+                                 VR ? a.s.w + base : nullptr, nullptr, a.owner_g + base, view_check(N, a.st)};
         for (uint32_t r = threadIdx.x; r < N; r += T) view.clear_own(r);
         __syncthreads();
         const CellPrefetch pf = prefetch_cell<R, VR, false>(a, cell);

@@ -49,10 +49,27 @@ struct DevState {
     unsigned int queue[kStepSlots * kQueues * kQueueStride];
 };
 enum { kDiagOvershoot = 0, kDiagWallHits, kDiagLearned, kDiagFallback, kDiagSkip, kDiagVrNonfinite,
-       kDiagBig };
+       kDiagBig, kDiagBounds };
 
 __device__ __forceinline__ void diag_add(DevState *st, int which, unsigned long long v) {
     atomicAdd(&st->diag[(blockIdx.x & (kDiagStripes - 1)) * kDiagPerStripe + which], v);
+}
+
+// Index check of the bounds-checking build (compiled with
+// -DDSMC_BOUNDS_CHECK): an index outside [0, n) is counted in the
+// diagnostics and replaced by 0, so that the access stays inside the array.
+// The release build returns the index unchanged.
+__device__ __forceinline__ uint32_t bounds_ck(uint32_t i, uint32_t n, DevState *st) {
+#ifdef DSMC_BOUNDS_CHECK
+    if (i >= n) {
+        diag_add(st, kDiagBounds, 1ull);
+        return 0u;
+    }
+#else
+    (void)n;
+    (void)st;
+#endif
+    return i;
 }
 
 __device__ __forceinline__ void set_error(DevState *st, int code) {
@@ -240,14 +257,15 @@ struct Regroup {
     uint32_t *far_head;   // [ncell] overflow list heads (reset by the collision wave)
     uint32_t *far_src, *far_next;
     uint32_t slots;       // mover slots per cell: 64, 128 or 256
+    uint32_t n, ncell;    // particles and cells (the sizes of the lists above)
 };
 
 __device__ __forceinline__ void push_mover(const Regroup &rg, uint32_t p, uint32_t cell, uint32_t slot,
                                            DevState *st) {
     if (slot < rg.slots) {
-        rg.movers[(size_t)cell * rg.slots + slot] = p;
+        rg.movers[(size_t)bounds_ck(cell, rg.ncell, st) * rg.slots + slot] = p;
     } else {
-        const uint32_t q = atomicAdd(&st->far_count, 1u);
+        const uint32_t q = bounds_ck(atomicAdd(&st->far_count, 1u), rg.n, st);
         rg.far_src[q] = p;
         rg.far_next[q] = atomicExch(&rg.far_head[cell], q);
     }
@@ -411,7 +429,9 @@ __global__ __launch_bounds__(256) void k_stream_code(Geo g, Soa<R> s, int64_t n,
             uint32_t b0 = 0;
             if (lane == leader) b0 = atomicAdd(&st->wall_count, (uint32_t)__popcll(bal));
             b0 = (uint32_t)__shfl((int)b0, leader, 64);
-            if (wall) wall_list[b0 + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull))] = (uint32_t)(p0 + k);
+            if (wall)
+                wall_list[bounds_ck(b0 + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull)), (uint32_t)n, st)] =
+                    (uint32_t)(p0 + k);
         }
     }
     __syncthreads();
