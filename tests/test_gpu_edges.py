@@ -6,6 +6,7 @@ import pytest
 
 import oracle
 from paper_2301_05985_amd import workloads as W
+from tests.sums_check import assert_sums_close
 
 pytestmark = pytest.mark.gpu
 
@@ -41,8 +42,7 @@ def _check(g, sums, cnt, seq, d, orc, fields=("x", "y", "cx", "cy", "cz", "w")):
         if g[k] is None or len(g[k]) == 0:
             continue
         assert np.array_equal(g[k], o[k]), k
-    scale = np.abs(orc.sums).max(axis=0, keepdims=True) + 1.0
-    assert (np.abs(sums - orc.sums) / scale).max() < 1e-11
+    assert_sums_close(sums, orc.sums, 1e-11)
 
 
 def _spec(p):
