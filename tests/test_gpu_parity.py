@@ -335,10 +335,15 @@ def test_relaxation_full_size_f64(gpu):
     assert g["cnt"][0, 1] > 40000
 
 
-def test_checkpoint_restore_bit_exact(gpu):
-    _announce("checkpoint restore")
+@pytest.mark.parametrize("reest", [0, 3])
+def test_checkpoint_restore_bit_exact(gpu, reest):
+    # with re-estimation every third step the checkpoint falls inside the
+    # cycle: the restored step index must keep its phase
+    _announce("checkpoint restore, re-estimation every %d" % reest)
     from paper_2301_05985_amd.binding import Simulation
     p, parts = W.cavity(nx=8, ny=8, per_cell=20, Kn=0.05, real="f64", dt=2e-3)
+    if reest:
+        p = dict(p, vr_reconstruct=reest, vr_kappa=1.5)
     a = Simulation(p, parts)
     a.step(10)
     sa = a.particles()

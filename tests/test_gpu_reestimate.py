@@ -185,3 +185,43 @@ def test_reestimated_cavity_weights_stay_finite(gpu):
         sim.close()
     assert res[0][0] > 0, res
     assert res[1][0] == 0 and res[1][1] < 0.01 and res[1][2] == 0, res
+
+
+@pytest.mark.parametrize("real", ["f32", "f64"])
+def test_learned_majorant_walled_weights_reestimated(gpu, real):
+    # walled cells with the learned majorant (verified proposal or exact
+    # fallback), weights re-estimated every second step and the majorant
+    # factor 1.5; a crowded corner cell runs on the global-memory learned
+    # kernel; walls without transcendental functions keep the motion
+    # bit-exact
+    from oracle import mlp_oracle as M
+    from paper_2301_05985_amd.binding import Simulation
+    _announce("learned majorant, walled, weights re-estimated %s" % real)
+    dtype = np.float64 if real == "f64" else np.float32
+    p, parts = W.cavity(nx=10, ny=10, per_cell=40, Kn=0.03, real=real, dt=2e-3)
+    p["wall_kind"] = (W.WALL_PERIODIC, W.WALL_PERIODIC, W.WALL_SPECULAR, W.WALL_SPECULAR)
+    p.update(vr_reconstruct=2, vr_kappa=1.5)
+    n = len(parts["cx"])
+    x, y = parts["x"].copy(), parts["y"].copy()
+    x[:230] *= 0.1  # 230 more particles in cell (0, 0): above its LDS capacity
+    y[:230] *= 0.1
+    parts = dict(parts, x=x, y=y, w=_weights(n, 5, spread=0.1))
+    net = M.init_params(7) * 0.05
+    net[-1] = 2.5  # log2 of a typical cell's largest pair speed
+    bits = M.to_bf16(net.astype(np.float32))
+    delta = 0.01
+    orc = oracle.Oracle(dict(p, majorant=1, mlp=M.from_bf16(bits).astype(np.float32), mlp_delta=delta), parts,
+                        dtype)
+    log = orc.run(8, learned_log=True)
+    assert (log == 1).any() and (log == -1).any() and (log == 0).any(), np.unique(log, return_counts=True)
+    sim = Simulation(dict(p, majorant=1), parts)
+    sim.set_majorant_model(bits, delta, 0)
+    sim.step(8)
+    sums, cnt, _ = sim.sample()
+    g = dict(sums=sums, cnt=cnt, st=sim.particles(), diag=sim.diagnostics(), seq=sim.sequence()["id"])
+    sim.close()
+    assert g["diag"]["big_cells"] > 0
+    assert g["diag"]["learned_used"] == (log == 1).sum()
+    assert g["diag"]["fallback"] == (log == -1).sum()
+    assert g["diag"]["learned_skip"] == (log == 0).sum()
+    _check(g, orc, real, motion_exact=True)
