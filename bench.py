@@ -372,6 +372,10 @@ def main():
             pk, partsk = W.cavity(Kn=kn, real="f32")
             pk.update(VR_SETTINGS)
             sec.append(run_workload("cavity 256x256 x 100, Kn=%g, VR, FP32" % kn, pk, partsk, 100, 10, torch))
+        # the same cavity without importance weights (plain DSMC estimators)
+        p8, parts8 = W.cavity(Kn=args.kn, real="f32", vr=0)
+        sec.append(run_workload("cavity 256x256 x 100, Kn=%g, no weights, FP32" % args.kn, p8, parts8, 100, 10,
+                                torch))
         p1, parts1 = W.relaxation()
         sec.append(run_workload("relaxation 10,000 particles one cell FP64", p1, parts1, 200, 0, torch))
         line["secondary"] = sec

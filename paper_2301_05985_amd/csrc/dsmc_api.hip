@@ -668,8 +668,14 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
         }
         c->persistent_grid = cfg->persistent_waves > 0 ? cfg->persistent_waves : 8 * ncu;
     } else {
+        // LDS capacity of a walled cell.  Without weights the collision
+        // kernel fits six waves per SIMD in registers, so a capacity of
+        // 2 x mean + 64 lets LDS hold nearly as many (8% faster on the
+        // 100-per-cell cavity); with weights the registers allow five, and
+        // 3 x mean + 64 keeps more dense cells out of the global-memory
+        // kernel.  Either way a cell above capacity gives the same results.
         const double mean = (double)c->n / (double)c->ncell;
-        int want = (int)std::ceil(3.0 * mean + 64.0);
+        int want = (int)std::ceil((cfg->vr ? 3.0 : 2.0) * mean + 64.0);
         want = (want + 31) / 32 * 32;
         c->cap = std::max(64, std::min(want, cap_fit));
         const int64_t maxbig = c->n / (c->cap + 1);

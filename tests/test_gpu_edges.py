@@ -154,13 +154,15 @@ def test_instances_at_lds_capacity_and_one_above(gpu, real):
     _check(g, sums, cnt, seq, d, orc, fields=("cx", "cy", "cz"))
 
 
+@pytest.mark.parametrize("vr", [1, 0])
 @pytest.mark.parametrize("extra", [0, 1])
-def test_walled_cell_at_lds_capacity_and_one_above(gpu, extra):
-    # 160 particles in 8 cells: the per-cell capacity is 3 x 20 + 64 rounded
-    # up to 128; cell 0 holds 128 (staged in LDS) or 129 (global memory).
-    # A tiny time step keeps every particle in its cell.
-    _announce("walled cell at capacity + %d" % extra)
-    p, _ = W.fourier(n_cells=8, per_cell=1, Kn=0.05, dt=1e-7)
+def test_walled_cell_at_lds_capacity_and_one_above(gpu, extra, vr):
+    # 160 particles in 8 cells: the per-cell capacity is 3 x 20 + 64 with
+    # weights, 2 x 20 + 64 without, both rounded up to 128; cell 0 holds 128
+    # (staged in LDS) or 129 (global memory).  A tiny time step keeps every
+    # particle in its cell.
+    _announce("walled cell at capacity + %d, weights %d" % (extra, vr))
+    p, _ = W.fourier(n_cells=8, per_cell=1, Kn=0.05, dt=1e-7, vr=vr)
     p["wall_kind"] = (W.WALL_SPECULAR, W.WALL_SPECULAR, 0, 0)
     p["sigma"] = 1300.0
     n, n0 = 160, 128 + extra
