@@ -286,10 +286,12 @@ struct Launcher {
     }
 };
 
-// One-wave collision kernel with the configured occupancy variant
-// (homogeneous instances on the grid schedule; walled runs always take the
-// default).  Six waves per SIMD fits the weighted kernel into 80 registers at
-// the price of a few spills; without weights both variants are the same code.
+// One-wave collision kernel with its occupancy variant.  Walled FP32 cells
+// run at six waves per SIMD (the kernel fits 80 registers, and the LDS
+// capacity below leaves room for six cells per SIMD); FP64 walled cells,
+// whose LDS holds fewer waves anyway, keep five.  Homogeneous instances on
+// the grid schedule take the configured variant (five by default; six fits
+// the weighted kernel into 80 registers at the price of a few spills).
 template <typename R, bool VR, int D>
 void launch_collide_wave(dsmc_ctx *c, dim3 grid, size_t lds, hipStream_t s, const CollideArgs<R> &a) {
     if constexpr (D == 0) {
@@ -297,8 +299,10 @@ void launch_collide_wave(dsmc_ctx *c, dim3 grid, size_t lds, hipStream_t s, cons
             hipLaunchKernelGGL((k_collide<R, VR, D, 6>), grid, dim3(64), lds, s, a);
             return;
         }
+        hipLaunchKernelGGL((k_collide<R, VR, D, 5>), grid, dim3(64), lds, s, a);
+    } else {
+        hipLaunchKernelGGL((k_collide<R, VR, D, (sizeof(R) == 4 ? 6 : 5)>), grid, dim3(64), lds, s, a);
     }
-    hipLaunchKernelGGL((k_collide<R, VR, D, 5>), grid, dim3(64), lds, s, a);
 }
 
 template <typename R, bool VR, int D>
@@ -651,14 +655,14 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
                    cfg->inst_offset[sched_host[nw] + 1] - cfg->inst_offset[sched_host[nw]] > (int64_t)wide_min)
                 ++nw;
             const size_t lw = std::max<size_t>((size_t)c->cap * per + 16 + 16 + sizeof(GroupScratch),
-                                               (size_t)13 * 66 * 8);
+                                               kRedBytes);
             if (nw > 0 && lw <= kMaxLds) {
                 c->nwide = nw;
                 c->lds_wide = lw;
                 const int64_t nsmall = nw < (uint32_t)c->ncell
                     ? cfg->inst_offset[sched_host[nw] + 1] - cfg->inst_offset[sched_host[nw]] : 0;
                 c->cap_small = (int)std::min<int64_t>(std::max<int64_t>((nsmall + 31) / 32 * 32, 32), cap_fit);
-                c->lds_small = std::max<size_t>((size_t)c->cap_small * per + 16 + 16, (size_t)13 * 66 * 8);
+                c->lds_small = std::max<size_t>((size_t)c->cap_small * per + 16 + 16, kRedBytes);
             }
         }
         int dev = 0, ncu = 256;
@@ -668,14 +672,16 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
         }
         c->persistent_grid = cfg->persistent_waves > 0 ? cfg->persistent_waves : 8 * ncu;
     } else {
-        // LDS capacity of a walled cell.  Without weights the collision
-        // kernel fits six waves per SIMD in registers, so a capacity of
-        // 2 x mean + 64 lets LDS hold nearly as many (8% faster on the
-        // 100-per-cell cavity); with weights the registers allow five, and
-        // 3 x mean + 64 keeps more dense cells out of the global-memory
-        // kernel.  Either way a cell above capacity gives the same results.
+        // LDS capacity of a walled cell, chosen so that LDS holds six
+        // one-wave cells per SIMD where the registers allow six (FP32):
+        // 2 x mean + 64 without weights (16 bytes and an owner mark per
+        // particle), 2.5 x mean + 64 with them (20 bytes); on the 100-per-cell
+        // cavity the collision kernel runs 8% faster than at five.  FP64
+        // cells keep 3 x mean + 64.  A cell above capacity runs in the
+        // global-memory kernel with the same results.
         const double mean = (double)c->n / (double)c->ncell;
-        int want = (int)std::ceil((cfg->vr ? 3.0 : 2.0) * mean + 64.0);
+        const double mult = cfg->real_bytes == 8 ? 3.0 : (cfg->vr ? 2.5 : 2.0);
+        int want = (int)std::ceil(mult * mean + 64.0);
         want = (want + 31) / 32 * 32;
         c->cap = std::max(64, std::min(want, cap_fit));
         const int64_t maxbig = c->n / (c->cap + 1);
@@ -695,7 +701,7 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
             }
     }
     // (at least the transpose area of the moment reduction: 13 x 66 doubles)
-    c->lds = std::max<size_t>((size_t)c->cap * per + 16 + 16, (size_t)13 * 66 * 8);
+    c->lds = std::max<size_t>((size_t)c->cap * per + 16 + 16, kRedBytes);
 
     // graphs are recorded on a private stream (capture is not allowed on
     // the legacy default stream the caller may use)

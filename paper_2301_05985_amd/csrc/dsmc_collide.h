@@ -67,6 +67,10 @@ struct CollideArgs {
 };
 
 constexpr int kNsum = 26;
+// Transpose area of the moment reduction of a cell staged in LDS: 13 rows
+// of kRedStride doubles (the cell's LDS area is at least this large).
+constexpr int kRedStride = 64;
+constexpr size_t kRedBytes = (size_t)13 * kRedStride * 8;
 // Most NTC candidates one cell may take in one step (2^24); a larger count
 // stops the step with DSMC_ECAPACITY, so that a run whose velocities have
 // blown up ends with an error instead of keeping a wave busy for minutes.
@@ -1011,23 +1015,35 @@ __device__ __forceinline__ int owned_sum(int lane) {
     return (r < 13 && h < (VR ? 2 : 1)) ? 13 * h + r : -1;
 }
 
-// The cell's running sums and counters, read at the start of the cell's work
-// so that the final read-modify-write does not wait on memory: each lane the
-// sum it owns, lane 0 the counters.
-struct CellPrefetch {
+// The cell's running sums and counters.  Without weights they are read at
+// the start of the cell's work, so that the final read-modify-write does not
+// wait on memory (each lane the sum it owns, lane 0 the counters).  With
+// weights they are read at the end: held through the whole cell they would
+// take the six registers that let the one-wave kernel run six waves per SIMD.
+template <bool ON>
+struct CellPrefetch {};
+template <>
+struct CellPrefetch<true> {
     double sum;
     unsigned long long cand, acc;
 };
 
 template <typename R, bool VR, bool IN_LDS>
-__device__ __forceinline__ CellPrefetch prefetch_cell(const CollideArgs<R> &a, uint32_t cell) {
-    const int lane = lane_id();
-    CellPrefetch pf{0.0, 0ull, 0ull};
-    const int idx = owned_sum<IN_LDS, VR>(lane);
-    if (idx >= 0) pf.sum = a.sums[(size_t)cell * kNsum + idx];
-    if (lane == 0) {
-        pf.cand = a.counters[2 * (size_t)cell];
-        pf.acc = a.counters[2 * (size_t)cell + 1];
+__device__ __forceinline__ CellPrefetch<!VR> prefetch_cell(const CollideArgs<R> &a, uint32_t cell) {
+    CellPrefetch<!VR> pf{};
+    if constexpr (!VR) {
+        const int lane = lane_id();
+        const int idx = owned_sum<IN_LDS, VR>(lane);
+        pf.sum = idx >= 0 ? a.sums[(size_t)cell * kNsum + idx] : 0.0;
+        pf.cand = 0ull;
+        pf.acc = 0ull;
+        if (lane == 0) {
+            pf.cand = a.counters[2 * (size_t)cell];
+            pf.acc = a.counters[2 * (size_t)cell + 1];
+        }
+    } else {
+        (void)a;
+        (void)cell;
     }
     return pf;
 }
@@ -1038,14 +1054,15 @@ __device__ __forceinline__ CellPrefetch prefetch_cell(const CollideArgs<R> &a, u
 // reduced over the wave.  A cell in global memory reduces by shuffles
 // (recursive halving).  A cell staged in LDS writes its velocities and
 // weights back to the particle arrays at wb_base during the accumulation,
-// and then uses its LDS area (`red`, at least 13 x 66 doubles) for a
-// transpose, once per set of 13 sums: every lane stores its partial sums as
-// a column, the four lanes of quad r add up a quarter of row r each
-// (interleaved 16-byte columns) and the quad combines its four parts.
+// and then uses its LDS area (`red`, at least kRedBytes) for a transpose,
+// once per set of 13 sums: every lane stores its partial sums as a column,
+// the four lanes of quad r add up a quarter of row r each (interleaved
+// 16-byte columns, starting at column block r mod 8 so that the rows read
+// different banks) and the quad combines its four parts.
 template <typename R, bool VR, typename View, int T = 64>
 __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cell, uint32_t N, uint32_t M,
-                            uint32_t acc, uint32_t over, const CellPrefetch &pf, double *red, uint32_t wb_base,
-                            GroupScratch *gs = nullptr) {
+                            uint32_t acc, uint32_t over, const CellPrefetch<!VR> &pf, double *red,
+                            uint32_t wb_base, GroupScratch *gs = nullptr) {
     const int lane = lane_id();
     const uint32_t tid = threadIdx.x;
     constexpr int K = VR ? 32 : 16;  // 26 or 13 sums, padded to a power of two
@@ -1111,7 +1128,7 @@ __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cel
             for (int w = 0; w < T / 64; ++w) tot += gs->d[w][tid];
         }
     } else if constexpr (View::kInLds) {
-        constexpr int RS = 66;  // row stride (doubles): 16-byte aligned rows
+        constexpr int RS = kRedStride;
         const int row = lane >> 2, part = lane & 3;
         __syncthreads();
 #pragma unroll
@@ -1125,7 +1142,7 @@ __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cel
                 double s0 = 0.0, s1 = 0.0;
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
-                    const double2 e = rp[4 * c + part];
+                    const double2 e = rp[4 * ((c + row) & 7) + part];
                     s0 += e.x;
                     s1 += e.y;
                 }
@@ -1147,10 +1164,21 @@ __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cel
     const bool bad_plain = __ballot(nonfinite && idx < 13) != 0ull;
     const bool bad_vr = __ballot(nonfinite && idx >= 13) != 0ull;
     const uint32_t ce = bounds_ck(cell, a.n_cells, a.st);
-    if (writer) a.sums[(size_t)ce * kNsum + idx] = pf.sum + tot;
+    double *sum_at = a.sums + (size_t)ce * kNsum + idx;
+    unsigned long long *cnt_at = a.counters + 2 * (size_t)ce;
+    if constexpr (!VR) {
+        if (writer) *sum_at = pf.sum + tot;
+    } else {
+        if (writer) *sum_at = *sum_at + tot;
+    }
     if (tid == 0) {
-        a.counters[2 * (size_t)ce] = pf.cand + M;
-        a.counters[2 * (size_t)ce + 1] = pf.acc + acc;
+        if constexpr (!VR) {
+            cnt_at[0] = pf.cand + M;
+            cnt_at[1] = pf.acc + acc;
+        } else {
+            cnt_at[0] = cnt_at[0] + M;
+            cnt_at[1] = cnt_at[1] + acc;
+        }
         if (over) diag_add(a.st, kDiagOvershoot, (unsigned long long)over);
         if (bad_plain) set_error(a.st, DSMC_ENONFINITE);
         if (bad_vr) diag_add(a.st, kDiagVrNonfinite, 1ull);
@@ -1179,7 +1207,7 @@ __device__ __forceinline__ bool reestimate_now(const CollideArgs<R> &a, uint32_t
 // already holds the cell in canonical order.
 template <typename R, bool VR, typename View, int T = 64>
 __device__ void process_cell(const CollideArgs<R> &a, const View &v, uint32_t cell, uint32_t N,
-                             uint32_t step, const CellPrefetch &pf, double *red = nullptr, uint32_t wb_base = 0,
+                             uint32_t step, const CellPrefetch<!VR> &pf, double *red = nullptr, uint32_t wb_base = 0,
                              GroupScratch *gs = nullptr) {
     uint32_t M = 0, acc = 0, over = 0;
     if (N >= 2) {

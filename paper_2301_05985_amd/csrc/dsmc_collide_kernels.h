@@ -270,7 +270,7 @@ __device__ __forceinline__ void collide_lds_body(const CollideArgs<R> &a, unsign
         return;
     }
     const uint32_t step = (uint32_t)(a.st->step_cur + a.step_off);
-    const CellPrefetch pf = prefetch_cell<R, VR, true>(a, cell);
+    const auto pf = prefetch_cell<R, VR, true>(a, cell);
     const int cap = a.cap;
     constexpr bool kPacked = D == 0 && !VR;  // owner marks in the weight slots
     Vel4<R> *vel = (Vel4<R> *)smem;
@@ -327,7 +327,7 @@ __device__ __forceinline__ void collide_big_body(const CollideArgs<R> &a) {
                                  VR ? a.s.w + base : nullptr, nullptr, a.owner_g + base, view_check(N, a.st)};
         for (uint32_t r = lane; r < N; r += 64) view.clear_own(r);
         __syncthreads();
-        const CellPrefetch pf = prefetch_cell<R, VR, false>(a, cell);
+        const auto pf = prefetch_cell<R, VR, false>(a, cell);
         if (LEARNED) process_cell_learned<R, VR>(a, view, cell, N, step, pf);
         else process_cell<R, VR>(a, view, cell, N, step, pf);
         if (lane == 0) diag_add(a.st, kDiagBig, 1ull);
@@ -363,7 +363,7 @@ __device__ __forceinline__ void collide_wide_body(const CollideArgs<R> &a, unsig
         return;
     }
     const uint32_t step = (uint32_t)(a.st->step_cur + a.step_off);
-    const CellPrefetch pf = prefetch_cell<R, VR, false>(a, cell);
+    const auto pf = prefetch_cell<R, VR, false>(a, cell);
     const int cap = a.cap;
     constexpr bool kPacked = !VR;  // owner marks in the weight slots
     Vel4<R> *vel = (Vel4<R> *)smem;
@@ -408,7 +408,7 @@ __device__ __forceinline__ void collide_big_wide_body(const CollideArgs<R> &a) {
                                  VR ? a.s.w + base : nullptr, nullptr, a.owner_g + base, view_check(N, a.st)};
         for (uint32_t r = threadIdx.x; r < N; r += T) view.clear_own(r);
         __syncthreads();
-        const CellPrefetch pf = prefetch_cell<R, VR, false>(a, cell);
+        const auto pf = prefetch_cell<R, VR, false>(a, cell);
         if (LEARNED) process_cell_learned<R, VR, GlobalView<R>, T>(a, view, cell, N, step, pf, nullptr, 0, &gs);
         else process_cell<R, VR, GlobalView<R>, T>(a, view, cell, N, step, pf, nullptr, 0, &gs);
         if (threadIdx.x == 0) diag_add(a.st, kDiagBig, 1ull);

@@ -254,7 +254,7 @@ __device__ double learned_majorant(const CollideArgs<R> &a, const View &v, uint3
 // Same as process_cell, with the learned majorant.
 template <typename R, bool VR, typename View, int T = 64>
 __device__ void process_cell_learned(const CollideArgs<R> &a, const View &v, uint32_t cell, uint32_t N,
-                                     uint32_t step, const CellPrefetch &pf, double *red = nullptr,
+                                     uint32_t step, const CellPrefetch<!VR> &pf, double *red = nullptr,
                                      uint32_t wb_base = 0, GroupScratch *gs = nullptr) {
     uint32_t M = 0, acc = 0, over = 0;
     if (N >= 2) {
