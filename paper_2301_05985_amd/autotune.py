@@ -35,7 +35,7 @@ CANDIDATES = [GRID] + [
 ]
 LAUNCH_KEYS = ("schedule", "persistent_waves", "chunk_work", "wide_min", "occupancy")
 # refinements of the grid schedule, each tried against the best so far
-WIDE_MIN = (512, 2048)
+WIDE_MIN = (128, 256, 384, 512, 768, 2048)
 OCCUPANCY = (6,)
 
 
