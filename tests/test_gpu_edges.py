@@ -157,8 +157,8 @@ def test_instances_at_lds_capacity_and_one_above(gpu, real):
 @pytest.mark.parametrize("vr", [1, 0])
 @pytest.mark.parametrize("extra", [0, 1])
 def test_walled_cell_at_lds_capacity_and_one_above(gpu, extra, vr):
-    # 160 particles in 8 cells: the per-cell capacity is 3 x 20 + 64 with
-    # weights, 2 x 20 + 64 without, both rounded up to 128; cell 0 holds 128
+    # 160 particles in 8 cells: the FP32 per-cell capacity is 2.5 x 20 + 64
+    # with weights, 2 x 20 + 64 without, both rounded up to 128; cell 0 holds 128
     # (staged in LDS) or 129 (global memory).  A tiny time step keeps every
     # particle in its cell.
     _announce("walled cell at capacity + %d, weights %d" % (extra, vr))
