@@ -241,11 +241,17 @@ def main():
           flush=True)
 
     # ---------------- headline: full-size cavity
+    from paper_2301_05985_amd import autotune
+    tlog = lambda s: print("[bench] " + s, file=sys.stderr, flush=True)
     p, parts = W.cavity(Kn=args.kn, real="f32")
     p.update(VR_SETTINGS)
     name = "cavity 256x256 cells x 100 particles (6,553,600), Kn=%g, diffuse walls, lid 0.01*sqrt(2), " \
            "VR weights re-estimated every 4 steps, majorant factor 1.5, FP32 state / FP64 sums" % args.kn
     print("[bench] headline: %s" % name, file=sys.stderr, flush=True)
+    # launch of the collision step (one or two cells per wave; identical
+    # decisions either way), picked by timing both
+    launch, launch_times = autotune.tune(p, parts, log=tlog)
+    p.update(launch)
     sim = Simulation(p, parts)
     ms, wall, cand, acc = _timed_steps(sim, torch, args.steps, args.warmup)
     n = len(parts["cx"])
@@ -289,7 +295,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": name, "particles": n, "cells": 65536, "Kn": args.kn, "dt": p["dt"],
-                   "parallelism": "single GPU"},
+                   "launch": launch, "parallelism": "single GPU"},
+        "launch_candidates_ms_per_step": launch_times,
         "collisions_per_s": acc / (ms * 1e-3), "candidates_per_s": cand / (ms * 1e-3),
         "acceptance": acc / max(cand, 1),
         "diagnostics": {k: diag[k] for k in ("steps", "overshoot", "wall_hits", "vr_nonfinite", "big_cells")},
@@ -306,8 +313,6 @@ def main():
         p3, parts3 = W.batched(real="f32")
         # launch parameters of the collision step picked by the autotuner
         # (grid vs persistent work queue; identical results either way)
-        from paper_2301_05985_amd import autotune
-        tlog = lambda s: print("[bench] " + s, file=sys.stderr, flush=True)
         best3, times3 = autotune.tune(p3, parts3, steps=20, warmup=8, log=tlog)
         r3 = run_workload("batched 4096 cells, N uniform in [50,2000], exact majorant, FP32",
                           dict(p3, **best3), parts3, 200, 20, torch)
@@ -358,24 +363,28 @@ def main():
         p6s = dict(p3, molecule=W.VSS, omega=0.81, alpha=1.4)
         sec.append(run_workload("batched 4096 cells, variable soft spheres (omega 0.81, alpha 1.4), exact majorant, "
                                 "FP32", dict(p6s, **best3), parts3, 200, 20, torch))
+        def walled(label, q, qparts, steps, warm):
+            best, times = autotune.tune(q, qparts, log=tlog)
+            r = run_workload(label, dict(q, **best), qparts, steps, warm, torch)
+            r["launch"], r["launch_candidates_ms_per_step"] = best, times
+            return r
+
         p7, parts7 = W.cavity(Kn=args.kn, real="f32")
         p7 = dict(p7, molecule=W.VHS, omega=0.74, **VR_SETTINGS)
-        sec.append(run_workload("cavity 256x256 x 100, variable hard spheres (omega 0.74), VR, FP32", p7, parts7,
-                                100, 10, torch))
+        sec.append(walled("cavity 256x256 x 100, variable hard spheres (omega 0.74), VR, FP32", p7, parts7, 100, 10))
         p7s = dict(p7, molecule=W.VSS, alpha=1.4)
-        sec.append(run_workload("cavity 256x256 x 100, variable soft spheres (omega 0.74, alpha 1.4), VR, FP32",
-                                p7s, parts7, 100, 10, torch))
+        sec.append(walled("cavity 256x256 x 100, variable soft spheres (omega 0.74, alpha 1.4), VR, FP32", p7s,
+                          parts7, 100, 10))
         # the rest of the cavity's Knudsen sweep
         for kn in (0.1, 1.0):
             if kn == args.kn:
                 continue
             pk, partsk = W.cavity(Kn=kn, real="f32")
             pk.update(VR_SETTINGS)
-            sec.append(run_workload("cavity 256x256 x 100, Kn=%g, VR, FP32" % kn, pk, partsk, 100, 10, torch))
+            sec.append(walled("cavity 256x256 x 100, Kn=%g, VR, FP32" % kn, pk, partsk, 100, 10))
         # the same cavity without importance weights (plain DSMC estimators)
         p8, parts8 = W.cavity(Kn=args.kn, real="f32", vr=0)
-        sec.append(run_workload("cavity 256x256 x 100, Kn=%g, no weights, FP32" % args.kn, p8, parts8, 100, 10,
-                                torch))
+        sec.append(walled("cavity 256x256 x 100, Kn=%g, no weights, FP32" % args.kn, p8, parts8, 100, 10))
         p1, parts1 = W.relaxation()
         sec.append(run_workload("relaxation 10,000 particles one cell FP64", p1, parts1, 200, 0, torch))
         line["secondary"] = sec

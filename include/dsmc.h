@@ -125,6 +125,10 @@ typedef struct {
     int32_t occupancy;        /* homogeneous instances, grid schedule: waves per SIMD the one-wave
                                  collision kernel is compiled for, 5 or 6 (0 -> 5; DSMC_EINVAL
                                  otherwise).  Changes no result. */
+    int32_t cells_per_wave;   /* walled runs (dims 1, 2): 2 -> each wave collides two cells, 32
+                                 lanes each (exact or brute-force majorant, mean cell population
+                                 at most 128; DSMC_EINVAL otherwise); 0 or 1 -> one cell per wave.
+                                 Changes no result. */
 } dsmc_config;
 
 /* How homogeneous instances are distributed over the GPU.  Both process the

@@ -1,4 +1,4 @@
-"""Launch-parameter autotuner for batched homogeneous instances.
+"""Launch-parameter autotuner.
 
 The collision step of many independent homogeneous cells can run as one
 workgroup per instance (``schedule=0``, grid launch in longest-first order)
@@ -17,10 +17,15 @@ weighted runs, ``occupancy``, the waves per SIMD the one-wave kernel is
 compiled for (5, or 6 with a few register spills).  Neither changes a bit of
 the result either.
 
+Walled workloads (dims 1, 2) choose between one cell per wave and two cells
+per wave (``cells_per_wave``, 32 lanes per cell; exact or brute-force
+majorant, mean cell population at most 128), again without changing a
+decision of the method.
+
 The tuner times each candidate on a scratch simulation built from a copy of
 the caller's initial state and caches the winner in a JSON file keyed by the
 GPU architecture and a signature of the workload (kind, precision, weights,
-majorant, and the instance-size histogram).
+majorant, and the instance-size histogram or the grid).
 """
 import hashlib
 import json
@@ -33,7 +38,8 @@ CANDIDATES = [GRID] + [
     {"schedule": 1, "persistent_waves": w, "chunk_work": c}
     for w in (1024, 2048, 4096) for c in (0, 256, 1024)
 ]
-LAUNCH_KEYS = ("schedule", "persistent_waves", "chunk_work", "wide_min", "occupancy")
+LAUNCH_KEYS = ("schedule", "persistent_waves", "chunk_work", "wide_min", "occupancy", "cells_per_wave")
+WALLED = [{"cells_per_wave": 1}, {"cells_per_wave": 2}]
 # refinements of the grid schedule, each tried against the best so far
 WIDE_MIN = (128, 256, 384, 512, 768, 2048)
 OCCUPANCY = (6,)
@@ -46,8 +52,21 @@ def cache_path():
     return os.path.join(os.path.expanduser("~"), ".cache", "dsmc_hip", "autotune.json")
 
 
-def signature(params):
+def pair_allowed(params, n_particles):
+    """Whether a walled workload may run two cells per wave."""
+    if params.get("dims", 0) == 0 or params.get("majorant", 0) == 1:
+        return False
+    nc = int(np.prod(params["n_cells"][:params["dims"]]))
+    return n_particles <= 128 * nc
+
+
+def signature(params, n_particles=0):
     """Key of a workload: everything that changes the collision kernel's cost."""
+    if params.get("dims", 0) != 0:
+        return "d%d_%s_vr%d_re%d_ka%g_m%d_mol%d_c%s_n%d" % (
+            params["dims"], params.get("real", "f64"), params.get("vr", 0), params.get("vr_reconstruct", 0),
+            params.get("vr_kappa", 1.0), params.get("majorant", 0), params.get("molecule", 0),
+            "x".join(str(int(c)) for c in params["n_cells"][:params["dims"]]), n_particles)
     off = np.asarray(params["inst_offset"], dtype=np.int64)
     n = np.diff(off)
     hist = np.bincount(np.minimum(n // 64, 255), minlength=256)
@@ -112,13 +131,20 @@ def tune(params, particles, candidates=None, steps=8, warmup=8, model=None, use_
          refine=None):
     """Return (best launch parameters, {candidate label: ms per step}).
 
-    Walled workloads have a single schedule and return it untimed.
+    Walled workloads time one against two cells per wave where both apply
+    (else return one cell per wave untimed).
     ``model`` is ``(bf16_weights, delta, min_n)`` for learned-majorant runs.
     ``refine`` (default: only when ``candidates`` is not given) adds the
     coordinate-descent stage over the grid schedule's kernel parameters."""
-    if params.get("dims", 0) != 0:
-        return dict(GRID), {}
-    key = "%s/%s" % (_arch(), signature(params))
+    walled = params.get("dims", 0) != 0
+    n_particles = len(particles["cx"])
+    if walled:
+        if not pair_allowed(params, n_particles):
+            return dict(WALLED[0]), {}
+        candidates = candidates or WALLED
+        refine = False
+        steps = max(steps, 24)  # every phase of a re-estimation interval, several times
+    key = "%s/%s" % (_arch(), signature(params, n_particles))
     path = cache_path()
     if use_cache:
         hit = _load_cache(path).get(key)

@@ -50,6 +50,16 @@ int64_t n_cells_of(const dsmc_config &c) {
     return c.n_cells[0];
 }
 
+// Mover slots per cell: the mean cell population rounded up to a power of
+// two, between 64 and 256 (the whole cell moving in one step still fits).
+uint32_t mover_slots(const dsmc_config &c) {
+    const int64_t nc = n_cells_of(c);
+    const double mean = nc > 0 ? (double)c.n_particles / (double)nc : 0.0;
+    uint32_t s = 64;
+    while ((double)s < mean && s < kMaxMoverSlots) s *= 2;
+    return s;
+}
+
 dsmc_status validate(const dsmc_config *c) {
     if (!c) return DSMC_EINVAL;
     if (c->abi_version != DSMC_ABI_VERSION) return DSMC_EABI;
@@ -71,6 +81,12 @@ dsmc_status validate(const dsmc_config *c) {
         return DSMC_EINVAL;
     if (c->wide_min < 0 || (c->wide_min > 0 && c->wide_min < 64)) return DSMC_EINVAL;
     if (c->occupancy != 0 && c->occupancy != 5 && c->occupancy != 6) return DSMC_EINVAL;
+    if (c->cells_per_wave < 0 || c->cells_per_wave > 2) return DSMC_EINVAL;
+    if (c->cells_per_wave == 2) {
+        // walled cells with the exact or brute-force majorant, at most 128
+        // mover slots (a mean cell population of at most 128)
+        if (c->dims == 0 || c->majorant == DSMC_MAJORANT_LEARNED || mover_slots(*c) > 128) return DSMC_EINVAL;
+    }
     if (c->dims >= 1) {
         if (!(c->length[0] > 0) || (c->dims == 2 && !(c->length[1] > 0))) return DSMC_EINVAL;
         for (int k = 0; k < (c->dims == 2 ? 4 : 2); ++k) {
@@ -94,16 +110,6 @@ dsmc_status validate(const dsmc_config *c) {
     if (c->schedule != DSMC_SCHEDULE_GRID && c->schedule != DSMC_SCHEDULE_PERSISTENT) return DSMC_EINVAL;
     if (c->persistent_waves < 0 || c->chunk_work < 0) return DSMC_EINVAL;
     return DSMC_OK;
-}
-
-// Mover slots per cell: the mean cell population rounded up to a power of
-// two, between 64 and 256 (the whole cell moving in one step still fits).
-uint32_t mover_slots(const dsmc_config &c) {
-    const int64_t nc = n_cells_of(c);
-    const double mean = nc > 0 ? (double)c.n_particles / (double)nc : 0.0;
-    uint32_t s = 64;
-    while ((double)s < mean && s < kMaxMoverSlots) s *= 2;
-    return s;
 }
 
 Layout make_layout(const dsmc_config &c) {
@@ -136,7 +142,7 @@ Layout make_layout(const dsmc_config &c) {
     L.big_list = take(nc * 4);
     L.perm = take(n * 4);
     L.owner = take(n * 4);
-    L.sched = take(nc * 4);
+    L.sched = take((nc + 16) * 4);  // the two-cells-per-wave order may pad up to 16 entries
     L.units = take(nc * 8);
     L.mlp = take(DSMC_MLP_NPARAM * 4);
     L.lattice = take(kLatticeSize * 8);
@@ -163,6 +169,8 @@ struct dsmc_ctx {
     int64_t n = 0, ncell = 0;
     int cap = 0;
     size_t lds = 0;
+    bool pair = false;               // walled cells: two per wave (cells_per_wave 2)
+    unsigned pair_grid = 0;          // its workgroups
     int big_grid = 0;
     bool any_big_possible = false;
     uint64_t *flags = nullptr;
@@ -342,6 +350,8 @@ void launch_collide(dsmc_ctx *c, Launcher &L, int src, int slot) {
     } else if (learned)
         hipLaunchKernelGGL((k_collide_learned<R, VR, D>), dim3((unsigned)c->ncell), dim3(64), c->lds,
                            L.s, a);
+    else if (D > 0 && c->pair)
+        hipLaunchKernelGGL((k_collide_pair<R, VR, D>), dim3(c->pair_grid), dim3(64), c->lds, L.s, a);
     else
         launch_collide_wave<R, VR, D>(c, dim3((unsigned)c->ncell), c->lds, L.s, a);
     if (c->any_big_possible) {
@@ -684,6 +694,15 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
         int want = (int)std::ceil(mult * mean + 64.0);
         want = (want + 31) / 32 * 32;
         c->cap = std::max(64, std::min(want, cap_fit));
+        c->pair = cfg->cells_per_wave == 2;
+        if (c->pair) {
+            // two cells per wave: 1.6 x mean + 64 per cell, so that a wave's
+            // two cells leave LDS room for four waves per SIMD (FP32)
+            const int cap_fit_pair = (int)std::min<size_t>((kMaxLds / 2 - 64) / per, 65535) / 32 * 32;
+            int wp = (int)std::ceil(1.6 * mean + 64.0);
+            wp = (wp + 31) / 32 * 32;
+            c->cap = std::max(64, std::min(wp, cap_fit_pair));
+        }
         const int64_t maxbig = c->n / (c->cap + 1);
         c->any_big_possible = maxbig > 0;
         c->big_grid = (int)std::max<int64_t>(1, std::min<int64_t>(maxbig, 256));
@@ -691,17 +710,33 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
         // (block b on XCD b mod 8), so XCD x is given the x-th contiguous
         // eighth of the cells and the neighbour cells a cell gathers from
         // are mostly read through the same L2
-        sched_host.resize(c->ncell);
-        const int64_t per8 = (c->ncell + 7) / 8;
-        int64_t blk = 0;
-        for (int64_t k = 0; k < per8; ++k)
-            for (int64_t x = 0; x < 8; ++x) {
-                const int64_t cell = x * per8 + k;
-                if (cell < c->ncell) sched_host[blk++] = (uint32_t)cell;
-            }
+        if (c->pair) {
+            // workgroup w = 8 k + x takes cells x per8 + 2 k and x per8 + 2 k + 1
+            // (per8 even; entries past the last cell hold kNoCell)
+            const int64_t per8 = ((c->ncell + 7) / 8 + 1) / 2 * 2;
+            const int64_t waves = 8 * (per8 / 2);
+            sched_host.assign((size_t)(2 * waves), kNoCell);
+            for (int64_t w = 0; w < waves; ++w)
+                for (int64_t h = 0; h < 2; ++h) {
+                    const int64_t cell = (w % 8) * per8 + 2 * (w / 8) + h;
+                    if (cell < c->ncell) sched_host[(size_t)(2 * w + h)] = (uint32_t)cell;
+                }
+            c->pair_grid = (unsigned)waves;
+        } else {
+            sched_host.resize(c->ncell);
+            const int64_t per8 = (c->ncell + 7) / 8;
+            int64_t blk = 0;
+            for (int64_t k = 0; k < per8; ++k)
+                for (int64_t x = 0; x < 8; ++x) {
+                    const int64_t cell = x * per8 + k;
+                    if (cell < c->ncell) sched_host[blk++] = (uint32_t)cell;
+                }
+        }
     }
-    // (at least the transpose area of the moment reduction: 13 x 66 doubles)
+    // (at least the transpose area of the moment reduction: 13 x 64 doubles;
+    // two cells per wave: two areas of pair_area_bytes)
     c->lds = std::max<size_t>((size_t)c->cap * per + 16 + 16, kRedBytes);
+    if (c->pair) c->lds = 2 * (cfg->real_bytes == 8 ? pair_area_bytes<double>(c->cap) : pair_area_bytes<float>(c->cap));
 
     // graphs are recorded on a private stream (capture is not allowed on
     // the legacy default stream the caller may use)

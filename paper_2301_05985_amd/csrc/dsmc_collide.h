@@ -123,6 +123,102 @@ __device__ __forceinline__ void grp_sync() {
     if constexpr (T > 64) __syncthreads();
 }
 
+// ------------------------------------------------- lanes of one cell
+// T = 32: a cell takes one half of a wave (lanes 0-31 or 32-63), so that a
+// wave works on two cells at once; every cross-lane operation below stays
+// inside the half, and a value that is uniform over the cell lives in a
+// vector register.  T = 64: the whole wave (the results are wave-uniform).
+// T > 64: the wave-level operation of the thread's own wave (combined over
+// the workgroup by the grp_* helpers).
+template <int T>
+__device__ __forceinline__ uint32_t cell_tid() {
+    if constexpr (T == 32) return (uint32_t)lane_id() & 31u;
+    else return threadIdx.x;
+}
+template <int T>
+__device__ __forceinline__ int cell_lane() {
+    if constexpr (T == 32) return lane_id() & 31;
+    else return lane_id();
+}
+// Ballot over the cell's lanes: bit l for cell lane l.
+template <int T>
+__device__ __forceinline__ unsigned long long cell_ballot(bool p) {
+    const unsigned long long b = __ballot(p);
+    if constexpr (T == 32) return (lane_id() & 32) ? (b >> 32) : (b & 0xFFFFFFFFull);
+    else return b;
+}
+// Value of cell lane l (l in [0, T) for T <= 64).
+template <int T, typename V>
+__device__ __forceinline__ V cell_shfl(V x, int l) {
+    if constexpr (T == 32) return __shfl(x, (lane_id() & 32) | l, 64);
+    else return __shfl(x, l, 64);
+}
+template <int T>
+__device__ __forceinline__ uint32_t cell_min_u32(uint32_t v) {
+    if constexpr (T == 32) {
+        const auto mn = [](uint32_t a, uint32_t b) { return a < b ? a : b; };
+        const uint32_t id = 0xFFFFFFFFu;
+        v = mn(v, dpp_any(id, v, 0x111));
+        v = mn(v, dpp_any(id, v, 0x112));
+        v = mn(v, dpp_any(id, v, 0x114));
+        v = mn(v, dpp_any(id, v, 0x118));
+        v = mn(v, dpp_any(id, v, 0x142));  // rows 1 and 3 take the last lane of rows 0 and 2
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)v, 31);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+        return (lane_id() & 32) ? hi : lo;
+    } else {
+        return wave_min_u32(v);
+    }
+}
+template <int T, typename V, typename Op>
+__device__ __forceinline__ V cell_reduce_dpp(V v, V id, Op op) {
+    if constexpr (T == 32) {
+        v = op(v, dpp_any(id, v, 0x111));
+        v = op(v, dpp_any(id, v, 0x112));
+        v = op(v, dpp_any(id, v, 0x114));
+        v = op(v, dpp_any(id, v, 0x118));
+        v = op(v, dpp_any(id, v, 0x142));
+        return __shfl(v, (lane_id() & 32) | 31, 64);
+    } else {
+        return wave_reduce_dpp(v, id, op);
+    }
+}
+template <int T>
+__device__ __forceinline__ uint32_t cell_sum_u32(uint32_t v) {
+    if constexpr (T == 32) {
+#pragma unroll
+        for (int off = 16; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        return v;
+    } else {
+        return wave_sum_u32(v);
+    }
+}
+template <int T, typename V>
+__device__ __forceinline__ V cell_max_t(V v) {
+    if constexpr (T == 32) {
+#pragma unroll
+        for (int off = 16; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+        return v;
+    } else {
+        return wave_max_t(v);
+    }
+}
+// Sum of K per-lane values over the cell's lanes by recursive halving: on
+// return cell lane l holds the total of value index l / (T / K) (T <= 64).
+template <int T, int K>
+__device__ __forceinline__ double cell_sum_many(double (&v)[K]) {
+    if constexpr (T == 32) {
+        static_assert(K >= 1 && K <= 32 && (K & (K - 1)) == 0, "K must be a power of two <= 32");
+        HalvingStep<K, K / 2, 16>::run(v, lane_id());
+        double r = v[0];
+#pragma unroll
+        for (int o = 32 / (2 * K); o >= 1; o >>= 1) r += __shfl_xor(r, o, 64);
+        return r;
+    } else {
+        return wave_sum_many<K>(v);
+    }
+}
+
 // Rank check of a cell view in the bounds-checking build: a rank at or
 // above the limit (the staged cell's capacity, or the size of a cell in
 // global memory) is counted in the diagnostics and replaced by rank 0.  The
@@ -241,12 +337,14 @@ __device__ __forceinline__ float from_order_key(uint32_t k) {
     return __uint_as_float((k & 0x80000000u) ? (k ^ 0x80000000u) : ~k);
 }
 
-// Wave maximum of non-negative doubles (exact, as 64-bit patterns).
-__device__ __forceinline__ double wave_max_nonneg(double v) {
+// Maximum of non-negative doubles over the cell's lanes (exact, as 64-bit
+// patterns).
+template <int T>
+__device__ __forceinline__ double cell_max_nonneg(double v) {
     const uint64_t b = (uint64_t)__double_as_longlong(v);
     const uint32_t hi = (uint32_t)(b >> 32), lo = (uint32_t)b;
-    const uint32_t hmax = ~wave_min_u32(~hi);
-    const uint32_t lmax = ~wave_min_u32(hi == hmax ? ~lo : 0xFFFFFFFFu);
+    const uint32_t hmax = ~cell_min_u32<T>(~hi);
+    const uint32_t lmax = ~cell_min_u32<T>(hi == hmax ? ~lo : 0xFFFFFFFFu);
     return __longlong_as_double((long long)(((uint64_t)hmax << 32) | lmax));
 }
 
@@ -256,7 +354,7 @@ __device__ __forceinline__ double wave_max_nonneg(double v) {
 template <typename R, typename View, int T = 64, bool SUMS = false>
 __device__ double exact_bound(const View &v, uint32_t N, double &r_top, GroupScratch *gs = nullptr,
                               double *mid = nullptr, double *sums = nullptr) {
-    const uint32_t tid = threadIdx.x;
+    const uint32_t tid = cell_tid<T>();
     double m0, m1, m2;
     if constexpr (sizeof(R) == 4) {
         uint32_t lo0 = ~0u, lo1 = ~0u, lo2 = ~0u, nh0 = ~0u, nh1 = ~0u, nh2 = ~0u;  // min keys, min inverted keys
@@ -268,8 +366,8 @@ __device__ double exact_bound(const View &v, uint32_t N, double &r_top, GroupScr
             lo1 = min(lo1, kb); nh1 = min(nh1, ~kb);
             lo2 = min(lo2, kc); nh2 = min(nh2, ~kc);
         }
-        lo0 = wave_min_u32(lo0); lo1 = wave_min_u32(lo1); lo2 = wave_min_u32(lo2);
-        nh0 = wave_min_u32(nh0); nh1 = wave_min_u32(nh1); nh2 = wave_min_u32(nh2);
+        lo0 = cell_min_u32<T>(lo0); lo1 = cell_min_u32<T>(lo1); lo2 = cell_min_u32<T>(lo2);
+        nh0 = cell_min_u32<T>(nh0); nh1 = cell_min_u32<T>(nh1); nh2 = cell_min_u32<T>(nh2);
         grp_put<T>(gs, 0, lo0); grp_put<T>(gs, 1, lo1); grp_put<T>(gs, 2, lo2);
         grp_put<T>(gs, 3, nh0); grp_put<T>(gs, 4, nh1); grp_put<T>(gs, 5, nh2);
         grp_sync<T>();
@@ -292,8 +390,10 @@ __device__ double exact_bound(const View &v, uint32_t N, double &r_top, GroupScr
         const auto mn = [](R a, R b) { return fmin(a, b); };
         const auto mx = [](R a, R b) { return fmax(a, b); };
         const R inf = (R)INFINITY;
-        lo0 = wave_reduce_dpp(lo0, inf, mn); lo1 = wave_reduce_dpp(lo1, inf, mn); lo2 = wave_reduce_dpp(lo2, inf, mn);
-        hi0 = wave_reduce_dpp(hi0, -inf, mx); hi1 = wave_reduce_dpp(hi1, -inf, mx); hi2 = wave_reduce_dpp(hi2, -inf, mx);
+        lo0 = cell_reduce_dpp<T>(lo0, inf, mn); lo1 = cell_reduce_dpp<T>(lo1, inf, mn);
+        lo2 = cell_reduce_dpp<T>(lo2, inf, mn);
+        hi0 = cell_reduce_dpp<T>(hi0, -inf, mx); hi1 = cell_reduce_dpp<T>(hi1, -inf, mx);
+        hi2 = cell_reduce_dpp<T>(hi2, -inf, mx);
         if constexpr (T > 64) {
             grp_putd<T>(gs, 0, (double)lo0); grp_putd<T>(gs, 1, (double)lo1); grp_putd<T>(gs, 2, (double)lo2);
             grp_putd<T>(gs, 3, (double)hi0); grp_putd<T>(gs, 4, (double)hi1); grp_putd<T>(gs, 5, (double)hi2);
@@ -327,10 +427,10 @@ __device__ double exact_bound(const View &v, uint32_t N, double &r_top, GroupScr
             sums[3] += vx * vx; sums[4] += vy * vy; sums[5] += vz * vz; sums[6] += vx * vy;
         }
     }
-    double t1 = wave_max_nonneg(a1);
-    const unsigned long long at = __ballot(a1 == t1);
-    const bool first = lane_id() == __ffsll((long long)at) - 1;
-    double t2 = wave_max_nonneg(first ? a2 : a1);
+    double t1 = cell_max_nonneg<T>(a1);
+    const unsigned long long at = cell_ballot<T>(a1 == t1);
+    const bool first = cell_lane<T>() == __ffsll((long long)at) - 1;
+    double t2 = cell_max_nonneg<T>(first ? a2 : a1);
     if constexpr (T > 64) {
         // top two of the waves' top twos
         grp_putd<T>(gs, 6, t1);
@@ -359,7 +459,7 @@ __device__ double exact_bound(const View &v, uint32_t N, double &r_top, GroupScr
 template <typename R, typename View, int T = 64>
 __device__ double pair_diameter(const View &v, uint32_t N, GroupScratch *gs = nullptr) {
     double best = 0.0;
-    for (uint32_t r = threadIdx.x; r < N; r += T) {
+    for (uint32_t r = cell_tid<T>(); r < N; r += T) {
         R x, y, z;
         v.get(r, x, y, z);
         for (uint32_t t = r + 1; t < N; ++t) {
@@ -370,7 +470,7 @@ __device__ double pair_diameter(const View &v, uint32_t N, GroupScratch *gs = nu
             best = g2 > best ? g2 : best;
         }
     }
-    best = wave_max_t(best);
+    best = cell_max_t<T>(best);
     if constexpr (T > 64) {
         grp_putd<T>(gs, 0, best);
         __syncthreads();
@@ -609,7 +709,7 @@ __device__ __forceinline__ uint32_t velocity_window(const View &v, bool live, ui
     __syncthreads();
     const bool bad = live && (v.read_own(i) < k || v.read_own(j) < k);
     // first candidate that must wait; the window ends there (or at wend)
-    uint32_t kend = wave_min_u32(bad ? k : 0xFFFFFFFFu);
+    uint32_t kend = cell_min_u32<T>(bad ? k : 0xFFFFFFFFu);
     grp_put<T>(gs, 0, kend);
     __syncthreads();
     kend = grp_min<T>(gs, 0, kend);
@@ -636,7 +736,7 @@ __device__ __forceinline__ uint32_t velocity_window(const View &v, bool live, ui
         }
     }
     if (molecule != DSMC_MAXWELL && commit && g2 > gm2) over++;
-    acc += (uint32_t)__popcll(__ballot(coll));
+    acc += (uint32_t)__popcll(cell_ballot<T>(coll));
     g2_out = g2;
     __syncthreads();
     return kend;
@@ -652,7 +752,7 @@ __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uin
     const R gm2 = gm * gm;
     const double gmax2 = gmax * gmax;
     uint32_t kb = 0, acc = 0, over = 0;
-    uint32_t k = threadIdx.x;  // candidate held by this thread; k in [kb, kb + W)
+    uint32_t k = cell_tid<T>();  // candidate held by this thread; k in [kb, kb + W)
     bool fresh = true;   // its draws are still to be computed
     bool done = false;   // committed, waiting for the end of its generation (weights)
     bool acc_k = false;  // committed candidate's acceptance (weights)
@@ -707,7 +807,7 @@ __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uin
         const bool mine = act && k < gend;  // this lane's candidate belongs to the generation
         bool pend = mine;
         for (;;) {
-            bool any = __ballot(pend) != 0ull;
+            bool any = cell_ballot<T>(pend) != 0ull;
             if constexpr (T > 64) {
                 grp_put<T>(gs, 1, any ? 1u : 0u);
                 __syncthreads();
@@ -754,7 +854,7 @@ __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uin
         g0 = gend;
     }
     // acc counts this wave's lanes; the workgroup adds its waves
-    over = wave_sum_u32(over);
+    over = cell_sum_u32<T>(over);
     grp_put<T>(gs, 2, acc);
     grp_put<T>(gs, 3, over);
     grp_sync<T>();
@@ -846,10 +946,11 @@ struct Reest {
 };
 
 // Sum q[0..15] over the cell's threads: on return lane L of every wave holds
-// the total of q[L >> 2] (the waves of a workgroup added in a fixed order).
+// the total of q[L >> 2] (the waves of a workgroup added in a fixed order);
+// a half-wave cell (T = 32): cell lane l the total of q[l >> 1].
 template <int T>
 __device__ __forceinline__ double cell_sum16(double (&q)[16], GroupScratch *gs) {
-    double t = wave_sum_many<16>(q);
+    double t = cell_sum_many<T == 32 ? 32 : 64, 16>(q);
     if constexpr (T > 64) {
         const int lane = lane_id();
         if ((lane & 3) == 0) gs->d[threadIdx.x >> 6][lane >> 2] = t;
@@ -875,7 +976,7 @@ __device__ __forceinline__ double gram_pass(const View &v, uint32_t N, double sc
     double q[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) q[u] = 0.0;
-    for (uint32_t r = threadIdx.x; r < N; r += T) {
+    for (uint32_t r = cell_tid<T>(); r < N; r += T) {
         R a, b, c;
         v.get(r, a, b, c);
         const double x = (double)a * sc, y = (double)b * sc, z = (double)c * sc;
@@ -914,6 +1015,60 @@ __device__ __forceinline__ double gram_pass(const View &v, uint32_t N, double sc
         }
     }
     return cell_sum16<T>(q, gs);
+}
+
+// Normal equations of a half-wave cell (T = 32) from the four passes' sums
+// (pass p's sum s on cell lanes 2 s and 2 s + 1): the same Gauss-Jordan
+// elimination as the one-wave form, with two lanes per row: cell lane 2 r + q
+// holds the entries (r, q + 2 j), j = 0..6 (column 13 is b).  The solution
+// goes to coef[0..13) (LDS of the half; vector registers for all thirteen
+// would cost the kernel a wave per SIMD).  Returns false, writing nothing,
+// if the cell keeps its weights.
+__device__ __forceinline__ bool solve_half(double t0, double t1, double t2, double t3, double *coef) {
+    const int cl = lane_id() & 31;
+    // sum g (pass g / 16, index g mod 16) from cell lane 2 (g mod 16) + (g / 16) mod 2
+    const double sa = (cl & 1) ? t1 : t0, sb = (cl & 1) ? t3 : t2;
+    const auto fetch = [&](int g) {
+        const double x = cell_shfl<32>(sa, 2 * (g & 15) + ((g >> 4) & 1));
+        const double y = cell_shfl<32>(sb, 2 * (g & 15) + ((g >> 4) & 1));
+        return (g >> 5) ? y : x;
+    };
+    const int row = cl >> 1, qc = cl & 1;
+    const bool has_row = row < kReBasis;
+    const int rr = has_row ? row : 0;
+    double M[7];
+#pragma unroll
+    for (int j = 0; j < 7; ++j) {
+        const int col = qc + 2 * j;
+        const int cc = col < kReBasis ? col : 0;
+        const int nt = kGram.n[rr][cc];
+        const double e0 = fetch(col == kReBasis ? 51 + rr : kGram.t[rr][cc][0]);
+        const double e1 = fetch(nt == 3 ? kGram.t[rr][cc][1] : 0);
+        const double e2 = fetch(nt == 3 ? kGram.t[rr][cc][2] : 0);
+        M[j] = (!has_row || col > kReBasis) ? 0.0 : ((col < kReBasis && nt == 3) ? (e0 + e1) + e2 : e0);
+    }
+    // this lane's original diagonal entry (row r: column r, slot r >> 1 on lane 2 r + (r & 1))
+    double mdiag = M[0];
+#pragma unroll
+    for (int j = 1; j < 7; ++j) mdiag = (row >> 1) == j ? M[j] : mdiag;
+    const double dg = (has_row && qc == (row & 1)) ? mdiag : 0.0;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < kReBasis; ++k) {
+        const int kl = 2 * k + (k & 1);
+        const double piv = cell_shfl<32>(M[k >> 1], kl);
+        ok = ok && piv > 1e-12 * cell_shfl<32>(dg, kl);
+        double inv = __builtin_amdgcn_rcp(piv);
+        inv = fma(inv, fma(-piv, inv, 1.0), inv);
+        const double mrk = cell_shfl<32>(M[k >> 1], 2 * rr + (k & 1));
+        const double f = row == k ? 1.0 - inv : mrk * inv;
+#pragma unroll
+        for (int j = 0; j < 7; ++j) M[j] = fma(-f, cell_shfl<32>(M[j], 2 * k + qc), M[j]);
+    }
+    if (!ok) return false;  // a pivot not above 1e-12 G_kk: the cell keeps its weights
+    // solution: column 13 (cell lane 2 r + 1, slot 6)
+    if (has_row && qc == 1) coef[row] = M[6];
+    return true;
 }
 
 // Coefficients of the re-estimated deviations of the cell (identical on
@@ -977,29 +1132,50 @@ __device__ void reestimate_cell(const View &v, uint32_t N, double sc, Reest &re,
     re.on = true;
 }
 
-// New weight of a particle from the re-estimated deviation.
-template <typename R>
-__device__ __forceinline__ R reestimated_weight(const Reest &re, R a, R b, R c) {
-    const double x = (double)a * re.sc, y = (double)b * re.sc, z = (double)c * re.sc;
+// New weight of a particle from the re-estimated deviation (k: the thirteen
+// coefficients, in registers or in LDS).
+template <typename R, typename Coef>
+__device__ __forceinline__ R reestimated_weight(const Coef &k, double sc, R a, R b, R c) {
+    const double x = (double)a * sc, y = (double)b * sc, z = (double)c * sc;
     const double s = (x * x + y * y) + z * z;
-    double d = re.a[0];
-    d = fma(re.a[1], x, d); d = fma(re.a[2], y, d); d = fma(re.a[3], z, d);
-    d = fma(re.a[4], x * x, d); d = fma(re.a[5], y * y, d); d = fma(re.a[6], z * z, d);
-    d = fma(re.a[7], x * y, d); d = fma(re.a[8], x * z, d); d = fma(re.a[9], y * z, d);
-    d = fma((re.a[10] * x + re.a[11] * y) + re.a[12] * z, s, d);
+    double d = k[0];
+    d = fma(k[1], x, d); d = fma(k[2], y, d); d = fma(k[3], z, d);
+    d = fma(k[4], x * x, d); d = fma(k[5], y * y, d); d = fma(k[6], z * z, d);
+    d = fma(k[7], x * y, d); d = fma(k[8], x * z, d); d = fma(k[9], y * z, d);
+    d = fma((k[10] * x + k[11] * y) + k[12] * z, s, d);
     return (R)(1.0 + d);
 }
 
 // Re-estimate the weights of the cell held by the view (in place), if due.
 template <typename R, typename View, int T>
 __device__ __forceinline__ void reestimate_weights(const View &v, uint32_t N, double sc, GroupScratch *gs) {
+    if constexpr (T == 32) {
+        // half-wave cell: the coefficients in the owner array of its LDS
+        // area (the candidates, which use the marks, are done)
+        static_assert(View::kInLds, "half-wave cells are staged in LDS");
+        double *coef = reinterpret_cast<double *>(v.owner);
+        const double t0 = gram_pass<0, R, View, T>(v, N, sc, gs);
+        const double t1 = gram_pass<1, R, View, T>(v, N, sc, gs);
+        const double t2 = gram_pass<2, R, View, T>(v, N, sc, gs);
+        const double t3 = gram_pass<3, R, View, T>(v, N, sc, gs);
+        if (!solve_half(t0, t1, t2, t3, coef)) return;
+        __syncthreads();
+        const double *k = coef;
+        for (uint32_t r = cell_tid<T>(); r < N; r += T) {
+            R a, b, c;
+            v.get(r, a, b, c);
+            v.putw(r, reestimated_weight<R>(k, sc, a, b, c));
+        }
+        __syncthreads();
+        return;
+    }
     Reest re;
     reestimate_cell<R, View, T>(v, N, sc, re, gs);
     if (!re.on) return;
-    for (uint32_t r = threadIdx.x; r < N; r += T) {
+    for (uint32_t r = cell_tid<T>(); r < N; r += T) {
         R a, b, c;
         v.get(r, a, b, c);
-        v.putw(r, reestimated_weight<R>(re, a, b, c));
+        v.putw(r, reestimated_weight<R>(re.a, re.sc, a, b, c));
     }
     grp_sync<T>();
 }
@@ -1007,10 +1183,16 @@ __device__ __forceinline__ void reestimate_weights(const View &v, uint32_t N, do
 // The running sum a lane owns in the moment reduction, or -1.  Cells in
 // global memory: lane L owns sum L.  Cells staged in LDS: the four lanes of
 // quad r add up row r (moment r) together, and lane 4 r + h keeps the total
-// of set h (h = 0 plain, 1 weighted): sum 13 h + r.
-template <bool IN_LDS, bool VR>
+// of set h (h = 0 plain, 1 weighted): sum 13 h + r.  Half-wave cells (T =
+// 32, staged in LDS): cell lanes 2 r and 2 r + 1 add up row r, and cell lane
+// 2 r + h keeps sum 13 h + r.
+template <bool IN_LDS, bool VR, int T = 64>
 __device__ __forceinline__ int owned_sum(int lane) {
     if (!IN_LDS) return lane < (VR ? kNsum : 13) ? lane : -1;
+    if constexpr (T == 32) {
+        const int r = lane >> 1, h = lane & 1;
+        return (r < 13 && h < (VR ? 2 : 1)) ? 13 * h + r : -1;
+    }
     const int r = lane >> 2, h = lane & 3;
     return (r < 13 && h < (VR ? 2 : 1)) ? 13 * h + r : -1;
 }
@@ -1028,12 +1210,12 @@ struct CellPrefetch<true> {
     unsigned long long cand, acc;
 };
 
-template <typename R, bool VR, bool IN_LDS>
+template <typename R, bool VR, bool IN_LDS, int T = 64>
 __device__ __forceinline__ CellPrefetch<!VR> prefetch_cell(const CollideArgs<R> &a, uint32_t cell) {
     CellPrefetch<!VR> pf{};
     if constexpr (!VR) {
-        const int lane = lane_id();
-        const int idx = owned_sum<IN_LDS, VR>(lane);
+        const int lane = cell_lane<T>();
+        const int idx = owned_sum<IN_LDS, VR, T>(lane);
         pf.sum = idx >= 0 ? a.sums[(size_t)cell * kNsum + idx] : 0.0;
         pf.cand = 0ull;
         pf.acc = 0ull;
@@ -1063,8 +1245,8 @@ template <typename R, bool VR, typename View, int T = 64>
 __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cell, uint32_t N, uint32_t M,
                             uint32_t acc, uint32_t over, const CellPrefetch<!VR> &pf, double *red,
                             uint32_t wb_base, GroupScratch *gs = nullptr) {
-    const int lane = lane_id();
-    const uint32_t tid = threadIdx.x;
+    const int lane = cell_lane<T>();
+    const uint32_t tid = cell_tid<T>();
     constexpr int K = VR ? 32 : 16;  // 26 or 13 sums, padded to a power of two
     double q[K];
 #pragma unroll
@@ -1127,6 +1309,35 @@ __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cel
 #pragma unroll
             for (int w = 0; w < T / 64; ++w) tot += gs->d[w][tid];
         }
+    } else if constexpr (T == 32) {
+        // the transpose in the half's own area: 13 rows of 32 doubles, two
+        // lanes per row, each adding 16 of its doubles (8 interleaved
+        // 16-byte columns, starting at column block r mod 8)
+        static_assert(View::kInLds, "half-wave cells are staged in LDS");
+        constexpr int RS = 32;
+        const int row = lane >> 1, part = lane & 1;
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < (VR ? 2 : 1); ++h) {
+#pragma unroll
+            for (int u = 0; u < 13; ++u) red[u * RS + lane] = q[13 * h + u];
+            __syncthreads();
+            double t = 0.0;
+            if (row < 13) {
+                const double2 *rp = (const double2 *)(red + row * RS);
+                double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const double2 e = rp[2 * ((c + row) & 7) + part];
+                    s0 += e.x;
+                    s1 += e.y;
+                }
+                t = s0 + s1;
+            }
+            t = t + quad_perm_f64<0xB1>(t);
+            if (part == h) tot = t;
+            __syncthreads();
+        }
     } else if constexpr (View::kInLds) {
         constexpr int RS = kRedStride;
         const int row = lane >> 2, part = lane & 3;
@@ -1157,12 +1368,12 @@ __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cel
         const double t = wave_sum_many<K>(q);  // lane L: total of index L >> (VR ? 1 : 2)
         tot = __shfl(t, (lane << (VR ? 1 : 2)) & 63, 64);
     }
-    const int owned = owned_sum<View::kInLds && T == 64, VR>((int)tid);
+    const int owned = owned_sum<View::kInLds && T <= 64, VR, T>((int)tid);
     const uint32_t idx = (uint32_t)owned;
     const bool writer = owned >= 0;
     const bool nonfinite = writer && !isfinite(tot);
-    const bool bad_plain = __ballot(nonfinite && idx < 13) != 0ull;
-    const bool bad_vr = __ballot(nonfinite && idx >= 13) != 0ull;
+    const bool bad_plain = cell_ballot<T>(nonfinite && idx < 13) != 0ull;
+    const bool bad_vr = cell_ballot<T>(nonfinite && idx >= 13) != 0ull;
     const uint32_t ce = bounds_ck(cell, a.n_cells, a.st);
     double *sum_at = a.sums + (size_t)ce * kNsum + idx;
     unsigned long long *cnt_at = a.counters + 2 * (size_t)ce;
@@ -1225,7 +1436,7 @@ __device__ void process_cell(const CollideArgs<R> &a, const View &v, uint32_t ce
         double Mf = floor(Mreal + unif53(r.v[0], r.v[1]));
         if (!(Mf >= 0.0)) Mf = 0.0;
         if (Mf > kMaxCandidates) {
-            if (threadIdx.x == 0) set_error(a.st, DSMC_ECAPACITY);
+            if (cell_tid<T>() == 0) set_error(a.st, DSMC_ECAPACITY);
             Mf = 0.0;
         }
         M = (uint32_t)Mf;

@@ -54,16 +54,17 @@ __device__ __forceinline__ uint32_t bitonic_sort(uint32_t v, uint32_t lane) {
     return v;
 }
 
-// Ascending sort of C values per lane (element lane + 64 r in register r,
-// 64 C elements): the same bitonic network, with the stages of distance 64
-// and more exchanging registers within a lane.
-template <int C, int K, int J>
+// Ascending sort of C values per lane (element lane + L r in register r,
+// L C elements; L = 64 a wave, 32 a half-wave cell with `lane` its cell
+// lane): the same bitonic network, with the stages of distance L and more
+// exchanging registers within a lane.
+template <int C, int K, int J, int L = 64>
 __device__ __forceinline__ void bitonic_stage_regs(uint32_t (&v)[4], uint32_t lane) {
 #pragma unroll
     for (int r = 0; r < C; ++r) {
-        const bool asc = ((lane + 64u * (uint32_t)r) & (uint32_t)K) == 0u;
-        if constexpr (J >= 64) {
-            constexpr int R = J / 64;
+        const bool asc = ((lane + (uint32_t)L * (uint32_t)r) & (uint32_t)K) == 0u;
+        if constexpr (J >= L) {
+            constexpr int R = J / L;
             if ((r & R) == 0) {
                 const uint32_t a = v[r], b = v[r | R];
                 const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
@@ -78,24 +79,27 @@ __device__ __forceinline__ void bitonic_stage_regs(uint32_t (&v)[4], uint32_t la
         }
     }
 }
-template <int C, int K, int J>
+template <int C, int K, int J, int L = 64>
 __device__ __forceinline__ void bitonic_merge_regs(uint32_t (&v)[4], uint32_t lane) {
-    bitonic_stage_regs<C, K, J>(v, lane);
-    if constexpr (J > 1) bitonic_merge_regs<C, K, J / 2>(v, lane);
+    bitonic_stage_regs<C, K, J, L>(v, lane);
+    if constexpr (J > 1) bitonic_merge_regs<C, K, J / 2, L>(v, lane);
 }
-template <int C, int K>
+template <int C, int K, int L = 64>
 __device__ __forceinline__ void bitonic_sort_regs(uint32_t (&v)[4], uint32_t lane) {
-    if constexpr (K > 2) bitonic_sort_regs<C, K / 2>(v, lane);
-    bitonic_merge_regs<C, K, K / 2>(v, lane);
+    if constexpr (K > 2) bitonic_sort_regs<C, K / 2, L>(v, lane);
+    bitonic_merge_regs<C, K, K / 2, L>(v, lane);
 }
 
 // Selection of `cell`: source positions written to sel[0..N) (sel holds at
 // least N entries); returns whether they must still be merged by position
 // (overflow movers).  Any mismatch with the cell's count is reported, and sel
-// is filled with valid positions.
-template <typename R>
+// is filled with valid positions.  T = 64: the wave; T = 32: the cell's half
+// of a wave (at most 128 mover slots).
+template <typename R, int T = 64>
 __device__ __forceinline__ bool select_cell(const CollideArgs<R> &a, uint32_t cell, uint32_t N, uint32_t *sel) {
-    const uint32_t lane = (uint32_t)lane_id();
+    constexpr uint32_t L = (uint32_t)T;
+    constexpr int P = 128 / T;  // chunks of codes loaded at once
+    const uint32_t lane = (uint32_t)cell_lane<T>();
     const unsigned long long lt = (1ull << lane) - 1ull;
     if (N == 0) return false;  // nothing lands here (and the sequence may be empty)
     const uint32_t b = a.src_start[cell], e = a.src_start[cell + 1];
@@ -106,54 +110,59 @@ __device__ __forceinline__ bool select_cell(const CollideArgs<R> &a, uint32_t ce
     uint32_t v[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const uint32_t el = lane + 64u * (uint32_t)r;
+        const uint32_t el = lane + L * (uint32_t)r;
         v[r] = 0xFFFFFFFFu;
-        if (r == 0 || nm > 64u * (uint32_t)r) v[r] = el < nm ? ml[el] : 0xFFFFFFFFu;  // uniform test
+        if (r == 0 || nm > L * (uint32_t)r) v[r] = el < nm ? ml[el] : 0xFFFFFFFFu;  // uniform test
     }
-    // the codes of the cell's own range, the first two chunks loaded at once
+    // the codes of the cell's own range, the first chunks loaded at once;
     // every load below is issued from an in-bounds address (the sequence is
     // not empty) and masked afterwards
     const uint32_t last = e > b ? e - 1u : (b > 0u ? b - 1u : 0u);
-    const uint32_t i0 = b + lane, i1 = b + 64u + lane;
-    const uint8_t c0 = a.rg.code[i0 < e ? i0 : last], c1 = a.rg.code[i1 < e ? i1 : last];
-    if (nm <= 32) v[0] = bitonic_sort<32>(v[0], lane);
-    else if (nm <= 64) v[0] = bitonic_sort<64>(v[0], lane);
-    else if (nm <= 128) bitonic_sort_regs<2, 128>(v, lane);
-    else bitonic_sort_regs<4, 256>(v, lane);
+    uint32_t ic[P];
+    uint8_t cc[P];
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+        ic[t] = b + L * (uint32_t)t + lane;
+        cc[t] = a.rg.code[ic[t] < e ? ic[t] : last];
+    }
+    if constexpr (T == 64) {
+        if (nm <= 32) v[0] = bitonic_sort<32>(v[0], lane);
+        else if (nm <= 64) v[0] = bitonic_sort<64>(v[0], lane);
+        else if (nm <= 128) bitonic_sort_regs<2, 128>(v, lane);
+        else bitonic_sort_regs<4, 256>(v, lane);
+    } else {
+        if (nm <= 32) v[0] = bitonic_sort<32>(v[0], lane);
+        else if (nm <= 64) bitonic_sort_regs<2, 64, 32>(v, lane);
+        else bitonic_sort_regs<4, 128, 32>(v, lane);
+    }
     uint32_t nlow = 0;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        if (r > 0 && nm <= 64u * (uint32_t)r) break;
-        const uint32_t el = lane + 64u * (uint32_t)r;
-        nlow += (uint32_t)__popcll(__ballot(el < nm && v[r] < b));
+        if (r > 0 && nm <= L * (uint32_t)r) break;
+        const uint32_t el = lane + L * (uint32_t)r;
+        nlow += (uint32_t)__popcll(cell_ballot<T>(el < nm && v[r] < b));
     }
     uint32_t nstay = 0;
-    {
-        const bool m = i0 < e && c0 == kStay;
-        const unsigned long long bal = __ballot(m);
-        const uint32_t pos = nlow + (uint32_t)__popcll(bal & lt);
-        if (m && pos < N) sel[pos] = i0;
-        nstay += (uint32_t)__popcll(bal);
-    }
-    {
-        const bool m = i1 < e && c1 == kStay;
-        const unsigned long long bal = __ballot(m);
+#pragma unroll
+    for (int t = 0; t < P; ++t) {
+        const bool m = ic[t] < e && cc[t] == kStay;
+        const unsigned long long bal = cell_ballot<T>(m);
         const uint32_t pos = nlow + nstay + (uint32_t)__popcll(bal & lt);
-        if (m && pos < N) sel[pos] = i1;
+        if (m && pos < N) sel[pos] = ic[t];
         nstay += (uint32_t)__popcll(bal);
     }
-    for (uint32_t c = b + 128u; c < e; c += 64u) {
+    for (uint32_t c = b + 128u; c < e; c += L) {
         const uint32_t i = c + lane;
         const bool m = i < e && a.rg.code[i] == kStay;
-        const unsigned long long bal = __ballot(m);
+        const unsigned long long bal = cell_ballot<T>(m);
         const uint32_t pos = nlow + nstay + (uint32_t)__popcll(bal & lt);
         if (m && pos < N) sel[pos] = i;
         nstay += (uint32_t)__popcll(bal);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        if (r > 0 && nm <= 64u * (uint32_t)r) break;
-        const uint32_t el = lane + 64u * (uint32_t)r;
+        if (r > 0 && nm <= L * (uint32_t)r) break;
+        const uint32_t el = lane + L * (uint32_t)r;
         if (el < nm) {
             const uint32_t pos = el < nlow ? el : el + nstay;
             if (pos < N) sel[pos] = v[r];
@@ -187,18 +196,18 @@ __device__ __forceinline__ uint32_t merged_rank(const uint32_t *sel, uint32_t N,
     return r;
 }
 
-// J elements per lane (e0 + 64 j + lane): every load issued before the first
-// store.  Positions, ids go straight to the new sequence; velocities and
-// weights to LDS at the element's rank.
-template <typename R, bool VR, int D, int J>
+// J elements per lane (e0 + T j + lane, T the cell's lanes): every load
+// issued before the first store.  Positions, ids go straight to the new
+// sequence; velocities and weights to LDS at the element's rank.
+template <typename R, bool VR, int D, int J, int T = 64>
 __device__ __forceinline__ void gather_j(const CollideArgs<R> &a, uint32_t base, uint32_t e0, uint32_t N,
                                          const uint32_t *sel, bool merge, Vel4<R> *vel) {
-    const uint32_t lane = (uint32_t)lane_id();
+    const uint32_t lane = (uint32_t)cell_lane<T>();
     uint32_t q[J], r[J], id[J];
     R x[J], y[J], c0[J], c1[J], c2[J], ww[J];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-        const uint32_t el = e0 + 64u * (uint32_t)j + lane;
+        const uint32_t el = e0 + (uint32_t)T * (uint32_t)j + lane;
         q[j] = el < N ? sel[el] : 0u;
         r[j] = el;
     }
@@ -209,7 +218,7 @@ __device__ __forceinline__ void gather_j(const CollideArgs<R> &a, uint32_t base,
     }
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-        if (e0 + 64u * (uint32_t)j + lane < N) {
+        if (e0 + (uint32_t)T * (uint32_t)j + lane < N) {
             q[j] = bounds_ck(q[j], a.n_total, a.st);
             x[j] = a.src.x[q[j]];
             if (D == 2) y[j] = a.src.y[q[j]];
@@ -220,7 +229,7 @@ __device__ __forceinline__ void gather_j(const CollideArgs<R> &a, uint32_t base,
     }
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-        if (e0 + 64u * (uint32_t)j + lane < N) {
+        if (e0 + (uint32_t)T * (uint32_t)j + lane < N) {
             const uint32_t o = bounds_ck(base + (r[j] < N ? r[j] : N - 1), a.n_total, a.st);
             a.s.x[o] = x[j];
             if (D == 2) a.s.y[o] = y[j];
@@ -240,18 +249,19 @@ __device__ __forceinline__ void gather_j(const CollideArgs<R> &a, uint32_t base,
 // of at least N entries), then the particles into the new sequence at
 // `base` (velocities and weights into LDS when vel is given, else into the
 // new sequence too).
-template <typename R, bool VR, int D>
+template <typename R, bool VR, int D, int T = 64>
 __device__ __forceinline__ void gather_cell(const CollideArgs<R> &a, uint32_t cell, uint32_t base, uint32_t N,
                                             uint32_t *sel, Vel4<R> *vel) {
-    const bool merge = select_cell(a, cell, N, sel);
+    constexpr uint32_t L = (uint32_t)T;
+    const bool merge = select_cell<R, T>(a, cell, N, sel);
     __syncthreads();
     uint32_t e0 = 0;
-    for (; e0 + 256 <= N; e0 += 256) gather_j<R, VR, D, 4>(a, base, e0, N, sel, merge, vel);
+    for (; e0 + 4 * L <= N; e0 += 4 * L) gather_j<R, VR, D, 4, T>(a, base, e0, N, sel, merge, vel);
     const uint32_t left = N - e0;
-    if (left > 192) gather_j<R, VR, D, 4>(a, base, e0, N, sel, merge, vel);
-    else if (left > 128) gather_j<R, VR, D, 3>(a, base, e0, N, sel, merge, vel);
-    else if (left > 64) gather_j<R, VR, D, 2>(a, base, e0, N, sel, merge, vel);
-    else if (left > 0) gather_j<R, VR, D, 1>(a, base, e0, N, sel, merge, vel);
+    if (left > 3 * L) gather_j<R, VR, D, 4, T>(a, base, e0, N, sel, merge, vel);
+    else if (left > 2 * L) gather_j<R, VR, D, 3, T>(a, base, e0, N, sel, merge, vel);
+    else if (left > L) gather_j<R, VR, D, 2, T>(a, base, e0, N, sel, merge, vel);
+    else if (left > 0) gather_j<R, VR, D, 1, T>(a, base, e0, N, sel, merge, vel);
 }
 
 // LDS kernel body: one wave per cell.  Homogeneous instances (D 0) collide
@@ -307,6 +317,51 @@ __device__ __forceinline__ void collide_lds_body(const CollideArgs<R> &a, unsign
     __syncthreads();
 }
 
+// Two walled cells per wave, 32 lanes each: lanes 0-31 take schedule entry
+// 2 b of workgroup b, lanes 32-63 entry 2 b + 1 (kNoCell: none).  Each half
+// gathers, collides and samples its cell in its own LDS area of
+// pair_area_bytes(cap) bytes by the same steps as the one-wave kernel, every
+// cross-lane operation staying inside the half; a wave's 64 lanes then carry
+// two windows of candidates instead of one mostly idle one.
+constexpr uint32_t kNoCell = 0xFFFFFFFFu;
+template <typename R>
+__host__ __device__ constexpr size_t pair_area_bytes(int cap) {
+    const size_t part = (size_t)cap * (sizeof(Vel4<R>) + 4) + 16 + 16;  // particles, owner marks (+4)
+    const size_t red = (size_t)13 * 32 * 8;                             // moment transpose
+    return ((part > red ? part : red) + 15) / 16 * 16;
+}
+
+template <typename R, bool VR, int D>
+__device__ __forceinline__ void collide_pair_body(const CollideArgs<R> &a, unsigned char *smem) {
+    constexpr int T = 32;
+    const uint32_t half = (uint32_t)lane_id() >> 5;
+    const uint32_t lane = cell_tid<T>();
+    const uint32_t cell = a.sched[2 * blockIdx.x + half];
+    if (cell == kNoCell) return;
+    const uint32_t base = a.start[cell];
+    const uint32_t N = a.start[cell + 1] - base;
+    if (N > (uint32_t)a.cap) {
+        if (lane == 0) {
+            const uint32_t q = atomicAdd(a.bigc, 1u);
+            a.big_list[q] = cell;
+        }
+        return;
+    }
+    const uint32_t step = (uint32_t)(a.st->step_cur + a.step_off);
+    const auto pf = prefetch_cell<R, VR, true, T>(a, cell);
+    const int cap = a.cap;
+    unsigned char *area = smem + (size_t)half * pair_area_bytes<R>(cap);
+    Vel4<R> *vel = (Vel4<R> *)area;
+    uint32_t *owner = (uint32_t *)(vel + cap);  // cap + 4 entries; first the gather's selection
+    gather_cell<R, VR, D, T>(a, cell, base, N, owner, vel);
+    __syncthreads();
+    const LdsView<R, false> view{vel, owner, view_check((uint32_t)cap, a.st)};
+    for (uint32_t r = lane; r < N; r += T) view.clear_own(r);
+    __syncthreads();
+    process_cell<R, VR, LdsView<R, false>, T>(a, view, cell, N, step, pf, (double *)area, base);
+    __syncthreads();
+}
+
 // Global-memory kernel for cells larger than the LDS capacity: walled cells
 // are gathered into the new sequence (selection in a global scratch array),
 // then every cell is operated on in place.
@@ -342,6 +397,14 @@ template <typename R, bool VR, int D, int OCC = 5>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void k_collide(CollideArgs<R> a) {
     extern __shared__ __align__(16) unsigned char smem[];
     collide_lds_body<R, VR, D, false>(a, smem, a.sched ? a.sched[blockIdx.x] : blockIdx.x);
+}
+
+// Two walled cells per wave (FP32: four waves per SIMD, the LDS of two cells
+// of the pair capacity allowing about as many).
+template <typename R, bool VR, int D, int OCC = 4>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void k_collide_pair(CollideArgs<R> a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    collide_pair_body<R, VR, D>(a, smem);
 }
 
 // Large homogeneous instances: one workgroup of kWideThreads threads per

@@ -61,7 +61,8 @@ def test_workspace_size_valid_configs(lib):
     ("FN", -1.0, -1), ("molecule", 5, -1), ("majorant", 7, -1), ("n_particles", -5, -1),
     ("schedule", 2, -1), ("persistent_waves", -1, -1), ("chunk_work", -3, -1),
     ("vr_reconstruct", -1, -1), ("vr_kappa", 0.5, -1), ("vr_kappa", 17.0, -1), ("wide_min", 32, -1),
-    ("wide_min", -1, -1), ("occupancy", 4, -1), ("occupancy", 7, -1),
+    ("wide_min", -1, -1), ("occupancy", 4, -1), ("occupancy", 7, -1), ("cells_per_wave", 3, -1),
+    ("cells_per_wave", -1, -1),
 ])
 def test_workspace_size_rejects_invalid(lib, field, value, code):
     p, parts = W.cavity(nx=4, ny=4, per_cell=5)
@@ -183,6 +184,42 @@ def test_grid_kernel_parameters_accepted(lib):
         cfg = binding.make_config(dict(p, **over), len(parts["cx"]))
         cfg.inst_offset = off.ctypes.data
         assert _ws(lib, cfg)[0] == 0, over
+
+
+def test_autotune_walled_signature_and_pair_rule():
+    from paper_2301_05985_amd import autotune
+    p, parts = W.cavity(nx=8, ny=8, per_cell=20)
+    n = len(parts["cx"])
+    sig = autotune.signature(p, n)
+    assert sig == autotune.signature(dict(p), n)
+    for q in (dict(p, vr=1 - p.get("vr", 0)), dict(p, vr_reconstruct=4), dict(p, vr_kappa=1.5),
+              dict(p, real="f64"), dict(p, molecule=W.VHS), dict(p, n_cells=(8, 4))):
+        assert autotune.signature(q, n) != sig
+    assert autotune.signature(p, n + 1) != sig
+    assert autotune.pair_allowed(p, n) and autotune.pair_allowed(dict(p, majorant=2), n)
+    assert not autotune.pair_allowed(dict(p, majorant=1), n)
+    assert autotune.pair_allowed(p, 128 * 64) and not autotune.pair_allowed(p, 128 * 64 + 1)
+    pb, partsb = W.batched(n_inst=8, nmin=10, nmax=20)
+    assert not autotune.pair_allowed(pb, len(partsb["cx"]))
+    assert "cells_per_wave" in autotune.LAUNCH_KEYS
+
+
+def test_two_cells_per_wave_accepted_only_where_it_applies(lib):
+    # walled runs with the exact or brute-force majorant and a mean cell
+    # population of at most 128 (128 mover slots)
+    for p, parts in (W.cavity(nx=4, ny=4, per_cell=5), W.fourier(n_cells=8, per_cell=128, real="f64")):
+        for maj, code in ((0, 0), (2, 0), (1, -1)):
+            cfg = binding.make_config(dict(p, cells_per_wave=2, majorant=maj), len(parts["cx"]))
+            assert _ws(lib, cfg)[0] == code, (maj, p["dims"])
+    p, parts = W.fourier(n_cells=8, per_cell=129)
+    assert _ws(lib, binding.make_config(dict(p, cells_per_wave=2), len(parts["cx"])))[0] == -1
+    assert _ws(lib, binding.make_config(dict(p, cells_per_wave=1), len(parts["cx"])))[0] == 0
+    p, parts = W.batched(n_inst=8, nmin=10, nmax=20)
+    off = np.ascontiguousarray(p["inst_offset"], dtype=np.int64)
+    for cpw, code in ((0, 0), (1, 0), (2, -1)):
+        cfg = binding.make_config(dict(p, cells_per_wave=cpw), len(parts["cx"]))
+        cfg.inst_offset = off.ctypes.data
+        assert _ws(lib, cfg)[0] == code, cpw
 
 
 def test_autotune_refines_only_the_grid_schedule():

@@ -22,13 +22,16 @@ def _announce(name):
     print("[gpu case] %s" % name, flush=True)
 
 
-def test_cavity_full_size_one_step_against_the_oracle(gpu):
-    # cavity at full size (6,553,600 particles, 65,536 cells, FP32, weights):
-    # the GPU's state after step 1, in its particle sequence, goes into the
-    # oracle, which takes step 2 (fly, regroup, collide every cell, sample)
-    _announce("cavity full size one step")
+@pytest.mark.parametrize("cpw", [1, 2])
+def test_cavity_full_size_one_step_against_the_oracle(gpu, cpw):
+    # cavity at full size (6,553,600 particles, 65,536 cells, FP32, weights,
+    # the benchmark's weight settings), one or two cells per wave: the GPU's
+    # state after step 1, in its particle sequence, goes into the oracle,
+    # which takes step 2 (fly, regroup, collide every cell, sample)
+    _announce("cavity full size one step, %d cell(s) per wave" % cpw)
     from paper_2301_05985_amd.binding import Simulation
     p, parts = W.cavity(Kn=0.01, real="f32")
+    p.update(vr_reconstruct=4, vr_kappa=1.5, cells_per_wave=cpw)
     sim = Simulation(p, parts)
     sim.step(1)
     s1 = sim.sequence()

@@ -139,3 +139,18 @@ def test_autotune_refines_grid(gpu, tmp_path, monkeypatch):
     assert len(times) == 1 + len(autotune.WIDE_MIN) + len(autotune.OCCUPANCY)
     assert best["schedule"] == 0
     assert set(best) <= set(autotune.LAUNCH_KEYS)
+
+
+def test_autotune_walled_launch(gpu, tmp_path, monkeypatch):
+    # a walled cavity: one against two cells per wave, cached; a learned
+    # majorant (no two-cell kernel) returns one cell per wave untimed
+    _announce("autotune walled")
+    from paper_2301_05985_amd import autotune
+    monkeypatch.setenv("DSMC_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    p, parts = W.cavity(nx=64, ny=64, per_cell=60, Kn=0.02, real="f32")
+    p = dict(p, vr_reconstruct=2, vr_kappa=1.5)
+    best, times = autotune.tune(p, parts, warmup=4)
+    assert best in autotune.WALLED and len(times) == 2
+    again, t2 = autotune.tune(p, parts)
+    assert again == best and t2 == times
+    assert autotune.tune(dict(p, majorant=1), parts) == ({"cells_per_wave": 1}, {})
