@@ -696,12 +696,15 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
         c->cap = std::max(64, std::min(want, cap_fit));
         c->pair = cfg->cells_per_wave == 2;
         if (c->pair) {
-            // two cells per wave: 1.6 x mean + 64 per cell, so that a wave's
-            // two cells leave LDS room for four waves per SIMD (FP32)
+            // two cells per wave: 1.28 x mean + 64 per cell, so that a wave's
+            // two cells leave LDS room for five waves per SIMD (FP32, the
+            // kernel's register budget; 192 on the 100-per-cell cavity); at
+            // least 128, so that a cell's owner marks (cap + 4 words) can
+            // hold the 64 FP64 sums of the weight re-estimation
             const int cap_fit_pair = (int)std::min<size_t>((kMaxLds / 2 - 64) / per, 65535) / 32 * 32;
-            int wp = (int)std::ceil(1.6 * mean + 64.0);
+            int wp = (int)std::ceil(1.28 * mean + 64.0);
             wp = (wp + 31) / 32 * 32;
-            c->cap = std::max(64, std::min(wp, cap_fit_pair));
+            c->cap = std::max(128, std::min(wp, cap_fit_pair));
         }
         const int64_t maxbig = c->n / (c->cap + 1);
         c->any_big_possible = maxbig > 0;

@@ -1020,32 +1020,32 @@ __device__ __forceinline__ double gram_pass(const View &v, uint32_t N, double sc
 // Normal equations of a half-wave cell (T = 32) from the four passes' sums
 // (pass p's sum s on cell lanes 2 s and 2 s + 1): the same Gauss-Jordan
 // elimination as the one-wave form, with two lanes per row: cell lane 2 r + q
-// holds the entries (r, q + 2 j), j = 0..6 (column 13 is b).  The solution
-// goes to coef[0..13) (LDS of the half; vector registers for all thirteen
-// would cost the kernel a wave per SIMD).  Returns false, writing nothing,
-// if the cell keeps its weights.
-__device__ __forceinline__ bool solve_half(double t0, double t1, double t2, double t3, double *coef) {
+// holds the entries (r, q + 2 j), j = 0..6 (column 13 is b).  The 64 sums
+// are staged in lds[0..64) (the half's owner marks, free once the candidates
+// are done), from which every lane assembles its entries; the solution goes
+// to lds[0..13).  Returns false, writing no solution, if the cell keeps its
+// weights.
+__device__ __forceinline__ bool solve_half(double t0, double t1, double t2, double t3, double *lds) {
     const int cl = lane_id() & 31;
-    // sum g (pass g / 16, index g mod 16) from cell lane 2 (g mod 16) + (g / 16) mod 2
-    const double sa = (cl & 1) ? t1 : t0, sb = (cl & 1) ? t3 : t2;
-    const auto fetch = [&](int g) {
-        const double x = cell_shfl<32>(sa, 2 * (g & 15) + ((g >> 4) & 1));
-        const double y = cell_shfl<32>(sb, 2 * (g & 15) + ((g >> 4) & 1));
-        return (g >> 5) ? y : x;
-    };
     const int row = cl >> 1, qc = cl & 1;
+    // sum g = 16 p + s of pass p (p = qc and 2 + qc on cell lane 2 s + qc)
+    lds[16 * qc + row] = qc ? t1 : t0;
+    lds[16 * (2 + qc) + row] = qc ? t3 : t2;
+    __syncthreads();
     const bool has_row = row < kReBasis;
     const int rr = has_row ? row : 0;
     double M[7];
 #pragma unroll
     for (int j = 0; j < 7; ++j) {
         const int col = qc + 2 * j;
-        const int cc = col < kReBasis ? col : 0;
-        const int nt = kGram.n[rr][cc];
-        const double e0 = fetch(col == kReBasis ? 51 + rr : kGram.t[rr][cc][0]);
-        const double e1 = fetch(nt == 3 ? kGram.t[rr][cc][1] : 0);
-        const double e2 = fetch(nt == 3 ? kGram.t[rr][cc][2] : 0);
-        M[j] = (!has_row || col > kReBasis) ? 0.0 : ((col < kReBasis && nt == 3) ? (e0 + e1) + e2 : e0);
+        double e = 0.0;
+        if (has_row && col < kReBasis) {
+            e = lds[kGram.t[rr][col][0]];
+            if (kGram.n[rr][col] == 3) e = (e + lds[kGram.t[rr][col][1]]) + lds[kGram.t[rr][col][2]];
+        } else if (has_row && col == kReBasis) {
+            e = lds[51 + rr];
+        }
+        M[j] = e;
     }
     // this lane's original diagonal entry (row r: column r, slot r >> 1 on lane 2 r + (r & 1))
     double mdiag = M[0];
@@ -1066,8 +1066,10 @@ __device__ __forceinline__ bool solve_half(double t0, double t1, double t2, doub
         for (int j = 0; j < 7; ++j) M[j] = fma(-f, cell_shfl<32>(M[j], 2 * k + qc), M[j]);
     }
     if (!ok) return false;  // a pivot not above 1e-12 G_kk: the cell keeps its weights
-    // solution: column 13 (cell lane 2 r + 1, slot 6)
-    if (has_row && qc == 1) coef[row] = M[6];
+    // solution: column 13 (cell lane 2 r + 1, slot 6); every lane has read
+    // the sums it needed (the reads above precede these writes in the wave)
+    __syncthreads();
+    if (has_row && qc == 1) lds[row] = M[6];
     return true;
 }
 
@@ -1150,8 +1152,10 @@ __device__ __forceinline__ R reestimated_weight(const Coef &k, double sc, R a, R
 template <typename R, typename View, int T>
 __device__ __forceinline__ void reestimate_weights(const View &v, uint32_t N, double sc, GroupScratch *gs) {
     if constexpr (T == 32) {
-        // half-wave cell: the coefficients in the owner array of its LDS
-        // area (the candidates, which use the marks, are done)
+        // half-wave cell: the sums and the coefficients in the owner array
+        // of its LDS area (the candidates, which use the marks, are done;
+        // the two-cell launch gives a cell at least 128 + 4 marks, room for
+        // 64 doubles)
         static_assert(View::kInLds, "half-wave cells are staged in LDS");
         double *coef = reinterpret_cast<double *>(v.owner);
         const double t0 = gram_pass<0, R, View, T>(v, N, sc, gs);

@@ -399,9 +399,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
     collide_lds_body<R, VR, D, false>(a, smem, a.sched ? a.sched[blockIdx.x] : blockIdx.x);
 }
 
-// Two walled cells per wave (FP32: four waves per SIMD, the LDS of two cells
-// of the pair capacity allowing about as many).
-template <typename R, bool VR, int D, int OCC = 4>
+// Two walled cells per wave: five waves per SIMD (the kernel fits their 96
+// registers without spills; in FP32 the LDS of two cells of the pair
+// capacity allows as many).
+template <typename R, bool VR, int D, int OCC = 5>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void k_collide_pair(CollideArgs<R> a) {
     extern __shared__ __align__(16) unsigned char smem[];
     collide_pair_body<R, VR, D>(a, smem);

@@ -225,14 +225,14 @@ def test_two_cells_per_wave_matches_oracle_and_one_cell_launch(gpu, name):
 
 @pytest.mark.parametrize("extra", [0, 1])
 def test_cell_at_pair_capacity_and_one_above(gpu, extra):
-    # 160 particles in 8 cells: the pair capacity is 1.6 x 20 + 64 = 96 per
-    # cell; cell 0 holds 96 (staged in LDS) or 97 (global memory).  A tiny
-    # time step keeps every particle in its cell.
+    # 160 particles in 8 cells: the pair capacity is 1.28 x 20 + 64 rounded
+    # up to 32, at least 128; cell 0 holds 128 (staged in LDS) or 129 (global
+    # memory).  A tiny time step keeps every particle in its cell.
     _announce("cell at pair capacity + %d" % extra)
     p, _ = W.fourier(n_cells=8, per_cell=1, Kn=0.05, dt=1e-7, vr=1)
     p["wall_kind"] = (W.WALL_SPECULAR, W.WALL_SPECULAR, 0, 0)
     p["sigma"] = 1300.0
-    n, n0 = 160, 96 + extra
+    n, n0 = 160, 128 + extra
     rng = np.random.default_rng(12)
     x = np.concatenate([rng.uniform(0.01, 0.115, n0), rng.uniform(0.135, 0.99, n - n0)])
     c = rng.standard_normal((3, n))
