@@ -1252,6 +1252,20 @@ __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cel
     const int lane = cell_lane<T>();
     const uint32_t tid = cell_tid<T>();
     constexpr int K = VR ? 32 : 16;  // 26 or 13 sums, padded to a power of two
+    const int owned = owned_sum<View::kInLds && T <= 64, VR, T>((int)tid);
+    const uint32_t idx = (uint32_t)owned;
+    const bool writer = owned >= 0;
+    const uint32_t ce = bounds_ck(cell, a.n_cells, a.st);
+    double *sum_at = a.sums + (size_t)ce * kNsum + idx;
+    unsigned long long *cnt_at = a.counters + 2 * (size_t)ce;
+    // half-wave cells with weights read their running sums here, so that
+    // the latency overlaps the accumulation below (the one-wave kernel at six
+    // waves per SIMD has no registers to spare and reads them at the end)
+    constexpr bool kEarly = VR && T == 32;
+    double old_sum = 0.0;
+    if constexpr (kEarly) {
+        if (writer) old_sum = *sum_at;
+    }
     double q[K];
 #pragma unroll
     for (int t = VR ? 26 : 13; t < K; ++t) q[t] = 0.0;  // padding
@@ -1372,17 +1386,13 @@ __device__ void sample_cell(const CollideArgs<R> &a, const View &v, uint32_t cel
         const double t = wave_sum_many<K>(q);  // lane L: total of index L >> (VR ? 1 : 2)
         tot = __shfl(t, (lane << (VR ? 1 : 2)) & 63, 64);
     }
-    const int owned = owned_sum<View::kInLds && T <= 64, VR, T>((int)tid);
-    const uint32_t idx = (uint32_t)owned;
-    const bool writer = owned >= 0;
     const bool nonfinite = writer && !isfinite(tot);
     const bool bad_plain = cell_ballot<T>(nonfinite && idx < 13) != 0ull;
     const bool bad_vr = cell_ballot<T>(nonfinite && idx >= 13) != 0ull;
-    const uint32_t ce = bounds_ck(cell, a.n_cells, a.st);
-    double *sum_at = a.sums + (size_t)ce * kNsum + idx;
-    unsigned long long *cnt_at = a.counters + 2 * (size_t)ce;
     if constexpr (!VR) {
         if (writer) *sum_at = pf.sum + tot;
+    } else if constexpr (kEarly) {
+        if (writer) *sum_at = old_sum + tot;
     } else {
         if (writer) *sum_at = *sum_at + tot;
     }
