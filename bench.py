@@ -35,7 +35,7 @@ METRIC = "accepted collisions/s + particle-steps/s on 1 MI355X; learned vs exact
 # algorithmic bytes per particle and launch, FP32 2-D with weights, 100
 # particles per cell
 ALGO_BYTES = {
-    "stream": 25.0,    # read x, y, cx, cy; write x, y and one code byte
+    "stream": 17.0,    # read x, y, cx, cy; write one code byte (the gather advances the positions)
     # gather-collide: read the 28 B state (x, y, cx, cy, cz, w, id) and one
     # code byte, write the 28 B state into the new sequence, read and
     # write the cell's 26 FP64 running sums (416 B per cell of 100)

@@ -90,11 +90,12 @@ __device__ __forceinline__ void bitonic_sort_regs(uint32_t (&v)[4], uint32_t lan
     bitonic_merge_regs<C, K, K / 2, L>(v, lane);
 }
 
-// Selection of `cell`: source positions written to sel[0..N) (sel holds at
-// least N entries); returns whether they must still be merged by position
-// (overflow movers).  Any mismatch with the cell's count is reported, and sel
-// is filled with valid positions.  T = 64: the wave; T = 32: the cell's half
-// of a wave (at most 128 mover slots).
+// Selection of `cell`: source entries 2 p + flown (p the source position,
+// flown set where the wall kernel already stored the final position) written
+// to sel[0..N) (sel holds at least N entries); returns whether they must
+// still be merged by position (overflow movers).  Any mismatch with the
+// cell's count is reported, and sel is filled with valid positions.  T = 64:
+// the wave; T = 32: the cell's half of a wave (at most 128 mover slots).
 template <typename R, int T = 64>
 __device__ __forceinline__ bool select_cell(const CollideArgs<R> &a, uint32_t cell, uint32_t N, uint32_t *sel) {
     constexpr uint32_t L = (uint32_t)T;
@@ -140,23 +141,24 @@ __device__ __forceinline__ bool select_cell(const CollideArgs<R> &a, uint32_t ce
     for (int r = 0; r < 4; ++r) {
         if (r > 0 && nm <= L * (uint32_t)r) break;
         const uint32_t el = lane + L * (uint32_t)r;
-        nlow += (uint32_t)__popcll(cell_ballot<T>(el < nm && v[r] < b));
+        nlow += (uint32_t)__popcll(cell_ballot<T>(el < nm && v[r] < 2u * b));  // entries sort by position
     }
     uint32_t nstay = 0;
 #pragma unroll
     for (int t = 0; t < P; ++t) {
-        const bool m = ic[t] < e && cc[t] == kStay;
+        const bool m = ic[t] < e && (cc[t] & kStay) != 0;
         const unsigned long long bal = cell_ballot<T>(m);
         const uint32_t pos = nlow + nstay + (uint32_t)__popcll(bal & lt);
-        if (m && pos < N) sel[pos] = ic[t];
+        if (m && pos < N) sel[pos] = 2u * ic[t] + ((cc[t] & kFlown) ? 1u : 0u);
         nstay += (uint32_t)__popcll(bal);
     }
     for (uint32_t c = b + 128u; c < e; c += L) {
         const uint32_t i = c + lane;
-        const bool m = i < e && a.rg.code[i] == kStay;
+        const uint8_t ci = i < e ? a.rg.code[i] : (uint8_t)0;
+        const bool m = (ci & kStay) != 0;
         const unsigned long long bal = cell_ballot<T>(m);
         const uint32_t pos = nlow + nstay + (uint32_t)__popcll(bal & lt);
-        if (m && pos < N) sel[pos] = i;
+        if (m && pos < N) sel[pos] = 2u * i + ((ci & kFlown) ? 1u : 0u);
         nstay += (uint32_t)__popcll(bal);
     }
 #pragma unroll
@@ -182,13 +184,13 @@ __device__ __forceinline__ bool select_cell(const CollideArgs<R> &a, uint32_t ce
             a.rg.far_head[cell] = kEmpty;
         }
         if (m != N) set_error(a.st, DSMC_ECAPACITY);
-        while (m < N) sel[m++] = last;  // valid positions only (b itself may be the end of the sequence)
+        while (m < N) sel[m++] = 2u * last;  // valid positions only (b itself may be the end of the sequence)
         if (mc) a.rg.mcount[cell] = 0u;
     }
     return merge;
 }
 
-// Position of source position q in the merged order: the number of smaller
+// Position of source entry q in the merged order: the number of smaller
 // entries of sel[0..N) (only cells with overflow movers need it).
 __device__ __forceinline__ uint32_t merged_rank(const uint32_t *sel, uint32_t N, uint32_t q) {
     uint32_t r = 0;
@@ -198,7 +200,8 @@ __device__ __forceinline__ uint32_t merged_rank(const uint32_t *sel, uint32_t N,
 
 // J elements per lane (e0 + T j + lane, T the cell's lanes): every load
 // issued before the first store.  Positions, ids go straight to the new
-// sequence; velocities and weights to LDS at the element's rank.
+// sequence; velocities and weights to LDS at the element's rank.  A particle
+// the wall kernel did not fly is moved to its end point x + c dt here.
 template <typename R, bool VR, int D, int J, int T = 64>
 __device__ __forceinline__ void gather_j(const CollideArgs<R> &a, uint32_t base, uint32_t e0, uint32_t N,
                                          const uint32_t *sel, bool merge, Vel4<R> *vel) {
@@ -216,20 +219,27 @@ __device__ __forceinline__ void gather_j(const CollideArgs<R> &a, uint32_t base,
         for (int j = 0; j < J; ++j)
             if (r[j] < N) r[j] = merged_rank(sel, N, q[j]);
     }
+    bool flown[J];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
+        flown[j] = (q[j] & 1u) != 0u;
         if (e0 + (uint32_t)T * (uint32_t)j + lane < N) {
-            q[j] = bounds_ck(q[j], a.n_total, a.st);
-            x[j] = a.src.x[q[j]];
-            if (D == 2) y[j] = a.src.y[q[j]];
-            c0[j] = a.src.cx[q[j]]; c1[j] = a.src.cy[q[j]]; c2[j] = a.src.cz[q[j]];
-            if (VR) ww[j] = a.src.w[q[j]];
-            id[j] = a.src.id[q[j]];
+            const uint32_t p = bounds_ck(q[j] >> 1, a.n_total, a.st);
+            x[j] = a.src.x[p];
+            if (D == 2) y[j] = a.src.y[p];
+            c0[j] = a.src.cx[p]; c1[j] = a.src.cy[p]; c2[j] = a.src.cz[p];
+            if (VR) ww[j] = a.src.w[p];
+            id[j] = a.src.id[p];
         }
     }
+    const R tau = (R)a.dt;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         if (e0 + (uint32_t)T * (uint32_t)j + lane < N) {
+            if (!flown[j]) {
+                x[j] = x[j] + c0[j] * tau;
+                if (D == 2) y[j] = y[j] + c1[j] * tau;
+            }
             const uint32_t o = bounds_ck(base + (r[j] < N ? r[j] : N - 1), a.n_total, a.st);
             a.s.x[o] = x[j];
             if (D == 2) a.s.y[o] = y[j];

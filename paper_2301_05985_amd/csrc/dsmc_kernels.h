@@ -1,7 +1,8 @@
 // dsmc_kernels.h -- the per-step kernels of the DSMC hot path on gfx950.
 //
 // One time step (Bird 1994, direct simulation Monte Carlo), walled runs:
-//   k_stream_code     free flight of the particles that stay in the box, new
+//   k_stream_code     end points of the particles that stay in the box (the
+//                     positions themselves are advanced by the gather), new
 //                     cell counted, one code byte each, movers listed; the others go
 //                     to the wall list                       [grid over particles]
 //   k_stream_walls    exact flight with wall conditions of the wall list
@@ -239,42 +240,52 @@ __device__ __forceinline__ uint32_t cell_index(const Geo &g, double x, double y)
 // ------------------------------------------------------------ regrouping
 // The particle sequence is regrouped every step by a stable counting sort on
 // the new cell.  Streaming marks each particle that stays in its cell
-// (code byte kStay) and appends the position of each particle that changes
+// (code byte with kStay) and appends the position of each particle that changes
 // cell (a mover) to a list of its new cell: 64, 128 or 256 slots per cell, the
 // rest (rare) linked into a per-cell overflow list.  The collision wave of
 // cell t then has, in ascending position, the movers from cells before t,
 // the particles that stayed in t, and the movers from cells after t: the
 // stays are found from t's own codes, the movers by sorting t's short list.
+//
+// Particles whose end point lies in the box keep their stored position: the
+// gather, which loads every particle anyway, moves them to x + c dt (the
+// same float operations as the streaming kernel's end point).  Particles of
+// the wall list are flown exactly by the second kernel, which stores their
+// final position and flags it: kFlown in the code byte, and bit 0 of the list
+// entry, which holds position p as 2 p + flown (the entries still sort by
+// position).
 constexpr uint8_t kStay = 1;
 constexpr uint8_t kMoved = 0;
+constexpr uint8_t kFlown = 2;
 constexpr uint32_t kMaxMoverSlots = 256;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 
 struct Regroup {
-    uint8_t *code;        // [n] kStay or kMoved per position of the streamed sequence
+    uint8_t *code;        // [n] kStay or kMoved, with kFlown, per position of the streamed sequence
     uint32_t *mcount;     // [ncell] movers into each cell this step (reset by the collision wave)
-    uint32_t *movers;     // [ncell][slots] their positions, in no particular order
+    uint32_t *movers;     // [ncell][slots] 2 p + flown for their positions p, in no particular order
     uint32_t *far_head;   // [ncell] overflow list heads (reset by the collision wave)
     uint32_t *far_src, *far_next;
     uint32_t slots;       // mover slots per cell: 64, 128 or 256
     uint32_t n, ncell;    // particles and cells (the sizes of the lists above)
 };
 
-__device__ __forceinline__ void push_mover(const Regroup &rg, uint32_t p, uint32_t cell, uint32_t slot,
+// (e: the list entry, 2 p + flown)
+__device__ __forceinline__ void push_mover(const Regroup &rg, uint32_t e, uint32_t cell, uint32_t slot,
                                            DevState *st) {
     if (slot < rg.slots) {
-        rg.movers[(size_t)bounds_ck(cell, rg.ncell, st) * rg.slots + slot] = p;
+        rg.movers[(size_t)bounds_ck(cell, rg.ncell, st) * rg.slots + slot] = e;
     } else {
         const uint32_t q = bounds_ck(atomicAdd(&st->far_count, 1u), rg.n, st);
-        rg.far_src[q] = p;
+        rg.far_src[q] = e;
         rg.far_next[q] = atomicExch(&rg.far_head[cell], q);
     }
 }
 
 // Streaming, in sequence order and in place, in two kernels.  The first
 // takes every particle whose free end point x + c dt lies inside the closed
-// box (the rule the flight itself applies first): it writes the new position
-// and the code byte, counts the new cell and lists the movers.  Particles
+// box (the rule the flight itself applies first): it writes the code byte,
+// counts the new cell and lists the movers (the gather moves the particle).  Particles
 // that would leave the box go to a list that the second kernel flies
 // exactly, wall conditions included, and finishes in the same way.  Keeping
 // the rare wall path out of the first kernel keeps its register use, and so
@@ -286,9 +297,9 @@ __device__ __forceinline__ void finish_move(const Geo &g, int64_t p, int fx, int
     cell_coords(g, (double)x, D == 2 ? (double)y : 0.0, tx, ty);
     const uint32_t cell = (uint32_t)ty * (uint32_t)g.nx + (uint32_t)tx;
     const bool stay = tx == fx && ty == fy;
-    rg.code[p] = stay ? kStay : kMoved;
+    rg.code[p] = (stay ? kStay : kMoved) | kFlown;
     atomicAdd(&count[cell], 1u);
-    if (!stay) push_mover(rg, (uint32_t)p, cell, atomicAdd(&rg.mcount[cell], 1u), st);
+    if (!stay) push_mover(rg, 2u * (uint32_t)p + 1u, cell, atomicAdd(&rg.mcount[cell], 1u), st);
 }
 
 template <typename R>
@@ -382,26 +393,16 @@ __global__ __launch_bounds__(256) void k_stream_code(Geo g, Soa<R> s, int64_t n,
         cell_coords(g, (double)xe, D == 2 ? (double)ye : 0.0, tx, ty);
         cell[k] = (uint32_t)ty * (uint32_t)g.nx + (uint32_t)tx;
         stay[k] = tx == fx && ty == fy;
-        if (in[k]) {
-            x[k] = xe;
-            y[k] = ye;
-        }
         // particles of the wall list get their code from the second kernel
         codes |= (uint32_t)(in[k] && stay[k] ? kStay : kMoved) << (8 * k);
     }
-    // particles of the wall list keep their stored position and velocity
+    // every position stays as stored (the gather advances it)
     if (nv == 4) {
-        store4(s.x + p0, x);
-        if (D == 2) store4(s.y + p0, y);
         *(uint32_t *)(rg.code + p0) = codes;
     } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            if (k < nv) {
-                s.x[p0 + k] = x[k];
-                if (D == 2) s.y[p0 + k] = y[k];
-                rg.code[p0 + k] = (uint8_t)(codes >> (8 * k));
-            }
+            if (k < nv) rg.code[p0 + k] = (uint8_t)(codes >> (8 * k));
     }
     if (tid == 0) base_sh = (uint32_t)fy0 * (uint32_t)g.nx + (uint32_t)fx0 - (D == 2 ? (uint32_t)g.nx : 0u) - 1u;
     __syncthreads();
@@ -417,7 +418,7 @@ __global__ __launch_bounds__(256) void k_stream_code(Geo g, Soa<R> s, int64_t n,
                 if (!stay[k]) local[k] = atomicAdd(&mbins[b], 1u);
             } else {
                 atomicAdd(&count[cell[k]], 1u);
-                if (!stay[k]) push_mover(rg, (uint32_t)(p0 + k), cell[k], atomicAdd(&rg.mcount[cell[k]], 1u), st);
+                if (!stay[k]) push_mover(rg, 2u * (uint32_t)(p0 + k), cell[k], atomicAdd(&rg.mcount[cell[k]], 1u), st);
             }
         }
         // particles that meet a wall: one list slot each, one atomic per wave
@@ -455,7 +456,7 @@ __global__ __launch_bounds__(256) void k_stream_code(Geo g, Soa<R> s, int64_t n,
     for (int k = 0; k < 4; ++k) {
         const uint32_t b = cell[k] - base;
         if (in[k] && !stay[k] && b < (uint32_t)kStreamBins)
-            push_mover(rg, (uint32_t)(p0 + k), cell[k], mbins[b] + local[k], st);
+            push_mover(rg, 2u * (uint32_t)(p0 + k), cell[k], mbins[b] + local[k], st);
     }
 }
 

@@ -44,8 +44,9 @@ def test_committed_counter_lines_parse():
 
 
 def test_algorithmic_bytes_per_particle():
-    # streaming: x, y, cx, cy read (16 B), x, y written (8 B), one code byte
-    assert bench.ALGO_BYTES["stream"] == 4 * 4 + 2 * 4 + 1
+    # streaming: x, y, cx, cy read (16 B) and one code byte written (the
+    # gather, which loads every particle anyway, stores the moved position)
+    assert bench.ALGO_BYTES["stream"] == 4 * 4 + 1
     # collision pass: 28 B of state read and written, a code byte, and
     # 26 running FP64 sums per cell of 100 particles read and written
     assert abs(bench.ALGO_BYTES["collide"] - (28 + 28 + 1 + 2 * 26 * 8 / 100.0)) < 1e-9
