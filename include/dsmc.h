@@ -128,7 +128,8 @@ typedef struct {
     int32_t cells_per_wave;   /* walled runs (dims 1, 2): 2 -> each wave collides two cells, 32
                                  lanes each (exact or brute-force majorant, mean cell population
                                  at most 128; DSMC_EINVAL otherwise); 0 or 1 -> one cell per wave.
-                                 Changes no result. */
+                                 Changes no result; with 2, cells above 0.96 x mean + 64 particles
+                                 (at least 128) take the slower global-memory path. */
 } dsmc_config;
 
 /* How homogeneous instances are distributed over the GPU.  Both process the

@@ -696,13 +696,16 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
         c->cap = std::max(64, std::min(want, cap_fit));
         c->pair = cfg->cells_per_wave == 2;
         if (c->pair) {
-            // two cells per wave: 1.28 x mean + 64 per cell, so that a wave's
-            // two cells leave LDS room for five waves per SIMD (FP32, the
-            // kernel's register budget; 192 on the 100-per-cell cavity); at
-            // least 128, so that a cell's owner marks (cap + 4 words) can
-            // hold the 64 FP64 sums of the weight re-estimation
+            // two cells per wave: 0.96 x mean + 64 per cell (160 on the
+            // 100-per-cell cavity, where a cell's area is then the moment
+            // transpose's 3,328 bytes: 204 us per step against 214 at 192);
+            // at least 128, so that a cell's owner marks (cap + 4 words) can
+            // hold the 64 FP64 sums of the weight re-estimation.  Cells above
+            // it run in the global-memory kernel (counted in big_cells), so a
+            // flow far from uniform density is better served by one cell per
+            // wave and its larger capacity
             const int cap_fit_pair = (int)std::min<size_t>((kMaxLds / 2 - 64) / per, 65535) / 32 * 32;
-            int wp = (int)std::ceil(1.28 * mean + 64.0);
+            int wp = (int)std::ceil(0.96 * mean + 64.0);
             wp = (wp + 31) / 32 * 32;
             c->cap = std::max(128, std::min(wp, cap_fit_pair));
         }

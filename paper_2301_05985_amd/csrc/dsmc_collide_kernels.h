@@ -411,7 +411,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void 
 
 // Two walled cells per wave: five waves per SIMD (the kernel fits their 96
 // registers without spills; in FP32 the LDS of two cells of the pair
-// capacity allows as many).
+// capacity allows more).
 template <typename R, bool VR, int D, int OCC = 5>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void k_collide_pair(CollideArgs<R> a) {
     extern __shared__ __align__(16) unsigned char smem[];

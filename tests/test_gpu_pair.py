@@ -225,7 +225,7 @@ def test_two_cells_per_wave_matches_oracle_and_one_cell_launch(gpu, name):
 
 @pytest.mark.parametrize("extra", [0, 1])
 def test_cell_at_pair_capacity_and_one_above(gpu, extra):
-    # 160 particles in 8 cells: the pair capacity is 1.28 x 20 + 64 rounded
+    # 160 particles in 8 cells: the pair capacity is 0.96 x 20 + 64 rounded
     # up to 32, at least 128; cell 0 holds 128 (staged in LDS) or 129 (global
     # memory).  A tiny time step keeps every particle in its cell.
     _announce("cell at pair capacity + %d" % extra)
