@@ -76,10 +76,13 @@ constexpr size_t kRedBytes = (size_t)13 * kRedStride * 8;
 // blown up ends with an error instead of keeping a wave busy for minutes.
 constexpr double kMaxCandidates = 16777216.0;
 
-// A cell is processed by T threads: one wave (T = 64), or a workgroup of
-// T / 64 waves for large homogeneous instances.  Wave-level results of a
-// workgroup are combined through a small LDS area after a barrier, every
-// thread combining the waves in the same order.
+// A cell is processed by T threads: one wave (T = 64), a workgroup of T / 64
+// waves for large homogeneous instances, or one half of a wave (T = 32, two
+// walled cells per wave).  Wave-level results of a workgroup are combined
+// through a small LDS area after a barrier, every thread combining the waves
+// in the same order.  In the one-wave workgroups of T = 64 and T = 32 a
+// __syncthreads() orders the wave's LDS accesses and waits for no other
+// wave, so the two halves of a wave may reach it on different paths.
 constexpr int kWideThreads = 256;
 struct GroupScratch {
     uint32_t u[kWideThreads / 64][8];

@@ -1,7 +1,8 @@
 // dsmc_collide_kernels.h -- the collision kernels: cells staged in LDS (one
-// wave per cell, or a workgroup of waves per large homogeneous instance)
-// and, for cells above the LDS capacity, a global-memory variant; each with
-// the exact or the learned majorant.
+// wave per cell, two walled cells per wave, or a workgroup of waves per large
+// homogeneous instance) and, for cells above the LDS capacity, a
+// global-memory variant; each with the exact or the learned majorant (the
+// two-cell kernel with the exact one).
 #pragma once
 #include "dsmc_collide.h"
 #include "dsmc_learned.h"

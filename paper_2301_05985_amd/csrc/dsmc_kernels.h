@@ -8,7 +8,8 @@
 //   k_stream_walls    exact flight with wall conditions of the wall list
 //   k_scan_lookback   exclusive scan of the counts into the new cell ranges,
 //                     step bookkeeping                   [decoupled look-back]
-//   k_collide         per cell (dsmc_collide_kernels.h): gather the cell's
+//   k_collide         per cell (dsmc_collide_kernels.h; k_collide_pair takes
+//                     two cells per wave): gather the cell's
 //                     particles from the previous sequence (stays and movers),
 //                     majorant, NTC candidates in conflict-free wave batches,
 //                     importance weights, FP64 moment sums [one wave per cell]
