@@ -81,13 +81,16 @@ def _instances(p, parts, ids):
     return q, {k: np.asarray(v)[idx] for k, v in parts.items()}, idx
 
 
+@pytest.mark.parametrize("launch", [{}, {"schedule": 0, "wide_min": 128}])
 @pytest.mark.parametrize("learned", [False, True])
-def test_batched_full_size_sampled_instances_bit_exact(gpu, learned):
+def test_batched_full_size_sampled_instances_bit_exact(gpu, learned, launch):
     # 4096 homogeneous cells, N uniform in [50, 2000] (4.2M particles), FP32,
-    # 20 steps; 32 sampled cells recomputed by the oracle bit for bit
-    _announce("batched full size learned=%s" % learned)
+    # 20 steps, in the default launch and in the one the autotuner picks on
+    # this workload; 32 sampled cells recomputed by the oracle bit for bit
+    _announce("batched full size learned=%s launch=%s" % (learned, launch))
     from paper_2301_05985_amd.binding import Simulation
     p, parts = W.batched(real="f32")
+    p = dict(p, **launch)
     if learned:
         rng = np.random.default_rng(7)
         net = M.init_params(7) * 0.05
@@ -131,6 +134,32 @@ def test_fourier_full_size_fp32(gpu):
         a, b = g[k].astype(np.float64), o[k].astype(np.float64)
         assert np.abs(a - b).max() <= 1e-5 * max(1.0, np.abs(b).max()), k
         assert np.mean(a == b) > 0.99, k
+    sim.close()
+
+
+def test_fourier_full_size_benchmark_weights_fp32(gpu):
+    # the Fourier workload as the benchmark runs it (weights re-estimated
+    # every step, majorant factor 1.5), 5 steps against the oracle's FP32
+    # build; re-estimated weights within a few ulp
+    _announce("fourier full size, re-estimation every step")
+    from paper_2301_05985_amd.binding import Simulation
+    p, parts = W.fourier(real="f32")
+    p.update(vr_reconstruct=1, vr_kappa=1.5)
+    sim = Simulation(p, parts)
+    orc = oracle.Oracle(p, parts, np.float32)
+    sim.step(5)
+    orc.run(5)
+    g, o = sim.particles(), orc.state()
+    _, cnt, _ = sim.sample()
+    assert np.array_equal(cnt, orc.counters)
+    for k in ("x", "cx", "cy", "cz"):
+        a, b = g[k].astype(np.float64), o[k].astype(np.float64)
+        assert np.abs(a - b).max() <= 1e-5 * max(1.0, np.abs(b).max()), k
+        assert np.mean(a == b) > 0.99, k
+    a, b = g["w"].astype(np.float64), o["w"].astype(np.float64)
+    assert np.isfinite(a).all()
+    assert (np.abs(a - b) / np.maximum(np.abs(b), 1.0)).max() <= 8 * 2.0 ** -23
+    assert np.mean(a == b) > 0.9
     sim.close()
 
 
