@@ -422,8 +422,11 @@ __device__ double exact_bound(const View &v, uint32_t N, double &r_top, GroupScr
         v.get(r, a, b, c);
         const double dx = (double)a - m0, dy = (double)b - m1, dz = (double)c - m2;
         const double r2 = (dx * dx + dy * dy) + dz * dz;
-        if (r2 > a1) { a2 = a1; a1 = r2; }
-        else if (r2 > a2) { a2 = r2; }
+        // the top two without branches: a1 = max, a2 = max(a2, the smaller
+        // of a1 and r2); a NaN r2 leaves both unchanged
+        const double lo = r2 > a1 ? a1 : r2;
+        a2 = fmax(a2, lo);
+        a1 = fmax(a1, r2);
         if constexpr (SUMS) {
             const double vx = (double)a, vy = (double)b, vz = (double)c;
             sums[0] += vx; sums[1] += vy; sums[2] += vz;
