@@ -251,8 +251,8 @@ def main():
     name = "cavity 256x256 cells x 100 particles (6,553,600), Kn=%g, diffuse walls, lid 0.01*sqrt(2), " \
            "VR weights re-estimated every 4 steps, majorant factor 1.5, FP32 state / FP64 sums" % args.kn
     print("[bench] headline: %s" % name, file=sys.stderr, flush=True)
-    # launch of the collision step (one or two cells per wave; identical
-    # decisions either way), picked by timing both
+    # launch of the collision step (one or two cells per wave, or four waves
+    # per cell; identical decisions either way), picked by timing them
     if args.launch:
         launch, launch_times = json.loads(args.launch), {}
     else:
@@ -312,10 +312,19 @@ def main():
     if not args.no_secondary:
         sec = []
         print("[bench] secondary workloads", file=sys.stderr, flush=True)
+
+        def walled(label, q, qparts, steps, warm):
+            # the walled launch (one or two cells per wave, four waves per
+            # cell) picked by timing the candidates
+            best, times = autotune.tune(q, qparts, log=tlog)
+            r = run_workload(label, dict(q, **best), qparts, steps, warm, torch)
+            r["launch"], r["launch_candidates_ms_per_step"] = best, times
+            return r
+
         p2, parts2 = W.fourier(real="f32")
         p2.update(vr_reconstruct=1, vr_kappa=1.5)
-        sec.append(run_workload("fourier 200 cells x 200 (40,000), Kn=0.1, VR re-estimated every step, majorant "
-                                "factor 1.5, FP32", p2, parts2, 2000, 100, torch))
+        sec.append(walled("fourier 200 cells x 200 (40,000), Kn=0.1, VR re-estimated every step, majorant "
+                          "factor 1.5, FP32", p2, parts2, 2000, 100))
         p3, parts3 = W.batched(real="f32")
         # launch parameters of the collision step picked by the autotuner
         # (grid vs persistent work queue; identical results either way)
@@ -369,12 +378,6 @@ def main():
         p6s = dict(p3, molecule=W.VSS, omega=0.81, alpha=1.4)
         sec.append(run_workload("batched 4096 cells, variable soft spheres (omega 0.81, alpha 1.4), exact majorant, "
                                 "FP32", dict(p6s, **best3), parts3, 200, 20, torch))
-        def walled(label, q, qparts, steps, warm):
-            best, times = autotune.tune(q, qparts, log=tlog)
-            r = run_workload(label, dict(q, **best), qparts, steps, warm, torch)
-            r["launch"], r["launch_candidates_ms_per_step"] = best, times
-            return r
-
         p7, parts7 = W.cavity(Kn=args.kn, real="f32")
         p7 = dict(p7, molecule=W.VHS, omega=0.74, **VR_SETTINGS)
         sec.append(walled("cavity 256x256 x 100, variable hard spheres (omega 0.74), VR, FP32", p7, parts7, 100, 10))

@@ -130,6 +130,11 @@ typedef struct {
                                  at most 128; DSMC_EINVAL otherwise); 0 or 1 -> one cell per wave.
                                  Changes no result; with 2, cells above 0.96 x mean + 64 particles
                                  (at least 128) take the slower global-memory path. */
+    int32_t waves_per_cell;   /* walled runs (dims 1, 2): 4 -> each cell collides on a workgroup
+                                 of four waves (exact or brute-force majorant, one cell per wave
+                                 otherwise; DSMC_EINVAL if combined with cells_per_wave 2); 0 or
+                                 1 -> one wave.  For grids of few, populous cells.  Changes no
+                                 result. */
 } dsmc_config;
 
 /* How homogeneous instances are distributed over the GPU.  Both process the

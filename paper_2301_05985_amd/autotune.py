@@ -17,9 +17,10 @@ weighted runs, ``occupancy``, the waves per SIMD the one-wave kernel is
 compiled for (5, or 6 with a few register spills).  Neither changes a bit of
 the result either.
 
-Walled workloads (dims 1, 2) choose between one cell per wave and two cells
-per wave (``cells_per_wave``, 32 lanes per cell; exact or brute-force
-majorant, mean cell population at most 128), again without changing a
+Walled workloads (dims 1, 2) choose between one cell per wave, two cells
+per wave (``cells_per_wave``, 32 lanes per cell; mean cell population at
+most 128) and a workgroup of four waves per cell (``waves_per_cell``), the
+last two with the exact or brute-force majorant, again without changing a
 decision of the method.
 
 The tuner times each candidate on a scratch simulation built from a copy of
@@ -38,8 +39,9 @@ CANDIDATES = [GRID] + [
     {"schedule": 1, "persistent_waves": w, "chunk_work": c}
     for w in (1024, 2048, 4096) for c in (0, 256, 1024)
 ]
-LAUNCH_KEYS = ("schedule", "persistent_waves", "chunk_work", "wide_min", "occupancy", "cells_per_wave")
-WALLED = [{"cells_per_wave": 1}, {"cells_per_wave": 2}]
+LAUNCH_KEYS = ("schedule", "persistent_waves", "chunk_work", "wide_min", "occupancy", "cells_per_wave",
+               "waves_per_cell")
+WALLED = [{"cells_per_wave": 1}, {"cells_per_wave": 2}, {"waves_per_cell": 4}]
 # refinements of the grid schedule, each tried against the best so far
 WIDE_MIN = (128, 256, 384, 512, 768, 2048)
 OCCUPANCY = (6,)
@@ -58,6 +60,18 @@ def pair_allowed(params, n_particles):
         return False
     nc = int(np.prod(params["n_cells"][:params["dims"]]))
     return n_particles <= 128 * nc
+
+
+def walled_candidates(params, n_particles):
+    """Launches a walled workload may take (the first is the default)."""
+    if params.get("dims", 0) == 0:
+        return []
+    out = [dict(WALLED[0])]
+    if pair_allowed(params, n_particles):
+        out.append(dict(WALLED[1]))
+    if params.get("majorant", 0) != 1:
+        out.append(dict(WALLED[2]))
+    return out
 
 
 def signature(params, n_particles=0):
@@ -131,17 +145,18 @@ def tune(params, particles, candidates=None, steps=8, warmup=8, model=None, use_
          refine=None):
     """Return (best launch parameters, {candidate label: ms per step}).
 
-    Walled workloads time one against two cells per wave where both apply
-    (else return one cell per wave untimed).
+    Walled workloads time the launches of ``walled_candidates`` (one cell
+    per wave untimed where it is the only one).
     ``model`` is ``(bf16_weights, delta, min_n)`` for learned-majorant runs.
     ``refine`` (default: only when ``candidates`` is not given) adds the
     coordinate-descent stage over the grid schedule's kernel parameters."""
     walled = params.get("dims", 0) != 0
     n_particles = len(particles["cx"])
     if walled:
-        if not pair_allowed(params, n_particles):
-            return dict(WALLED[0]), {}
-        candidates = candidates or WALLED
+        allowed = walled_candidates(params, n_particles)
+        if len(allowed) == 1:
+            return allowed[0], {}
+        candidates = candidates or allowed
         refine = False
         steps = max(steps, 24)  # every phase of a re-estimation interval, several times
     key = "%s/%s" % (_arch(), signature(params, n_particles))

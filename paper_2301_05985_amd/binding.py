@@ -43,7 +43,7 @@ class Config(ctypes.Structure):
         ("schedule", ctypes.c_int32), ("persistent_waves", ctypes.c_int32), ("vr_reconstruct", ctypes.c_int32),
         ("chunk_work", ctypes.c_int64), ("omega", ctypes.c_double), ("alpha", ctypes.c_double),
         ("vr_kappa", ctypes.c_double), ("wide_min", ctypes.c_int32), ("occupancy", ctypes.c_int32),
-        ("cells_per_wave", ctypes.c_int32),
+        ("cells_per_wave", ctypes.c_int32), ("waves_per_cell", ctypes.c_int32),
     ]
 
 
@@ -173,6 +173,7 @@ def make_config(p, n_particles):
     c.wide_min = int(p.get("wide_min", 0))
     c.occupancy = int(p.get("occupancy", 0))
     c.cells_per_wave = int(p.get("cells_per_wave", 0))
+    c.waves_per_cell = int(p.get("waves_per_cell", 0))
     return c
 
 

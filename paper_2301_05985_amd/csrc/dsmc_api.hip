@@ -87,6 +87,10 @@ dsmc_status validate(const dsmc_config *c) {
         // mover slots (a mean cell population of at most 128)
         if (c->dims == 0 || c->majorant == DSMC_MAJORANT_LEARNED || mover_slots(*c) > 128) return DSMC_EINVAL;
     }
+    if (c->waves_per_cell != 0 && c->waves_per_cell != 1 && c->waves_per_cell != 4) return DSMC_EINVAL;
+    if (c->waves_per_cell == 4 &&
+        (c->dims == 0 || c->majorant == DSMC_MAJORANT_LEARNED || c->cells_per_wave == 2))
+        return DSMC_EINVAL;
     if (c->dims >= 1) {
         if (!(c->length[0] > 0) || (c->dims == 2 && !(c->length[1] > 0))) return DSMC_EINVAL;
         for (int k = 0; k < (c->dims == 2 ? 4 : 2); ++k) {
@@ -171,6 +175,7 @@ struct dsmc_ctx {
     size_t lds = 0;
     bool pair = false;               // walled cells: two per wave (cells_per_wave 2)
     unsigned pair_grid = 0;          // its workgroups
+    bool walled_wide = false;        // walled cells: a four-wave workgroup each (waves_per_cell 4)
     int big_grid = 0;
     bool any_big_possible = false;
     uint64_t *flags = nullptr;
@@ -352,6 +357,9 @@ void launch_collide(dsmc_ctx *c, Launcher &L, int src, int slot) {
                            L.s, a);
     else if (D > 0 && c->pair)
         hipLaunchKernelGGL((k_collide_pair<R, VR, D>), dim3(c->pair_grid), dim3(64), c->lds, L.s, a);
+    else if (D > 0 && c->walled_wide)
+        hipLaunchKernelGGL((k_collide_walled_wide<R, VR, D>), dim3((unsigned)c->ncell), dim3(kWideThreads), c->lds,
+                           L.s, a);
     else
         launch_collide_wave<R, VR, D>(c, dim3((unsigned)c->ncell), c->lds, L.s, a);
     if (c->any_big_possible) {
@@ -694,6 +702,12 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
         int want = (int)std::ceil(mult * mean + 64.0);
         want = (want + 31) / 32 * 32;
         c->cap = std::max(64, std::min(want, cap_fit));
+        if (cfg->waves_per_cell == 4) {
+            // the four-wave workgroup also keeps its GroupScratch in LDS
+            const int cap_fit_wide =
+                (int)std::min<size_t>((kMaxLds - 64 - sizeof(GroupScratch)) / per, 65535) / 32 * 32;
+            c->cap = std::max(64, std::min(c->cap, cap_fit_wide));
+        }
         c->pair = cfg->cells_per_wave == 2;
         if (c->pair) {
             // two cells per wave: 0.96 x mean + 64 per cell (160 on the
@@ -743,6 +757,11 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
     // two cells per wave: two areas of pair_area_bytes)
     c->lds = std::max<size_t>((size_t)c->cap * per + 16 + 16, kRedBytes);
     if (c->pair) c->lds = 2 * (cfg->real_bytes == 8 ? pair_area_bytes<double>(c->cap) : pair_area_bytes<float>(c->cap));
+    // four waves per walled cell: the workgroup's wave results meet in a
+    // GroupScratch after the owner marks (the moments are reduced through it,
+    // not through the cell's area)
+    c->walled_wide = cfg->dims >= 1 && cfg->waves_per_cell == 4;
+    if (c->walled_wide) c->lds = (size_t)c->cap * per + 16 + 16 + sizeof(GroupScratch);
 
     // graphs are recorded on a private stream (capture is not allowed on
     // the legacy default stream the caller may use)

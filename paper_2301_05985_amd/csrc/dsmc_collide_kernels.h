@@ -260,12 +260,19 @@ __device__ __forceinline__ void gather_j(const CollideArgs<R> &a, uint32_t base,
 // of at least N entries), then the particles into the new sequence at
 // `base` (velocities and weights into LDS when vel is given, else into the
 // new sequence too).
-template <typename R, bool VR, int D, int T = 64>
+// (WG_BARRIER false: called by one wave of a larger workgroup, which orders
+// its own LDS accesses with a wave-scope fence instead of a barrier)
+template <typename R, bool VR, int D, int T = 64, bool WG_BARRIER = true>
 __device__ __forceinline__ void gather_cell(const CollideArgs<R> &a, uint32_t cell, uint32_t base, uint32_t N,
                                             uint32_t *sel, Vel4<R> *vel) {
     constexpr uint32_t L = (uint32_t)T;
     const bool merge = select_cell<R, T>(a, cell, N, sel);
-    __syncthreads();
+    if constexpr (WG_BARRIER) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
     uint32_t e0 = 0;
     for (; e0 + 4 * L <= N; e0 += 4 * L) gather_j<R, VR, D, 4, T>(a, base, e0, N, sel, merge, vel);
     const uint32_t left = N - e0;
@@ -373,6 +380,40 @@ __device__ __forceinline__ void collide_pair_body(const CollideArgs<R> &a, unsig
     __syncthreads();
 }
 
+// Walled cells on a workgroup of kWideThreads threads each (four waves): the
+// first wave selects and gathers the cell into LDS exactly as the one-wave
+// kernel does, then the workgroup collides and samples it as a large
+// homogeneous instance is (particle loops over 256 threads, windows of 256
+// candidates).  For grids of few, populous cells, where one wave per cell
+// would leave most of the GPU idle.
+template <typename R, bool VR, int D>
+__device__ __forceinline__ void collide_walled_wide_body(const CollideArgs<R> &a, unsigned char *smem) {
+    constexpr int T = kWideThreads;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t cell = a.sched ? a.sched[blockIdx.x] : blockIdx.x;
+    const uint32_t base = a.start[cell];
+    const uint32_t N = a.start[cell + 1] - base;
+    if (N > (uint32_t)a.cap) {
+        if (tid == 0) {
+            const uint32_t q = atomicAdd(a.bigc, 1u);
+            a.big_list[q] = cell;
+        }
+        return;  // the whole workgroup
+    }
+    const uint32_t step = (uint32_t)(a.st->step_cur + a.step_off);
+    const auto pf = prefetch_cell<R, VR, false>(a, cell);
+    const int cap = a.cap;
+    Vel4<R> *vel = (Vel4<R> *)smem;
+    uint32_t *owner = (uint32_t *)(vel + cap);  // cap + 4 entries; first the gather's selection
+    GroupScratch *gs = (GroupScratch *)(owner + cap + 4);
+    if (tid < 64u) gather_cell<R, VR, D, 64, false>(a, cell, base, N, owner, vel);
+    __syncthreads();
+    const LdsView<R, false> view{vel, owner, view_check((uint32_t)cap, a.st)};
+    for (uint32_t r = tid; r < N; r += T) view.clear_own(r);
+    __syncthreads();
+    process_cell<R, VR, LdsView<R, false>, T>(a, view, cell, N, step, pf, nullptr, base, gs);
+}
+
 // Global-memory kernel for cells larger than the LDS capacity: walled cells
 // are gathered into the new sequence (selection in a global scratch array),
 // then every cell is operated on in place.
@@ -417,6 +458,12 @@ template <typename R, bool VR, int D, int OCC = 5>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(OCC))) void k_collide_pair(CollideArgs<R> a) {
     extern __shared__ __align__(16) unsigned char smem[];
     collide_pair_body<R, VR, D>(a, smem);
+}
+
+template <typename R, bool VR, int D>
+__global__ __launch_bounds__(kWideThreads) void k_collide_walled_wide(CollideArgs<R> a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    collide_walled_wide_body<R, VR, D>(a, smem);
 }
 
 // Large homogeneous instances: one workgroup of kWideThreads threads per

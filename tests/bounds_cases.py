@@ -2,7 +2,8 @@
 release build, for comparison) by tests/test_gpu_bounds.py.
 
 Every kernel of the path takes part: walled cells staged in LDS, one or two
-per wave (with the gather, diffuse walls, weights and their re-estimation),
+per wave or one per four-wave workgroup (with the gather, diffuse walls,
+weights and their re-estimation),
 walled cells above the LDS capacity (global-memory kernel) with overflow
 mover lists,
 homogeneous instances on one wave, on four-wave workgroups and above the LDS
@@ -42,6 +43,8 @@ def cases():
     out.append(("cavity_f32_vr_reest", dict(p, vr_reconstruct=2, vr_kappa=1.5), parts, 10, None))
     out.append(("cavity_f32_vr_reest_pair", dict(p, vr_reconstruct=2, vr_kappa=1.5, cells_per_wave=2), parts, 10,
                 None))
+    out.append(("cavity_f32_vr_reest_wide4", dict(p, vr_reconstruct=2, vr_kappa=1.5, waves_per_cell=4), parts, 10,
+                None))
     p, parts = W.fourier(n_cells=20, per_cell=50, Kn=0.1, dt=2e-3, real="f64", vr=1, seed=2)
     out.append(("fourier_f64_vr_reest", dict(p, vr_reconstruct=1, vr_kappa=1.5), parts, 10, None))
     out.append(("fourier_f64_vr_reest_pair", dict(p, vr_reconstruct=1, vr_kappa=1.5, cells_per_wave=2), parts, 10,
@@ -49,6 +52,7 @@ def cases():
     p, parts = _crowded_slab("f32")
     out.append(("slab_above_capacity_f32", p, parts, 8, None))
     out.append(("slab_above_capacity_f32_pair", dict(p, cells_per_wave=2), parts, 8, None))
+    out.append(("slab_above_capacity_f32_wide4", dict(p, waves_per_cell=4), parts, 8, None))
     p, parts = W.batched(n_inst=40, nmin=20, nmax=6000, real="f32", seed=4)
     out.append(("batched_grid_f32", dict(p, schedule=0), parts, 5, None))
     out.append(("batched_persistent_f32", dict(p, schedule=1, persistent_waves=256, chunk_work=2000), parts, 5, None))

@@ -62,7 +62,7 @@ def test_workspace_size_valid_configs(lib):
     ("schedule", 2, -1), ("persistent_waves", -1, -1), ("chunk_work", -3, -1),
     ("vr_reconstruct", -1, -1), ("vr_kappa", 0.5, -1), ("vr_kappa", 17.0, -1), ("wide_min", 32, -1),
     ("wide_min", -1, -1), ("occupancy", 4, -1), ("occupancy", 7, -1), ("cells_per_wave", 3, -1),
-    ("cells_per_wave", -1, -1),
+    ("cells_per_wave", -1, -1), ("waves_per_cell", 2, -1), ("waves_per_cell", -1, -1),
 ])
 def test_workspace_size_rejects_invalid(lib, field, value, code):
     p, parts = W.cavity(nx=4, ny=4, per_cell=5)
@@ -186,6 +186,20 @@ def test_grid_kernel_parameters_accepted(lib):
         assert _ws(lib, cfg)[0] == 0, over
 
 
+def test_four_waves_per_cell_accepted_only_where_it_applies(lib):
+    p, parts = W.fourier(n_cells=8, per_cell=300)
+    n = len(parts["cx"])
+    for over, code in ((dict(waves_per_cell=4), 0), (dict(waves_per_cell=4, majorant=2), 0),
+                       (dict(waves_per_cell=4, majorant=1), -1), (dict(waves_per_cell=4, cells_per_wave=2), -1),
+                       (dict(waves_per_cell=1), 0)):
+        assert _ws(lib, binding.make_config(dict(p, **over), n))[0] == code, over
+    pb, partsb = W.batched(n_inst=8, nmin=10, nmax=20)
+    cfg = binding.make_config(dict(pb, waves_per_cell=4), len(partsb["cx"]))
+    off = np.ascontiguousarray(pb["inst_offset"], dtype=np.int64)
+    cfg.inst_offset = off.ctypes.data
+    assert _ws(lib, cfg)[0] == -1
+
+
 def test_autotune_walled_signature_and_pair_rule():
     from paper_2301_05985_amd import autotune
     p, parts = W.cavity(nx=8, ny=8, per_cell=20)
@@ -201,7 +215,11 @@ def test_autotune_walled_signature_and_pair_rule():
     assert autotune.pair_allowed(p, 128 * 64) and not autotune.pair_allowed(p, 128 * 64 + 1)
     pb, partsb = W.batched(n_inst=8, nmin=10, nmax=20)
     assert not autotune.pair_allowed(pb, len(partsb["cx"]))
-    assert "cells_per_wave" in autotune.LAUNCH_KEYS
+    assert "cells_per_wave" in autotune.LAUNCH_KEYS and "waves_per_cell" in autotune.LAUNCH_KEYS
+    assert autotune.walled_candidates(p, n) == autotune.WALLED
+    assert autotune.walled_candidates(dict(p, majorant=1), n) == [autotune.WALLED[0]]
+    assert autotune.walled_candidates(p, 128 * 64 + 1) == [autotune.WALLED[0], autotune.WALLED[2]]
+    assert autotune.walled_candidates(pb, len(partsb["cx"])) == []
 
 
 def test_two_cells_per_wave_accepted_only_where_it_applies(lib):

@@ -1,5 +1,7 @@
-"""Two walled cells per wave (cells_per_wave = 2, 32 lanes per cell) against
-the CPU oracle and against the one-cell-per-wave launch, through the C ABI.
+"""The walled launches other than one cell per wave -- two cells per wave
+(cells_per_wave = 2, 32 lanes per cell) and a workgroup of four waves per
+cell (waves_per_cell = 4) -- against the CPU oracle and against the
+one-cell-per-wave launch, through the C ABI.
 
 Bar: as in the other walled parity tests.  Pair choices, counts and the
 particle sequence are bit-exact; the state is bit-exact where no
@@ -146,9 +148,11 @@ CASES = ["fourier_specular_f32", "fourier_specular_f64", "cavity_periodic_f32", 
          "fourier_periodic_3_f32", "many_movers_f64"]
 
 
-def _gpu(p, parts, steps, chunks, real, cpw):
+def _gpu(p, parts, steps, chunks, real, launch):
     from paper_2301_05985_amd.binding import Simulation
-    sim = Simulation(dict(p, real=real, cells_per_wave=cpw), parts)
+    if not isinstance(launch, dict):
+        launch = {"cells_per_wave": launch}
+    sim = Simulation(dict(p, real=real, **launch), parts)
     try:
         for _ in range(chunks):
             sim.step(steps // chunks)
@@ -192,11 +196,15 @@ def _against_oracle(g, orc, real, exact, reest):
         assert_sums_close(g["sums"], orc.sums, plain)
 
 
+LAUNCHES = [{"cells_per_wave": 2}, {"waves_per_cell": 4}]
+
+
+@pytest.mark.parametrize("launch", LAUNCHES, ids=["two_cells", "four_waves"])
 @pytest.mark.parametrize("name", CASES)
-def test_two_cells_per_wave_matches_oracle_and_one_cell_launch(gpu, name):
+def test_walled_launch_matches_oracle_and_one_cell_launch(gpu, name, launch):
     p, parts, steps, chunks, real, exact, reest = _case(name)
-    _announce(name)
-    g2 = _gpu(p, parts, steps, chunks, real, 2)
+    _announce("%s %s" % (name, launch))
+    g2 = _gpu(p, parts, steps, chunks, real, launch)
     g1 = _gpu(p, parts, steps, chunks, real, 1)
     orc = oracle.Oracle(dict(p, real=real), parts, np.float64 if real == "f64" else np.float32)
     orc.run(steps)
@@ -209,7 +217,7 @@ def test_two_cells_per_wave_matches_oracle_and_one_cell_launch(gpu, name):
         if g1["st"][k] is None:
             continue
         if k == "w" and reest:
-            # the Gram sums are added over 32 lanes instead of 64: the same
+            # the Gram sums are added over another number of lanes: the same
             # least-squares solution up to its rounding
             a, b = g2["st"][k].astype(np.float64), g1["st"][k].astype(np.float64)
             err = np.abs(a - b) / np.maximum(np.abs(b), 1.0)
@@ -245,9 +253,10 @@ def test_cell_at_pair_capacity_and_one_above(gpu, extra):
     _against_oracle(g, orc, "f32", True, False)
 
 
+@pytest.mark.parametrize("launch", LAUNCHES, ids=["two_cells", "four_waves"])
 @pytest.mark.parametrize("case", ["empty_slab", "empty_cavity", "one", "two"])
-def test_empty_and_tiny_runs(gpu, case):
-    _announce(case)
+def test_empty_and_tiny_runs(gpu, case, launch):
+    _announce("%s %s" % (case, launch))
     if case in ("empty_slab", "empty_cavity"):
         if case == "empty_cavity":
             p, _ = W.cavity(nx=6, ny=5, per_cell=1, Kn=0.05, dt=0.01)
@@ -264,7 +273,7 @@ def test_empty_and_tiny_runs(gpu, case):
         parts = dict(x=np.array([0.1, 0.15])[:n], cx=np.array([0.7, -0.3])[:n], cy=np.array([0.2, 0.1])[:n],
                      cz=np.array([-0.4, 0.9])[:n], w=np.ones(n), id=np.arange(n, dtype=np.uint32))
         steps = 20
-    g = _gpu(p, parts, steps, 1, "f64", 2)
+    g = _gpu(p, parts, steps, 1, "f64", launch)
     orc = oracle.Oracle(dict(p, real="f64"), parts, np.float64)
     orc.run(steps)
     assert g["diag"]["status"] == 0

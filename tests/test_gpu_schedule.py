@@ -142,15 +142,16 @@ def test_autotune_refines_grid(gpu, tmp_path, monkeypatch):
 
 
 def test_autotune_walled_launch(gpu, tmp_path, monkeypatch):
-    # a walled cavity: one against two cells per wave, cached; a learned
-    # majorant (no two-cell kernel) returns one cell per wave untimed
+    # a walled cavity: one cell per wave, two cells per wave and four waves
+    # per cell, cached; a learned majorant (neither of the others) returns
+    # one cell per wave untimed
     _announce("autotune walled")
     from paper_2301_05985_amd import autotune
     monkeypatch.setenv("DSMC_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
     p, parts = W.cavity(nx=64, ny=64, per_cell=60, Kn=0.02, real="f32")
     p = dict(p, vr_reconstruct=2, vr_kappa=1.5)
     best, times = autotune.tune(p, parts, warmup=4)
-    assert best in autotune.WALLED and len(times) == 2
+    assert best in autotune.WALLED and len(times) == 3
     again, t2 = autotune.tune(p, parts)
     assert again == best and t2 == times
     assert autotune.tune(dict(p, majorant=1), parts) == ({"cells_per_wave": 1}, {})
