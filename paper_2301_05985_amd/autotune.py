@@ -76,18 +76,20 @@ def walled_candidates(params, n_particles):
 
 def signature(params, n_particles=0):
     """Key of a workload: everything that changes the collision kernel's cost."""
+    # the collision rate (sigma, dt) sets the candidates per cell
+    rate = "s%.6g_t%.6g" % (params.get("sigma", 0.0), params.get("dt", 0.0))
     if params.get("dims", 0) != 0:
-        return "d%d_%s_vr%d_re%d_ka%g_m%d_mol%d_c%s_n%d" % (
+        return "d%d_%s_vr%d_re%d_ka%g_m%d_mol%d_c%s_n%d_%s" % (
             params["dims"], params.get("real", "f64"), params.get("vr", 0), params.get("vr_reconstruct", 0),
             params.get("vr_kappa", 1.0), params.get("majorant", 0), params.get("molecule", 0),
-            "x".join(str(int(c)) for c in params["n_cells"][:params["dims"]]), n_particles)
+            "x".join(str(int(c)) for c in params["n_cells"][:params["dims"]]), n_particles, rate)
     off = np.asarray(params["inst_offset"], dtype=np.int64)
     n = np.diff(off)
     hist = np.bincount(np.minimum(n // 64, 255), minlength=256)
     h = hashlib.sha1(hist.astype(np.int64).tobytes()).hexdigest()[:16]
-    return "d%d_%s_vr%d_m%d_mol%d_k%d_n%d_%s" % (
+    return "d%d_%s_vr%d_m%d_mol%d_k%d_n%d_%s_%s" % (
         params.get("dims", 0), params.get("real", "f64"), params.get("vr", 0),
-        params.get("majorant", 0), params.get("molecule", 0), len(n), int(off[-1]), h)
+        params.get("majorant", 0), params.get("molecule", 0), len(n), int(off[-1]), h, rate)
 
 
 def _arch():

@@ -111,6 +111,7 @@ def test_autotune_signature_separates_workloads():
     assert sig != autotune.signature(dict(p, vr=1))
     assert sig != autotune.signature(dict(p, majorant=1))
     assert sig != autotune.signature(dict(p, real="f64"))
+    assert sig != autotune.signature(dict(p, sigma=p["sigma"] * 10))  # another collision rate
     q, _ = W.batched(n_inst=64, nmin=10, nmax=200, seed=1)
     assert sig != autotune.signature(q)  # other instance sizes
     assert all(c["schedule"] in (0, 1) for c in autotune.CANDIDATES)
@@ -207,7 +208,8 @@ def test_autotune_walled_signature_and_pair_rule():
     sig = autotune.signature(p, n)
     assert sig == autotune.signature(dict(p), n)
     for q in (dict(p, vr=1 - p.get("vr", 0)), dict(p, vr_reconstruct=4), dict(p, vr_kappa=1.5),
-              dict(p, real="f64"), dict(p, molecule=W.VHS), dict(p, n_cells=(8, 4))):
+              dict(p, real="f64"), dict(p, molecule=W.VHS), dict(p, n_cells=(8, 4)), dict(p, sigma=p["sigma"] * 10),
+              dict(p, dt=p["dt"] * 2)):
         assert autotune.signature(q, n) != sig
     assert autotune.signature(p, n + 1) != sig
     assert autotune.pair_allowed(p, n) and autotune.pair_allowed(dict(p, majorant=2), n)
