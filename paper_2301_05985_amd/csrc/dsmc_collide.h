@@ -1058,20 +1058,32 @@ __device__ __forceinline__ bool solve_half(double t0, double t1, double t2, doub
 #pragma unroll
     for (int j = 1; j < 7; ++j) mdiag = (row >> 1) == j ? M[j] : mdiag;
     const double dg = (has_row && qc == (row & 1)) ? mdiag : 0.0;
-    bool ok = true;
+    // Step k reads only columns k and up, so the row-k entries of columns
+    // below k (eliminated) are neither broadcast nor updated; slot j holds
+    // column qc + 2 j, needed by some lane when 2 j + 1 > k.  The pivot and
+    // M[r][k] sit on lane 2 r + (k & 1) of each row's pair and reach its
+    // partner by a DPP pair broadcast; the pivot test runs on the pivot's
+    // own lane (the lane that holds the original G_kk).
+    bool ok_lane = true;
 #pragma unroll
     for (int k = 0; k < kReBasis; ++k) {
-        const int kl = 2 * k + (k & 1);
-        const double piv = cell_shfl<32>(M[k >> 1], kl);
-        ok = ok && piv > 1e-12 * cell_shfl<32>(dg, kl);
+        double bk[7];
+#pragma unroll
+        for (int j = 0; j < 7; ++j)
+            if (2 * j + 1 > k || j == (k >> 1)) bk[j] = cell_shfl<32>(M[j], 2 * k + qc);
+        const double own = M[k >> 1], rowk = bk[k >> 1];
+        const double piv = (k & 1) ? quad_perm_f64<0xF5>(rowk) : quad_perm_f64<0xA0>(rowk);
+        const double mrk = (k & 1) ? quad_perm_f64<0xF5>(own) : quad_perm_f64<0xA0>(own);
+        if (cl == 2 * k + (k & 1)) ok_lane = piv > 1e-12 * dg;
         double inv = __builtin_amdgcn_rcp(piv);
         inv = fma(inv, fma(-piv, inv, 1.0), inv);
-        const double mrk = cell_shfl<32>(M[k >> 1], 2 * rr + (k & 1));
         const double f = row == k ? 1.0 - inv : mrk * inv;
 #pragma unroll
-        for (int j = 0; j < 7; ++j) M[j] = fma(-f, cell_shfl<32>(M[j], 2 * k + qc), M[j]);
+        for (int j = 0; j < 7; ++j)
+            if (2 * j + 1 > k || j == (k >> 1)) M[j] = fma(-f, bk[j], M[j]);
     }
-    if (!ok) return false;  // a pivot not above 1e-12 G_kk: the cell keeps its weights
+    // a pivot not above 1e-12 G_kk: the cell keeps its weights
+    if (cell_ballot<32>(!ok_lane) != 0ull) return false;
     // solution: column 13 (cell lane 2 r + 1, slot 6); every lane has read
     // the sums it needed (the reads above precede these writes in the wave)
     __syncthreads();
@@ -1119,7 +1131,10 @@ __device__ void reestimate_cell(const View &v, uint32_t N, double sc, Reest &re,
     // Gauss-Jordan: row k is divided by the pivot, every other row r loses
     // M[r][k] / pivot times row k; for row k itself that is the same update
     // with the factor 1 - 1 / pivot.  The reciprocal is the hardware
-    // estimate refined by one Newton step.
+    // estimate refined by one Newton step.  Step k reads only columns k and
+    // up: slot j (column qc + 4 j) is broadcast and updated only when
+    // 4 j + 3 > k.  M[r][k] sits on lane 4 r + (k & 3) of the row's quad and
+    // reaches the other three by a DPP quad broadcast.
     bool ok = true;
 #pragma unroll
     for (int k = 0; k < kReBasis; ++k) {
@@ -1128,10 +1143,14 @@ __device__ void reestimate_cell(const View &v, uint32_t N, double sc, Reest &re,
         ok = ok && piv > 1e-12 * readlane_f64(dg, kl);
         double inv = __builtin_amdgcn_rcp(piv);
         inv = fma(inv, fma(-piv, inv, 1.0), inv);
-        const double mrk = __shfl(M[k >> 2], 4 * rr + (k & 3), 64);
+        const double own = M[k >> 2];
+        const double mrk = (k & 3) == 0 ? quad_perm_f64<0x00>(own)
+                         : (k & 3) == 1 ? quad_perm_f64<0x55>(own)
+                         : (k & 3) == 2 ? quad_perm_f64<0xAA>(own) : quad_perm_f64<0xFF>(own);
         const double f = row == k ? 1.0 - inv : mrk * inv;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) M[j] = fma(-f, __shfl(M[j], 4 * k + qc, 64), M[j]);
+        for (int j = 0; j < 4; ++j)
+            if (4 * j + 3 > k) M[j] = fma(-f, __shfl(M[j], 4 * k + qc, 64), M[j]);
     }
     if (!ok) return;  // a pivot not above 1e-12 G_kk: the cell keeps its weights
     // solution: column 13 (lane 4 r + 1, slot 3)
