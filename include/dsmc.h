@@ -53,7 +53,10 @@ typedef enum {
     DSMC_ENONFINITE = -4,  /* a velocity became NaN or infinite */
     DSMC_EWALLHITS = -5,   /* a particle hit walls more than max_wall_hits times in one step */
     DSMC_ECAPACITY = -6,   /* a per-cell candidate count (at most 2^24 per step) or cell size
-                              exceeded the kernels' limits */
+                              exceeded the kernels' limits: also a walled cell of more than
+                              131,072 particles at dsmc_init, or one whose overflow movers
+                              (beyond the per-cell mover slots) times its particles exceed
+                              2^28 in one step */
     DSMC_EABI = -7         /* abi_version mismatch */
 } dsmc_status;
 
@@ -206,7 +209,9 @@ dsmc_status dsmc_workspace_size(const dsmc_config *cfg, size_t *bytes);
  * dims == 0 the particle counts per instance come from inst_offset.  For
  * dims >= 1 the particles are rearranged in place into the initial sequence
  * (grouped by cell, ascending id inside a cell; the workspace's second
- * buffer is used in between).  No device allocation. */
+ * buffer is used in between); a cell of more than 131,072 initial particles
+ * returns DSMC_ECAPACITY (the ordering by id is quadratic in the cell size).
+ * No device allocation. */
 dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *particles, void *workspace,
                       size_t ws_bytes, void *hip_stream, dsmc_ctx **out);
 

@@ -410,36 +410,47 @@ void launch_ranges(dsmc_ctx *c, hipStream_t s, int b) {
                        c->count, c->off[b], c->cursor, (int)c->ncell, c->flags, c->done, c->st, 0);
 }
 
+// Largest cell of the initial positions: the set-up orders each cell by id
+// with one wave and a quadratic rank count, so a cell above this size (for
+// instance every particle at a NaN position, all in cell 0) makes dsmc_init
+// fail with DSMC_ECAPACITY instead of running for minutes.
+constexpr uint32_t kMaxSetupCell = 1u << 17;
+
 // Initial sequence in buffer 0: grouped by cell, ascending id inside a cell.
 template <typename R, int D, bool VR>
-void launch_initial_sequence(dsmc_ctx *c, hipStream_t s) {
+dsmc_status launch_initial_sequence(dsmc_ctx *c, hipStream_t s) {
     launch_ranges<R, D>(c, s, 0);
-    if (c->n == 0) return;
+    if (c->n == 0) return DSMC_OK;
+    std::vector<uint32_t> off((size_t)c->ncell + 1);
+    if (hipMemcpyAsync(off.data(), c->off[0], off.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return DSMC_EHIP;
+    for (int64_t k = 0; k < c->ncell; ++k)
+        if (off[(size_t)k + 1] - off[(size_t)k] > kMaxSetupCell) return DSMC_ECAPACITY;
     const unsigned grid = (unsigned)((c->n + 255) / 256);
     hipLaunchKernelGGL((k_place<R, D, VR>), dim3(grid), dim3(256), 0, s, c->geo, soa_of<R>(c->buf[0]),
                        soa_of<R>(c->buf[1]), (int64_t)c->n, c->cursor, c->st);
     hipLaunchKernelGGL((k_canonical<R, D, VR>), dim3((unsigned)c->ncell), dim3(64), 0, s, soa_of<R>(c->buf[1]),
                        soa_of<R>(c->buf[0]), (const uint32_t *)c->off[0]);
+    return DSMC_OK;
 }
 
 template <typename R, int D>
-void dispatch_vr(dsmc_ctx *c, hipStream_t s, bool initial) {
-    if (initial) {
-        if (c->cfg.vr) launch_initial_sequence<R, D, true>(c, s);
-        else launch_initial_sequence<R, D, false>(c, s);
-    } else {
-        launch_ranges<R, D>(c, s, c->cur);
-    }
+dsmc_status dispatch_vr(dsmc_ctx *c, hipStream_t s, bool initial) {
+    if (initial) return c->cfg.vr ? launch_initial_sequence<R, D, true>(c, s) : launch_initial_sequence<R, D, false>(c, s);
+    launch_ranges<R, D>(c, s, c->cur);
+    return DSMC_OK;
 }
 
 // Set-up (initial) or restore (ranges of the current buffer) of a walled run.
-void walled_setup(dsmc_ctx *c, bool initial) {
+dsmc_status walled_setup(dsmc_ctx *c, bool initial) {
     hipStream_t s = c->stream;
     if (c->cfg.real_bytes == 4) {
-        if (c->cfg.dims == 1) dispatch_vr<float, 1>(c, s, initial); else dispatch_vr<float, 2>(c, s, initial);
-    } else {
-        if (c->cfg.dims == 1) dispatch_vr<double, 1>(c, s, initial); else dispatch_vr<double, 2>(c, s, initial);
+        if (c->cfg.dims == 1) return dispatch_vr<float, 1>(c, s, initial);
+        return dispatch_vr<float, 2>(c, s, initial);
     }
+    if (c->cfg.dims == 1) return dispatch_vr<double, 1>(c, s, initial);
+    return dispatch_vr<double, 2>(c, s, initial);
 }
 
 // Step k of a batch of nsteps consecutive steps.  Homogeneous runs put one
@@ -795,7 +806,8 @@ dsmc_status dsmc_init(const dsmc_config *cfg, const dsmc_soa *p, void *workspace
         if (hipMemsetAsync(c->far_head, 0xFF, (size_t)c->ncell * 4, c->stream) != hipSuccess ||
             hipMemsetAsync(c->mcount, 0, (size_t)c->ncell * 4, c->stream) != hipSuccess)
             return fail(DSMC_EHIP);
-        walled_setup(c, true);
+        const dsmc_status rs = walled_setup(c, true);
+        if (rs != DSMC_OK) return fail(rs);
         if (hipGetLastError() != hipSuccess) return fail(DSMC_EHIP);
     }
     {
@@ -990,7 +1002,8 @@ dsmc_status dsmc_restore(dsmc_ctx *c, const void *blob, size_t bytes) {
     if (c->cfg.dims >= 1) {
         // the blob holds the particle sequence; its cell ranges follow from
         // the positions
-        walled_setup(c, false);
+        const dsmc_status rs = walled_setup(c, false);
+        if (rs != DSMC_OK) return rs;
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipStreamSynchronize(c->stream));
     }

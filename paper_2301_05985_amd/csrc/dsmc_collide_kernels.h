@@ -91,19 +91,28 @@ __device__ __forceinline__ void bitonic_sort_regs(uint32_t (&v)[4], uint32_t lan
     bitonic_merge_regs<C, K, K / 2, L>(v, lane);
 }
 
+// Work bound of the merge of overflow movers (N x overflow entries): a cell
+// above it reports DSMC_ECAPACITY and is not merged, so that a pathological
+// state (say every particle at a NaN position, all in cell 0) costs bounded
+// time.
+constexpr uint64_t kMergeBudget = 1ull << 28;
+
 // Selection of `cell`: source entries 2 p + flown (p the source position,
 // flown set where the wall kernel already stored the final position) written
-// to sel[0..N) (sel holds at least N entries); returns whether they must
-// still be merged by position (overflow movers).  Any mismatch with the
-// cell's count is reported, and sel is filled with valid positions.  T = 64:
-// the wave; T = 32: the cell's half of a wave (at most 128 mover slots).
+// to sel[0..N) (sel holds at least N entries).  Returns N, or, when overflow
+// movers must still be merged by position, the length S of the ascending
+// prefix sel[0..S) (the movers of the slot list and the stays; the overflow
+// movers follow it in list order).  Any mismatch with the cell's count is
+// reported, and sel is filled with valid positions.  T = 64: the wave;
+// T = 32: the cell's half of a wave (at most 128 mover slots).
 template <typename R, int T = 64>
-__device__ __forceinline__ bool select_cell(const CollideArgs<R> &a, uint32_t cell, uint32_t N, uint32_t *sel) {
+__device__ __forceinline__ uint32_t select_cell(const CollideArgs<R> &a, uint32_t cell, uint32_t N,
+                                                uint32_t *sel) {
     constexpr uint32_t L = (uint32_t)T;
     constexpr int P = 128 / T;  // chunks of codes loaded at once
     const uint32_t lane = (uint32_t)cell_lane<T>();
     const unsigned long long lt = (1ull << lane) - 1ull;
-    if (N == 0) return false;  // nothing lands here (and the sequence may be empty)
+    if (N == 0) return 0u;  // nothing lands here (and the sequence may be empty)
     const uint32_t b = a.src_start[cell], e = a.src_start[cell + 1];
     const uint32_t mc = a.rg.mcount[cell];
     const uint32_t K = a.rg.slots;
@@ -171,31 +180,50 @@ __device__ __forceinline__ bool select_cell(const CollideArgs<R> &a, uint32_t ce
             if (pos < N) sel[pos] = v[r];
         }
     }
-    const bool merge = mc > K;
+    const uint32_t S = nstay + nm;  // the ascending prefix (uniform over the cell)
+    const bool over = mc > K;
+    const uint32_t F = N > S ? N - S : 0u;
+    const bool merge = over && (uint64_t)N * (uint64_t)F <= kMergeBudget;
     if (lane == 0) {
-        uint32_t m = nstay + nm;
-        if (merge) {
-            // overflow movers from the list, merged by position afterwards
-            uint32_t q = a.rg.far_head[cell];
-            while (q != kEmpty && m < N) {
-                sel[m++] = a.rg.far_src[q];
-                q = a.rg.far_next[q];
+        uint32_t m = S;
+        if (over) {
+            if (merge) {
+                // overflow movers from the list, merged by position afterwards
+                uint32_t q = a.rg.far_head[cell];
+                while (q != kEmpty && m < N) {
+                    sel[m++] = a.rg.far_src[q];
+                    q = a.rg.far_next[q];
+                }
+                if (q != kEmpty) set_error(a.st, DSMC_ECAPACITY);
+            } else {
+                set_error(a.st, DSMC_ECAPACITY);
             }
-            if (q != kEmpty) set_error(a.st, DSMC_ECAPACITY);
             a.rg.far_head[cell] = kEmpty;
         }
         if (m != N) set_error(a.st, DSMC_ECAPACITY);
         while (m < N) sel[m++] = 2u * last;  // valid positions only (b itself may be the end of the sequence)
         if (mc) a.rg.mcount[cell] = 0u;
     }
-    return merge;
+    return merge && S < N ? S : N;
 }
 
-// Position of source entry q in the merged order: the number of smaller
-// entries of sel[0..N) (only cells with overflow movers need it).
-__device__ __forceinline__ uint32_t merged_rank(const uint32_t *sel, uint32_t N, uint32_t q) {
-    uint32_t r = 0;
-    for (uint32_t t = 0; t < N; ++t) r += sel[t] < q ? 1u : 0u;
+// Position in the merged order of entry i (value q) of sel[0..N), whose
+// prefix sel[0..S) ascends and whose rest holds the overflow movers: the
+// number of smaller entries (the entries are distinct positions), that is i
+// or the lower bound of q in the prefix, plus the smaller overflow entries.
+__device__ __forceinline__ uint32_t merged_rank(const uint32_t *sel, uint32_t S, uint32_t N, uint32_t i,
+                                                uint32_t q) {
+    uint32_t r = i;
+    if (i >= S) {
+        uint32_t lo = 0, hi = S;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (sel[mid] < q) lo = mid + 1u;
+            else hi = mid;
+        }
+        r = lo;
+    }
+    for (uint32_t t = S; t < N; ++t) r += sel[t] < q ? 1u : 0u;
     return r;
 }
 
@@ -205,7 +233,7 @@ __device__ __forceinline__ uint32_t merged_rank(const uint32_t *sel, uint32_t N,
 // the wall kernel did not fly is moved to its end point x + c dt here.
 template <typename R, bool VR, int D, int J, int T = 64>
 __device__ __forceinline__ void gather_j(const CollideArgs<R> &a, uint32_t base, uint32_t e0, uint32_t N,
-                                         const uint32_t *sel, bool merge, Vel4<R> *vel) {
+                                         const uint32_t *sel, uint32_t S, Vel4<R> *vel) {
     const uint32_t lane = (uint32_t)cell_lane<T>();
     uint32_t q[J], r[J], id[J];
     R x[J], y[J], c0[J], c1[J], c2[J], ww[J];
@@ -215,10 +243,10 @@ __device__ __forceinline__ void gather_j(const CollideArgs<R> &a, uint32_t base,
         q[j] = el < N ? sel[el] : 0u;
         r[j] = el;
     }
-    if (merge) {
+    if (S < N) {
 #pragma unroll
         for (int j = 0; j < J; ++j)
-            if (r[j] < N) r[j] = merged_rank(sel, N, q[j]);
+            if (r[j] < N) r[j] = merged_rank(sel, S, N, r[j], q[j]);
     }
     bool flown[J];
 #pragma unroll
@@ -266,7 +294,7 @@ template <typename R, bool VR, int D, int T = 64, bool WG_BARRIER = true>
 __device__ __forceinline__ void gather_cell(const CollideArgs<R> &a, uint32_t cell, uint32_t base, uint32_t N,
                                             uint32_t *sel, Vel4<R> *vel) {
     constexpr uint32_t L = (uint32_t)T;
-    const bool merge = select_cell<R, T>(a, cell, N, sel);
+    const uint32_t S = select_cell<R, T>(a, cell, N, sel);  // N: no merge
     if constexpr (WG_BARRIER) {
         __syncthreads();
     } else {
@@ -274,12 +302,12 @@ __device__ __forceinline__ void gather_cell(const CollideArgs<R> &a, uint32_t ce
         __builtin_amdgcn_wave_barrier();
     }
     uint32_t e0 = 0;
-    for (; e0 + 4 * L <= N; e0 += 4 * L) gather_j<R, VR, D, 4, T>(a, base, e0, N, sel, merge, vel);
+    for (; e0 + 4 * L <= N; e0 += 4 * L) gather_j<R, VR, D, 4, T>(a, base, e0, N, sel, S, vel);
     const uint32_t left = N - e0;
-    if (left > 3 * L) gather_j<R, VR, D, 4, T>(a, base, e0, N, sel, merge, vel);
-    else if (left > 2 * L) gather_j<R, VR, D, 3, T>(a, base, e0, N, sel, merge, vel);
-    else if (left > L) gather_j<R, VR, D, 2, T>(a, base, e0, N, sel, merge, vel);
-    else if (left > 0) gather_j<R, VR, D, 1, T>(a, base, e0, N, sel, merge, vel);
+    if (left > 3 * L) gather_j<R, VR, D, 4, T>(a, base, e0, N, sel, S, vel);
+    else if (left > 2 * L) gather_j<R, VR, D, 3, T>(a, base, e0, N, sel, S, vel);
+    else if (left > L) gather_j<R, VR, D, 2, T>(a, base, e0, N, sel, S, vel);
+    else if (left > 0) gather_j<R, VR, D, 1, T>(a, base, e0, N, sel, S, vel);
 }
 
 // LDS kernel body: one wave per cell.  Homogeneous instances (D 0) collide

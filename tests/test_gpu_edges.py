@@ -174,3 +174,42 @@ def test_walled_cell_at_lds_capacity_and_one_above(gpu, extra, vr):
     assert (d["big_cells"] > 0) == bool(extra)
     assert cnt[0, 1] > 20
     _check(g, sums, cnt, seq, d, orc)
+
+
+def test_setup_rejects_a_cell_above_the_ordering_bound(gpu):
+    # 140,000 particles in one cell of a 2 x 2 grid: above the 131,072 that
+    # the set-up's per-cell ordering by id accepts, so dsmc_init returns
+    # DSMC_ECAPACITY (at once, before any ordering kernel runs)
+    _announce("set-up cell above the ordering bound")
+    from paper_2301_05985_amd.binding import DsmcError, Simulation
+    p, _ = W.cavity(nx=2, ny=2, per_cell=1, Kn=0.05, dt=0.01)
+    p = dict(_spec(p), real="f32", sigma=0.0)
+    n = 140_000
+    rng = np.random.default_rng(21)
+    parts = dict(x=rng.uniform(0.05, 0.45, n), y=rng.uniform(0.05, 0.45, n), cx=rng.standard_normal(n),
+                 cy=rng.standard_normal(n), cz=rng.standard_normal(n), w=np.ones(n),
+                 id=np.arange(n, dtype=np.uint32))
+    with pytest.raises(DsmcError) as e:
+        Simulation(p, parts)
+    assert e.value.code == -6  # DSMC_ECAPACITY
+
+
+def test_overflow_merge_above_its_work_bound_reports_capacity(gpu):
+    # 20,000 particles cross from cell 1 into cell 0 of a two-cell slab in one
+    # step: 19,744 of them beyond the 256 mover slots, and 20,000 x 19,744 is
+    # above the merge's work bound (2^28), so the step ends at once with
+    # DSMC_ECAPACITY instead of ranking the entries (no collisions: sigma 0)
+    _announce("overflow merge above its work bound")
+    from paper_2301_05985_amd.binding import Simulation
+    p, _ = W.fourier(n_cells=2, per_cell=1, Kn=0.05, dt=0.01, vr=0, real="f32")
+    p = dict(p, wall_kind=(W.WALL_SPECULAR, W.WALL_SPECULAR, 0, 0), sigma=0.0)
+    n = 20_000
+    rng = np.random.default_rng(22)
+    parts = dict(x=rng.uniform(0.55, 0.95, n), cx=np.full(n, -50.0), cy=np.zeros(n), cz=np.zeros(n),
+                 w=np.ones(n), id=rng.permutation(n).astype(np.uint32))
+    sim = Simulation(p, parts)
+    assert sim.diagnostics()["status"] == 0
+    sim.step(1)
+    d = sim.diagnostics()
+    sim.close()
+    assert d["status"] == -6  # DSMC_ECAPACITY
