@@ -766,7 +766,8 @@ __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uin
     uint32_t i = 0, j = 0;
     R U = (R)0, nx = (R)0, ny = (R)0, nz = (R)1;
     uint32_t g0 = 0;     // first candidate of the current generation (weights)
-    while (kb < M) {
+    bool wpend = false;  // half-wave cell: generation complete, weights not yet replayed
+    while (kb < M || wpend) {
         const bool act = k < M;
         const bool draw_now = act && fresh;
         if constexpr (T == 64) {
@@ -806,7 +807,17 @@ __device__ void ntc_loop(const View &v, uint32_t N, double gmax, uint32_t M, uin
                     ? ((molecule == DSMC_VHS || molecule == DSMC_VSS) ? pacc : sqrt((double)g2) / gmax)
                     : 1.0;
         }
-        if (kb < gend) continue;
+        // (half-wave cells: a half whose generation is complete waits, its
+        // lanes idle in the windows, until the other half's is complete too,
+        // so that the wave replays both cells' weights in one set of rounds;
+        // a half that has left the loop does not hold the other back)
+        if constexpr (T == 32) {
+            wpend = kb >= gend;
+            if (__ballot(kb < gend) != 0ull) continue;
+            wpend = false;
+        } else {
+            if (kb < gend) continue;
+        }
         // generation complete: importance weights (Al-Mohssen & Hadjiconstantinou
         // 2010) of its candidates, in candidate order: accepted -> both W_i W_j;
         // rejected -> W_i (1 - p W_j) / (1 - p), p = g / g_max

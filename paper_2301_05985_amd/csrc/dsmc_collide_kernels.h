@@ -104,10 +104,12 @@ constexpr uint64_t kMergeBudget = 1ull << 28;
 // prefix sel[0..S) (the movers of the slot list and the stays; the overflow
 // movers follow it in list order).  Any mismatch with the cell's count is
 // reported, and sel is filled with valid positions.  T = 64: the wave;
-// T = 32: the cell's half of a wave (at most 128 mover slots).
+// T = 32: the cell's half of a wave (at most 128 mover slots), whose mover
+// sort is sized by m_wave, the larger mover count of the wave's two cells,
+// so that both halves take the same branch.
 template <typename R, int T = 64>
 __device__ __forceinline__ uint32_t select_cell(const CollideArgs<R> &a, uint32_t cell, uint32_t N,
-                                                uint32_t *sel) {
+                                                uint32_t *sel, uint32_t m_wave = 0u) {
     constexpr uint32_t L = (uint32_t)T;
     constexpr int P = 128 / T;  // chunks of codes loaded at once
     const uint32_t lane = (uint32_t)cell_lane<T>();
@@ -142,8 +144,9 @@ __device__ __forceinline__ uint32_t select_cell(const CollideArgs<R> &a, uint32_
         else if (nm <= 128) bitonic_sort_regs<2, 128>(v, lane);
         else bitonic_sort_regs<4, 256>(v, lane);
     } else {
-        if (nm <= 32) v[0] = bitonic_sort<32>(v[0], lane);
-        else if (nm <= 64) bitonic_sort_regs<2, 64, 32>(v, lane);
+        const uint32_t ns = m_wave > nm ? (m_wave < K ? m_wave : K) : nm;  // padded entries sort last
+        if (ns <= 32) v[0] = bitonic_sort<32>(v[0], lane);
+        else if (ns <= 64) bitonic_sort_regs<2, 64, 32>(v, lane);
         else bitonic_sort_regs<4, 128, 32>(v, lane);
     }
     uint32_t nlow = 0;
@@ -289,21 +292,26 @@ __device__ __forceinline__ void gather_j(const CollideArgs<R> &a, uint32_t base,
 // `base` (velocities and weights into LDS when vel is given, else into the
 // new sequence too).
 // (WG_BARRIER false: called by one wave of a larger workgroup, which orders
-// its own LDS accesses with a wave-scope fence instead of a barrier)
+// its own LDS accesses with a wave-scope fence instead of a barrier.  Half-wave
+// cells: N_wave and m_wave are the larger cell size and mover count of the
+// wave's two cells, from which the unrolling and the sort are chosen, so
+// that the halves do not run two variants one after the other.)
 template <typename R, bool VR, int D, int T = 64, bool WG_BARRIER = true>
 __device__ __forceinline__ void gather_cell(const CollideArgs<R> &a, uint32_t cell, uint32_t base, uint32_t N,
-                                            uint32_t *sel, Vel4<R> *vel) {
+                                            uint32_t *sel, Vel4<R> *vel, uint32_t N_wave = 0u,
+                                            uint32_t m_wave = 0u) {
     constexpr uint32_t L = (uint32_t)T;
-    const uint32_t S = select_cell<R, T>(a, cell, N, sel);  // N: no merge
+    const uint32_t S = select_cell<R, T>(a, cell, N, sel, m_wave);  // N: no merge
     if constexpr (WG_BARRIER) {
         __syncthreads();
     } else {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
     }
+    const uint32_t Nb = N_wave > N ? N_wave : N;  // elements at N and above are masked in gather_j
     uint32_t e0 = 0;
-    for (; e0 + 4 * L <= N; e0 += 4 * L) gather_j<R, VR, D, 4, T>(a, base, e0, N, sel, S, vel);
-    const uint32_t left = N - e0;
+    for (; e0 + 4 * L <= Nb; e0 += 4 * L) gather_j<R, VR, D, 4, T>(a, base, e0, N, sel, S, vel);
+    const uint32_t left = Nb - e0;
     if (left > 3 * L) gather_j<R, VR, D, 4, T>(a, base, e0, N, sel, S, vel);
     else if (left > 2 * L) gather_j<R, VR, D, 3, T>(a, base, e0, N, sel, S, vel);
     else if (left > L) gather_j<R, VR, D, 2, T>(a, base, e0, N, sel, S, vel);
@@ -383,9 +391,17 @@ __device__ __forceinline__ void collide_pair_body(const CollideArgs<R> &a, unsig
     const uint32_t half = (uint32_t)lane_id() >> 5;
     const uint32_t lane = cell_tid<T>();
     const uint32_t cell = a.sched[2 * blockIdx.x + half];
-    if (cell == kNoCell) return;
-    const uint32_t base = a.start[cell];
-    const uint32_t N = a.start[cell + 1] - base;
+    const bool has = cell != kNoCell;
+    const uint32_t base = has ? a.start[cell] : 0u;
+    const uint32_t N = has ? a.start[cell + 1] - base : 0u;
+    // the larger size and mover count of the wave's cells staged here (taken
+    // while all 64 lanes are active): the gather's unrolling and mover sort
+    // are chosen from them
+    const bool staged = has && N <= (uint32_t)a.cap;
+    const uint32_t Ns = staged ? N : 0u, ms = staged ? a.rg.mcount[cell] : 0u;
+    const uint32_t N_wave = max(Ns, (uint32_t)__shfl_xor((int)Ns, 32, 64));
+    const uint32_t m_wave = max(ms, (uint32_t)__shfl_xor((int)ms, 32, 64));
+    if (!has) return;
     if (N > (uint32_t)a.cap) {
         if (lane == 0) {
             const uint32_t q = atomicAdd(a.bigc, 1u);
@@ -399,7 +415,7 @@ __device__ __forceinline__ void collide_pair_body(const CollideArgs<R> &a, unsig
     unsigned char *area = smem + (size_t)half * pair_area_bytes<R>(cap);
     Vel4<R> *vel = (Vel4<R> *)area;
     uint32_t *owner = (uint32_t *)(vel + cap);  // cap + 4 entries; first the gather's selection
-    gather_cell<R, VR, D, T>(a, cell, base, N, owner, vel);
+    gather_cell<R, VR, D, T>(a, cell, base, N, owner, vel, N_wave, m_wave);
     __syncthreads();
     const LdsView<R, false> view{vel, owner, view_check((uint32_t)cap, a.st)};
     for (uint32_t r = lane; r < N; r += T) view.clear_own(r);
