@@ -156,19 +156,24 @@ __device__ __forceinline__ V cell_shfl(V x, int l) {
     if constexpr (T == 32) return __shfl(x, (lane_id() & 32) | l, 64);
     else return __shfl(x, l, 64);
 }
+// Combination of a value over each half-wave of 32 lanes, left in every lane:
+// a butterfly of DPP moves inside each row of 16 (quad swaps of 1 and 2
+// lanes, then the half-row and row mirrors, each pairing every lane with one
+// of the other group), then v_permlane16_swap pairs each row with the other
+// row of its half.  All sources lie in the lane's own half.
+template <typename Op>
+__device__ __forceinline__ uint32_t half_butterfly_u32(uint32_t v, Op op) {
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
+    v = op(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
+    const auto sw = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+    return op((uint32_t)sw[0], (uint32_t)sw[1]);
+}
 template <int T>
 __device__ __forceinline__ uint32_t cell_min_u32(uint32_t v) {
     if constexpr (T == 32) {
-        const auto mn = [](uint32_t a, uint32_t b) { return a < b ? a : b; };
-        const uint32_t id = 0xFFFFFFFFu;
-        v = mn(v, dpp_any(id, v, 0x111));
-        v = mn(v, dpp_any(id, v, 0x112));
-        v = mn(v, dpp_any(id, v, 0x114));
-        v = mn(v, dpp_any(id, v, 0x118));
-        v = mn(v, dpp_any(id, v, 0x142));  // rows 1 and 3 take the last lane of rows 0 and 2
-        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)v, 31);
-        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
-        return (lane_id() & 32) ? hi : lo;
+        return half_butterfly_u32(v, [](uint32_t a, uint32_t b) { return a < b ? a : b; });
     } else {
         return wave_min_u32(v);
     }
@@ -189,9 +194,7 @@ __device__ __forceinline__ V cell_reduce_dpp(V v, V id, Op op) {
 template <int T>
 __device__ __forceinline__ uint32_t cell_sum_u32(uint32_t v) {
     if constexpr (T == 32) {
-#pragma unroll
-        for (int off = 16; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-        return v;
+        return half_butterfly_u32(v, [](uint32_t a, uint32_t b) { return a + b; });
     } else {
         return wave_sum_u32(v);
     }
