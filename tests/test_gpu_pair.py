@@ -14,8 +14,9 @@ only by their order of summation.
 
 Cases: both precisions; specular, periodic and diffuse walls; weights with
 and without re-estimation; hard, variable hard and variable soft spheres;
-the brute-force majorant; cells above the pair capacity (global-memory
-kernel) and overflow mover lists; odd cell counts, so that a wave's second
+the brute-force majorant; several generations of candidates per cell with
+weights; cells above the pair capacity (global-memory kernel) and overflow
+mover lists; odd cell counts, so that a wave's second
 half has no cell; single-cell and tiny periodic grids; up to 128 movers per
 cell; empty runs and one or two particles."""
 import sys
@@ -131,6 +132,14 @@ def _case(name):
         p, parts = W.fourier(n_cells=3, per_cell=50, Kn=0.05, real="f32", dt=0.3)
         p["wall_kind"] = (W.WALL_PERIODIC, W.WALL_PERIODIC, 0, 0)
         return p, W.shuffle_storage(parts, seed=4), 6, 2, "f32", True, False
+    if name.startswith("vr_generations"):
+        # about 80 candidates per cell and step (40 to 120): two to four
+        # generations of 32 per half-wave cell, the two cells of a wave
+        # completing theirs in different windows
+        real = name[-3:]
+        p, parts = W.cavity(nx=8, ny=8, per_cell=60, Kn=0.01, real=real, dt=4e-3, lid=0.3)
+        p.update(vr_reconstruct=2, vr_kappa=1.5)
+        return p, parts, 10, 2, real, False, True
     if name == "many_movers_f64":
         # more than 64 particles enter a cell in one step: 128 mover slots,
         # sorted over four values per lane of a half
@@ -145,7 +154,7 @@ CASES = ["fourier_specular_f32", "fourier_specular_f64", "cavity_periodic_f32", 
          "reest_cavity_specular_f32", "reest_cavity_specular_f64", "reest_cavity_diffuse_kappa_f32",
          "reest_fourier_diffuse_k3_f64", "vhs_cavity_f64", "vss_cavity_f32", "maxwell_fourier_f32",
          "diameter_cavity_f32", "big_cell_f64", "big_cell_far_f64", "periodic_1x1_f64", "periodic_2x3_f64",
-         "fourier_periodic_3_f32", "many_movers_f64"]
+         "fourier_periodic_3_f32", "many_movers_f64", "vr_generations_f32", "vr_generations_f64"]
 
 
 def _gpu(p, parts, steps, chunks, real, launch):
@@ -163,7 +172,17 @@ def _gpu(p, parts, steps, chunks, real, launch):
         sim.close()
 
 
-def _against_oracle(g, orc, real, exact, reest):
+# FP32 re-estimated weights of the case with several generations per cell:
+# every particle takes several weight updates between two re-estimations,
+# and the rejection update (division by 1 - p, p up to 1 / kappa) carries
+# and amplifies the one-ulp rounding difference of a re-estimated weight
+# (the host's and the device's Gram sums add in different orders); every
+# launch on the device gives the same weights, 18.5 ulp from the oracle's
+# after 10 steps.
+W_ULP = {"vr_generations_f32": 64}
+
+
+def _against_oracle(g, orc, real, exact, reest, w_ulp=8):
     o = orc.state()
     assert g["diag"]["status"] == 0, g["diag"]
     assert np.array_equal(g["st"]["id"], o["id"])
@@ -177,7 +196,7 @@ def _against_oracle(g, orc, real, exact, reest):
             a, b = a.astype(np.float64), b.astype(np.float64)
             assert np.isfinite(a).all()
             err = np.abs(a - b) / np.maximum(np.abs(b), 1.0)
-            assert err.max() <= (1e-9 if real == "f64" else 8 * 2.0 ** -23), err.max()
+            assert err.max() <= (1e-9 if real == "f64" else w_ulp * 2.0 ** -23), err.max()
         elif exact:
             bad = np.flatnonzero(a != b)
             assert bad.size == 0, (k, bad[:5], a[bad[:5]], b[bad[:5]])
@@ -211,7 +230,7 @@ def test_walled_launch_matches_oracle_and_one_cell_launch(gpu, name, launch):
     assert orc.counters[:, 1].sum() > 10
     if name.startswith("big_cell"):
         assert g2["diag"]["big_cells"] > 0
-    _against_oracle(g2, orc, real, exact, reest)
+    _against_oracle(g2, orc, real, exact, reest, W_ULP.get(name, 8))
     assert np.array_equal(g2["seq"], g1["seq"]) and np.array_equal(g2["cnt"], g1["cnt"])
     for k in ("x", "y", "cx", "cy", "cz", "w"):
         if g1["st"][k] is None:
