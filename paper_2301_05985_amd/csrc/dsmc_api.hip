@@ -421,12 +421,15 @@ template <typename R, int D, bool VR>
 dsmc_status launch_initial_sequence(dsmc_ctx *c, hipStream_t s) {
     launch_ranges<R, D>(c, s, 0);
     if (c->n == 0) return DSMC_OK;
-    std::vector<uint32_t> off((size_t)c->ncell + 1);
-    if (hipMemcpyAsync(off.data(), c->off[0], off.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+    // the largest cell, reduced on the device (the state was zeroed at init)
+    const unsigned mgrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((c->ncell + 255) / 256, 1024));
+    hipLaunchKernelGGL(k_max_cell, dim3(mgrid), dim3(256), 0, s, (const uint32_t *)c->off[0], (int64_t)c->ncell,
+                       c->st);
+    uint32_t max_cell = 0;
+    if (hipMemcpyAsync(&max_cell, &c->st->max_cell, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return DSMC_EHIP;
-    for (int64_t k = 0; k < c->ncell; ++k)
-        if (off[(size_t)k + 1] - off[(size_t)k] > kMaxSetupCell) return DSMC_ECAPACITY;
+    if (max_cell > kMaxSetupCell) return DSMC_ECAPACITY;
     const unsigned grid = (unsigned)((c->n + 255) / 256);
     hipLaunchKernelGGL((k_place<R, D, VR>), dim3(grid), dim3(256), 0, s, c->geo, soa_of<R>(c->buf[0]),
                        soa_of<R>(c->buf[1]), (int64_t)c->n, c->cursor, c->st);

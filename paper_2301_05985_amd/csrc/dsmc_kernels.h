@@ -39,7 +39,7 @@ struct DevState {
     unsigned int big_count;         // walled runs: cells queued for the global-memory collision kernel
     unsigned int far_count;         // entries of this step's overflow mover list
     unsigned int wall_count;        // entries of this step's wall list
-    unsigned int pad0;
+    unsigned int max_cell;          // set-up: the largest initial cell
     unsigned long long pad[3];
     unsigned long long diag[kDiagStripes * kDiagPerStripe];
     // Homogeneous runs record up to kStepSlots steps per graph with a single
@@ -528,6 +528,18 @@ __global__ __launch_bounds__(256) void k_place(Geo g, Soa<R> src, Soa<R> dst, in
         if (VR) dst.w[slot] = src.w[p];
         dst.id[slot] = src.id[p];
     }
+}
+
+// Largest cell of the ranges start[0..ncell] (atomic maximum into
+// st->max_cell, zero before the launch; set-up only).
+__global__ __launch_bounds__(256) void k_max_cell(const uint32_t *start, int64_t ncell, DevState *st) {
+    uint32_t m = 0;
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < ncell; c += (int64_t)gridDim.x * 256) {
+        const uint32_t n = start[c + 1] - start[c];
+        m = n > m ? n : m;
+    }
+    m = ~wave_min_u32(~m);
+    if (lane_id() == 0 && m) atomicMax(&st->max_cell, m);
 }
 
 template <typename R, int D, bool VR>
