@@ -140,6 +140,14 @@ def _case(name):
         p["wall_kind"] = SPEC
         p.update(vr_reconstruct=2, vr_kappa=1.5)
         return p, W.shuffle_storage(parts, seed=9), 10, 2, "f32", True, True
+    if name == "vss_vr_generations_f64":
+        # variable soft spheres with weights (rejections weighted by the VSS
+        # acceptance probability), up to two generations per cell (about 27
+        # candidates, 16 to 38), re-estimated; denser cells with these
+        # weights diverge between re-estimations, on the host as on the device
+        p, parts = W.cavity(nx=8, ny=6, per_cell=60, Kn=0.01, real="f64", dt=4e-3, lid=0.3)
+        p.update(vr_reconstruct=3, vr_kappa=1.5, molecule=W.VSS, omega=0.74, alpha=1.4)
+        return p, parts, 9, 3, "f64", False, True
     if name.startswith("vr_generations"):
         # about 80 candidates per cell and step (40 to 120): two to four
         # generations of 32 per half-wave cell, the two cells of a wave
@@ -163,7 +171,7 @@ CASES = ["fourier_specular_f32", "fourier_specular_f64", "cavity_periodic_f32", 
          "reest_fourier_diffuse_k3_f64", "vhs_cavity_f64", "vss_cavity_f32", "maxwell_fourier_f32",
          "diameter_cavity_f32", "big_cell_f64", "big_cell_far_f64", "periodic_1x1_f64", "periodic_2x3_f64",
          "fourier_periodic_3_f32", "many_movers_f64", "vr_generations_f32", "vr_generations_f64",
-         "odd_grid_vr_generations_f32"]
+         "odd_grid_vr_generations_f32", "vss_vr_generations_f64"]
 
 
 def _gpu(p, parts, steps, chunks, real, launch):
