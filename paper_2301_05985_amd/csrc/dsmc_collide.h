@@ -354,23 +354,43 @@ __device__ __forceinline__ double cell_max_nonneg(double v) {
     return __longlong_as_double((long long)(((uint64_t)hmax << 32) | lmax));
 }
 
+// Running minima of the velocity keys of one particle (box[0..2]: the keys,
+// box[3..5]: the inverted keys), the first pass of the FP32 bound taken
+// elsewhere (the gather of a walled cell has the velocities in registers).
+// (a native vector type, so that it is passed in registers, not on the stack)
+typedef uint32_t BoxKeys __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ void box_keys_add(BoxKeys &box, float a, float b, float c) {
+    const uint32_t ka = order_key(a), kb = order_key(b), kc = order_key(c);
+    box[0] = min((uint32_t)box[0], ka); box[3] = min((uint32_t)box[3], ~ka);
+    box[1] = min((uint32_t)box[1], kb); box[4] = min((uint32_t)box[4], ~kb);
+    box[2] = min((uint32_t)box[2], kc); box[5] = min((uint32_t)box[5], ~kc);
+}
+
 // With SUMS the pass over r^2 also adds this thread's particles into the
 // seven first and second moments sums[0..6] (sx, sy, sz, sxx, syy, szz, sxy),
 // in the thread's particle order.
+// (use_box: box holds this thread's key minima of the cell, already taken;
+// FP32 only; the first pass over the cell is then skipped.)
 template <typename R, typename View, int T = 64, bool SUMS = false>
 __device__ double exact_bound(const View &v, uint32_t N, double &r_top, GroupScratch *gs = nullptr,
-                              double *mid = nullptr, double *sums = nullptr) {
+                              double *mid = nullptr, double *sums = nullptr, bool use_box = false,
+                              BoxKeys box = BoxKeys{}) {
     const uint32_t tid = cell_tid<T>();
     double m0, m1, m2;
     if constexpr (sizeof(R) == 4) {
         uint32_t lo0 = ~0u, lo1 = ~0u, lo2 = ~0u, nh0 = ~0u, nh1 = ~0u, nh2 = ~0u;  // min keys, min inverted keys
-        for (uint32_t r = tid; r < N; r += T) {
-            R a, b, c;
-            v.get(r, a, b, c);
-            const uint32_t ka = order_key(a), kb = order_key(b), kc = order_key(c);
-            lo0 = min(lo0, ka); nh0 = min(nh0, ~ka);
-            lo1 = min(lo1, kb); nh1 = min(nh1, ~kb);
-            lo2 = min(lo2, kc); nh2 = min(nh2, ~kc);
+        if (use_box) {
+            lo0 = box[0]; lo1 = box[1]; lo2 = box[2];
+            nh0 = box[3]; nh1 = box[4]; nh2 = box[5];
+        } else {
+            for (uint32_t r = tid; r < N; r += T) {
+                R a, b, c;
+                v.get(r, a, b, c);
+                const uint32_t ka = order_key(a), kb = order_key(b), kc = order_key(c);
+                lo0 = min(lo0, ka); nh0 = min(nh0, ~ka);
+                lo1 = min(lo1, kb); nh1 = min(nh1, ~kb);
+                lo2 = min(lo2, kc); nh2 = min(nh2, ~kc);
+            }
         }
         lo0 = cell_min_u32<T>(lo0); lo1 = cell_min_u32<T>(lo1); lo2 = cell_min_u32<T>(lo2);
         nh0 = cell_min_u32<T>(nh0); nh1 = cell_min_u32<T>(nh1); nh2 = cell_min_u32<T>(nh2);
@@ -1472,14 +1492,14 @@ __device__ __forceinline__ bool reestimate_now(const CollideArgs<R> &a, uint32_t
 template <typename R, bool VR, typename View, int T = 64>
 __device__ void process_cell(const CollideArgs<R> &a, const View &v, uint32_t cell, uint32_t N,
                              uint32_t step, const CellPrefetch<!VR> &pf, double *red = nullptr, uint32_t wb_base = 0,
-                             GroupScratch *gs = nullptr) {
+                             GroupScratch *gs = nullptr, bool use_box = false, BoxKeys box = BoxKeys{}) {
     uint32_t M = 0, acc = 0, over = 0;
     if (N >= 2) {
         double rt;
         double gmax = 1.0;
         if (a.molecule != DSMC_MAXWELL) {
             gmax = a.majorant == DSMC_MAJORANT_DIAMETER ? pair_diameter<R, View, T>(v, N, gs)
-                                                        : exact_bound<R, View, T>(v, N, rt, gs);
+                                                        : exact_bound<R, View, T>(v, N, rt, gs, nullptr, nullptr, use_box, box);
             if (VR && a.vr_kappa > 1.0) gmax = gmax * a.vr_kappa;
         }
         const double V = a.volume ? a.volume[cell] : a.Vuni;

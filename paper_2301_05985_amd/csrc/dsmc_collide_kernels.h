@@ -236,7 +236,7 @@ __device__ __forceinline__ uint32_t merged_rank(const uint32_t *sel, uint32_t S,
 // the wall kernel did not fly is moved to its end point x + c dt here.
 template <typename R, bool VR, int D, int J, int T = 64>
 __device__ __forceinline__ void gather_j(const CollideArgs<R> &a, uint32_t base, uint32_t e0, uint32_t N,
-                                         const uint32_t *sel, uint32_t S, Vel4<R> *vel) {
+                                         const uint32_t *sel, uint32_t S, Vel4<R> *vel, BoxKeys *box) {
     const uint32_t lane = (uint32_t)cell_lane<T>();
     uint32_t q[J], r[J], id[J];
     R x[J], y[J], c0[J], c1[J], c2[J], ww[J];
@@ -277,6 +277,9 @@ __device__ __forceinline__ void gather_j(const CollideArgs<R> &a, uint32_t base,
             if (D == 2) a.s.y[o] = y[j];
             a.s.id[o] = id[j];
             const uint32_t rr = r[j] < N ? r[j] : N - 1;
+            if constexpr (sizeof(R) == 4) {
+                if (box) box_keys_add(*box, c0[j], c1[j], c2[j]);
+            }
             if (vel) {
                 vel[rr] = Vel4<R>{c0[j], c1[j], c2[j], VR ? ww[j] : (R)1};
             } else {
@@ -291,6 +294,8 @@ __device__ __forceinline__ void gather_j(const CollideArgs<R> &a, uint32_t base,
 // of at least N entries), then the particles into the new sequence at
 // `base` (velocities and weights into LDS when vel is given, else into the
 // new sequence too).
+// (box, FP32: this lane's running minima of the velocity keys, which the
+// exact majorant takes instead of a pass of its own over the cell.)
 // (WG_BARRIER false: called by one wave of a larger workgroup, which orders
 // its own LDS accesses with a wave-scope fence instead of a barrier.  Half-wave
 // cells: N_wave and m_wave are the larger cell size and mover count of the
@@ -299,7 +304,7 @@ __device__ __forceinline__ void gather_j(const CollideArgs<R> &a, uint32_t base,
 template <typename R, bool VR, int D, int T = 64, bool WG_BARRIER = true>
 __device__ __forceinline__ void gather_cell(const CollideArgs<R> &a, uint32_t cell, uint32_t base, uint32_t N,
                                             uint32_t *sel, Vel4<R> *vel, uint32_t N_wave = 0u,
-                                            uint32_t m_wave = 0u) {
+                                            uint32_t m_wave = 0u, BoxKeys *box = nullptr) {
     constexpr uint32_t L = (uint32_t)T;
     const uint32_t S = select_cell<R, T>(a, cell, N, sel, m_wave);  // N: no merge
     if constexpr (WG_BARRIER) {
@@ -310,12 +315,12 @@ __device__ __forceinline__ void gather_cell(const CollideArgs<R> &a, uint32_t ce
     }
     const uint32_t Nb = N_wave > N ? N_wave : N;  // elements at N and above are masked in gather_j
     uint32_t e0 = 0;
-    for (; e0 + 4 * L <= Nb; e0 += 4 * L) gather_j<R, VR, D, 4, T>(a, base, e0, N, sel, S, vel);
+    for (; e0 + 4 * L <= Nb; e0 += 4 * L) gather_j<R, VR, D, 4, T>(a, base, e0, N, sel, S, vel, box);
     const uint32_t left = Nb - e0;
-    if (left > 3 * L) gather_j<R, VR, D, 4, T>(a, base, e0, N, sel, S, vel);
-    else if (left > 2 * L) gather_j<R, VR, D, 3, T>(a, base, e0, N, sel, S, vel);
-    else if (left > L) gather_j<R, VR, D, 2, T>(a, base, e0, N, sel, S, vel);
-    else if (left > 0) gather_j<R, VR, D, 1, T>(a, base, e0, N, sel, S, vel);
+    if (left > 3 * L) gather_j<R, VR, D, 4, T>(a, base, e0, N, sel, S, vel, box);
+    else if (left > 2 * L) gather_j<R, VR, D, 3, T>(a, base, e0, N, sel, S, vel, box);
+    else if (left > L) gather_j<R, VR, D, 2, T>(a, base, e0, N, sel, S, vel, box);
+    else if (left > 0) gather_j<R, VR, D, 1, T>(a, base, e0, N, sel, S, vel, box);
 }
 
 // LDS kernel body: one wave per cell.  Homogeneous instances (D 0) collide
@@ -415,12 +420,16 @@ __device__ __forceinline__ void collide_pair_body(const CollideArgs<R> &a, unsig
     unsigned char *area = smem + (size_t)half * pair_area_bytes<R>(cap);
     Vel4<R> *vel = (Vel4<R> *)area;
     uint32_t *owner = (uint32_t *)(vel + cap);  // cap + 4 entries; first the gather's selection
-    gather_cell<R, VR, D, T>(a, cell, base, N, owner, vel, N_wave, m_wave);
+    // FP32: the majorant's velocity box is taken while the gather holds the
+    // velocities in registers
+    constexpr bool kBox = sizeof(R) == 4;
+    BoxKeys box = ~0u;
+    gather_cell<R, VR, D, T>(a, cell, base, N, owner, vel, N_wave, m_wave, kBox ? &box : nullptr);
     __syncthreads();
     const LdsView<R, false> view{vel, owner, view_check((uint32_t)cap, a.st)};
     for (uint32_t r = lane; r < N; r += T) view.clear_own(r);
     __syncthreads();
-    process_cell<R, VR, LdsView<R, false>, T>(a, view, cell, N, step, pf, (double *)area, base);
+    process_cell<R, VR, LdsView<R, false>, T>(a, view, cell, N, step, pf, (double *)area, base, nullptr, kBox, box);
     __syncthreads();
 }
 
